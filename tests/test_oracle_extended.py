@@ -1,0 +1,84 @@
+"""Pins of the oracle's extended sparse system E and of sigma_0.
+
+Paper: Sec. 2.1, eq. (Ax=b_extended): solving E [x; 0] = [b; 0] gives the
+solution of A x = b; E is symmetric for symmetric A thanks to the ordering
+of the equations. Sec. 2.4: sigma_0(E) is the largest singular value of E.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle.extended import R2
+from oracle.h2 import H2
+from oracle.tree import Tree
+
+
+def build(n, dim, depth, order, eps, kernel="imq", kp=0.02, shift=1.0, seed=41, sigma0=None):
+    pts = W.uniform_cube(n, dim, seed)
+    tr = Tree(pts, depth)
+    h = H2(tr, kernel, kp, shift, order)
+    return pts, tr, h, R2(h, eps, sigma0=sigma0)
+
+
+@pytest.mark.parametrize("dim,depth,order", [(2, 3, 3), (3, 2, 2), (2, 4, 2)])
+def test_extended_solve_reproduces_Atilde(dim, depth, order):
+    pts, tr, h, r2 = build(300, dim, depth, order, 1e-15)
+    # bases are still complete at this tolerance, so E represents A~ exactly
+    E = r2.dense_E()
+    b = W.normal_rhs(300, 1, 5)[:, 0]
+    rhs = np.zeros(E.shape[0])
+    rhs[:300] = b[tr.perm]
+    xt = np.linalg.solve(E, rhs)[:300]
+    x = np.empty(300)
+    x[tr.perm] = xt
+    xd = np.linalg.solve(h.dense(), b)
+    assert np.linalg.norm(x - xd) <= 1e-12 * np.linalg.norm(xd)
+
+
+def test_E_symmetric_for_symmetric_kernel():
+    _, _, _, r2 = build(250, 2, 3, 3, 1e-15)
+    E = r2.dense_E()
+    assert np.linalg.norm(E - E.T) <= 1e-13 * np.linalg.norm(E)
+
+
+def test_bases_orthonormal_and_transfers_nested():
+    pts = W.uniform_cube(400, 3, 43)
+    tr = Tree(pts, 3)
+    h = H2(tr, "imq", 0.02, 1.0, 3)
+    r2 = R2(h, 1e-15, sigma0=1.0, weights=False)
+    r2.r_pre = r2.r
+    for i, U in r2.U.items():
+        assert np.allclose(U.T @ U, np.eye(U.shape[1]), atol=1e-12)
+    # the effective basis of a level-2 box on its points, blockdiag(U_c) stack(PU_c), is orthonormal
+    L = tr.L
+    assert L == 3
+    lev2 = tr.levels[2]
+    for p in range(lev2.nb):
+        cs = lev2.children[p]
+        rows = sum(r2.U[c].shape[0] for c in cs)
+        Ueff = np.zeros((rows, r2.r_pre[2][p]))
+        o = 0
+        for c in cs:
+            Ueff[o:o + r2.U[c].shape[0]] = r2.U[c] @ r2.PU[L][c]
+            o += r2.U[c].shape[0]
+        assert np.allclose(Ueff.T @ Ueff, np.eye(Ueff.shape[1]), atol=1e-11)
+
+
+def test_power_sigma0_matches_dense_svd():
+    # brute force: largest singular value of the dense E (unrotated operators)
+    pts = W.uniform_cube(200, 2, 47)
+    tr = Tree(pts, 3)
+    h = H2(tr, "imq", 0.02, 1.0, 2)
+    r2 = R2(h, 1e-15, weights=False)
+    sig = np.linalg.norm(r2.dense_E(), 2)
+    assert abs(r2.sigma0 - sig) <= 1e-8 * sig
+    assert r2.sigma0 >= 1.0
+
+
+def test_truncation_rank_rule_strict():
+    # tau scales with eps; a larger eps can only keep fewer directions
+    _, _, _, a = build(400, 2, 3, 4, 1e-2, seed=45)
+    _, _, _, b = build(400, 2, 3, 4, 1e-8, seed=45, sigma0=a.sigma0)
+    for l in a.k_init:
+        assert all(x <= y for x, y in zip(a.k_init[l], b.k_init[l]))
+    assert sum(map(sum, a.k_init.values())) < sum(map(sum, b.k_init.values()))
