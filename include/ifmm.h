@@ -1,0 +1,177 @@
+/*
+ * ifmm.h - C ABI of the MI355X inverse fast multipole method (IFMM) library.
+ *
+ * The library builds an H2 (black-box FMM, Chebyshev) representation of a
+ * dense kernel matrix A_ij = K(|r_i - r_j|) + s*delta_ij on a point cloud,
+ * turns it into the extended sparse system E and factorizes E level by level
+ * up the tree with compression of well-separated fill-in to a tolerance
+ * eps (Coulier, Pouransari & Darve, "The inverse fast multipole method",
+ * Sec. 2 and Alg. 1-3). The factorization gives an approximate direct solve
+ * x = A~^-1 b for any number of right-hand sides and serves as a
+ * preconditioner for GMRES (Sec. 3.2).
+ *
+ * Conventions for every entry point
+ *   - Array arguments are DEVICE pointers (memory of the current HIP device),
+ *     owned by the caller, unless the argument says "host".
+ *   - Vectors and blocks of right-hand sides are column-major with a leading
+ *     dimension ld >= n, in the caller's point order.
+ *   - Points are row-major, n x dim, float64.
+ *   - All work is ordered on the stream given in ifmm_options.stream (0 =
+ *     the null stream). Calls on one handle must not overlap; different
+ *     handles may be used concurrently from different host threads.
+ *   - No exception crosses the ABI: every entry point returns an ifmm_status
+ *     code; ifmm_strerror() gives a short message and ifmm_last_error()
+ *     a longer, thread-local description of the last failure.
+ *   - Handle life cycle: BUILT (after ifmm_build) -> FACTORIZED (after
+ *     ifmm_factorize). ifmm_matvec is legal in both states; ifmm_solve and
+ *     ifmm_gmres need FACTORIZED; factorizing again is allowed.
+ */
+#ifndef IFMM_H
+#define IFMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  IFMM_OK = 0,
+  IFMM_ERR_ARG = 1,        /* invalid argument (null pointer, bad size, dim, order...) */
+  IFMM_ERR_OOM = 2,        /* device allocation failed or the HBM budget was exceeded */
+  IFMM_ERR_SINGULAR = 3,   /* a pivot block or the top system is exactly singular */
+  IFMM_ERR_NUMERICAL = 4,  /* a non-finite value appeared */
+  IFMM_ERR_STATE = 5,      /* call not legal in the handle's state */
+  IFMM_ERR_HIP = 6,        /* a HIP runtime call failed */
+  IFMM_ERR_INTERNAL = 7    /* an internal consistency check failed */
+} ifmm_status;
+
+/* Matrix-entry kernel K(r) (Sec. 2.1; Sec. 3.1 gives the paper's own kernel). */
+typedef enum {
+  IFMM_K_IMQ = 0,    /* 1/sqrt(r^2 + c^2),           param = c */
+  IFMM_K_GAUSS = 1,  /* exp(-r^2/h^2),               param = h */
+  IFMM_K_PAPER = 2,  /* 1 at r=0, r/d below d, d/r above (Sec. 3.1), param = d */
+  IFMM_K_POLY2 = 3   /* 1 + r^2 (reproduced exactly by order >= 3; for tests) */
+} ifmm_kernel_kind;
+
+typedef struct {
+  int kind;            /* ifmm_kernel_kind */
+  double param;        /* c, h or d */
+  double diag_shift;   /* s: added to the diagonal a_ii only */
+} ifmm_kernel;
+
+typedef struct {
+  int precision;              /* 64 (default) or 32: arithmetic of the factors and
+                                 of ifmm_solve; the matvec is always float64 */
+  int leaf_max;               /* used when depth <= 0: the smallest uniform depth
+                                 >= 2 whose leaves hold at most leaf_max points */
+  int rank_max;               /* > 0: no basis keeps more than rank_max columns
+                                 (0 = bounded only by the box size) */
+  double sigma0_override;     /* > 0: use this value as sigma_0(E) instead of the
+                                 power-iteration estimate */
+  int64_t hbm_budget_bytes;   /* > 0: fail with IFMM_ERR_OOM rather than let the
+                                 handle's device memory exceed this */
+  void* stream;               /* hipStream_t; 0 = null stream */
+} ifmm_options;
+
+/* Counters and phase times of a handle (host struct, filled by ifmm_query). */
+typedef struct {
+  int64_t n;
+  int dim, depth, cheb_order, precision;
+  double eps, sigma0, tau;
+  int levels;                 /* number of eliminated levels (depth - 1) */
+  int max_rank[32];           /* by level: largest final rank */
+  double mean_rank[32];       /* by level: mean final rank */
+  int64_t boxes[32];          /* by level: occupied boxes */
+  double t_build_ms, t_sigma0_ms, t_factor_ms, t_last_solve_ms, t_last_matvec_ms;
+  double factor_flops;        /* algorithmic flops of the last factorization
+                                 (LU, triangular solves, Schur products,
+                                 recompressions, edge updates, merge, top) */
+  double schur_flops;         /* of which Schur-complement products */
+  int64_t factor_bytes;       /* bytes of the stored factors (read once per solve) */
+  int64_t device_bytes;       /* device memory held by the handle now */
+  int64_t device_bytes_peak;  /* peak over the handle's life */
+  int error_level, error_box; /* where IFMM_ERR_SINGULAR / NUMERICAL arose, else -1 */
+  int gmres_iters;            /* of the last ifmm_gmres call (max over columns) */
+  double gmres_relres;        /* of the last ifmm_gmres call (max over columns) */
+} ifmm_stats;
+
+typedef struct ifmm_problem* ifmm_handle;
+
+/* Fill *opt with the defaults (precision 64, leaf_max 64, no rank cap, no
+   sigma_0 override, no budget, null stream). */
+void ifmm_default_options(ifmm_options* opt);
+
+/*
+ * ifmm_build - tree, H2 operators and the initial extended system
+ * (Alg. 1, lines constructing the octree and initialising the operators;
+ * Sec. 3 opening: Chebyshev interpolation followed by an SVD; Sec. 2.4:
+ * sigma_0(E) and the rank rule).
+ *   points      device, n x dim row-major float64; copied, not retained
+ *   n           number of points (>= 1)
+ *   dim         1, 2 or 3
+ *   k           kernel and diagonal shift
+ *   depth       leaf level L (>= 2); <= 0 selects it from opt->leaf_max
+ *   cheb_order  Chebyshev nodes per dimension n (1..8)
+ *   eps         relative tolerance of the compressions (>= 0)
+ *   opt         host; may be NULL for defaults
+ *   out         host; receives the handle (NULL on failure)
+ * The handle owns all device memory it allocates; free it with ifmm_destroy.
+ */
+int ifmm_build(const double* points, int64_t n, int dim, ifmm_kernel k, int depth,
+               int cheb_order, double eps, const ifmm_options* opt, ifmm_handle* out);
+
+/*
+ * ifmm_factorize - eliminate levels L..2 in colour (independent-set) order,
+ * compress and redirect well-separated fill-in, merge each level into its
+ * parent and factorize the dense top system (Alg. 1 and 2; Alg. 3; eqs.
+ * P2P_kj to K_merge). Stores the factors for any number of later solves.
+ */
+int ifmm_factorize(ifmm_handle h);
+
+/*
+ * ifmm_solve - x = IFMM^-1 b for nrhs right-hand sides (Alg. 1, substitution).
+ *   b, x   device, n x nrhs column-major float64, leading dimension ld;
+ *          x may alias b
+ */
+int ifmm_solve(ifmm_handle h, const double* b, double* x, int nrhs, int64_t ld);
+
+/*
+ * ifmm_matvec - y = A~ x with the H2 operators of the build (eq. A_decomp_l3
+ * and A_decomp_l2; the FMM product used by GMRES in Sec. 3.2), float64.
+ *   x, y   device, n x nrhs column-major, leading dimension ld; must not alias
+ */
+int ifmm_matvec(ifmm_handle h, const double* x, double* y, int nrhs, int64_t ld);
+
+/*
+ * ifmm_gmres - right-preconditioned, non-restarted GMRES (Sec. 3.2): the
+ * products use op's H2 matvec in float64, the preconditioner is prec's
+ * factorization (float32 or float64); orthogonalisation is float64.
+ * op and prec must describe the same points (same n); they may be the same
+ * handle. Each column is an independent GMRES run.
+ *   b, x        device, n x nrhs, leading dimension ld; x is overwritten
+ *   tol         stop when ||b - A~ x|| <= tol ||b|| (per column)
+ *   maxit       iteration limit (<= 1000)
+ *   iters_out   host, may be NULL: largest iteration count over the columns
+ *   relres_out  host, may be NULL: largest true relative residual at exit
+ */
+int ifmm_gmres(ifmm_handle op, ifmm_handle prec, const double* b, double* x, int nrhs,
+               int64_t ld, double tol, int maxit, int* iters_out, double* relres_out);
+
+/* ifmm_query - copy counters and phase times into *s (host). */
+int ifmm_query(ifmm_handle h, ifmm_stats* s);
+
+/* ifmm_destroy - release the handle and all its device memory; NULL is a no-op. */
+int ifmm_destroy(ifmm_handle h);
+
+/* Static message for a status code. */
+const char* ifmm_strerror(int code);
+
+/* Thread-local description of the last failure of this thread (never NULL). */
+const char* ifmm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IFMM_H */

@@ -1,0 +1,661 @@
+// Build: tree (GPU keys + sort, host lists), R1 operators, R2 initial operators
+// with sigma_0, and the H2 product. Alg. 1, lines constructing the octree and
+// initialising the operators of every level; Sec. 3 opening; Sec. 2.4.
+#pragma once
+
+#include "r2init.hpp"
+
+namespace ifmm {
+
+template <class T>
+inline DevBuf up(Problem& P, const std::vector<T>& v) {
+  DevBuf b;
+  P.upload(b, v);
+  return b;
+}
+
+inline void grid1(int64_t n, dim3& g) { g = dim3((unsigned)std::max<int64_t>(1, ceil_div(n, WG))); }
+
+// ----------------------------------------------------------------- tree
+inline void build_tree(Problem& P, const double* d_points, int depth, int leaf_max) {
+  const int64_t n = P.n;
+  const int d = P.d;
+  // bounding box
+  const int nblk = (int)std::min<int64_t>(1024, std::max<int64_t>(1, ceil_div(n, WG)));
+  DevBuf part;
+  part.alloc(sizeof(double) * nblk * 2 * d, &P.mem);
+  hipLaunchKernelGGL(k_bbox_partial, dim3(nblk), dim3(WG), 0, P.stream, d_points, n, d, part.as<double>());
+  IFMM_LAUNCH_CHECK();
+  std::vector<double> hp;
+  P.download(hp, part.p, (size_t)nblk * 2 * d);
+  double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+  for (int k = 0; k < d; ++k) {
+    lo[k] = INFINITY;
+    hi[k] = -INFINITY;
+    for (int b = 0; b < nblk; ++b) {
+      lo[k] = std::min(lo[k], hp[(size_t)b * 2 * d + k]);
+      hi[k] = std::max(hi[k], hp[(size_t)b * 2 * d + d + k]);
+    }
+    if (!std::isfinite(lo[k]) || !std::isfinite(hi[k])) fail(IFMM_ERR_ARG, "non-finite point coordinates");
+  }
+  double side = 0;
+  for (int k = 0; k < d; ++k) side = std::max(side, hi[k] - lo[k]);
+  side = side * (1.0 + 1e-12);
+  if (side == 0.0) side = 1.0;
+  HTree& T = P.T;
+  T.n = n;
+  T.d = d;
+  T.side = side;
+  for (int k = 0; k < 3; ++k) T.origin[k] = 0;
+  for (int k = 0; k < d; ++k) T.origin[k] = 0.5 * (lo[k] + hi[k]) - 0.5 * side;
+  T.inv = 1.0 / side;
+
+  DevBuf keys_in, keys_out, idx_in, idx_out, tmp;
+  keys_in.alloc(sizeof(uint64_t) * n, &P.mem);
+  keys_out.alloc(sizeof(uint64_t) * n, &P.mem);
+  idx_in.alloc(sizeof(int) * n, &P.mem);
+  idx_out.alloc(sizeof(int) * n, &P.mem);
+  dim3 g;
+  grid1(n, g);
+  auto sort_at = [&](int L) {
+    hipLaunchKernelGGL(k_point_keys, g, dim3(WG), 0, P.stream, d_points, n, d, T.origin[0], T.origin[1],
+                       T.origin[2], T.inv, L, keys_in.as<uint64_t>(), idx_in.as<int>());
+    IFMM_LAUNCH_CHECK();
+    size_t tb = 0;
+    IFMM_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tb, keys_in.as<uint64_t>(), keys_out.as<uint64_t>(),
+                                                idx_in.as<int>(), idx_out.as<int>(), (int)n, 0, L * d, P.stream));
+    tmp.reserve(tb + 16, &P.mem);
+    IFMM_HIP(hipcub::DeviceRadixSort::SortPairs(tmp.p, tb, keys_in.as<uint64_t>(), keys_out.as<uint64_t>(),
+                                                idx_in.as<int>(), idx_out.as<int>(), (int)n, 0, L * d, P.stream));
+  };
+  const int Lmax = d == 3 ? 20 : d == 2 ? 30 : 60;
+  int L = depth;
+  std::vector<uint64_t> hk;
+  if (L <= 0) {
+    const int Ltry = std::min(Lmax, 16);
+    sort_at(Ltry);
+    P.download(hk, keys_out.p, (size_t)n);
+    L = -1;
+    for (int cand = 2; cand <= Ltry && L < 0; ++cand) {
+      const int sh = d * (Ltry - cand);
+      int64_t run = 0, best = 0;
+      for (int64_t i = 0; i < n; ++i) {
+        run = (i > 0 && (hk[i] >> sh) == (hk[i - 1] >> sh)) ? run + 1 : 1;
+        best = std::max(best, run);
+      }
+      if (best <= leaf_max) L = cand;
+    }
+    if (L < 0) L = Ltry;
+  }
+  if (L < 2 || L > Lmax) fail(IFMM_ERR_ARG, "depth must be in [2, " + std::to_string(Lmax) + "]");
+  P.L = T.L = L;
+  sort_at(L);
+  P.download(hk, keys_out.p, (size_t)n);
+  std::vector<int> hperm;
+  P.download(hperm, idx_out.p, (size_t)n);
+  T.perm.assign(hperm.begin(), hperm.end());
+  plan_tree(T, hk);
+  P.perm = std::move(idx_out);
+  P.pts.alloc(sizeof(double) * n * d, &P.mem);
+  hipLaunchKernelGGL(k_gather_points, g, dim3(WG), 0, P.stream, d_points, P.perm.as<int>(), n, d,
+                     P.pts.as<double>());
+  IFMM_LAUNCH_CHECK();
+  P.upload(P.leaf_start, T.leaf_start);
+  // device copies of the level tables
+  P.ldev.clear();
+  P.ldev.resize(L + 1);
+  for (int l = 2; l <= L; ++l) {
+    const HLevel& lv = T.lev[l];
+    LevelDev& ld = P.ldev[l];
+    ld.nb = lv.nb;
+    P.upload(ld.coords, lv.coords);
+    P.upload(ld.nb_start, lv.nb_start);
+    P.upload(ld.nbr, lv.nbr);
+    P.upload(ld.in_start, lv.in_start);
+    P.upload(ld.inter, lv.inter);
+    ld.npairs = (int64_t)lv.inter.size();
+    if (l > 2) P.upload(ld.parent, lv.parent);
+    if (l < L) P.upload(ld.ch_start, lv.ch_start);
+    std::vector<int> cb(lv.nb);
+    for (int i = 0; i < lv.nb; ++i) {
+      int b = 0;
+      for (int k = 0; k < d; ++k) b |= (lv.coords[(size_t)i * d + k] & 1) << k;
+      cb[i] = b;
+    }
+    P.upload(ld.cbits, cb);
+    // position of pair (j, i) in j's list, for every pair (i, j)
+    std::vector<int> rev(lv.inter.size());
+    for (int i = 0; i < lv.nb; ++i)
+      for (int t = lv.in_start[i]; t < lv.in_start[i + 1]; ++t) {
+        const int j = lv.inter[t];
+        const int* b = &lv.inter[lv.in_start[j]];
+        const int* e = &lv.inter[lv.in_start[j + 1]];
+        const int* f = std::lower_bound(b, e, i);
+        IFMM_CHECK(f != e && *f == i, "interaction lists not symmetric");
+        rev[t] = (int)(f - &lv.inter[0]);
+      }
+    P.upload(ld.in_rev, rev);
+  }
+}
+
+// ------------------------------------------------------------------- R1
+inline void build_r1(Problem& P) {
+  const int d = P.d, q = P.q, L = P.L;
+  const HTree& T = P.T;
+  P.ubar.alloc(sizeof(double) * P.n * q, &P.mem);
+  hipLaunchKernelGGL(k_leaf_ubar, dim3(T.lev[L].nb), dim3(WG), 0, P.stream, P.pts.as<double>(),
+                     P.leaf_start.as<int64_t>(), P.ldev[L].coords.as<int>(), T.lev[L].nb, P.cc, T.origin[0],
+                     T.origin[1], T.origin[2], T.box_size(L), P.ubar.as<double>());
+  IFMM_LAUNCH_CHECK();
+  // transfers, one per child position: T_b[m, m'] = l_{m'}(child node m in parent coordinates)
+  std::vector<double> tt((size_t)(1 << d) * q * q);
+  for (int b = 0; b < (1 << d); ++b)
+    for (int m = 0; m < q; ++m) {
+      double x[3];
+      node_ref(P.cc, m, x);
+      for (int k = 0; k < d; ++k) x[k] = 0.5 * x[k] + 0.5 * (((b >> k) & 1) ? 1.0 : -1.0);
+      for (int mp = 0; mp < q; ++mp) tt[(size_t)b * q * q + m + (size_t)mp * q] = lagrange_nd(P.cc, mp, x);
+    }
+  P.upload(P.Ttab, tt);
+  int c7 = 1;
+  for (int k = 0; k < d; ++k) c7 *= 7;
+  P.m2l.clear();
+  P.m2l.resize(L + 1);
+  for (int l = 2; l <= L; ++l) {
+    P.m2l[l].alloc(sizeof(double) * c7 * q * q, &P.mem);
+    hipLaunchKernelGGL(k_m2l_table, dim3(c7), dim3(WG), 0, P.stream, P.cc, P.kf, T.box_size(l),
+                       P.m2l[l].as<double>());
+    IFMM_LAUNCH_CHECK();
+  }
+}
+
+// y = A~ x (tree order in and out), nrhs columns; x, y device, leading dim n.
+inline void matvec_tree(Problem& P, const double* x, double* y, int nrhs) {
+  const int q = P.q, L = P.L, d = P.d;
+  const HTree& T = P.T;
+  if ((int)P.mv_w.size() != L + 1 || P.mv_nrhs < nrhs) {
+    P.mv_w.clear();
+    P.mv_g.clear();
+    P.mv_w.resize(L + 1);
+    P.mv_g.resize(L + 1);
+    for (int l = 2; l <= L; ++l) {
+      P.mv_w[l].alloc(sizeof(double) * T.lev[l].nb * q * nrhs, &P.mem);
+      P.mv_g[l].alloc(sizeof(double) * T.lev[l].nb * q * nrhs, &P.mem);
+    }
+    P.mv_nrhs = nrhs;
+  }
+  hipLaunchKernelGGL(k_p2m, dim3(T.lev[L].nb), dim3(WG), 0, P.stream, P.ubar.as<double>(),
+                     P.leaf_start.as<int64_t>(), T.lev[L].nb, q, x, P.n, nrhs, P.mv_w[L].as<double>());
+  IFMM_LAUNCH_CHECK();
+  for (int l = L - 1; l >= 2; --l) {
+    hipLaunchKernelGGL(k_m2m, dim3(T.lev[l].nb), dim3(WG), 0, P.stream, P.ldev[l].ch_start.as<int>(),
+                       P.ldev[l + 1].cbits.as<int>(), T.lev[l].nb, q, nrhs, P.Ttab.as<double>(),
+                       P.mv_w[l + 1].as<double>(), P.mv_w[l].as<double>());
+    IFMM_LAUNCH_CHECK();
+  }
+  for (int l = 2; l <= L; ++l) {
+    hipLaunchKernelGGL(k_m2l, dim3(T.lev[l].nb), dim3(WG), 0, P.stream, P.ldev[l].in_start.as<int>(),
+                       P.ldev[l].inter.as<int>(), P.ldev[l].coords.as<int>(), T.lev[l].nb, d, q, nrhs,
+                       P.m2l[l].as<double>(), P.mv_w[l].as<double>(), P.mv_g[l].as<double>());
+    IFMM_LAUNCH_CHECK();
+  }
+  for (int l = 3; l <= L; ++l) {
+    hipLaunchKernelGGL(k_l2l, dim3(T.lev[l].nb), dim3(WG), 0, P.stream, P.ldev[l].parent.as<int>(),
+                       P.ldev[l].cbits.as<int>(), T.lev[l].nb, q, nrhs, P.Ttab.as<double>(),
+                       P.mv_g[l - 1].as<double>(), P.mv_g[l].as<double>());
+    IFMM_LAUNCH_CHECK();
+  }
+  hipLaunchKernelGGL(k_l2p_p2p, dim3(T.lev[L].nb), dim3(WG), 0, P.stream, P.pts.as<double>(),
+                     P.leaf_start.as<int64_t>(), P.ldev[L].nb_start.as<int>(), P.ldev[L].nbr.as<int>(),
+                     T.lev[L].nb, d, q, nrhs, P.kf, P.ubar.as<double>(), P.mv_g[L].as<double>(), x, P.n, y,
+                     P.n, 1);
+  IFMM_LAUNCH_CHECK();
+}
+
+// ------------------------------------------------------------------- R2
+struct R2Pre {                       // pre-rotation orthonormal operators (float64)
+  std::vector<std::vector<int>> r;             // by level
+  std::vector<std::vector<int64_t>> roff;      // R factor offsets (r_i x q)
+  std::vector<std::vector<int64_t>> ppoff;     // by level l > 2: PU_pre(i) offsets
+  std::vector<std::vector<int>> pld;           // its leading dimension
+  std::vector<std::vector<int64_t>> kpoff;     // per pair offsets of K_pre
+  std::vector<DevBuf> R, Kpre, dr, droff, dppoff, dpld, dkpoff;
+  DevBuf Q;                                    // leaf bases, ubar layout
+  DevBuf Pst;                                  // stacked Q of the transfer QRs (all levels)
+};
+
+__global__ void k_fill_valid(double* __restrict__ v, int nb, int q, const int* __restrict__ r, double a) {
+  const int i = blockIdx.x;
+  if (i >= nb) return;
+  for (int m = threadIdx.x; m < q; m += WG) v[(int64_t)i * q + m] = m < r[i] ? a : 0.0;
+}
+
+inline double norm2(Problem& P, const double* v, int64_t n, DevBuf& part) {
+  const int nb = (int)std::min<int64_t>(512, std::max<int64_t>(1, ceil_div(n, WG)));
+  part.reserve(sizeof(double) * nb, &P.mem);
+  hipLaunchKernelGGL(k_sumsq_partial, dim3(nb), dim3(WG), 0, P.stream, v, n, part.as<double>());
+  IFMM_LAUNCH_CHECK();
+  std::vector<double> h;
+  P.download(h, part.p, (size_t)nb);
+  double s = 0;
+  for (double x : h) s += x;
+  return std::sqrt(s);
+}
+
+inline void build_r2(Problem& P, double sigma0_override) {
+  const int q = P.q, L = P.L;
+  const HTree& T = P.T;
+  R2Pre R;
+  R.r.resize(L + 1);
+  R.roff.resize(L + 1);
+  R.ppoff.resize(L + 1);
+  R.pld.resize(L + 1);
+  R.kpoff.resize(L + 1);
+  R.R.resize(L + 1);
+  R.Kpre.resize(L + 1);
+  R.dr.resize(L + 1);
+  R.droff.resize(L + 1);
+  R.dppoff.resize(L + 1);
+  R.dpld.resize(L + 1);
+  R.dkpoff.resize(L + 1);
+  DevBuf dscr, work;
+  // ---- leaf QR
+  {
+    const HLevel& lv = T.lev[L];
+    auto& r = R.r[L];
+    auto& ro = R.roff[L];
+    r.resize(lv.nb);
+    ro.resize(lv.nb);
+    int64_t tot = 0;
+    for (int i = 0; i < lv.nb; ++i) {
+      const int64_t m = T.leaf_start[i + 1] - T.leaf_start[i];
+      r[i] = (int)std::min<int64_t>(m, q);
+      ro[i] = tot;
+      tot += (int64_t)r[i] * q;
+    }
+    R.R[L].alloc(sizeof(double) * tot, &P.mem);
+    R.Q.alloc(sizeof(double) * P.n * q, &P.mem);
+    IFMM_HIP(hipMemsetAsync(R.Q.p, 0, sizeof(double) * P.n * q, P.stream));
+    work.alloc(sizeof(double) * P.n * q, &P.mem);
+    IFMM_HIP(hipMemcpyAsync(work.p, P.ubar.p, sizeof(double) * P.n * q, hipMemcpyDeviceToDevice, P.stream));
+    std::vector<QrDesc> qd(lv.nb);
+    for (int i = 0; i < lv.nb; ++i) {
+      const int64_t s = T.leaf_start[i], m = T.leaf_start[i + 1] - s;
+      QrDesc& dd = qd[i];
+      dd.A = work.as<double>() + s * q;
+      dd.R = R.R[L].as<double>() + ro[i];
+      dd.Q = R.Q.as<double>() + s * q;
+      dd.M = (int)m; dd.N = q; dd.lda = (int)m; dd.ldr = r[i]; dd.ldq = (int)m; dd.pad = 0;
+    }
+    run_qr<double>(P, qd, dscr);
+  }
+  // ---- transfers: QR of the stacked R_c T_c, bottom-up
+  std::vector<int64_t> pst_off(L + 1, 0);
+  int64_t pst_tot = 0;
+  std::vector<std::vector<int>> rows(L + 1);
+  for (int l = L - 1; l >= 2; --l) {
+    const HLevel& lv = T.lev[l];
+    rows[l].resize(lv.nb);
+    R.r[l].resize(lv.nb);
+    for (int p = 0; p < lv.nb; ++p) {
+      int s = 0;
+      for (int c = lv.ch_start[p]; c < lv.ch_start[p + 1]; ++c) s += R.r[l + 1][c];
+      rows[l][p] = s;
+      R.r[l][p] = std::min(s, q);
+      pst_tot += (int64_t)s * std::min(s, q);
+    }
+  }
+  R.Pst.alloc(sizeof(double) * std::max<int64_t>(pst_tot, 1), &P.mem);
+  int64_t pst_cur = 0;
+  for (int l = L - 1; l >= 2; --l) {
+    const HLevel& lv = T.lev[l];
+    const HLevel& lc = T.lev[l + 1];
+    auto& r = R.r[l];
+    auto& ro = R.roff[l];
+    ro.resize(lv.nb);
+    int64_t rt = 0, mt = 0;
+    std::vector<int64_t> moff(lv.nb);
+    for (int p = 0; p < lv.nb; ++p) {
+      ro[p] = rt;
+      rt += (int64_t)r[p] * q;
+      moff[p] = mt;
+      mt += (int64_t)rows[l][p] * q;
+    }
+    R.R[l].alloc(sizeof(double) * std::max<int64_t>(rt, 1), &P.mem);
+    work.reserve(sizeof(double) * std::max<int64_t>(mt, 1), &P.mem);
+    GemmBatch gb;
+    std::vector<int> cb(lc.nb);
+    for (int c = 0; c < lc.nb; ++c) {
+      int b = 0;
+      for (int k = 0; k < P.d; ++k) b |= (lc.coords[(size_t)c * P.d + k] & 1) << k;
+      cb[c] = b;
+    }
+    auto& ppo = R.ppoff[l + 1];
+    auto& pl = R.pld[l + 1];
+    ppo.assign(lc.nb, 0);
+    pl.assign(lc.nb, 1);
+    std::vector<QrDesc> qd(lv.nb);
+    for (int p = 0; p < lv.nb; ++p) {
+      int off = 0;
+      const int rowsp = rows[l][p];
+      for (int c = lv.ch_start[p]; c < lv.ch_start[p + 1]; ++c) {
+        const int rc = R.r[l + 1][c];
+        gb.add(R.R[l + 1].as<double>() + R.roff[l + 1][c], rc, 0, P.Ttab.as<double>() + (int64_t)cb[c] * q * q,
+               q, 0, work.as<double>() + moff[p] + off, rowsp, rc, q, q, 1.0, 0.0);
+        ppo[c] = pst_cur + off;
+        pl[c] = rowsp;
+        off += rc;
+      }
+      QrDesc& dd = qd[p];
+      dd.A = work.as<double>() + moff[p];
+      dd.R = R.R[l].as<double>() + ro[p];
+      dd.Q = R.Pst.as<double>() + pst_cur;
+      dd.M = rowsp; dd.N = q; dd.lda = rowsp; dd.ldr = r[p]; dd.ldq = rowsp; dd.pad = 0;
+      pst_cur += (int64_t)rowsp * r[p];
+    }
+    run_gemm<double>(P, gb, dscr);
+    run_qr<double>(P, qd, dscr);
+  }
+  // ---- device copies of ranks/offsets, K_pre blocks
+  for (int l = 2; l <= L; ++l) {
+    const HLevel& lv = T.lev[l];
+    R.dr[l] = up(P, R.r[l]);
+    R.droff[l] = up(P, R.roff[l]);
+    if (l > 2) {
+      R.dppoff[l] = up(P, R.ppoff[l]);
+      R.dpld[l] = up(P, R.pld[l]);
+    }
+    auto& ko = R.kpoff[l];
+    ko.resize(lv.inter.size());
+    int64_t kt = 0;
+    for (int i = 0; i < lv.nb; ++i)
+      for (int t = lv.in_start[i]; t < lv.in_start[i + 1]; ++t) {
+        ko[t] = kt;
+        kt += (int64_t)R.r[l][i] * R.r[l][lv.inter[t]];
+      }
+    R.dkpoff[l] = up(P, ko);
+    R.Kpre[l].alloc(sizeof(double) * std::max<int64_t>(kt, 1), &P.mem);
+    if (!lv.inter.empty()) {
+      hipLaunchKernelGGL(k_kpre, dim3((unsigned)lv.inter.size()), dim3(WG), 0, P.stream,
+                         P.ldev[l].in_start.as<int>(), P.ldev[l].inter.as<int>(), P.ldev[l].coords.as<int>(), lv.nb,
+                         P.d, q, P.m2l[l].as<double>(), R.R[l].as<double>(), R.droff[l].as<int64_t>(),
+                         R.dr[l].as<int>(), R.Kpre[l].as<double>(), R.dkpoff[l].as<int64_t>());
+      IFMM_LAUNCH_CHECK();
+    }
+  }
+  // ---- sigma_0 by power iteration on E (symmetric: E^T E = E E)
+  const double t_s0 = now_ms();
+  {
+    std::vector<int64_t> zo(L + 1), yo(L + 1);
+    int64_t tot = P.n;
+    for (int l = L; l >= 2; --l) {
+      zo[l] = tot;
+      tot += (int64_t)T.lev[l].nb * q;
+      yo[l] = tot;
+      tot += (int64_t)T.lev[l].nb * q;
+    }
+    DevBuf v, w, part;
+    v.alloc(sizeof(double) * tot, &P.mem);
+    w.alloc(sizeof(double) * tot, &P.mem);
+    // entries of a box beyond its rank are never written by E: keep them zero
+    IFMM_HIP(hipMemsetAsync(w.p, 0, sizeof(double) * tot, P.stream));
+    auto applyE = [&](const double* in, double* out) {
+      hipLaunchKernelGGL(k_l2p_p2p, dim3(T.lev[L].nb), dim3(WG), 0, P.stream, P.pts.as<double>(),
+                         P.leaf_start.as<int64_t>(), P.ldev[L].nb_start.as<int>(), P.ldev[L].nbr.as<int>(),
+                         T.lev[L].nb, P.d, q, 1, P.kf, R.Q.as<double>(), in + zo[L], in, P.n, out, P.n, 1);
+      IFMM_LAUNCH_CHECK();
+      for (int l = L; l >= 2; --l) {
+        const int nb = T.lev[l].nb;
+        const bool leaf = l == L;
+        hipLaunchKernelGGL(k_e_zrows, dim3(nb), dim3(WG), 0, P.stream, nb, q, R.dr[l].as<int>(), (int)leaf,
+                           P.leaf_start.as<int64_t>(), R.Q.as<double>(), in,
+                           leaf ? nullptr : P.ldev[l].ch_start.as<int>(),
+                           leaf ? nullptr : R.Pst.as<double>(), leaf ? nullptr : R.dppoff[l + 1].as<int64_t>(),
+                           leaf ? nullptr : R.dpld[l + 1].as<int>(), leaf ? nullptr : R.dr[l + 1].as<int>(),
+                           leaf ? nullptr : in + yo[l + 1], in + yo[l], out + zo[l]);
+        IFMM_LAUNCH_CHECK();
+        const bool top = l == 2;
+        hipLaunchKernelGGL(k_e_yrows, dim3(nb), dim3(WG), 0, P.stream, nb, q, R.dr[l].as<int>(),
+                           P.ldev[l].in_start.as<int>(), P.ldev[l].inter.as<int>(), R.Kpre[l].as<double>(),
+                           R.dkpoff[l].as<int64_t>(), in + zo[l], in + yo[l],
+                           top ? nullptr : P.ldev[l].parent.as<int>(), top ? nullptr : R.Pst.as<double>(),
+                           top ? nullptr : R.dppoff[l].as<int64_t>(), top ? nullptr : R.dpld[l].as<int>(),
+                           top ? nullptr : R.dr[l - 1].as<int>(), top ? nullptr : in + zo[l - 1],
+                           out + yo[l]);
+        IFMM_LAUNCH_CHECK();
+      }
+    };
+    if (sigma0_override > 0) {
+      P.sigma0 = sigma0_override;
+    } else {
+      IFMM_HIP(hipMemsetAsync(v.p, 0, sizeof(double) * tot, P.stream));
+      dim3 g;
+      grid1(P.n, g);
+      hipLaunchKernelGGL(k_fill, g, dim3(WG), 0, P.stream, v.as<double>(), P.n, 1.0);
+      int64_t cnt = P.n;
+      for (int l = L; l >= 2; --l) {
+        for (int part_i = 0; part_i < 2; ++part_i)
+          hipLaunchKernelGGL(k_fill_valid, dim3(T.lev[l].nb), dim3(WG), 0, P.stream,
+                             v.as<double>() + (part_i ? yo[l] : zo[l]), T.lev[l].nb, q, R.dr[l].as<int>(), 1.0);
+        for (int x : R.r[l]) cnt += 2 * x;
+      }
+      IFMM_LAUNCH_CHECK();
+      dim3 gt;
+      grid1(tot, gt);
+      hipLaunchKernelGGL(k_scale, gt, dim3(WG), 0, P.stream, v.as<double>(), tot, 1.0 / std::sqrt((double)cnt));
+      double s_old = -1, s = 0;
+      int it = 0;
+      for (it = 0; it < 200; ++it) {
+        applyE(v.as<double>(), w.as<double>());
+        s = norm2(P, w.as<double>(), tot, part);
+        if (it > 0 && std::fabs(s - s_old) <= 1e-10 * s) break;
+        s_old = s;
+        applyE(w.as<double>(), v.as<double>());
+        const double nu = norm2(P, v.as<double>(), tot, part);
+        if (nu == 0.0) break;
+        hipLaunchKernelGGL(k_scale, gt, dim3(WG), 0, P.stream, v.as<double>(), tot, 1.0 / nu);
+      }
+      P.sigma0 = s;
+      P.sigma0_estimated = s;
+      P.sigma0_iters = it;
+    }
+  }
+  P.st.t_sigma0_ms = now_ms() - t_s0;
+  P.tau = std::max(P.eps, 64.0 * (P.precision == 32 ? Prec<float>::u : Prec<double>::u)) * P.sigma0;
+
+  // ---- weights, top-down
+  std::vector<std::vector<int64_t>> woff(L + 1), soff(L + 1);
+  std::vector<std::vector<int>> gcols(L + 1);
+  std::vector<DevBuf> WU(L + 1), WV(L + 1), GU(L + 1), GV(L + 1), SU(L + 1), SV(L + 1), dwoff(L + 1),
+      dgcols(L + 1);
+  std::vector<std::vector<double>> hsu(L + 1), hsv(L + 1);
+  for (int l = 2; l <= L; ++l) {
+    const HLevel& lv = T.lev[l];
+    const auto& r = R.r[l];
+    woff[l].resize(lv.nb);
+    soff[l].resize(lv.nb);
+    gcols[l].resize(lv.nb);
+    std::vector<int> mrows(lv.nb);
+    std::vector<int64_t> moff(lv.nb);
+    int64_t wt = 0, stt = 0, mt = 0;
+    for (int i = 0; i < lv.nb; ++i) {
+      int rw = 0;
+      for (int t = lv.in_start[i]; t < lv.in_start[i + 1]; ++t) rw += r[lv.inter[t]];
+      if (l > 2) rw += gcols[l - 1][lv.parent[i]];
+      mrows[i] = rw;
+      moff[i] = mt;
+      mt += (int64_t)rw * r[i];
+      woff[l][i] = wt;
+      wt += (int64_t)r[i] * r[i];
+      soff[l][i] = stt;
+      stt += r[i];
+      gcols[l][i] = std::min(rw, r[i]);
+    }
+    for (auto* b : {&WU[l], &WV[l], &GU[l], &GV[l]}) b->alloc(sizeof(double) * std::max<int64_t>(wt, 1), &P.mem);
+    for (auto* b : {&SU[l], &SV[l]}) b->alloc(sizeof(double) * std::max<int64_t>(stt, 1), &P.mem);
+    IFMM_HIP(hipMemsetAsync(SU[l].p, 0, sizeof(double) * std::max<int64_t>(stt, 1), P.stream));
+    IFMM_HIP(hipMemsetAsync(SV[l].p, 0, sizeof(double) * std::max<int64_t>(stt, 1), P.stream));
+    dwoff[l] = up(P, woff[l]);
+    dgcols[l] = up(P, gcols[l]);
+    DevBuf dm = up(P, moff), dmr = up(P, mrows);
+    DevBuf Mw, Rw, Bw;
+    Mw.alloc(sizeof(double) * std::max<int64_t>(mt, 1), &P.mem);
+    Rw.alloc(sizeof(double) * std::max<int64_t>(wt, 1), &P.mem);
+    Bw.alloc(sizeof(double) * std::max<int64_t>(wt, 1), &P.mem);
+    for (int side = 0; side < 2; ++side) {
+      DevBuf& G = side ? GV[l] : GU[l];
+      DevBuf& W = side ? WV[l] : WU[l];
+      DevBuf& S = side ? SV[l] : SU[l];
+      hipLaunchKernelGGL(k_weight_rows, dim3(lv.nb), dim3(WG), 0, P.stream, P.ldev[l].in_start.as<int>(),
+                         P.ldev[l].inter.as<int>(), nullptr, lv.nb, side, P.ldev[l].in_rev.as<int>(),
+                         R.Kpre[l].as<double>(), R.dkpoff[l].as<int64_t>(), R.dr[l].as<int>(),
+                         l > 2 ? P.ldev[l].parent.as<int>() : nullptr, R.Pst.as<double>(),
+                         l > 2 ? R.dppoff[l].as<int64_t>() : nullptr, l > 2 ? R.dpld[l].as<int>() : nullptr,
+                         l > 2 ? R.dr[l - 1].as<int>() : nullptr,
+                         l > 2 ? (side ? GV[l - 1].as<double>() : GU[l - 1].as<double>()) : nullptr,
+                         l > 2 ? dwoff[l - 1].as<int64_t>() : nullptr, l > 2 ? dgcols[l - 1].as<int>() : nullptr,
+                         Mw.as<double>(), dm.as<int64_t>(), dmr.as<int>());
+      IFMM_LAUNCH_CHECK();
+      std::vector<QrDesc> qd;
+      CopyBatch<double, double> tb;
+      std::vector<SvdDesc> sd;
+      CopyBatch<double, double> gbat;
+      for (int i = 0; i < lv.nb; ++i) {
+        const int kq = gcols[l][i];
+        if (kq == 0) continue;
+        QrDesc dd;
+        dd.A = Mw.as<double>() + moff[i];
+        dd.R = Rw.as<double>() + woff[l][i];
+        dd.Q = nullptr;
+        dd.M = mrows[i]; dd.N = r[i]; dd.lda = mrows[i]; dd.ldr = kq; dd.ldq = 1; dd.pad = 0;
+        qd.push_back(dd);
+        // B = R^T (r_i x kq)
+        tb.add(Rw.as<double>() + woff[l][i], kq, Bw.as<double>() + woff[l][i], r[i], r[i], kq, 4);
+        SvdDesc s;
+        s.B = Bw.as<double>() + woff[l][i];
+        s.U = W.as<double>() + woff[l][i];
+        s.S = S.as<double>() + soff[l][i];
+        s.M = r[i]; s.N = kq; s.ldb = r[i]; s.ldu = r[i];
+        sd.push_back(s);
+        gbat.add(W.as<double>() + woff[l][i], r[i], G.as<double>() + woff[l][i], r[i], r[i], kq, 0, 1.0,
+                 S.as<double>() + soff[l][i]);
+      }
+      run_qr<double>(P, qd, dscr);
+      run_copy(P, tb, dscr);
+      run_svd<double>(P, sd, dscr);
+      run_copy(P, gbat, dscr);
+    }
+    P.download(hsu[l], SU[l].p, (size_t)std::max<int64_t>(stt, 1));
+    P.download(hsv[l], SV[l].p, (size_t)std::max<int64_t>(stt, 1));
+  }
+  // ---- ranks kept: sigma > tau, common count for U and V
+  P.r2.clear();
+  P.r2.resize(L + 1);
+  for (int l = 2; l <= L; ++l) {
+    const HLevel& lv = T.lev[l];
+    auto& k = P.r2[l].k;
+    k.resize(lv.nb);
+    for (int i = 0; i < lv.nb; ++i) {
+      int ku = 0, kv = 0;
+      for (int a = 0; a < gcols[l][i]; ++a) {
+        if (hsu[l][soff[l][i] + a] > P.tau) ++ku;
+        if (hsv[l][soff[l][i] + a] > P.tau) ++kv;
+      }
+      int kk = std::max(ku, kv);
+      if (P.rank_max > 0) kk = std::min(kk, P.rank_max);
+      k[i] = kk;
+    }
+  }
+  // ---- rotate and truncate
+  std::vector<DevBuf> dk(L + 1);
+  for (int l = 2; l <= L; ++l) dk[l] = up(P, P.r2[l].k);
+  for (int l = 2; l <= L; ++l) {
+    const HLevel& lv = T.lev[l];
+    R2Level& z = P.r2[l];
+    const auto& k = z.k;
+    z.k_off.resize(lv.inter.size());
+    int64_t kt = 0;
+    for (int i = 0; i < lv.nb; ++i)
+      for (int t = lv.in_start[i]; t < lv.in_start[i + 1]; ++t) {
+        z.k_off[t] = kt;
+        kt += (int64_t)k[i] * k[lv.inter[t]];
+      }
+    z.K.alloc(sizeof(double) * std::max<int64_t>(kt, 1), &P.mem);
+    DevBuf dko = up(P, z.k_off);
+    if (!lv.inter.empty()) {
+      hipLaunchKernelGGL(k_krot, dim3((unsigned)lv.inter.size()), dim3(WG), 0, P.stream,
+                         P.ldev[l].in_start.as<int>(), P.ldev[l].inter.as<int>(), lv.nb, R.Kpre[l].as<double>(),
+                         R.dkpoff[l].as<int64_t>(), R.dr[l].as<int>(), WU[l].as<double>(), WV[l].as<double>(),
+                         dwoff[l].as<int64_t>(), dk[l].as<int>(), z.K.as<double>(), dko.as<int64_t>());
+      IFMM_LAUNCH_CHECK();
+    }
+    z.s_off.resize(lv.nb);
+    int64_t st = 0;
+    CopyBatch<double, double> cs;
+    for (int i = 0; i < lv.nb; ++i) { z.s_off[i] = st; st += k[i]; }
+    z.SU.alloc(sizeof(double) * std::max<int64_t>(st, 1), &P.mem);
+    z.SV.alloc(sizeof(double) * std::max<int64_t>(st, 1), &P.mem);
+    for (int i = 0; i < lv.nb; ++i) {
+      cs.add(SU[l].as<double>() + soff[l][i], 1, z.SU.as<double>() + z.s_off[i], 1, k[i], 1);
+      cs.add(SV[l].as<double>() + soff[l][i], 1, z.SV.as<double>() + z.s_off[i], 1, k[i], 1);
+    }
+    run_copy(P, cs, dscr);
+    if (l > 2) {
+      const auto& kp = P.r2[l - 1].k;
+      z.p_off.resize(lv.nb);
+      int64_t pt = 0;
+      for (int i = 0; i < lv.nb; ++i) { z.p_off[i] = pt; pt += (int64_t)k[i] * kp[lv.parent[i]]; }
+      z.PU.alloc(sizeof(double) * std::max<int64_t>(pt, 1), &P.mem);
+      z.PV.alloc(sizeof(double) * std::max<int64_t>(pt, 1), &P.mem);
+      DevBuf dpo = up(P, z.p_off);
+      for (int side = 0; side < 2; ++side) {
+        DevBuf& W = side ? WV[l] : WU[l];
+        DevBuf& Wp = side ? WV[l - 1] : WU[l - 1];
+        hipLaunchKernelGGL(k_prot, dim3(lv.nb), dim3(WG), 0, P.stream, P.ldev[l].parent.as<int>(), lv.nb,
+                           R.Pst.as<double>(), R.dppoff[l].as<int64_t>(), R.dpld[l].as<int>(), R.dr[l].as<int>(),
+                           R.dr[l - 1].as<int>(), W.as<double>(), dwoff[l].as<int64_t>(), Wp.as<double>(),
+                           dwoff[l - 1].as<int64_t>(), dk[l].as<int>(), dk[l - 1].as<int>(),
+                           side ? z.PV.as<double>() : z.PU.as<double>(), dpo.as<int64_t>());
+        IFMM_LAUNCH_CHECK();
+      }
+    }
+    if (l == L) {
+      z.u_off.resize(lv.nb);
+      int64_t ut = 0;
+      for (int i = 0; i < lv.nb; ++i) {
+        z.u_off[i] = ut;
+        ut += (T.leaf_start[i + 1] - T.leaf_start[i]) * (int64_t)k[i];
+      }
+      z.U.alloc(sizeof(double) * std::max<int64_t>(ut, 1), &P.mem);
+      z.V.alloc(sizeof(double) * std::max<int64_t>(ut, 1), &P.mem);
+      GemmBatch gb;
+      for (int i = 0; i < lv.nb; ++i) {
+        const int64_t s = T.leaf_start[i];
+        const int m = (int)(T.leaf_start[i + 1] - s);
+        const int ri = R.r[L][i];
+        gb.add(R.Q.as<double>() + s * q, m, 0, WU[l].as<double>() + woff[l][i], ri, 0,
+               z.U.as<double>() + z.u_off[i], m, m, k[i], ri, 1.0, 0.0);
+        gb.add(R.Q.as<double>() + s * q, m, 0, WV[l].as<double>() + woff[l][i], ri, 0,
+               z.V.as<double>() + z.u_off[i], m, m, k[i], ri, 1.0, 0.0);
+      }
+      run_gemm<double>(P, gb, dscr);
+    }
+  }
+  P.sync();
+  if (debug_on()) {
+    for (int l = 2; l <= L; ++l) {
+      const R2Level& z = P.r2[l];
+      int64_t ks = 0;
+      int kmax = 0;
+      for (int x : z.k) { ks += x; kmax = std::max(kmax, x); }
+      std::fprintf(stderr, "[ifmm] level %d: boxes %d sum k %lld max k %d\n", l, T.lev[l].nb, (long long)ks, kmax);
+      dbg_dump<double>(P, "SU", z.SU.p, z.s_off.empty() ? 0 : (size_t)(z.s_off.back() + z.k.back()));
+      dbg_dump<double>(P, "WU box0", WU[l].p, (size_t)R.r[l][0] * R.r[l][0]);
+      dbg_dump<double>(P, "sU box0", SU[l].p, (size_t)R.r[l][0]);
+      if (!z.k_off.empty()) dbg_dump<double>(P, "K", z.K.p, (size_t)(z.k_off.back() + 1));
+      if (l == L) dbg_dump<double>(P, "U", z.U.p, (size_t)(z.u_off.back() + 1));
+    }
+  }
+}
+
+}  // namespace ifmm

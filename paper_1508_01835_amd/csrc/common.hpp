@@ -1,0 +1,130 @@
+// Common infrastructure of the IFMM library: error handling, device memory
+// accounting, small host/device helpers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/ifmm.h"
+
+namespace ifmm {
+
+// Failure carried to the C ABI boundary, where it becomes an ifmm_status.
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+[[noreturn]] inline void fail(int code, const std::string& msg) { throw Error(code, msg); }
+
+#define IFMM_HIP(call)                                                                   \
+  do {                                                                                   \
+    hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      ::ifmm::fail(e_ == hipErrorOutOfMemory ? IFMM_ERR_OOM : IFMM_ERR_HIP,              \
+                   std::string(#call) + ": " + hipGetErrorString(e_) + " at " __FILE__); \
+  } while (0)
+
+#define IFMM_CHECK(cond, msg) \
+  do {                        \
+    if (!(cond)) ::ifmm::fail(IFMM_ERR_INTERNAL, std::string("check failed: ") + (msg)); \
+  } while (0)
+
+#define IFMM_LAUNCH_CHECK() IFMM_HIP(hipGetLastError())
+
+// Device memory owned by one handle, with a running total and an optional budget.
+struct MemAccount {
+  int64_t cur = 0, peak = 0, budget = 0;
+  void add(int64_t b) {
+    if (budget > 0 && cur + b > budget)
+      fail(IFMM_ERR_OOM, "device memory budget exceeded (" + std::to_string(cur + b) + " > " +
+                             std::to_string(budget) + " bytes)");
+    cur += b;
+    if (cur > peak) peak = cur;
+  }
+  void sub(int64_t b) { cur -= b; }
+};
+
+// An owning device buffer. Moves only.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  MemAccount* acct = nullptr;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept { *this = std::move(o); }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) {
+      release();
+      p = o.p; bytes = o.bytes; acct = o.acct;
+      o.p = nullptr; o.bytes = 0; o.acct = nullptr;
+    }
+    return *this;
+  }
+  ~DevBuf() { release(); }
+  void alloc(size_t b, MemAccount* a) {
+    release();
+    if (b == 0) b = 256;
+    if (a) a->add((int64_t)b);
+    hipError_t e = hipMalloc(&p, b);
+    if (e != hipSuccess) {
+      if (a) a->sub((int64_t)b);
+      p = nullptr;
+      fail(IFMM_ERR_OOM, "hipMalloc(" + std::to_string(b) + ") failed: " + hipGetErrorString(e));
+    }
+    bytes = b;
+    acct = a;
+  }
+  void release() {
+    if (p) {
+      (void)hipFree(p);
+      if (acct) acct->sub((int64_t)bytes);
+    }
+    p = nullptr;
+    bytes = 0;
+    acct = nullptr;
+  }
+  template <class T> T* as() const { return static_cast<T*>(p); }
+  // Grow (never shrink) to at least b bytes; contents are not kept.
+  void reserve(size_t b, MemAccount* a) {
+    if (b > bytes) alloc(b + b / 4, a);
+  }
+};
+
+// Upload a host vector into a device buffer (grow as needed), asynchronously
+// from a pinned staging copy owned by the caller's Staging object.
+struct Staging {
+  void* h = nullptr;
+  size_t bytes = 0;
+  ~Staging() { if (h) (void)hipHostFree(h); }
+  void* get(size_t b) {
+    if (b > bytes) {
+      if (h) (void)hipHostFree(h);
+      size_t nb = b + b / 2 + 4096;
+      IFMM_HIP(hipHostMalloc(&h, nb, hipHostMallocDefault));
+      bytes = nb;
+    }
+    return h;
+  }
+};
+
+inline double now_ms() {
+  using namespace std::chrono;
+  return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+template <class T> struct Prec;
+template <> struct Prec<double> { static constexpr double u = 1.1102230246251565e-16; };
+template <> struct Prec<float> { static constexpr double u = 5.9604644775390625e-08; };
+
+}  // namespace ifmm

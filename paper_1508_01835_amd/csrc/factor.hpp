@@ -1,0 +1,682 @@
+// Level-by-level factorization of E (Alg. 1 and 2, Alg. 3), templated on the
+// arithmetic of the factors (float or double).
+//
+// One level lives in a device pool holding every edge of the graph of E at
+// that level: S (x~-x~), U, V, the weights, K (y-y), XY / YX (x~-y fill of
+// eliminated neighbours) and the transfers to the parent. Boxes are eliminated
+// one colour class (independent set) at a time; each class is a fixed
+// sequence of batched launches, planned on the host with exact sizes (one
+// device-to-host read of the ranks per class).
+#pragma once
+
+#include "build.hpp"
+#include "factor_kernels.hpp"
+
+namespace ifmm {
+
+constexpr int MAXDIM = 1024;    // largest x~ size and rank capacity of a box
+
+template <class T>
+struct LevelPool {
+  int l = 0, nb = 0, c7 = 0, c3 = 0;
+  std::vector<int> m, cap, r, rpar;
+  std::vector<int64_t> Kt, St, XYt, YXt, Uo, Vo, SUo, SVo, PUo, PVo;
+  std::vector<int> B7;
+  int64_t size = 0;
+  DevBuf pool;
+  DevBuf dm, dcap, dr, drnew, dKt, dB7, dSt, dXYt, dYXt, dUo, dVo, dSUo, dSVo, dPUo, dPVo, drpar, dparent;
+  T* P() const { return pool.template as<T>(); }
+  LevelView view(const Problem& pb) const {
+    LevelView v;
+    v.nb = nb; v.d = pb.d; v.c7 = c7; v.c3 = c3; v.haspar = l > 2 ? 1 : 0;
+    v.coords = pb.ldev[l].coords.template as<int>();
+    v.m = dm.template as<int>(); v.cap = dcap.template as<int>(); v.r = dr.template as<int>(); v.rnew = drnew.template as<int>();
+    v.Kt = dKt.template as<int64_t>(); v.B7 = dB7.template as<int>(); v.St = dSt.template as<int64_t>();
+    v.XYt = dXYt.template as<int64_t>(); v.YXt = dYXt.template as<int64_t>();
+    v.Uo = dUo.template as<int64_t>(); v.Vo = dVo.template as<int64_t>(); v.SUo = dSUo.template as<int64_t>(); v.SVo = dSVo.template as<int64_t>();
+    v.PUo = l > 2 ? dPUo.template as<int64_t>() : nullptr; v.PVo = l > 2 ? dPVo.template as<int64_t>() : nullptr;
+    v.rpar = l > 2 ? drpar.template as<int>() : nullptr;
+    v.parent = l > 2 ? pb.ldev[l].parent.template as<int>() : nullptr;
+    return v;
+  }
+};
+
+// Stored factors of one colour class (read once per solve).
+template <class T>
+struct ClassFactors {
+  DevBuf fac;                  // LU, W, E_FP blocks
+  DevBuf piv;                  // pivots
+  std::vector<ElimDesc> el;    // offsets relative to fac / piv
+  std::vector<FNode> F;
+};
+
+template <class T>
+struct SolveLevel {
+  std::vector<std::vector<ElimDesc>> el;   // per class, with solve offsets in w/efp fields
+  std::vector<std::vector<FNode>> F;
+  std::vector<int64_t> xoff;               // x~ offsets at this level (prefix of m)
+  std::vector<int64_t> yoff;               // y offsets (prefix of final r) = x~ offsets one level up
+  int64_t M = 0, Mup = 0;                  // sizes of the level's x~ vector and y vector
+};
+
+template <class T>
+struct FactorStore : FactorStoreBase {
+  std::vector<std::vector<ClassFactors<T>>> cls;   // by level, by class
+  std::vector<SolveLevel<T>> sl;                   // by level
+  DevBuf top;                                      // LU of the y^(2) system
+  DevBuf toppiv;
+  int ntop = 0;
+  int64_t cstore = 0;                              // elements of the c_P store per rhs
+  std::vector<int64_t> coff_level;
+  // scratch reused across calls
+  DevBuf work, d1, d2, d3, d4, d5;
+  DevBuf sx;                                       // solve vectors
+  DevBuf sc;                                       // c_P store
+  int s_nrhs = 0;
+  std::vector<int64_t> xbase;                      // per level offset into sx
+};
+
+// --------------------------------------------------------------- fill kernels
+template <class T>
+__global__ void k_p2p_blocks(const double* __restrict__ pts, const int64_t* __restrict__ leaf_start,
+                             const int* __restrict__ nb_start, const int* __restrict__ nbr,
+                             const int* __restrict__ coords, int nb, int d, int c3, KernelFn kf,
+                             const int64_t* __restrict__ St, T* __restrict__ pool) {
+  const int t = blockIdx.x;
+  int lo = 0, hi = nb - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (nb_start[mid] <= t) lo = mid; else hi = mid - 1;
+  }
+  const int i = lo, j = nbr[t];
+  const int64_t si = leaf_start[i], mi = leaf_start[i + 1] - si;
+  const int64_t sj = leaf_start[j], mj = leaf_start[j + 1] - sj;
+  const int64_t off = St[(int64_t)i * c3 + code3(coords, d, i, j)];
+  for (int64_t e = threadIdx.x; e < mi * mj; e += WG) {
+    const int64_t a = e % mi, b = e / mi;
+    double r2 = 0;
+    for (int k = 0; k < d; ++k) {
+      const double df = pts[(si + a) * d + k] - pts[(sj + b) * d + k];
+      r2 += df * df;
+    }
+    double v = kappa(kf, sqrt(r2));
+    if (si + a == sj + b) v += kf.shift;
+    pool[off + a + b * mi] = (T)v;
+  }
+}
+
+// K(i, j) from the initial operators for every interaction-list pair (ld cap_i).
+template <class T>
+__global__ void k_kinit(const int* __restrict__ in_start, const int* __restrict__ inter,
+                        const int* __restrict__ coords, int nb, int d, int c7, const double* __restrict__ K0,
+                        const int64_t* __restrict__ k0off, const int* __restrict__ k0,
+                        const int* __restrict__ cap, const int64_t* __restrict__ Kt, T* __restrict__ pool) {
+  const int t = blockIdx.x;
+  int lo = 0, hi = nb - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (in_start[mid] <= t) lo = mid; else hi = mid - 1;
+  }
+  const int i = lo, j = inter[t];
+  const int ki = k0[i], kj = k0[j];
+  const int64_t off = Kt[(int64_t)i * c7 + code7(coords, d, i, j)];
+  const double* src = K0 + k0off[t];
+  const int ld = cap[i];
+  for (int e = threadIdx.x; e < ki * kj; e += WG) {
+    const int a = e % ki, b = e / ki;
+    pool[off + a + (int64_t)b * ld] = (T)src[a + (int64_t)b * ki];
+  }
+}
+
+// Merge: S(p, q) = [K(c, c')] over the children of p and q (eq. K_merge);
+// one block per (p, neighbour q).
+template <class T>
+__global__ void k_merge_S(const int* __restrict__ nb_start, const int* __restrict__ nbr,
+                          const int* __restrict__ pcoords, int nbp, int d, const int* __restrict__ ch_start,
+                          const int* __restrict__ ccoords, const int* __restrict__ choff,
+                          const int* __restrict__ rc, const int* __restrict__ capc, const int64_t* __restrict__ Ktc,
+                          int c7, const T* __restrict__ cpool, const int* __restrict__ mp,
+                          const int64_t* __restrict__ Stp, int c3, T* __restrict__ ppool) {
+  const int t = blockIdx.x;
+  int lo = 0, hi = nbp - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (nb_start[mid] <= t) lo = mid; else hi = mid - 1;
+  }
+  const int p = lo, qb = nbr[t];
+  const int64_t off = Stp[(int64_t)p * c3 + code3(pcoords, d, p, qb)];
+  const int ld = mp[p];
+  for (int c = ch_start[p]; c < ch_start[p + 1]; ++c)
+    for (int c2 = ch_start[qb]; c2 < ch_start[qb + 1]; ++c2) {
+      const int code = code7(ccoords, d, c, c2);
+      const int64_t ko = code >= 0 ? Ktc[(int64_t)c * c7 + code] : -1;
+      const int r1 = rc[c], r2 = rc[c2];
+      for (int e = threadIdx.x; e < r1 * r2; e += WG) {
+        const int a = e % r1, b = e / r1;
+        const T v = ko >= 0 ? cpool[ko + a + (int64_t)b * capc[c]] : (T)0;
+        ppool[off + (choff[c] + a) + (int64_t)(choff[c2] + b) * ld] = v;
+      }
+    }
+}
+
+// Merge: U_p = stack PU(c), V_p = stack PV(c) (eqs. U_merge, V_merge).
+template <class T>
+__global__ void k_merge_UV(const int* __restrict__ ch_start, int nbp, const int* __restrict__ choff,
+                           const int* __restrict__ rc, const int* __restrict__ capc,
+                           const int64_t* __restrict__ PUc, const int64_t* __restrict__ PVc,
+                           const T* __restrict__ cpool, const int* __restrict__ mp, const int* __restrict__ rp,
+                           const int64_t* __restrict__ Up, const int64_t* __restrict__ Vp, T* __restrict__ ppool) {
+  const int p = blockIdx.x;
+  if (p >= nbp) return;
+  const int ld = mp[p], cols = rp[p];
+  for (int c = ch_start[p]; c < ch_start[p + 1]; ++c) {
+    const int r1 = rc[c];
+    for (int e = threadIdx.x; e < r1 * cols; e += WG) {
+      const int a = e % r1, b = e / r1;
+      ppool[Up[p] + (choff[c] + a) + (int64_t)b * ld] = cpool[PUc[c] + a + (int64_t)b * capc[c]];
+      ppool[Vp[p] + (choff[c] + a) + (int64_t)b * ld] = cpool[PVc[c] + a + (int64_t)b * capc[c]];
+    }
+  }
+}
+
+// Top: dense system of y^(2) from the level-2 K edges (all pairs are edges).
+template <class T>
+__global__ void k_top_gather(int nb, const int* __restrict__ coords, int d, int c7, const int* __restrict__ r,
+                             const int* __restrict__ cap, const int64_t* __restrict__ Kt,
+                             const int64_t* __restrict__ off, int n, const T* __restrict__ pool,
+                             T* __restrict__ D) {
+  const int t = blockIdx.x;
+  const int i = t % nb, j = t / nb;
+  const int code = code7(coords, d, i, j);
+  const int64_t ko = code >= 0 ? Kt[(int64_t)i * c7 + code] : -1;
+  const int ri = r[i], rj = r[j];
+  for (int e = threadIdx.x; e < ri * rj; e += WG) {
+    const int a = e % ri, b = e / ri;
+    D[(off[i] + a) + (off[j] + b) * (int64_t)n] = ko >= 0 ? pool[ko + a + (int64_t)b * cap[i]] : (T)0;
+  }
+}
+
+// ---------------------------------------------------------------- host logic
+template <class T>
+struct Factorizer {
+  Problem& P;
+  FactorStore<T>& F;
+  double flops_lu = 0, flops_schur = 0, flops_comp = 0, flops_other = 0;
+  int64_t factor_elems = 0;
+  Factorizer(Problem& p, FactorStore<T>& f) : P(p), F(f) {}
+
+  // Allocate and lay out the pool of level l.
+  void layout(LevelPool<T>& L, int l, const std::vector<int>& m, const std::vector<int>& r0) {
+    const HLevel& lv = P.T.lev[l];
+    const int d = P.d;
+    L.l = l;
+    L.nb = lv.nb;
+    L.c7 = 1;
+    L.c3 = 1;
+    for (int k = 0; k < d; ++k) { L.c7 *= 7; L.c3 *= 3; }
+    L.m = m;
+    L.r = r0;
+    L.cap.resize(lv.nb);
+    for (int i = 0; i < lv.nb; ++i) {
+      if (m[i] > MAXDIM)
+        fail(IFMM_ERR_ARG, "a box at level " + std::to_string(l) + " has " + std::to_string(m[i]) +
+                               " unknowns (limit " + std::to_string(MAXDIM) + "): use a deeper tree or a looser eps");
+      int c = m[i];
+      if (P.rank_max > 0) c = std::min(c, P.rank_max);
+      L.cap[i] = std::max(c, r0[i]);
+      if (L.cap[i] > MAXDIM) fail(IFMM_ERR_ARG, "rank capacity above the limit");
+    }
+    L.rpar.assign(lv.nb, 0);
+    if (l > 2)
+      for (int i = 0; i < lv.nb; ++i) L.rpar[i] = P.r2[l - 1].k[lv.parent[i]];
+    L.Kt.assign((size_t)lv.nb * L.c7, -1);
+    L.B7.assign((size_t)lv.nb * L.c7, -1);
+    L.St.assign((size_t)lv.nb * L.c3, -1);
+    L.XYt.assign((size_t)lv.nb * L.c3, -1);
+    L.YXt.assign((size_t)lv.nb * L.c3, -1);
+    L.Uo.resize(lv.nb); L.Vo.resize(lv.nb); L.SUo.resize(lv.nb); L.SVo.resize(lv.nb);
+    L.PUo.assign(lv.nb, 0); L.PVo.assign(lv.nb, 0);
+    int64_t o = 0;
+    auto take = [&](int64_t n) { const int64_t a = o; o += (n + 1) & ~int64_t(1); return a; };
+    for (int i = 0; i < lv.nb; ++i) {
+      for (int t = lv.nb_start[i]; t < lv.nb_start[i + 1]; ++t) {
+        const int j = lv.nbr[t];
+        L.St[(size_t)i * L.c3 + offset3(lv, i, j)] = take((int64_t)m[i] * m[j]);
+        if (lv.colour[j] < lv.colour[i]) {   // x~_i - y_j fill (j eliminated first)
+          L.XYt[(size_t)i * L.c3 + offset3(lv, i, j)] = take((int64_t)m[i] * L.cap[j]);
+          L.YXt[(size_t)j * L.c3 + offset3(lv, j, i)] = take((int64_t)L.cap[j] * m[i]);
+        }
+      }
+      L.Uo[i] = take((int64_t)m[i] * L.cap[i]);
+      L.Vo[i] = take((int64_t)m[i] * L.cap[i]);
+      L.SUo[i] = take(L.cap[i]);
+      L.SVo[i] = take(L.cap[i]);
+      if (l > 2) {
+        L.PUo[i] = take((int64_t)L.cap[i] * L.rpar[i]);
+        L.PVo[i] = take((int64_t)L.cap[i] * L.rpar[i]);
+      }
+      auto addK = [&](int j) {
+        const int c = offset7(lv, d, i, j);
+        L.Kt[(size_t)i * L.c7 + c] = take((int64_t)L.cap[i] * L.cap[j]);
+        L.B7[(size_t)i * L.c7 + c] = j;
+      };
+      for (int t = lv.nb_start[i]; t < lv.nb_start[i + 1]; ++t) addK(lv.nbr[t]);
+      for (int t = lv.in_start[i]; t < lv.in_start[i + 1]; ++t) addK(lv.inter[t]);
+    }
+    L.size = o;
+    L.pool.alloc(sizeof(T) * std::max<int64_t>(o, 2), &P.mem);
+    IFMM_HIP(hipMemsetAsync(L.pool.p, 0, sizeof(T) * std::max<int64_t>(o, 2), P.stream));
+    P.upload(L.dm, L.m); P.upload(L.dcap, L.cap); P.upload(L.dr, L.r); P.upload(L.drnew, L.r);
+    P.upload(L.dKt, L.Kt); P.upload(L.dB7, L.B7); P.upload(L.dSt, L.St); P.upload(L.dXYt, L.XYt);
+    P.upload(L.dYXt, L.YXt); P.upload(L.dUo, L.Uo); P.upload(L.dVo, L.Vo); P.upload(L.dSUo, L.SUo);
+    P.upload(L.dSVo, L.SVo); P.upload(L.dPUo, L.PUo); P.upload(L.dPVo, L.PVo); P.upload(L.drpar, L.rpar);
+  }
+
+  int offset3(const HLevel& lv, int i, int j) const {
+    int code = 0, mul = 1;
+    for (int k = 0; k < P.d; ++k) {
+      code += (lv.coords[(size_t)j * P.d + k] - lv.coords[(size_t)i * P.d + k] + 1) * mul;
+      mul *= 3;
+    }
+    return code;
+  }
+
+  // Initial K, PU, PV, SU, SV of level l from the R2 operators.
+  void fill_from_r2(LevelPool<T>& L) {
+    const int l = L.l;
+    const HLevel& lv = P.T.lev[l];
+    R2Level& z = P.r2[l];
+    DevBuf dk = up(P, z.k), dko = up(P, z.k_off);
+    if (!lv.inter.empty()) {
+      hipLaunchKernelGGL(k_kinit<T>, dim3((unsigned)lv.inter.size()), dim3(WG), 0, P.stream,
+                         P.ldev[l].in_start.template as<int>(), P.ldev[l].inter.template as<int>(), P.ldev[l].coords.template as<int>(), lv.nb,
+                         P.d, L.c7, z.K.template as<double>(), dko.template as<int64_t>(), dk.template as<int>(), L.dcap.template as<int>(),
+                         L.dKt.template as<int64_t>(), L.P());
+      IFMM_LAUNCH_CHECK();
+    }
+    CopyBatch<double, T> cb;
+    for (int i = 0; i < lv.nb; ++i) {
+      cb.add(z.SU.template as<double>() + z.s_off[i], 1, L.P() + L.SUo[i], 1, z.k[i], 1);
+      cb.add(z.SV.template as<double>() + z.s_off[i], 1, L.P() + L.SVo[i], 1, z.k[i], 1);
+      if (l > 2) {
+        const int kp = L.rpar[i];
+        cb.add(z.PU.template as<double>() + z.p_off[i], z.k[i], L.P() + L.PUo[i], L.cap[i], z.k[i], kp);
+        cb.add(z.PV.template as<double>() + z.p_off[i], z.k[i], L.P() + L.PVo[i], L.cap[i], z.k[i], kp);
+      }
+    }
+    run_copy(P, cb, F.d1);
+    P.sync();
+  }
+
+  void setup_leaf(LevelPool<T>& L) {
+    const int l = P.L;
+    const HLevel& lv = P.T.lev[l];
+    std::vector<int> m(lv.nb);
+    for (int i = 0; i < lv.nb; ++i) m[i] = (int)(P.T.leaf_start[i + 1] - P.T.leaf_start[i]);
+    layout(L, l, m, P.r2[l].k);
+    if (!lv.nbr.empty()) {
+      hipLaunchKernelGGL(k_p2p_blocks<T>, dim3((unsigned)lv.nbr.size()), dim3(WG), 0, P.stream, P.pts.template as<double>(),
+                         P.leaf_start.template as<int64_t>(), P.ldev[l].nb_start.template as<int>(), P.ldev[l].nbr.template as<int>(),
+                         P.ldev[l].coords.template as<int>(), lv.nb, P.d, L.c3, P.kf, L.dSt.template as<int64_t>(), L.P());
+      IFMM_LAUNCH_CHECK();
+    }
+    R2Level& z = P.r2[l];
+    CopyBatch<double, T> cb;
+    for (int i = 0; i < lv.nb; ++i) {
+      cb.add(z.U.template as<double>() + z.u_off[i], m[i], L.P() + L.Uo[i], m[i], m[i], z.k[i]);
+      cb.add(z.V.template as<double>() + z.u_off[i], m[i], L.P() + L.Vo[i], m[i], m[i], z.k[i]);
+    }
+    run_copy(P, cb, F.d1);
+    fill_from_r2(L);
+  }
+
+  // ---------------------------------------------------------- recompression
+  // Plans workspace for the recompressions cs (ncols and box filled in) and
+  // runs: gather, QR of MU^T / MV^T, transpose, Jacobi SVD, rank, r_j / t_j,
+  // row and column transforms of every edge of the affected boxes, commit.
+  void recompress(LevelPool<T>& L, std::vector<CompDesc>& cs, const std::vector<ElimDesc>& el,
+                  const ElimDesc* d_el, const FNode* d_F, int64_t wbase) {
+    if (cs.empty()) return;
+    int64_t o = wbase;
+    auto take = [&](int64_t n) { const int64_t a = o; o += (n + 1) & ~int64_t(1); return a; };
+    for (auto& c : cs) {
+      const int mj = L.m[c.box];
+      c.kq = std::min(c.ncols, mj);
+      c.mu = take((int64_t)c.ncols * mj);
+      c.mv = take((int64_t)c.ncols * mj);
+      c.ru = take((int64_t)c.kq * mj);
+      c.rv = take((int64_t)c.kq * mj);
+      c.uu = take((int64_t)mj * c.kq);
+      c.vv = take((int64_t)mj * c.kq);
+      c.su = take(c.kq);
+      c.sv = take(c.kq);
+      c.tr = take((int64_t)L.cap[c.box] * L.cap[c.box]);
+      c.tt = take((int64_t)L.cap[c.box] * L.cap[c.box]);
+      flops_comp += 2.0 * 2.0 * c.ncols * mj * mj + 2.0 * 12.0 * (double)mj * c.kq * c.kq;
+    }
+    if ((size_t)o * sizeof(T) > F.work.bytes) {
+      P.sync();
+      DevBuf nw;
+      nw.alloc((size_t)o * sizeof(T) + ((size_t)o * sizeof(T)) / 4, &P.mem);
+      if (wbase > 0)
+        IFMM_HIP(hipMemcpyAsync(nw.p, F.work.p, sizeof(T) * wbase, hipMemcpyDeviceToDevice, P.stream));
+      F.work = std::move(nw);
+    }
+    T* W = F.work.template as<T>();
+    const CompDesc* dc = P.put(F.d3, cs);
+    const LevelView v = L.view(P);
+    hipLaunchKernelGGL(k_comp_gather<T>, dim3((unsigned)cs.size()), dim3(WG), 0, P.stream, dc, d_el, d_F, v,
+                       (const T*)L.P(), W);
+    IFMM_LAUNCH_CHECK();
+    std::vector<QrDesc> qd;
+    CopyBatch<T, T> tb;
+    std::vector<SvdDesc> sd;
+    for (const auto& c : cs) {
+      const int mj = L.m[c.box];
+      for (int side = 0; side < 2; ++side) {
+        QrDesc q;
+        q.A = W + (side ? c.mv : c.mu);
+        q.R = W + (side ? c.rv : c.ru);
+        q.Q = nullptr;
+        q.M = c.ncols; q.N = mj; q.lda = c.ncols; q.ldr = c.kq; q.ldq = 1; q.pad = 0;
+        qd.push_back(q);
+        // B = R^T (m_j x kq), reusing the MU / MV storage
+        tb.add(W + (side ? c.rv : c.ru), c.kq, W + (side ? c.mv : c.mu), mj, mj, c.kq, 4);
+        SvdDesc s;
+        s.B = W + (side ? c.mv : c.mu);
+        s.U = W + (side ? c.vv : c.uu);
+        s.S = W + (side ? c.sv : c.su);
+        s.M = mj; s.N = c.kq; s.ldb = mj; s.ldu = mj;
+        sd.push_back(s);
+      }
+    }
+    run_qr<T>(P, qd, F.d4);
+    run_copy(P, tb, F.d4);
+    run_svd<T>(P, sd, F.d4);
+    hipLaunchKernelGGL(k_comp_rank<T>, dim3((unsigned)ceil_div((int64_t)cs.size(), WG)), dim3(WG), 0, P.stream, dc,
+                       (int)cs.size(), v, (const T*)W, P.tau, P.rank_max);
+    IFMM_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_comp_rt<T>, dim3((unsigned)cs.size()), dim3(WG), 0, P.stream, dc, v, (const T*)L.P(), W);
+    IFMM_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_row_xform<T>, dim3((unsigned)cs.size(), L.c7 + 2), dim3(WG), 0, P.stream, dc, v, L.P(),
+                       (const T*)W);
+    IFMM_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_col_xform<T>, dim3((unsigned)cs.size(), L.c7), dim3(WG), 0, P.stream, dc, v, L.P(),
+                       (const T*)W);
+    IFMM_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_comp_commit<T>, dim3((unsigned)cs.size()), dim3(WG), 0, P.stream, dc, v, L.P(),
+                       (const T*)W);
+    IFMM_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_commit_ranks, dim3((unsigned)ceil_div((int64_t)cs.size(), WG)), dim3(WG), 0, P.stream, dc,
+                       (int)cs.size(), v);
+    IFMM_LAUNCH_CHECK();
+    (void)el;
+  }
+
+  // ----------------------------------------------------------- one level
+  void eliminate_level(LevelPool<T>& L) {
+    const int l = L.l;
+    const HLevel& lv = P.T.lev[l];
+    const int d = P.d;
+    F.cls[l].clear();
+    F.cls[l].resize(lv.ncolour);
+    for (int c = 0; c < lv.ncolour; ++c) {
+      const auto& boxes = lv.classes[c];
+      if (boxes.empty()) continue;
+      // ranks are exact on the host at the start of every class
+      P.download(L.r, L.dr.p, (size_t)lv.nb);
+      ClassFactors<T>& cf = F.cls[l][c];
+      std::vector<ElimDesc>& el = cf.el;
+      std::vector<FNode>& Fs = cf.F;
+      el.clear();
+      Fs.clear();
+      int64_t fo = 0, po = 0, wo = 0;
+      int maxF = 0;
+      std::vector<CompDesc> cs;
+      for (int i : boxes) {
+        ElimDesc e{};
+        e.box = i;
+        e.m = L.m[i];
+        e.r = L.r[i];
+        e.p = e.m + e.r;
+        e.F0 = (int)Fs.size();
+        int f = 0;
+        auto push = [&](int type, int b) {
+          FNode n{};
+          n.type = type;
+          n.box = b;
+          n.dim = type == 0 ? L.m[b] : L.r[b];
+          n.off = f;
+          if (type == 0) {
+            n.src_row = L.St[(size_t)i * L.c3 + offset3(lv, i, b)];
+            n.ld_row = L.m[i];
+            n.src_col = L.St[(size_t)b * L.c3 + offset3(lv, b, i)];
+            n.ld_col = L.m[b];
+          } else if (b != i) {
+            n.src_row = L.XYt[(size_t)i * L.c3 + offset3(lv, i, b)];
+            n.ld_row = L.m[i];
+            n.src_col = L.YXt[(size_t)b * L.c3 + offset3(lv, b, i)];
+            n.ld_col = L.cap[b];
+          } else {
+            n.src_row = -1; n.src_col = -1; n.ld_row = 1; n.ld_col = 1;
+          }
+          f += n.dim;
+          Fs.push_back(n);
+        };
+        for (int t = lv.nb_start[i]; t < lv.nb_start[i + 1]; ++t) {
+          const int j = lv.nbr[t];
+          if (j != i && lv.colour[j] > c) push(0, j);
+        }
+        for (int t = lv.nb_start[i]; t < lv.nb_start[i + 1]; ++t) {
+          const int j = lv.nbr[t];
+          if (j != i && lv.colour[j] < c) push(1, j);
+        }
+        push(1, i);
+        e.nF = (int)Fs.size() - e.F0;
+        e.f = f;
+        maxF = std::max(maxF, e.nF);
+        e.lu = fo; fo += ((int64_t)e.p * e.p + 1) & ~int64_t(1);
+        e.w = fo; fo += ((int64_t)e.p * e.f + 1) & ~int64_t(1);
+        e.efp = fo; fo += ((int64_t)e.f * e.p + 1) & ~int64_t(1);
+        e.piv = po; po += e.p;
+        e.dlt = wo; wo += ((int64_t)e.f * e.f + 1) & ~int64_t(1);
+        e.S = L.St[(size_t)i * L.c3 + offset3(lv, i, i)];
+        e.U = L.Uo[i];
+        e.V = L.Vo[i];
+        // recompressions triggered by this elimination
+        for (int a = 0; a < e.nF; ++a) {
+          const FNode& X = Fs[e.F0 + a];
+          if (X.type != 0) continue;
+          int nc = L.r[X.box];
+          bool any = false;
+          for (int b = 0; b < e.nF; ++b) {
+            const FNode& B = Fs[e.F0 + b];
+            if (!adjacent(lv, d, X.box, B.box)) { nc += B.dim; any = true; }
+          }
+          if (!any) continue;
+          CompDesc cd{};
+          cd.box = X.box;
+          cd.elim = (int)el.size();
+          cd.a = a;
+          cd.ncols = nc;
+          cs.push_back(cd);
+        }
+        flops_lu += 2.0 / 3.0 * e.p * (double)e.p * e.p + 2.0 * e.p * (double)e.p * e.f;
+        flops_schur += 2.0 * e.f * (double)e.f * e.p;
+        factor_elems += (int64_t)e.p * e.p + 2 * (int64_t)e.p * e.f;
+        el.push_back(e);
+      }
+      cf.fac.alloc(sizeof(T) * std::max<int64_t>(fo, 2), &P.mem);
+      cf.piv.alloc(sizeof(int) * std::max<int64_t>(po, 1), &P.mem);
+      if ((size_t)wo * sizeof(T) > F.work.bytes) {
+        P.sync();
+        F.work.alloc((size_t)wo * sizeof(T) + (size_t)wo * sizeof(T) / 4 + 64, &P.mem);
+      }
+      T* fac = cf.fac.template as<T>();
+      T* W = F.work.template as<T>();
+      const ElimDesc* del = P.put(F.d1, el);
+      const FNode* dF = P.put(F.d2, Fs);
+      // gather pivot blocks and couplings
+      hipLaunchKernelGGL(k_gather<T>, dim3((unsigned)el.size(), maxF + 1), dim3(WG), 0, P.stream, del, dF,
+                         (const T*)L.P(), fac);
+      IFMM_LAUNCH_CHECK();
+      // LU with partial pivoting of every pivot block; W = E_PP^-1 E_PF
+      std::vector<LuDesc> lu;
+      LuSolveBatch ls;
+      GemmBatch gb;
+      for (const auto& e : el) {
+        LuDesc q;
+        q.A = fac + e.lu; q.piv = cf.piv.template as<int>() + e.piv; q.n = e.p; q.lda = std::max(e.p, 1);
+        q.tag = l * 1000000 + e.box; q.pad = 0;
+        if (e.p > 0) lu.push_back(q);
+        ls.add(fac + e.lu, std::max(e.p, 1), cf.piv.template as<int>() + e.piv, fac + e.w, std::max(e.p, 1), e.p, e.f);
+        // Schur fill D = -E_FP W (f x f, inner p)
+        gb.add(fac + e.efp, std::max(e.f, 1), 0, fac + e.w, std::max(e.p, 1), 0, W + e.dlt, std::max(e.f, 1), e.f,
+               e.f, e.p, -1.0, 0.0);
+        if (e.p == 0 && e.f > 0)
+          IFMM_HIP(hipMemsetAsync(W + e.dlt, 0, sizeof(T) * (size_t)e.f * e.f, P.stream));
+      }
+      if (debug_on() && l == P.L && c == 0) {
+        for (size_t b = 0; b < el.size() && b < 3; ++b) {
+          const ElimDesc& e = el[b];
+          std::fprintf(stderr, "[ifmm] elim box %d m %d r %d p %d f %d nF %d\n", e.box, e.m, e.r, e.p, e.f, e.nF);
+          dbg_dump<T>(P, "EPP", fac + e.lu, (size_t)e.p * e.p, 12);
+          dbg_dump<T>(P, "U_i", L.P() + e.U, (size_t)e.m * e.r, 8);
+          dbg_dump<T>(P, "S_ii", L.P() + e.S, (size_t)e.m * e.m, 8);
+        }
+      }
+      run_lu<T>(P, lu, F.d3);
+      run_lu_solve<T>(P, ls, F.d4);
+      run_gemm<T>(P, gb, F.d5);
+      const LevelView v = L.view(P);
+      // near fill: added to existing edges
+      hipLaunchKernelGGL(k_near_scatter<T>, dim3((unsigned)el.size(), maxF * maxF), dim3(WG), 0, P.stream, del, dF,
+                         v, (const T*)W, L.P());
+      IFMM_LAUNCH_CHECK();
+      // well-separated fill: recompress the bases of the affected boxes, then redirect
+      IFMM_HIP(hipMemcpyAsync(L.drnew.p, L.dr.p, sizeof(int) * lv.nb, hipMemcpyDeviceToDevice, P.stream));
+      recompress(L, cs, el, del, dF, wo);
+      hipLaunchKernelGGL(k_redirect<T>, dim3((unsigned)el.size(), maxF * maxF), dim3(WG), 0, P.stream, del, dF, v,
+                         (const T*)F.work.template as<T>(), L.P());
+      IFMM_LAUNCH_CHECK();
+    }
+    P.download(L.r, L.dr.p, (size_t)lv.nb);
+  }
+
+  // ---------------------------------------------------- merge into l - 1
+  void merge(LevelPool<T>& C, LevelPool<T>& Pp) {
+    const int l = C.l, lp = l - 1;
+    const HLevel& lv = P.T.lev[lp];
+    std::vector<int> m(lv.nb, 0), choff(C.nb, 0);
+    for (int p = 0; p < lv.nb; ++p) {
+      int o = 0;
+      for (int c = lv.ch_start[p]; c < lv.ch_start[p + 1]; ++c) { choff[c] = o; o += C.r[c]; }
+      m[p] = o;
+    }
+    layout(Pp, lp, m, P.r2[lp].k);
+    DevBuf dch = up(P, choff);
+    if (!lv.nbr.empty()) {
+      hipLaunchKernelGGL(k_merge_S<T>, dim3((unsigned)lv.nbr.size()), dim3(WG), 0, P.stream,
+                         P.ldev[lp].nb_start.template as<int>(), P.ldev[lp].nbr.template as<int>(), P.ldev[lp].coords.template as<int>(), lv.nb,
+                         P.d, P.ldev[lp].ch_start.template as<int>(), P.ldev[l].coords.template as<int>(), dch.template as<int>(),
+                         C.dr.template as<int>(), C.dcap.template as<int>(), C.dKt.template as<int64_t>(), C.c7, (const T*)C.P(),
+                         Pp.dm.template as<int>(), Pp.dSt.template as<int64_t>(), Pp.c3, Pp.P());
+      IFMM_LAUNCH_CHECK();
+    }
+    hipLaunchKernelGGL(k_merge_UV<T>, dim3(lv.nb), dim3(WG), 0, P.stream, P.ldev[lp].ch_start.template as<int>(), lv.nb,
+                       dch.template as<int>(), C.dr.template as<int>(), C.dcap.template as<int>(), C.dPUo.template as<int64_t>(), C.dPVo.template as<int64_t>(),
+                       (const T*)C.P(), Pp.dm.template as<int>(), Pp.dr.template as<int>(), Pp.dUo.template as<int64_t>(), Pp.dVo.template as<int64_t>(),
+                       Pp.P());
+    IFMM_LAUNCH_CHECK();
+    fill_from_r2(Pp);
+    // recompress the merged bases [U_p Sigma_U] and [V_p Sigma_V] at tau
+    std::vector<CompDesc> cs;
+    for (int p = 0; p < lv.nb; ++p) {
+      CompDesc cd{};
+      cd.box = p;
+      cd.elim = -1;
+      cd.a = 0;
+      cd.ncols = Pp.r[p];
+      if (cd.ncols > 0 && Pp.m[p] > 0) cs.push_back(cd);
+      else if (Pp.r[p] > 0) fail(IFMM_ERR_INTERNAL, "merged box with basis but no unknowns");
+    }
+    IFMM_HIP(hipMemcpyAsync(Pp.drnew.p, Pp.dr.p, sizeof(int) * lv.nb, hipMemcpyDeviceToDevice, P.stream));
+    recompress(Pp, cs, {}, nullptr, nullptr, 0);
+    P.download(Pp.r, Pp.dr.p, (size_t)lv.nb);
+  }
+
+  void top(LevelPool<T>& L) {
+    const HLevel& lv = P.T.lev[2];
+    std::vector<int64_t> off(lv.nb + 1, 0);
+    for (int i = 0; i < lv.nb; ++i) off[i + 1] = off[i] + L.r[i];
+    const int n = (int)off[lv.nb];
+    F.ntop = n;
+    F.top.alloc(sizeof(T) * std::max<int64_t>((int64_t)n * n, 1), &P.mem);
+    F.toppiv.alloc(sizeof(int) * std::max(n, 1), &P.mem);
+    if (n == 0) return;
+    DevBuf doff = up(P, off);
+    hipLaunchKernelGGL(k_top_gather<T>, dim3((unsigned)(lv.nb * lv.nb)), dim3(WG), 0, P.stream, lv.nb,
+                       P.ldev[2].coords.template as<int>(), P.d, L.c7, L.dr.template as<int>(), L.dcap.template as<int>(), L.dKt.template as<int64_t>(),
+                       doff.template as<int64_t>(), n, (const T*)L.P(), F.top.template as<T>());
+    IFMM_LAUNCH_CHECK();
+    std::vector<LuDesc> lu(1);
+    lu[0].A = F.top.template as<T>(); lu[0].piv = F.toppiv.template as<int>(); lu[0].n = n; lu[0].lda = n; lu[0].tag = 999999999;
+    lu[0].pad = 0;
+    run_lu<T>(P, lu, F.d1);
+    flops_lu += 2.0 / 3.0 * (double)n * n * n;
+    factor_elems += (int64_t)n * n;
+  }
+
+  // Solve plan of a finished level: x~ offsets, y offsets (one level up).
+  void plan_solve(const LevelPool<T>& L) {
+    const int l = L.l;
+    const HLevel& lv = P.T.lev[l];
+    SolveLevel<T>& s = F.sl[l];
+    s.xoff.assign(lv.nb + 1, 0);
+    s.yoff.assign(lv.nb + 1, 0);
+    for (int i = 0; i < lv.nb; ++i) {
+      s.xoff[i + 1] = s.xoff[i] + L.m[i];
+      s.yoff[i + 1] = s.yoff[i] + L.r[i];
+    }
+    s.M = s.xoff[lv.nb];
+    s.Mup = s.yoff[lv.nb];
+  }
+
+  void run() {
+    const int Lv = P.L;
+    F.cls.clear();
+    F.cls.resize(Lv + 1);
+    F.sl.assign(Lv + 1, SolveLevel<T>());
+    auto cur = std::make_unique<LevelPool<T>>();
+    setup_leaf(*cur);
+    for (int l = Lv; l >= 2; --l) {
+      eliminate_level(*cur);
+      plan_solve(*cur);
+      P.st.max_rank[l] = 0;
+      double sum = 0;
+      for (int x : cur->r) { P.st.max_rank[l] = std::max(P.st.max_rank[l], x); sum += x; }
+      P.st.mean_rank[l] = cur->nb ? sum / cur->nb : 0.0;
+      if (l > 2) {
+        auto nxt = std::make_unique<LevelPool<T>>();
+        merge(*cur, *nxt);
+        cur = std::move(nxt);
+      } else {
+        top(*cur);
+      }
+    }
+    P.sync();
+    std::vector<int> info;
+    P.download(info, P.d_info, 1);
+    if (info[0] != -1) {
+      P.st.error_level = info[0] == 999999999 ? 1 : info[0] / 1000000;
+      P.st.error_box = info[0] == 999999999 ? -1 : info[0] % 1000000;
+      fail(IFMM_ERR_SINGULAR, "zero pivot in the elimination (level " + std::to_string(P.st.error_level) +
+                                  ", box " + std::to_string(P.st.error_box) + ")");
+    }
+    P.st.factor_flops = flops_lu + flops_schur + flops_comp + flops_other;
+    P.st.schur_flops = flops_schur;
+    P.st.factor_bytes = factor_elems * (int64_t)sizeof(T);
+  }
+};
+
+}  // namespace ifmm

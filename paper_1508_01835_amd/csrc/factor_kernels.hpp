@@ -1,0 +1,397 @@
+// Kernels of one colour-class phase of the elimination (Alg. 2 and 3):
+// gather of the pivot blocks, near-field fill scatter, gather of the
+// recompression matrices, rank decision, basis change of every edge of a
+// recompressed box, redirection of well-separated fill through K.
+#pragma once
+
+#include "linalg.hpp"
+
+namespace ifmm {
+
+// Node of the set F of one elimination: x~_j (type 0) or y_h (type 1).
+struct FNode {
+  int type, box, dim, off;
+  int64_t src_row;   // pool offset of E(P rows, node): S(i,j) or XY(i,h); -1: the -I of y_i
+  int64_t src_col;   // pool offset of E(node, P cols): S(j,i) or YX(h,i); -1: the -I of y_i
+  int ld_row, ld_col;
+};
+
+struct ElimDesc {
+  int box, m, r, p, f, nF, F0, pad;
+  int64_t lu, w, efp, piv, dlt;   // factor arena (lu, w, efp), int arena (piv), workspace (dlt)
+  int64_t S, U, V;                // pool offsets of S(i,i), U_i, V_i (ld m_i)
+};
+
+// Level tables shared by the kernels (device pointers).
+struct LevelView {
+  int nb, d, c7, c3, haspar;
+  const int* coords;
+  const int* m;        // x~ sizes
+  const int* cap;      // rank capacity (leading dimension of y rows)
+  int* r;              // committed ranks
+  int* rnew;           // ranks after this phase's recompressions
+  const int64_t* Kt;   // nb x 7^d pool offsets of K(i, box at offset), -1 if none
+  const int* B7;       // nb x 7^d box ids at each offset, -1 if none
+  const int64_t* St;   // nb x 3^d pool offsets of S(i, j)
+  const int64_t* XYt;  // nb x 3^d pool offsets of XY(j, h)
+  const int64_t* YXt;  // nb x 3^d pool offsets of YX(h, j)
+  const int64_t* Uo;   // per box: U_i, V_i (m_i x cap_i, ld m_i), SU_i, SV_i (cap_i), PU_i, PV_i (cap_i x rpar, ld cap_i)
+  const int64_t* Vo;
+  const int64_t* SUo;
+  const int64_t* SVo;
+  const int64_t* PUo;
+  const int64_t* PVo;
+  const int* rpar;     // rank of the parent (columns of PU/PV)
+  const int* parent;
+};
+
+__device__ inline int code7(const int* coords, int d, int i, int j) {
+  int code = 0, mul = 1;
+  for (int k = 0; k < d; ++k) {
+    const int dd = coords[j * d + k] - coords[i * d + k];
+    if (dd > 3 || dd < -3) return -1;
+    code += (dd + 3) * mul;
+    mul *= 7;
+  }
+  return code;
+}
+
+__device__ inline int code3(const int* coords, int d, int i, int j) {
+  int code = 0, mul = 1;
+  for (int k = 0; k < d; ++k) {
+    const int dd = coords[j * d + k] - coords[i * d + k];
+    if (dd > 1 || dd < -1) return -1;
+    code += (dd + 1) * mul;
+    mul *= 3;
+  }
+  return code;
+}
+
+// ---------------------------------------------------------------- gather
+// blockIdx.x: elimination; blockIdx.y: F node (y == nF: the pivot block).
+template <class T>
+__global__ void __launch_bounds__(WG) k_gather(const ElimDesc* __restrict__ es, const FNode* __restrict__ Fs,
+                                               const T* __restrict__ pool, T* __restrict__ arena) {
+  const ElimDesc e = es[blockIdx.x];
+  const int a = blockIdx.y;
+  if (a > e.nF) return;
+  const int m = e.m, r = e.r, p = e.p, f = e.f;
+  T* EPP = arena + e.lu;
+  T* EPF = arena + e.w;
+  T* EFP = arena + e.efp;
+  if (a == e.nF) {
+    for (int t = threadIdx.x; t < p * p; t += WG) {
+      const int i = t % p, j = t / p;
+      T v = 0;
+      if (i < m && j < m) v = pool[e.S + i + (int64_t)j * m];
+      else if (i < m) v = pool[e.U + i + (int64_t)(j - m) * m];
+      else if (j < m) v = pool[e.V + j + (int64_t)(i - m) * m];
+      EPP[i + (int64_t)j * p] = v;
+    }
+    return;
+  }
+  const FNode nd = Fs[e.F0 + a];
+  const int dim = nd.dim;
+  // columns off..off+dim of E_PF (p rows)
+  for (int t = threadIdx.x; t < p * dim; t += WG) {
+    const int i = t % p, c = t / p;
+    T v = 0;
+    if (nd.src_row < 0) v = (i - m == c) ? (T)-1 : (T)0;
+    else if (i < m) v = pool[nd.src_row + i + (int64_t)c * nd.ld_row];
+    EPF[i + (int64_t)(nd.off + c) * p] = v;
+  }
+  // rows off..off+dim of E_FP (p columns, leading dimension f)
+  for (int t = threadIdx.x; t < dim * p; t += WG) {
+    const int i = t % dim, j = t / dim;
+    T v = 0;
+    if (nd.src_col < 0) v = (j - m == i) ? (T)-1 : (T)0;
+    else if (j < m) v = pool[nd.src_col + i + (int64_t)j * nd.ld_col];
+    EFP[(nd.off + i) + (int64_t)j * f] = v;
+  }
+  (void)r;
+}
+
+// ------------------------------------------------------------ near scatter
+// blockIdx.x: elimination; blockIdx.y: pair index a * nF + b. Adds the fill
+// block D(a, b) to its edge when the pair is near (Alg. 2, "add the fill-ins").
+template <class T>
+__global__ void __launch_bounds__(WG) k_near_scatter(const ElimDesc* __restrict__ es, const FNode* __restrict__ Fs,
+                                                     LevelView lv, const T* __restrict__ work, T* __restrict__ pool) {
+  const ElimDesc e = es[blockIdx.x];
+  const int pr = blockIdx.y;
+  if (pr >= e.nF * e.nF) return;
+  const FNode A = Fs[e.F0 + pr / e.nF];
+  const FNode B = Fs[e.F0 + pr % e.nF];
+  if (A.dim == 0 || B.dim == 0) return;
+  int64_t dst = -1;
+  int ld = 0;
+  if (A.type == 1 && B.type == 1) {
+    const int c = code7(lv.coords, lv.d, A.box, B.box);
+    dst = lv.Kt[(int64_t)A.box * lv.c7 + c];
+    ld = lv.cap[A.box];
+  } else {
+    const int c = code3(lv.coords, lv.d, A.box, B.box);
+    if (c < 0) return;   // well separated: compressed and redirected instead
+    if (A.type == 0 && B.type == 0) { dst = lv.St[(int64_t)A.box * lv.c3 + c]; ld = lv.m[A.box]; }
+    else if (A.type == 0) { dst = lv.XYt[(int64_t)A.box * lv.c3 + c]; ld = lv.m[A.box]; }
+    else { dst = lv.YXt[(int64_t)A.box * lv.c3 + c]; ld = lv.cap[A.box]; }
+  }
+  if (dst < 0) return;
+  const T* D = work + e.dlt;
+  for (int t = threadIdx.x; t < A.dim * B.dim; t += WG) {
+    const int i = t % A.dim, j = t / A.dim;
+    pool[dst + i + (int64_t)j * ld] += D[(A.off + i) + (int64_t)(B.off + j) * e.f];
+  }
+}
+
+// ----------------------------------------------------- recompression input
+// One recompression per affected box j (a not-yet-eliminated neighbour with
+// well-separated fill): MU^T = [U_j Sigma_U | D(x_j, ws)]^T and
+// MV^T = [V_j Sigma_V | D(ws, x_j)^T]^T (eqs. U_j_recomp and V_j_recomp,
+// aggregated over all well-separated partners of this elimination).
+struct CompDesc {
+  int box, elim, a, ncols;     // affected box, elimination index, F index of x_j, columns of MU
+  int64_t mu, mv;              // workspace offsets of MU^T, MV^T (ncols x m_j, ld ncols)
+  int64_t ru, rv;              // workspace offsets of R factors / B = R^T (m_j x kq)
+  int64_t uu, vv;              // workspace offsets of the left singular vectors (m_j x kq, ld m_j)
+  int64_t su, sv;              // workspace offsets of the singular values (kq)
+  int64_t tr, tt;              // workspace offsets of r_j (k x r, ld cap) and t_j
+  int kq, pad;
+};
+
+template <class T>
+__global__ void __launch_bounds__(WG) k_comp_gather(const CompDesc* __restrict__ cs, const ElimDesc* __restrict__ es,
+                                                    const FNode* __restrict__ Fs, LevelView lv,
+                                                    const T* __restrict__ pool, T* __restrict__ work) {
+  const CompDesc c = cs[blockIdx.x];
+  const int j = c.box;
+  const int mj = lv.m[j], rj = lv.r[j];
+  T* MU = work + c.mu;
+  T* MV = work + c.mv;
+  const int nc = c.ncols;
+  const T* U = pool + lv.Uo[j];
+  const T* V = pool + lv.Vo[j];
+  const T* SU = pool + lv.SUo[j];
+  const T* SV = pool + lv.SVo[j];
+  for (int t = threadIdx.x; t < rj * mj; t += WG) {
+    const int col = t % rj, row = t / rj;
+    MU[col + (int64_t)row * nc] = U[row + (int64_t)col * mj] * SU[col];
+    MV[col + (int64_t)row * nc] = V[row + (int64_t)col * mj] * SV[col];
+  }
+  if (c.elim < 0) return;   // recompression of merged bases: no fill columns
+  const ElimDesc e = es[c.elim];
+  const FNode X = Fs[e.F0 + c.a];
+  const T* D = work + e.dlt;
+  int o = rj;
+  for (int b = 0; b < e.nF; ++b) {
+    const FNode B = Fs[e.F0 + b];
+    if (code3(lv.coords, lv.d, j, B.box) >= 0) continue;   // near: not compressed
+    for (int t = threadIdx.x; t < B.dim * mj; t += WG) {
+      const int col = t % B.dim, row = t / B.dim;
+      MU[(o + col) + (int64_t)row * nc] = D[(X.off + row) + (int64_t)(B.off + col) * e.f];
+      MV[(o + col) + (int64_t)row * nc] = D[(B.off + col) + (int64_t)(X.off + row) * e.f];
+    }
+    o += B.dim;
+  }
+}
+
+// Rank kept: sigma > tau on each side, the larger count, capped by capacity.
+template <class T>
+__global__ void k_comp_rank(const CompDesc* __restrict__ cs, int nc, LevelView lv, const T* __restrict__ work,
+                            double tau, int rank_max) {
+  const int t = blockIdx.x * WG + threadIdx.x;
+  if (t >= nc) return;
+  const CompDesc c = cs[t];
+  int ku = 0, kv = 0;
+  for (int a = 0; a < c.kq; ++a) {
+    if ((double)work[c.su + a] > tau) ++ku;
+    if ((double)work[c.sv + a] > tau) ++kv;
+  }
+  int k = ku > kv ? ku : kv;
+  if (rank_max > 0 && k > rank_max) k = rank_max;
+  if (k > lv.cap[c.box]) k = lv.cap[c.box];
+  lv.rnew[c.box] = k;
+}
+
+// r_j = Uhat^T U_j and t_j = Vhat^T V_j (k x r_old, ld cap_j).
+template <class T>
+__global__ void __launch_bounds__(WG) k_comp_rt(const CompDesc* __restrict__ cs, LevelView lv,
+                                                const T* __restrict__ pool, T* __restrict__ work) {
+  const CompDesc c = cs[blockIdx.x];
+  const int j = c.box;
+  const int mj = lv.m[j], r = lv.r[j], k = lv.rnew[j], cap = lv.cap[j];
+  const T* U = pool + lv.Uo[j];
+  const T* V = pool + lv.Vo[j];
+  const T* Uh = work + c.uu;
+  const T* Vh = work + c.vv;
+  for (int t = threadIdx.x; t < k * r; t += WG) {
+    const int a = t % k, b = t / k;
+    T su = 0, sv = 0;
+    for (int i = 0; i < mj; ++i) {
+      su += Uh[i + (int64_t)a * mj] * U[i + (int64_t)b * mj];
+      sv += Vh[i + (int64_t)a * mj] * V[i + (int64_t)b * mj];
+    }
+    work[c.tr + a + (int64_t)b * cap] = su;
+    work[c.tt + a + (int64_t)b * cap] = sv;
+  }
+}
+
+constexpr int XF_CHUNK = 8;    // columns (rows) of an edge transformed at a time
+
+// Row transform of every y-y edge of an affected box j and of its transfers:
+// K(j, q) <- r_j K(j, q), PU(j) <- r_j PU(j), PV(j) <- t_j PV(j)
+// (eqs. K_jq_update, U_parent_j_update, V_parent_j_update).
+// blockIdx.x: affected box; blockIdx.y: offset code (c7 = PU, c7 + 1 = PV).
+template <class T>
+__global__ void __launch_bounds__(WG) k_row_xform(const CompDesc* __restrict__ cs, LevelView lv, T* __restrict__ pool,
+                                                  const T* __restrict__ work) {
+  const CompDesc c = cs[blockIdx.x];
+  const int j = c.box;
+  const int code = blockIdx.y;
+  int64_t off;
+  int cols;
+  const T* X;
+  if (code < lv.c7) {
+    off = lv.Kt[(int64_t)j * lv.c7 + code];
+    if (off < 0) return;
+    cols = lv.r[lv.B7[(int64_t)j * lv.c7 + code]];
+    X = work + c.tr;
+  } else {
+    if (!lv.haspar) return;
+    off = code == lv.c7 ? lv.PUo[j] : lv.PVo[j];
+    cols = lv.rpar[j];
+    X = work + (code == lv.c7 ? c.tr : c.tt);
+  }
+  const int r = lv.r[j], k = lv.rnew[j], cap = lv.cap[j];
+  __shared__ T sh[XF_CHUNK * 1024];   // rank <= 1024
+  T* E = pool + off;
+  for (int c0 = 0; c0 < cols; c0 += XF_CHUNK) {
+    const int nc = (cols - c0) < XF_CHUNK ? (cols - c0) : XF_CHUNK;
+    for (int t = threadIdx.x; t < r * nc; t += WG) {
+      const int i = t % r, cc = t / r;
+      sh[i + cc * r] = E[i + (int64_t)(c0 + cc) * cap];
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < k * nc; t += WG) {
+      const int i = t % k, cc = t / k;
+      T s = 0;
+      for (int b = 0; b < r; ++b) s += X[i + (int64_t)b * cap] * sh[b + cc * r];
+      E[i + (int64_t)(c0 + cc) * cap] = s;
+    }
+    __syncthreads();
+  }
+}
+
+// Column transform: K(q, j) <- K(q, j) t_j^T for every edge into y_j (eq. K_qj_update).
+template <class T>
+__global__ void __launch_bounds__(WG) k_col_xform(const CompDesc* __restrict__ cs, LevelView lv, T* __restrict__ pool,
+                                                  const T* __restrict__ work) {
+  const CompDesc c = cs[blockIdx.x];
+  const int j = c.box;
+  const int code = blockIdx.y;
+  const int qb = lv.B7[(int64_t)j * lv.c7 + code];
+  if (qb < 0) return;
+  const int back = lv.c7 - 1 - code;   // offset of j seen from q
+  const int64_t off = lv.Kt[(int64_t)qb * lv.c7 + back];
+  if (off < 0) return;
+  const int rows = lv.rnew[qb], r = lv.r[j], k = lv.rnew[j];
+  const int ldq = lv.cap[qb], capj = lv.cap[j];
+  const T* X = work + c.tt;
+  __shared__ T sh[XF_CHUNK * 1024];   // rank <= 1024
+  T* E = pool + off;
+  for (int r0 = 0; r0 < rows; r0 += XF_CHUNK) {
+    const int nr = (rows - r0) < XF_CHUNK ? (rows - r0) : XF_CHUNK;
+    for (int t = threadIdx.x; t < nr * r; t += WG) {
+      const int i = t % nr, b = t / nr;
+      sh[i + b * XF_CHUNK] = E[(r0 + i) + (int64_t)b * ldq];
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < nr * k; t += WG) {
+      const int i = t % nr, a = t / nr;
+      T s = 0;
+      for (int b = 0; b < r; ++b) s += sh[i + b * XF_CHUNK] * X[a + (int64_t)b * capj];
+      E[(r0 + i) + (int64_t)a * ldq] = s;
+    }
+    __syncthreads();
+  }
+}
+
+// Commit the new bases: U_j <- Uhat, V_j <- Vhat, Sigma <- Sigma_hat, r_j <- k.
+template <class T>
+__global__ void __launch_bounds__(WG) k_comp_commit(const CompDesc* __restrict__ cs, LevelView lv, T* __restrict__ pool,
+                                                    const T* __restrict__ work) {
+  const CompDesc c = cs[blockIdx.x];
+  const int j = c.box;
+  const int mj = lv.m[j], k = lv.rnew[j];
+  T* U = pool + lv.Uo[j];
+  T* V = pool + lv.Vo[j];
+  for (int t = threadIdx.x; t < mj * k; t += WG) {
+    U[t] = work[c.uu + t];
+    V[t] = work[c.vv + t];
+  }
+  for (int a = threadIdx.x; a < k; a += WG) {
+    pool[lv.SUo[j] + a] = a < c.kq ? work[c.su + a] : (T)0;
+    pool[lv.SVo[j] + a] = a < c.kq ? work[c.sv + a] : (T)0;
+  }
+}
+
+__global__ void k_commit_ranks(const CompDesc* __restrict__ cs, int nc, LevelView lv) {
+  const int t = blockIdx.x * WG + threadIdx.x;
+  if (t < nc) lv.r[cs[t].box] = lv.rnew[cs[t].box];
+}
+
+// Redirect the compressed well-separated fill through K (eq. K_kj_update and
+// Alg. 3): K(a, b) += op_a(D(a, b)) op_b with op = Uhat^T on an x~ row side
+// and Vhat on an x~ column side. blockIdx.x: elimination; blockIdx.y: pair.
+template <class T>
+__global__ void __launch_bounds__(WG) k_redirect(const ElimDesc* __restrict__ es, const FNode* __restrict__ Fs,
+                                                 LevelView lv, const T* __restrict__ work, T* __restrict__ pool) {
+  const ElimDesc e = es[blockIdx.x];
+  const int pr = blockIdx.y;
+  if (pr >= e.nF * e.nF) return;
+  const FNode A = Fs[e.F0 + pr / e.nF];
+  const FNode B = Fs[e.F0 + pr % e.nF];
+  if (A.type == 1 && B.type == 1) return;
+  if (code3(lv.coords, lv.d, A.box, B.box) >= 0) return;
+  const int64_t dst = lv.Kt[(int64_t)A.box * lv.c7 + code7(lv.coords, lv.d, A.box, B.box)];
+  if (dst < 0) return;
+  const int ld = lv.cap[A.box];
+  const int ka = A.type == 0 ? lv.r[A.box] : A.dim;     // ranks already committed
+  const int kb = B.type == 0 ? lv.r[B.box] : B.dim;
+  if (ka == 0 || kb == 0) return;
+  const T* D = work + e.dlt;
+  const T* Ua = A.type == 0 ? pool + lv.Uo[A.box] : nullptr;
+  const T* Vb = B.type == 0 ? pool + lv.Vo[B.box] : nullptr;
+  const int ma = A.dim, mb = B.dim;
+  __shared__ T sh[8 * 1024];
+  T* out = pool + dst;
+  // rows of (D Vb) in chunks of 8, then Ua^T times them
+  for (int a0 = 0; a0 < ka; a0 += 8) {
+    const int na = (ka - a0) < 8 ? (ka - a0) : 8;
+    // sh[ii, jj] = sum_x opA(a0+ii, x) * D(x, :) ... computed directly per output
+    for (int t = threadIdx.x; t < na * mb; t += WG) {
+      const int ii = t % na, x = t / na;
+      T s = 0;
+      if (Ua) {
+        for (int y = 0; y < ma; ++y) s += Ua[y + (int64_t)(a0 + ii) * ma] * D[(A.off + y) + (int64_t)(B.off + x) * e.f];
+      } else {
+        s = D[(A.off + a0 + ii) + (int64_t)(B.off + x) * e.f];
+      }
+      sh[ii + x * 8] = s;
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < na * kb; t += WG) {
+      const int ii = t % na, jj = t / na;
+      T s = 0;
+      if (Vb) {
+        for (int x = 0; x < mb; ++x) s += sh[ii + x * 8] * Vb[x + (int64_t)jj * mb];
+      } else {
+        s = sh[ii + jj * 8];
+      }
+      out[(a0 + ii) + (int64_t)jj * ld] += s;
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace ifmm

@@ -1,0 +1,260 @@
+// R1: the Chebyshev H2 representation of A (Sec. 2.1, eqs. A_decomp_l3 and
+// A_decomp_l2; Sec. 3 opening) and its product y = A~ x (the black-box FMM
+// product that GMRES uses in Sec. 3.2).
+//   leaf U_i = V_i : Lagrange basis of box i at its points      (m_i x q)
+//   transfer T_b   : parent basis at the child's nodes           (q x q), b = child position
+//   M2L Kbar(l, d) : kernel between the nodes of two boxes at offset d (q x q)
+//   P2P            : kernel between the points of adjacent leaves, evaluated on the fly
+// q = n^d, first-kind Chebyshev nodes cos((2k+1) pi / (2n)), k = 0..n-1,
+// tensor index m = sum_k m_k n^k.
+#pragma once
+
+#include <cmath>
+
+#include "linalg.hpp"
+#include "tree.hpp"
+
+namespace ifmm {
+
+constexpr int MAXN = 8;          // Chebyshev order limit
+constexpr int P2P_TILE = 256;    // source points staged in LDS at a time
+
+struct KernelFn {
+  int kind;
+  double param, shift;
+};
+
+__host__ __device__ inline double kappa(const KernelFn& k, double r) {
+  switch (k.kind) {
+    case IFMM_K_IMQ: return 1.0 / sqrt(r * r + k.param * k.param);
+    case IFMM_K_GAUSS: return exp(-(r * r) / (k.param * k.param));
+    case IFMM_K_PAPER:
+      if (r == 0.0) return 1.0;
+      return r < k.param ? r / k.param : k.param / r;
+    default: return 1.0 + r * r;
+  }
+}
+
+struct ChebConst {
+  int n, d, q;
+  double t[MAXN];
+};
+
+__host__ __device__ inline double lagrange1(const ChebConst& c, int m, double x) {
+  double v = 1.0;
+  for (int k = 0; k < c.n; ++k)
+    if (k != m) v *= (x - c.t[k]) / (c.t[m] - c.t[k]);
+  return v;
+}
+
+__host__ __device__ inline double lagrange_nd(const ChebConst& c, int m, const double* x) {
+  double v = 1.0;
+  for (int k = 0; k < c.d; ++k) {
+    const int mk = m % c.n;
+    m /= c.n;
+    v *= lagrange1(c, mk, x[k]);
+  }
+  return v;
+}
+
+__host__ __device__ inline void node_ref(const ChebConst& c, int m, double* x) {
+  for (int k = 0; k < c.d; ++k) {
+    x[k] = c.t[m % c.n];
+    m /= c.n;
+  }
+}
+
+// Leaf interpolation matrices, column-major per leaf at offset leaf_start[i] * q.
+__global__ void k_leaf_ubar(const double* __restrict__ pts, const int64_t* __restrict__ leaf_start,
+                            const int* __restrict__ coords, int nb, ChebConst c, double o0, double o1,
+                            double o2, double h, double* __restrict__ ubar) {
+  const int i = blockIdx.x;
+  if (i >= nb) return;
+  const int64_t s = leaf_start[i], m = leaf_start[i + 1] - s;
+  const double o[3] = {o0, o1, o2};
+  double ctr[3];
+  for (int k = 0; k < c.d; ++k) ctr[k] = o[k] + ((double)coords[i * c.d + k] + 0.5) * h;
+  double* U = ubar + s * c.q;
+  for (int64_t e = threadIdx.x; e < m * c.q; e += WG) {
+    const int64_t a = e % m;
+    const int mm = (int)(e / m);
+    double x[3];
+    for (int k = 0; k < c.d; ++k) x[k] = (pts[(s + a) * c.d + k] - ctr[k]) * (2.0 / h);
+    U[a + (int64_t)mm * m] = lagrange_nd(c, mm, x);
+  }
+}
+
+// M2L table of one level: 7^d offsets, each q x q column-major.
+__global__ void k_m2l_table(ChebConst c, KernelFn kf, double h, double* __restrict__ tab) {
+  const int code = blockIdx.x;
+  int dl[3] = {0, 0, 0};
+  int r = code;
+  for (int k = 0; k < c.d; ++k) { dl[k] = r % 7 - 3; r /= 7; }
+  double* K = tab + (int64_t)code * c.q * c.q;
+  for (int e = threadIdx.x; e < c.q * c.q; e += WG) {
+    const int m = e % c.q, mp = e / c.q;
+    double xi[3], xj[3];
+    node_ref(c, m, xi);
+    node_ref(c, mp, xj);
+    double r2 = 0;
+    for (int k = 0; k < c.d; ++k) {
+      const double a = xi[k] * (0.5 * h);
+      const double b = xj[k] * (0.5 * h) + (double)dl[k] * h;
+      const double df = a - b;
+      r2 += df * df;
+    }
+    K[m + (int64_t)mp * c.q] = kappa(kf, sqrt(r2));
+  }
+}
+
+// ------------------------------------------------------------------ matvec
+// Multipole/local arrays: per box a q x nrhs column-major block.
+__global__ void k_p2m(const double* __restrict__ ubar, const int64_t* __restrict__ leaf_start, int nb,
+                      int q, const double* __restrict__ x, int64_t ldx, int nrhs,
+                      double* __restrict__ w) {
+  const int i = blockIdx.x;
+  if (i >= nb) return;
+  const int64_t s = leaf_start[i], m = leaf_start[i + 1] - s;
+  const double* U = ubar + s * q;
+  for (int e = threadIdx.x; e < q * nrhs; e += WG) {
+    const int mm = e % q, rr = e / q;
+    double acc = 0;
+    for (int64_t a = 0; a < m; ++a) acc += U[a + (int64_t)mm * m] * x[(s + a) + rr * ldx];
+    w[(int64_t)i * q * nrhs + e] = acc;
+  }
+}
+
+// Upward pass (M2M): w_p = sum_c T_c^T w_c; tcodes[c] = child position bits.
+__global__ void k_m2m(const int* __restrict__ ch_start, const int* __restrict__ cbits, int nbp, int q,
+                      int nrhs, const double* __restrict__ T, const double* __restrict__ wc,
+                      double* __restrict__ wp) {
+  const int p = blockIdx.x;
+  if (p >= nbp) return;
+  for (int e = threadIdx.x; e < q * nrhs; e += WG) {
+    const int mp = e % q, rr = e / q;
+    double acc = 0;
+    for (int c = ch_start[p]; c < ch_start[p + 1]; ++c) {
+      const double* Tc = T + (int64_t)cbits[c] * q * q;
+      const double* w = wc + (int64_t)c * q * nrhs + (int64_t)rr * q;
+      for (int m = 0; m < q; ++m) acc += Tc[m + (int64_t)mp * q] * w[m];
+    }
+    wp[(int64_t)p * q * nrhs + e] = acc;
+  }
+}
+
+// Interaction lists (M2L): g_i = sum_{j in I(i)} Kbar(offset(i, j)) w_j.
+__global__ void k_m2l(const int* __restrict__ in_start, const int* __restrict__ inter,
+                      const int* __restrict__ coords, int nb, int d, int q, int nrhs,
+                      const double* __restrict__ tab, const double* __restrict__ w,
+                      double* __restrict__ g) {
+  const int i = blockIdx.x;
+  if (i >= nb) return;
+  for (int e = threadIdx.x; e < q * nrhs; e += WG) {
+    const int m = e % q, rr = e / q;
+    double acc = 0;
+    for (int t = in_start[i]; t < in_start[i + 1]; ++t) {
+      const int j = inter[t];
+      int code = 0, mul = 1;
+      for (int k = 0; k < d; ++k) {
+        code += (coords[j * d + k] - coords[i * d + k] + 3) * mul;
+        mul *= 7;
+      }
+      const double* K = tab + (int64_t)code * q * q;
+      const double* wj = w + (int64_t)j * q * nrhs + (int64_t)rr * q;
+      for (int mp = 0; mp < q; ++mp) acc += K[m + (int64_t)mp * q] * wj[mp];
+    }
+    g[(int64_t)i * q * nrhs + e] = acc;
+  }
+}
+
+// Downward pass (L2L): g_c += T_c g_parent.
+__global__ void k_l2l(const int* __restrict__ parent, const int* __restrict__ cbits, int nbc, int q,
+                      int nrhs, const double* __restrict__ T, const double* __restrict__ gp,
+                      double* __restrict__ gc) {
+  const int c = blockIdx.x;
+  if (c >= nbc) return;
+  const double* Tc = T + (int64_t)cbits[c] * q * q;
+  const double* g = gp + (int64_t)parent[c] * q * nrhs;
+  for (int e = threadIdx.x; e < q * nrhs; e += WG) {
+    const int m = e % q, rr = e / q;
+    double acc = 0;
+    for (int mp = 0; mp < q; ++mp) acc += Tc[m + (int64_t)mp * q] * g[mp + (int64_t)rr * q];
+    gc[(int64_t)c * q * nrhs + e] += acc;
+  }
+}
+
+// Leaf output: y_a = U_i g_i + sum over adjacent leaves of K(|x_a - x_b|) x_b (+ shift at a = b).
+__global__ void __launch_bounds__(WG) k_l2p_p2p(const double* __restrict__ pts, const int64_t* __restrict__ leaf_start,
+                          const int* __restrict__ nb_start, const int* __restrict__ nbr, int nb, int d,
+                          int q, int nrhs, KernelFn kf, const double* __restrict__ ubar,
+                          const double* __restrict__ g, const double* __restrict__ x, int64_t ldx,
+                          double* __restrict__ y, int64_t ldy, int with_far) {
+  const int i = blockIdx.x;
+  if (i >= nb) return;
+  const int64_t s = leaf_start[i], m = leaf_start[i + 1] - s;
+  __shared__ double sp[P2P_TILE * 3];
+  __shared__ int64_t sidx[P2P_TILE];
+  // one thread per (target point, rhs); loop in chunks so any leaf size works
+  for (int64_t base = 0; base < m * nrhs; base += WG) {
+    const int64_t e = base + threadIdx.x;
+    const bool act = e < m * nrhs;
+    const int64_t a = act ? e % m : 0;
+    const int rr = act ? (int)(e / m) : 0;
+    double xa[3] = {0, 0, 0};
+    if (act)
+      for (int k = 0; k < d; ++k) xa[k] = pts[(s + a) * d + k];
+    double acc = 0;
+    if (act && with_far) {
+      const double* U = ubar + s * q;
+      const double* gi = g + (int64_t)i * q * nrhs + (int64_t)rr * q;
+      for (int mm = 0; mm < q; ++mm) acc += U[a + (int64_t)mm * m] * gi[mm];
+    }
+    for (int t = nb_start[i]; t < nb_start[i + 1]; ++t) {
+      const int j = nbr[t];
+      const int64_t sj = leaf_start[j], mj = leaf_start[j + 1] - sj;
+      for (int64_t b0 = 0; b0 < mj; b0 += P2P_TILE) {
+        const int cnt = (int)((mj - b0) < P2P_TILE ? (mj - b0) : P2P_TILE);
+        __syncthreads();
+        for (int u = threadIdx.x; u < cnt; u += WG) {
+          for (int k = 0; k < d; ++k) sp[u * 3 + k] = pts[(sj + b0 + u) * d + k];
+          sidx[u] = sj + b0 + u;
+        }
+        __syncthreads();
+        if (act) {
+          for (int u = 0; u < cnt; ++u) {
+            double r2 = 0;
+            for (int k = 0; k < d; ++k) {
+              const double df = xa[k] - sp[u * 3 + k];
+              r2 += df * df;
+            }
+            double kv = kappa(kf, sqrt(r2));
+            if (sidx[u] == s + a) kv += kf.shift;
+            acc += kv * x[sidx[u] + (int64_t)rr * ldx];
+          }
+        }
+      }
+    }
+    if (act) y[(s + a) + (int64_t)rr * ldy] = acc;
+  }
+}
+
+// caller order <-> tree order
+__global__ void k_perm_gather(const double* __restrict__ src, int64_t lds, const int* __restrict__ perm,
+                              int64_t n, int nrhs, double* __restrict__ dst, int64_t ldd) {
+  const int64_t e = (int64_t)blockIdx.x * WG + threadIdx.x;
+  if (e >= n * nrhs) return;
+  const int64_t t = e % n;
+  const int r = (int)(e / n);
+  dst[t + r * ldd] = src[(int64_t)perm[t] + r * lds];
+}
+
+__global__ void k_perm_scatter(const double* __restrict__ src, int64_t lds, const int* __restrict__ perm,
+                               int64_t n, int nrhs, double* __restrict__ dst, int64_t ldd) {
+  const int64_t e = (int64_t)blockIdx.x * WG + threadIdx.x;
+  if (e >= n * nrhs) return;
+  const int64_t t = e % n;
+  const int r = (int)(e / n);
+  dst[(int64_t)perm[t] + r * ldd] = src[t + r * lds];
+}
+
+}  // namespace ifmm

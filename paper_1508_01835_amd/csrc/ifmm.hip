@@ -1,0 +1,257 @@
+// C ABI of the IFMM library (include/ifmm.h). Every entry point converts
+// failures into status codes; nothing throws across the boundary.
+#include "gmres.hpp"
+
+using namespace ifmm;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+template <class T>
+struct Factors : FactorStoreBase {
+  FactorStore<T> F;
+  SolvePlan<T> S;
+};
+
+template <class F>
+int guarded(F&& fn) {
+  try {
+    fn();
+    g_last_error.clear();
+    return IFMM_OK;
+  } catch (const Error& e) {
+    g_last_error = e.what();
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    return IFMM_ERR_OOM;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return IFMM_ERR_INTERNAL;
+  } catch (...) {
+    g_last_error = "unknown failure";
+    return IFMM_ERR_INTERNAL;
+  }
+}
+
+void check_finite_vec(Problem& P, const double* v, int64_t n, int nrhs, int64_t ld, const char* what) {
+  (void)P; (void)v; (void)n; (void)nrhs; (void)ld; (void)what;
+}
+
+}  // namespace
+
+struct ifmm_problem {
+  Problem P;
+  GmresWork G;
+};
+
+extern "C" {
+
+void ifmm_default_options(ifmm_options* opt) {
+  if (!opt) return;
+  opt->precision = 64;
+  opt->leaf_max = 64;
+  opt->rank_max = 0;
+  opt->sigma0_override = 0.0;
+  opt->hbm_budget_bytes = 0;
+  opt->stream = nullptr;
+}
+
+const char* ifmm_strerror(int code) {
+  switch (code) {
+    case IFMM_OK: return "ok";
+    case IFMM_ERR_ARG: return "invalid argument";
+    case IFMM_ERR_OOM: return "out of device memory or over the HBM budget";
+    case IFMM_ERR_SINGULAR: return "singular pivot block";
+    case IFMM_ERR_NUMERICAL: return "non-finite value";
+    case IFMM_ERR_STATE: return "call not legal in the handle's state";
+    case IFMM_ERR_HIP: return "HIP runtime error";
+    case IFMM_ERR_INTERNAL: return "internal error";
+    default: return "unknown status";
+  }
+}
+
+const char* ifmm_last_error(void) { return g_last_error.c_str(); }
+
+int ifmm_build(const double* points, int64_t n, int dim, ifmm_kernel k, int depth, int cheb_order, double eps,
+               const ifmm_options* opt, ifmm_handle* out) {
+  if (out) *out = nullptr;
+  ifmm_problem* h = nullptr;
+  const int rc = guarded([&] {
+    if (!points || !out) fail(IFMM_ERR_ARG, "null pointer");
+    if (n < 1 || n > (int64_t)INT32_MAX) fail(IFMM_ERR_ARG, "n out of range");
+    if (dim < 1 || dim > 3) fail(IFMM_ERR_ARG, "dim must be 1, 2 or 3");
+    if (cheb_order < 1 || cheb_order > MAXN) fail(IFMM_ERR_ARG, "cheb_order must be in [1, 8]");
+    if (!(eps >= 0.0) || !std::isfinite(eps)) fail(IFMM_ERR_ARG, "eps must be finite and >= 0");
+    if (k.kind < 0 || k.kind > 3) fail(IFMM_ERR_ARG, "unknown kernel kind");
+    if ((k.kind == IFMM_K_GAUSS || k.kind == IFMM_K_PAPER) && !(k.param > 0)) fail(IFMM_ERR_ARG, "kernel parameter must be > 0");
+    ifmm_options o;
+    ifmm_default_options(&o);
+    if (opt) o = *opt;
+    if (o.precision != 32 && o.precision != 64) fail(IFMM_ERR_ARG, "precision must be 32 or 64");
+    int q = 1;
+    for (int a = 0; a < dim; ++a) q *= cheb_order;
+    if (q > SW_MAXC) fail(IFMM_ERR_ARG, "cheb_order^dim above 512");
+    h = new ifmm_problem();
+    Problem& P = h->P;
+    P.mem.budget = o.hbm_budget_bytes;
+    P.stream = static_cast<hipStream_t>(o.stream);
+    P.n = n;
+    P.d = dim;
+    P.order = cheb_order;
+    P.q = q;
+    P.precision = o.precision;
+    P.eps = eps;
+    P.rank_max = o.rank_max;
+    P.kf.kind = k.kind;
+    P.kf.param = k.param;
+    P.kf.shift = k.diag_shift;
+    P.cc.n = cheb_order;
+    P.cc.d = dim;
+    P.cc.q = q;
+    for (int a = 0; a < cheb_order; ++a) P.cc.t[a] = std::cos((2.0 * a + 1.0) * M_PI / (2.0 * cheb_order));
+    P.info_buf.alloc(sizeof(int) * 4, &P.mem);
+    P.d_info = P.info_buf.as<int>();
+    IFMM_HIP(hipMemsetAsync(P.d_info, 0xff, sizeof(int) * 4, P.stream));
+    const double t0 = now_ms();
+    build_tree(P, points, depth, o.leaf_max);
+    build_r1(P);
+    build_r2(P, o.sigma0_override);
+    P.st.t_build_ms = now_ms() - t0;
+    *out = h;
+  });
+  if (rc != IFMM_OK) delete h;
+  return rc;
+}
+
+int ifmm_factorize(ifmm_handle h) {
+  return guarded([&] {
+    if (!h) fail(IFMM_ERR_ARG, "null handle");
+    Problem& P = h->P;
+    P.factorized = false;
+    P.fac.reset();
+    IFMM_HIP(hipMemsetAsync(P.d_info, 0xff, sizeof(int) * 4, P.stream));
+    P.st.error_level = P.st.error_box = -1;
+    const double t0 = now_ms();
+    if (P.precision == 64) {
+      auto f = std::make_unique<Factors<double>>();
+      Factorizer<double> z(P, f->F);
+      z.run();
+      P.fac = std::move(f);
+    } else {
+      auto f = std::make_unique<Factors<float>>();
+      Factorizer<float> z(P, f->F);
+      z.run();
+      P.fac = std::move(f);
+    }
+    P.st.t_factor_ms = now_ms() - t0;
+    P.factorized = true;
+  });
+}
+
+static void solve_any(Problem& P, const double* b, double* x, int nrhs, int64_t ld) {
+  if (P.precision == 64) {
+    auto* f = static_cast<Factors<double>*>(P.fac.get());
+    solve_impl<double>(P, f->F, f->S, b, x, nrhs, ld);
+  } else {
+    auto* f = static_cast<Factors<float>*>(P.fac.get());
+    solve_impl<float>(P, f->F, f->S, b, x, nrhs, ld);
+  }
+}
+
+int ifmm_solve(ifmm_handle h, const double* b, double* x, int nrhs, int64_t ld) {
+  return guarded([&] {
+    if (!h || !b || !x) fail(IFMM_ERR_ARG, "null pointer");
+    Problem& P = h->P;
+    if (!P.factorized) fail(IFMM_ERR_STATE, "ifmm_solve needs a factorized handle");
+    if (nrhs < 1 || ld < P.n) fail(IFMM_ERR_ARG, "nrhs must be >= 1 and ld >= n");
+    const double t0 = now_ms();
+    solve_any(P, b, x, nrhs, ld);
+    P.sync();
+    P.st.t_last_solve_ms = now_ms() - t0;
+  });
+}
+
+static void matvec_any(Problem& P, const double* x, double* y, int nrhs, int64_t ld) {
+  const int64_t n = P.n;
+  P.mv_x.reserve(sizeof(double) * n * nrhs, &P.mem);
+  P.mv_y.reserve(sizeof(double) * n * nrhs, &P.mem);
+  dim3 g((unsigned)std::max<int64_t>(1, ceil_div(n * nrhs, WG)));
+  hipLaunchKernelGGL(k_perm_gather, g, dim3(WG), 0, P.stream, x, ld, P.perm.as<int>(), n, nrhs,
+                     P.mv_x.as<double>(), n);
+  IFMM_LAUNCH_CHECK();
+  matvec_tree(P, P.mv_x.as<double>(), P.mv_y.as<double>(), nrhs);
+  hipLaunchKernelGGL(k_perm_scatter, g, dim3(WG), 0, P.stream, (const double*)P.mv_y.as<double>(), n,
+                     P.perm.as<int>(), n, nrhs, y, ld);
+  IFMM_LAUNCH_CHECK();
+}
+
+int ifmm_matvec(ifmm_handle h, const double* x, double* y, int nrhs, int64_t ld) {
+  return guarded([&] {
+    if (!h || !x || !y) fail(IFMM_ERR_ARG, "null pointer");
+    Problem& P = h->P;
+    if (nrhs < 1 || ld < P.n) fail(IFMM_ERR_ARG, "nrhs must be >= 1 and ld >= n");
+    if (x == y) fail(IFMM_ERR_ARG, "x and y must not alias");
+    const double t0 = now_ms();
+    matvec_any(P, x, y, nrhs, ld);
+    P.sync();
+    P.st.t_last_matvec_ms = now_ms() - t0;
+  });
+}
+
+int ifmm_gmres(ifmm_handle op, ifmm_handle prec, const double* b, double* x, int nrhs, int64_t ld, double tol,
+               int maxit, int* iters_out, double* relres_out) {
+  return guarded([&] {
+    if (!op || !prec || !b || !x) fail(IFMM_ERR_ARG, "null pointer");
+    Problem& A = op->P;
+    Problem& M = prec->P;
+    if (A.n != M.n) fail(IFMM_ERR_ARG, "op and prec have different sizes");
+    if (!M.factorized) fail(IFMM_ERR_STATE, "the preconditioner handle is not factorized");
+    if (nrhs < 1 || ld < A.n) fail(IFMM_ERR_ARG, "nrhs must be >= 1 and ld >= n");
+    if (maxit < 1 || maxit > 1000) fail(IFMM_ERR_ARG, "maxit must be in [1, 1000]");
+    if (!(tol > 0)) fail(IFMM_ERR_ARG, "tol must be > 0");
+    if (M.stream != A.stream) M.sync();
+    auto applyA = [&](const double* in, double* out) { matvec_any(A, in, out, nrhs, A.n); };
+    auto applyM = [&](const double* in, double* out) {
+      solve_any(M, in, out, nrhs, M.n);
+      if (M.stream != A.stream) M.sync();
+    };
+    const GmresResult r = gmres_run(A, op->G, applyA, applyM, b, x, nrhs, ld, tol, maxit);
+    A.sync();
+    A.st.gmres_iters = r.iters;
+    A.st.gmres_relres = r.relres;
+    if (iters_out) *iters_out = r.iters;
+    if (relres_out) *relres_out = r.relres;
+  });
+}
+
+int ifmm_query(ifmm_handle h, ifmm_stats* s) {
+  return guarded([&] {
+    if (!h || !s) fail(IFMM_ERR_ARG, "null pointer");
+    Problem& P = h->P;
+    P.st.n = P.n;
+    P.st.dim = P.d;
+    P.st.depth = P.L;
+    P.st.cheb_order = P.order;
+    P.st.precision = P.precision;
+    P.st.eps = P.eps;
+    P.st.sigma0 = P.sigma0;
+    P.st.tau = P.tau;
+    P.st.levels = P.L - 1;
+    for (int l = 0; l <= P.L && l < 32; ++l) P.st.boxes[l] = l < (int)P.T.lev.size() ? P.T.lev[l].nb : 0;
+    P.st.device_bytes = P.mem.cur;
+    P.st.device_bytes_peak = P.mem.peak;
+    *s = P.st;
+  });
+}
+
+int ifmm_destroy(ifmm_handle h) {
+  return guarded([&] {
+    if (!h) return;
+    (void)hipStreamSynchronize(h->P.stream);
+    delete h;
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,500 @@
+// Batched, variable-size dense linear algebra on gfx950: GEMM, LU with partial
+// pivoting and its solve, Householder QR, one-sided Jacobi SVD, block copies.
+// Every batch is described by an array of descriptors in device memory; one
+// workgroup (or a set of tiles) serves one descriptor.
+#pragma once
+
+#include "common.hpp"
+
+namespace ifmm {
+
+constexpr int WG = 256;     // threads per workgroup (4 wavefronts of 64)
+constexpr int WAVE = 64;
+
+// ---------------------------------------------------------------- reductions
+template <class T>
+__device__ inline T wave_sum(T v) {
+  for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+  return v;
+}
+
+template <class T>
+__device__ inline T block_sum(T v, T* sh /* >= WG/WAVE */) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+  __syncthreads();
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  T s = 0;
+  for (int i = 0; i < (int)(blockDim.x / WAVE); ++i) s += sh[i];
+  __syncthreads();
+  return s;
+}
+
+// =================================================================== GEMM
+// C = alpha * op(A) * op(B) + beta * C, op(A) is M x K, op(B) is K x N.
+struct GemmDesc {
+  const void* A;
+  const void* B;
+  void* C;
+  int M, N, K;
+  int lda, ldb, ldc;
+  int tA, tB;
+  double alpha, beta;
+  int tile0;       // first tile of this problem in the flattened grid
+  int tiles_n;     // tiles along N
+};
+
+constexpr int GT = 64;   // output tile edge
+constexpr int GK = 16;   // K chunk
+
+template <class T>
+__global__ void __launch_bounds__(WG) k_gemm(const GemmDesc* __restrict__ ds, int nd) {
+  // find the problem owning this tile (descriptors sorted by tile0)
+  int lo = 0, hi = nd - 1;
+  const int t = blockIdx.x;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (ds[mid].tile0 <= t) lo = mid; else hi = mid - 1;
+  }
+  const GemmDesc d = ds[lo];
+  const int local = t - d.tile0;
+  const int tm = local / d.tiles_n, tn = local % d.tiles_n;
+  const int m0 = tm * GT, n0 = tn * GT;
+  if (m0 >= d.M || n0 >= d.N) return;
+  const T* __restrict__ A = static_cast<const T*>(d.A);
+  const T* __restrict__ B = static_cast<const T*>(d.B);
+  T* __restrict__ C = static_cast<T*>(d.C);
+  __shared__ T As[GK][GT + 1];
+  __shared__ T Bs[GK][GT + 1];
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;   // 16 x 16 threads, 4x4 each
+  T acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = 0;
+  for (int k0 = 0; k0 < d.K; k0 += GK) {
+    // load op(A)[m0:m0+64, k0:k0+16] and op(B)[k0:k0+16, n0:n0+64]
+    for (int e = threadIdx.x; e < GT * GK; e += WG) {
+      int mm, kk;
+      if (d.tA == 0) { mm = e % GT; kk = e / GT; } else { kk = e % GK; mm = e / GK; }
+      const int gm = m0 + mm, gk = k0 + kk;
+      T v = 0;
+      if (gm < d.M && gk < d.K)
+        v = d.tA == 0 ? A[(int64_t)gm + (int64_t)gk * d.lda] : A[(int64_t)gk + (int64_t)gm * d.lda];
+      As[kk][mm] = v;
+      int nn;
+      if (d.tB == 0) { kk = e % GK; nn = e / GK; } else { nn = e % GT; kk = e / GT; }
+      const int gn = n0 + nn;
+      const int gk2 = k0 + kk;
+      T w = 0;
+      if (gn < d.N && gk2 < d.K)
+        w = d.tB == 0 ? B[(int64_t)gk2 + (int64_t)gn * d.ldb] : B[(int64_t)gn + (int64_t)gk2 * d.ldb];
+      Bs[kk][nn] = w;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < GK; ++kk) {
+      T a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = As[kk][tx + 16 * i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = Bs[kk][ty + 16 * j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * b[j];
+    }
+    __syncthreads();
+  }
+  const T alpha = (T)d.alpha, beta = (T)d.beta;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int gn = n0 + ty + 16 * j;
+    if (gn >= d.N) continue;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int gm = m0 + tx + 16 * i;
+      if (gm >= d.M) continue;
+      T* c = &C[(int64_t)gm + (int64_t)gn * d.ldc];
+      *c = beta == (T)0 ? alpha * acc[i][j] : alpha * acc[i][j] + beta * (*c);
+    }
+  }
+}
+
+// Host-side batch builder: append problems, then launch once.
+struct GemmBatch {
+  std::vector<GemmDesc> v;
+  int tiles = 0;
+  void add(const void* A, int lda, int tA, const void* B, int ldb, int tB, void* C, int ldc,
+           int M, int N, int K, double alpha, double beta) {
+    if (M <= 0 || N <= 0) return;
+    GemmDesc d;
+    d.A = A; d.B = B; d.C = C; d.M = M; d.N = N; d.K = K; d.lda = lda; d.ldb = ldb; d.ldc = ldc;
+    d.tA = tA; d.tB = tB; d.alpha = alpha; d.beta = beta;
+    d.tiles_n = (int)ceil_div(N, GT);
+    d.tile0 = tiles;
+    tiles += (int)ceil_div(M, GT) * d.tiles_n;
+    v.push_back(d);
+  }
+  void clear() { v.clear(); tiles = 0; }
+};
+
+// ================================================================ LU
+struct LuDesc {
+  void* A;       // n x n, column-major, leading dimension lda; overwritten by L\U
+  int* piv;      // n: row k was swapped with row piv[k] (0-based)
+  int n, lda;
+  int tag;       // reported through *info when a zero pivot is met
+  int pad;
+};
+
+template <class T>
+__global__ void __launch_bounds__(WG) k_lu(const LuDesc* __restrict__ ds, int* info) {
+  const LuDesc d = ds[blockIdx.x];
+  T* __restrict__ A = static_cast<T*>(d.A);
+  const int n = d.n;
+  const int64_t ld = d.lda;
+  __shared__ T smax[WG];
+  __shared__ int sidx[WG];
+  __shared__ T spv;
+  __shared__ int sp;
+  for (int k = 0; k < n; ++k) {
+    T best = -1;
+    int bi = k;
+    for (int i = k + threadIdx.x; i < n; i += WG) {
+      T v = fabs(A[i + k * ld]);
+      if (v > best) { best = v; bi = i; }
+    }
+    smax[threadIdx.x] = best;
+    sidx[threadIdx.x] = bi;
+    __syncthreads();
+    for (int s = WG / 2; s > 0; s >>= 1) {
+      if ((int)threadIdx.x < s) {
+        T o = smax[threadIdx.x + s];
+        int oi = sidx[threadIdx.x + s];
+        if (o > smax[threadIdx.x] || (o == smax[threadIdx.x] && oi < sidx[threadIdx.x])) {
+          smax[threadIdx.x] = o;
+          sidx[threadIdx.x] = oi;
+        }
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      sp = sidx[0];
+      d.piv[k] = sp;
+      if (!(smax[0] > (T)0) && info) atomicCAS(info, -1, d.tag);
+    }
+    __syncthreads();
+    const int p = sp;
+    if (p != k)
+      for (int j = threadIdx.x; j < n; j += WG) {
+        T a = A[k + j * ld];
+        A[k + j * ld] = A[p + j * ld];
+        A[p + j * ld] = a;
+      }
+    __syncthreads();
+    if (threadIdx.x == 0) spv = A[k + k * ld];
+    __syncthreads();
+    const T pv = spv;
+    const T inv = pv != (T)0 ? (T)1 / pv : (T)0;
+    for (int i = k + 1 + threadIdx.x; i < n; i += WG) A[i + k * ld] *= inv;
+    __syncthreads();
+    const int rem = n - k - 1;
+    for (int e = threadIdx.x; e < rem * rem; e += WG) {
+      const int i = k + 1 + e % rem, j = k + 1 + e / rem;
+      A[i + j * ld] -= A[i + k * ld] * A[k + j * ld];
+    }
+    __syncthreads();
+  }
+}
+
+// Solve (L U) X = P B in place: B is n x nrhs (leading dimension ldb).
+struct LuSolveDesc {
+  const void* LU;
+  const int* piv;
+  void* B;
+  int n, lda, nrhs, ldb;
+  int blk0;     // first 1D block of this problem
+  int pad;
+};
+
+template <class T>
+__global__ void __launch_bounds__(WG) k_lu_solve(const LuSolveDesc* __restrict__ ds, int nd) {
+  int lo = 0, hi = nd - 1;
+  const int t = blockIdx.x;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (ds[mid].blk0 <= t) lo = mid; else hi = mid - 1;
+  }
+  const LuSolveDesc d = ds[lo];
+  const int col = (t - d.blk0) * WG + threadIdx.x;
+  if (col >= d.nrhs) return;
+  const T* __restrict__ LU = static_cast<const T*>(d.LU);
+  T* __restrict__ b = static_cast<T*>(d.B) + (int64_t)col * d.ldb;
+  const int n = d.n;
+  const int64_t ld = d.lda;
+  for (int k = 0; k < n; ++k) {
+    const int p = d.piv[k];
+    if (p != k) { T a = b[k]; b[k] = b[p]; b[p] = a; }
+  }
+  for (int k = 0; k < n; ++k) {
+    const T bk = b[k];
+    if (bk != (T)0)
+      for (int i = k + 1; i < n; ++i) b[i] -= LU[i + k * ld] * bk;
+  }
+  for (int k = n - 1; k >= 0; --k) {
+    const T bk = b[k] / LU[k + k * ld];
+    b[k] = bk;
+    if (bk != (T)0)
+      for (int i = 0; i < k; ++i) b[i] -= LU[i + k * ld] * bk;
+  }
+}
+
+struct LuSolveBatch {
+  std::vector<LuSolveDesc> v;
+  int blocks = 0;
+  void add(const void* LU, int lda, const int* piv, void* B, int ldb, int n, int nrhs) {
+    if (n <= 0 || nrhs <= 0) return;
+    LuSolveDesc d;
+    d.LU = LU; d.piv = piv; d.B = B; d.n = n; d.lda = lda; d.nrhs = nrhs; d.ldb = ldb;
+    d.blk0 = blocks; d.pad = 0;
+    blocks += (int)ceil_div(nrhs, WG);
+    v.push_back(d);
+  }
+};
+
+// ================================================================ QR
+// Householder QR of A (M x N, lda), in place. On exit R (kq x N, upper
+// trapezoidal, kq = min(M, N)) is written to Rout (ldr) and, if Qout is not
+// null, the thin orthonormal factor Q (M x kq) to Qout (ldq).
+struct QrDesc {
+  void* A;
+  void* R;
+  void* Q;
+  int M, N, lda, ldr, ldq;
+  int pad;
+};
+
+constexpr int QR_MAXK = 1024;
+
+template <class T>
+__global__ void __launch_bounds__(WG) k_qr(const QrDesc* __restrict__ ds) {
+  const QrDesc d = ds[blockIdx.x];
+  T* __restrict__ A = static_cast<T*>(d.A);
+  T* __restrict__ R = static_cast<T*>(d.R);
+  T* __restrict__ Q = static_cast<T*>(d.Q);
+  const int M = d.M, N = d.N;
+  const int64_t lda = d.lda, ldr = d.ldr, ldq = d.ldq;
+  const int kq = M < N ? M : N;
+  __shared__ T tau[QR_MAXK];
+  __shared__ T alph[QR_MAXK];
+  __shared__ T red[WG / WAVE];
+  const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE, nw = WG / WAVE;
+  for (int j = 0; j < kq; ++j) {
+    T s = 0;
+    for (int i = j + threadIdx.x; i < M; i += WG) { T x = A[i + j * lda]; s += x * x; }
+    s = block_sum(s, red);
+    const T x0 = A[j + j * lda];
+    const T nrm = sqrt(s);
+    T tj = 0, al = x0;
+    if (nrm > (T)0) {
+      al = x0 >= (T)0 ? -nrm : nrm;
+      const T v0 = x0 - al;
+      const T vn2 = s - x0 * x0 + v0 * v0;
+      tj = vn2 > (T)0 ? (T)2 / vn2 : (T)0;
+      __syncthreads();
+      if (threadIdx.x == 0) A[j + j * lda] = v0;
+    }
+    if (threadIdx.x == 0) { tau[j] = tj; alph[j] = al; }
+    __syncthreads();
+    if (tj != (T)0) {
+      for (int c = j + 1 + wv; c < N; c += nw) {
+        T dot = 0;
+        for (int i = j + lane; i < M; i += WAVE) dot += A[i + j * lda] * A[i + c * lda];
+        dot = wave_sum(dot) * tj;
+        for (int i = j + lane; i < M; i += WAVE) A[i + c * lda] -= dot * A[i + j * lda];
+      }
+    }
+    __syncthreads();
+  }
+  if (R) {
+    for (int e = threadIdx.x; e < kq * N; e += WG) {
+      const int i = e % kq, c = e / kq;
+      T v = 0;
+      if (i == c) v = alph[i];
+      else if (i < c) v = A[i + c * lda];
+      R[i + c * ldr] = v;
+    }
+  }
+  if (Q) {
+    for (int e = threadIdx.x; e < M * kq; e += WG) {
+      const int i = e % M, c = e / M;
+      Q[i + c * ldq] = i == c ? (T)1 : (T)0;
+    }
+    __syncthreads();
+    for (int j = kq - 1; j >= 0; --j) {
+      const T tj = tau[j];
+      if (tj != (T)0) {
+        for (int c = j + wv; c < kq; c += nw) {
+          T dot = 0;
+          for (int i = j + lane; i < M; i += WAVE) dot += A[i + j * lda] * Q[i + c * ldq];
+          dot = wave_sum(dot) * tj;
+          for (int i = j + lane; i < M; i += WAVE) Q[i + c * ldq] -= dot * A[i + j * lda];
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// ======================================================= one-sided Jacobi SVD
+// Orthogonalises the columns of B (M x N, ldb) in place by plane rotations
+// (Hestenes). On exit U (M x N, ldu) holds the normalised columns sorted by
+// decreasing norm and S (N) the norms = singular values of the input. A column
+// of zero norm is left as zeros in U.
+struct SvdDesc {
+  void* B;
+  void* U;
+  void* S;
+  int M, N, ldb, ldu;
+};
+
+constexpr int SVD_MAXN = 1024;
+
+template <class T>
+__device__ inline void jacobi_pair(T* __restrict__ B, int64_t ldb, int M, int p, int q, T tol,
+                                   int lane, int* rotated) {
+  T a = 0, b = 0, g = 0;
+  for (int i = lane; i < M; i += WAVE) {
+    const T x = B[i + p * ldb], y = B[i + q * ldb];
+    a += x * x; b += y * y; g += x * y;
+  }
+  a = wave_sum(a); b = wave_sum(b); g = wave_sum(g);
+  if (g == (T)0 || !(fabs(g) > tol * sqrt(a * b))) return;
+  const T zeta = (b - a) / ((T)2 * g);
+  const T t = (zeta >= (T)0 ? (T)1 : (T)-1) / (fabs(zeta) + sqrt((T)1 + zeta * zeta));
+  const T c = (T)1 / sqrt((T)1 + t * t);
+  const T s = c * t;
+  for (int i = lane; i < M; i += WAVE) {
+    const T x = B[i + p * ldb], y = B[i + q * ldb];
+    B[i + p * ldb] = c * x - s * y;
+    B[i + q * ldb] = s * x + c * y;
+  }
+  if (lane == 0) *rotated = 1;
+}
+
+template <class T>
+__global__ void __launch_bounds__(WG) k_jacobi_svd(const SvdDesc* __restrict__ ds, double tol_d,
+                                                    int max_sweeps) {
+  const SvdDesc d = ds[blockIdx.x];
+  T* __restrict__ B = static_cast<T*>(d.B);
+  T* __restrict__ U = static_cast<T*>(d.U);
+  T* __restrict__ S = static_cast<T*>(d.S);
+  const int M = d.M, N = d.N;
+  const int64_t ldb = d.ldb, ldu = d.ldu;
+  const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE, nw = WG / WAVE;
+  __shared__ int rotated;
+  __shared__ T nrm[SVD_MAXN];
+  __shared__ int order[SVD_MAXN];
+  const T tol = (T)tol_d;
+  const int Np = N + (N & 1);   // even number of players; player N (if odd) is a bye
+  if (N > 1) {
+    for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+      if (threadIdx.x == 0) rotated = 0;
+      __syncthreads();
+      // round-robin tournament: player 0 fixed, others rotate
+      for (int round = 0; round < Np - 1; ++round) {
+        for (int pr = wv; pr < Np / 2; pr += nw) {
+          int x, y;
+          if (pr == 0) { x = 0; y = 1 + (round % (Np - 1)); }
+          else {
+            x = 1 + ((round + pr) % (Np - 1));
+            y = 1 + ((round + Np - 1 - pr) % (Np - 1));
+          }
+          if (x < N && y < N) {
+            const int p = x < y ? x : y, q = x < y ? y : x;
+            jacobi_pair(B, ldb, M, p, q, tol, lane, &rotated);
+          }
+        }
+        __syncthreads();
+      }
+      if (!rotated) break;
+      __syncthreads();
+    }
+  }
+  for (int c = wv; c < N; c += nw) {
+    T s = 0;
+    for (int i = lane; i < M; i += WAVE) { T x = B[i + c * ldb]; s += x * x; }
+    s = wave_sum(s);
+    if (lane == 0) nrm[c] = sqrt(s);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int c = 0; c < N; ++c) order[c] = c;
+    for (int a = 0; a < N; ++a) {   // selection sort, decreasing norm, stable
+      int best = a;
+      for (int b = a + 1; b < N; ++b)
+        if (nrm[order[b]] > nrm[order[best]]) best = b;
+      const int tmp = order[best];
+      for (int b = best; b > a; --b) order[b] = order[b - 1];
+      order[a] = tmp;
+    }
+  }
+  __syncthreads();
+  for (int c = wv; c < N; c += nw) {
+    const int src = order[c];
+    const T s = nrm[src];
+    const T inv = s > (T)0 ? (T)1 / s : (T)0;
+    for (int i = lane; i < M; i += WAVE) U[i + c * ldu] = B[i + src * ldb] * inv;
+    if (lane == 0) S[c] = s;
+  }
+}
+
+// ============================================================ block copies
+// dst[i, j] (op)= alpha * src[i, j] * (cs ? cs[j] : 1). mode 0: assign,
+// 1: accumulate, 2: assign alpha * identity (src unused), 3: assign zero,
+// 4: assign alpha * src[j, i] (transpose; dst is rows x cols).
+template <class Ts, class Td>
+struct CopyDesc {
+  const Ts* src;
+  Td* dst;
+  const Ts* cs;
+  int rows, cols, lds, ldd;
+  int mode, pad;
+  double alpha;
+};
+
+template <class Ts, class Td>
+__global__ void __launch_bounds__(WG) k_copy(const CopyDesc<Ts, Td>* __restrict__ ds, int nd) {
+  const int b = blockIdx.y * gridDim.x + blockIdx.x;
+  if (b >= nd) return;
+  const CopyDesc<Ts, Td> d = ds[b];
+  const int64_t total = (int64_t)d.rows * d.cols;
+  for (int64_t e = threadIdx.x; e < total; e += WG) {
+    const int i = (int)(e % d.rows), j = (int)(e / d.rows);
+    Td* o = &d.dst[i + (int64_t)j * d.ldd];
+    if (d.mode == 3) { *o = (Td)0; continue; }
+    if (d.mode == 2) { *o = i == j ? (Td)d.alpha : (Td)0; continue; }
+    if (d.mode == 4) { *o = (Td)(d.alpha * (double)d.src[j + (int64_t)i * d.lds]); continue; }
+    double v = d.alpha * (double)d.src[i + (int64_t)j * d.lds];
+    if (d.cs) v *= (double)d.cs[j];
+    if (d.mode == 1) *o = (Td)((double)*o + v);
+    else *o = (Td)v;
+  }
+}
+
+template <class Ts, class Td>
+struct CopyBatch {
+  std::vector<CopyDesc<Ts, Td>> v;
+  void add(const Ts* src, int lds, Td* dst, int ldd, int rows, int cols, int mode = 0,
+           double alpha = 1.0, const Ts* cs = nullptr) {
+    if (rows <= 0 || cols <= 0) return;
+    CopyDesc<Ts, Td> d;
+    d.src = src; d.dst = dst; d.cs = cs; d.rows = rows; d.cols = cols; d.lds = lds; d.ldd = ldd;
+    d.mode = mode; d.pad = 0; d.alpha = alpha;
+    v.push_back(d);
+  }
+};
+
+}  // namespace ifmm

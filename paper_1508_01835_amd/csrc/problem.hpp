@@ -1,0 +1,189 @@
+// State of one IFMM handle: tree, R1 operators (matvec), the weighted and
+// truncated initial operators of E (R2, float64), the factors, timers.
+#pragma once
+
+#include <memory>
+
+#include "h2.hpp"
+
+namespace ifmm {
+
+// Device copies of one level's tables.
+struct LevelDev {
+  int nb = 0;
+  DevBuf coords, nb_start, nbr, in_start, inter, parent, ch_start, cbits, in_rev;
+  int64_t npairs = 0;   // size of the interaction-list CSR
+};
+
+// Initial operators of one level after QR, weighting and truncation (float64).
+//   K   y_i row, y_j column, one block per interaction-list pair (k_i x k_j, ld k_i)
+//   PU  y_i row, z_parent column (k_i x k_parent, ld k_i);  PV likewise
+//   SU, SV weights (k_i)
+//   leaf only: U, V (m_i x k_i, ld m_i)
+struct R2Level {
+  std::vector<int> k;
+  std::vector<int64_t> k_off;      // per pair (CSR-aligned)
+  std::vector<int64_t> p_off;      // per box (PU / PV)
+  std::vector<int64_t> s_off;      // per box (SU / SV)
+  std::vector<int64_t> u_off;      // leaf: per box (U / V)
+  DevBuf K, PU, PV, SU, SV, U, V;
+};
+
+struct FactorLevelBase;   // defined in factor.hpp (templated on precision)
+struct FactorStoreBase {
+  virtual ~FactorStoreBase() = default;
+};
+
+struct Problem {
+  // configuration
+  int64_t n = 0;
+  int d = 0, L = 0, order = 0, q = 0, precision = 64;
+  double eps = 0, sigma0 = 0, tau = 0;
+  int rank_max = 0;
+  KernelFn kf{};
+  ChebConst cc{};
+  hipStream_t stream = nullptr;
+  MemAccount mem;
+  Staging stage;
+  bool factorized = false;
+
+  // tree
+  HTree T;
+  std::vector<LevelDev> ldev;      // by level
+  DevBuf pts;                      // tree-ordered points (n x d)
+  DevBuf perm;                     // int32: tree position -> caller index
+  DevBuf leaf_start;               // int64 (nb_L + 1)
+
+  // R1
+  DevBuf ubar;                     // leaf interpolation, per leaf at leaf_start * q
+  DevBuf Ttab;                     // 2^d transfers (q x q)
+  std::vector<DevBuf> m2l;         // by level: 7^d tables of q x q
+  std::vector<DevBuf> mv_w, mv_g;  // matvec scratch by level
+  int mv_nrhs = 0;
+  DevBuf mv_x, mv_y;
+
+  // R2 (float64 initial operators of E)
+  std::vector<R2Level> r2;
+  double sigma0_estimated = 0;
+  int sigma0_iters = 0;
+
+  // factors (precision-specific)
+  std::unique_ptr<FactorStoreBase> fac;
+
+  // statistics
+  ifmm_stats st{};
+  int* d_info = nullptr;           // device error word (first failing tag)
+  DevBuf info_buf;
+
+  void sync() { IFMM_HIP(hipStreamSynchronize(stream)); }
+
+  template <class T>
+  void upload(DevBuf& b, const std::vector<T>& v) {
+    b.alloc(v.size() * sizeof(T) + 16, &mem);
+    if (!v.empty()) {
+      void* h = stage.get(v.size() * sizeof(T));
+      std::memcpy(h, v.data(), v.size() * sizeof(T));
+      IFMM_HIP(hipMemcpyAsync(b.p, h, v.size() * sizeof(T), hipMemcpyHostToDevice, stream));
+      sync();   // the staging buffer is reused by the next upload
+    }
+  }
+  template <class T>
+  void download(std::vector<T>& v, const void* src, size_t count) {
+    v.resize(count);
+    if (!count) return;
+    void* h = stage.get(count * sizeof(T));
+    IFMM_HIP(hipMemcpyAsync(h, src, count * sizeof(T), hipMemcpyDeviceToHost, stream));
+    sync();
+    std::memcpy(v.data(), h, count * sizeof(T));
+  }
+  // Upload descriptors into a reusable device buffer (no sync beyond the copy).
+  template <class D>
+  const D* put(DevBuf& b, const std::vector<D>& v) {
+    const size_t bytes = v.size() * sizeof(D);
+    if (bytes + 16 > b.bytes) sync();   // kernels still reading the old buffer must finish
+    b.reserve(bytes + 16, &mem);
+    if (bytes) {
+      void* h = stage.get(bytes);
+      std::memcpy(h, v.data(), bytes);
+      IFMM_HIP(hipMemcpyAsync(b.p, h, bytes, hipMemcpyHostToDevice, stream));
+      sync();
+    }
+    return b.as<D>();
+  }
+};
+
+// Diagnostics (IFMM_DEBUG=1 in the environment): norm and first values of a
+// device array, printed to stderr.
+inline bool debug_on() {
+  static const bool on = std::getenv("IFMM_DEBUG") != nullptr;
+  return on;
+}
+
+template <class T>
+inline void dbg_dump(Problem& P, const char* name, const void* d, size_t count, size_t show = 6) {
+  if (!debug_on() || count == 0) return;
+  std::vector<T> h;
+  P.download(h, d, count);
+  double s = 0;
+  size_t nonfinite = 0;
+  for (auto v : h) {
+    if (!std::isfinite((double)v)) ++nonfinite;
+    else s += (double)v * (double)v;
+  }
+  std::fprintf(stderr, "[ifmm] %s n=%zu norm=%.6e nonfinite=%zu :", name, count, std::sqrt(s), nonfinite);
+  for (size_t i = 0; i < count && i < show; ++i) std::fprintf(stderr, " %.6e", (double)h[i]);
+  std::fprintf(stderr, "\n");
+}
+
+// ------------------------------------------------------------ batched launchers
+template <class T>
+inline void run_gemm(Problem& P, GemmBatch& gb, DevBuf& scratch) {
+  if (gb.v.empty()) return;
+  const GemmDesc* d = P.put(scratch, gb.v);
+  hipLaunchKernelGGL(k_gemm<T>, dim3(gb.tiles), dim3(WG), 0, P.stream, d, (int)gb.v.size());
+  IFMM_LAUNCH_CHECK();
+}
+
+template <class Ts, class Td>
+inline void run_copy(Problem& P, CopyBatch<Ts, Td>& cb, DevBuf& scratch) {
+  if (cb.v.empty()) return;
+  const CopyDesc<Ts, Td>* d = P.put(scratch, cb.v);
+  hipLaunchKernelGGL((k_copy<Ts, Td>), dim3((unsigned)cb.v.size()), dim3(WG), 0, P.stream, d,
+                     (int)cb.v.size());
+  IFMM_LAUNCH_CHECK();
+}
+
+template <class T>
+inline void run_qr(Problem& P, const std::vector<QrDesc>& v, DevBuf& scratch) {
+  if (v.empty()) return;
+  const QrDesc* d = P.put(scratch, v);
+  hipLaunchKernelGGL(k_qr<T>, dim3((unsigned)v.size()), dim3(WG), 0, P.stream, d);
+  IFMM_LAUNCH_CHECK();
+}
+
+template <class T>
+inline void run_svd(Problem& P, const std::vector<SvdDesc>& v, DevBuf& scratch) {
+  if (v.empty()) return;
+  const SvdDesc* d = P.put(scratch, v);
+  const double tol = 4.0 * Prec<T>::u;
+  hipLaunchKernelGGL(k_jacobi_svd<T>, dim3((unsigned)v.size()), dim3(WG), 0, P.stream, d, tol, 60);
+  IFMM_LAUNCH_CHECK();
+}
+
+template <class T>
+inline void run_lu(Problem& P, const std::vector<LuDesc>& v, DevBuf& scratch) {
+  if (v.empty()) return;
+  const LuDesc* d = P.put(scratch, v);
+  hipLaunchKernelGGL(k_lu<T>, dim3((unsigned)v.size()), dim3(WG), 0, P.stream, d, P.d_info);
+  IFMM_LAUNCH_CHECK();
+}
+
+template <class T>
+inline void run_lu_solve(Problem& P, LuSolveBatch& b, DevBuf& scratch) {
+  if (b.v.empty()) return;
+  const LuSolveDesc* d = P.put(scratch, b.v);
+  hipLaunchKernelGGL(k_lu_solve<T>, dim3(b.blocks), dim3(WG), 0, P.stream, d, (int)b.v.size());
+  IFMM_LAUNCH_CHECK();
+}
+
+}  // namespace ifmm

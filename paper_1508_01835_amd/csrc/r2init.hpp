@@ -1,0 +1,259 @@
+// Initial operators of the extended system E (float64):
+//  * orthonormal bases by an exact QR of the Chebyshev bases, bottom-up, the
+//    R factors folded into K and the transfers (Sec. 3 opening: an SVD after
+//    interpolation reduces the rank; here the rank is min(rows, n^d));
+//  * sigma_0(E) by a deterministic power iteration (Sec. 2.4);
+//  * weights Sigma_U, Sigma_V from an SVD of each box's far-field block row /
+//    column (Sec. 2.2, footnote on initial weights), top-down so that the
+//    parent's far field is included;
+//  * rotation to the singular bases and truncation at tau = max(eps, 64u) sigma_0
+//    (eq. methods_SVD_rank_spectralnorm), U and V keeping the same count.
+#pragma once
+
+#include "problem.hpp"
+
+namespace ifmm {
+
+constexpr int SW_ROWS = 8;       // rows of the intermediate product held in LDS
+constexpr int SW_MAXC = 512;     // largest inner dimension (n^d)
+
+// O(ii, jj) = sum_{kb, kc} X(ii, kb) Y(kb, kc) Z(kc, jj) for an a x e output.
+template <class FX, class FY, class FZ, class FO>
+__device__ inline void sandwich(int a, int b, int c, int e, FX X, FY Y, FZ Z, FO O, double* sh) {
+  for (int a0 = 0; a0 < a; a0 += SW_ROWS) {
+    const int ra = (a - a0) < SW_ROWS ? (a - a0) : SW_ROWS;
+    for (int t = threadIdx.x; t < ra * c; t += WG) {
+      const int ii = t % ra, kc = t / ra;
+      double s = 0;
+      for (int kb = 0; kb < b; ++kb) s += X(a0 + ii, kb) * Y(kb, kc);
+      sh[ii + kc * SW_ROWS] = s;
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < ra * e; t += WG) {
+      const int ii = t % ra, jj = t / ra;
+      double s = 0;
+      for (int kc = 0; kc < c; ++kc) s += sh[ii + kc * SW_ROWS] * Z(kc, jj);
+      O(a0 + ii, jj, s);
+    }
+    __syncthreads();
+  }
+}
+
+__device__ inline int find_row(const int* __restrict__ start, int nb, int t) {
+  int lo = 0, hi = nb - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (start[mid] <= t) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ inline int offset_code(const int* coords, int d, int i, int j) {
+  int code = 0, mul = 1;
+  for (int k = 0; k < d; ++k) {
+    code += (coords[j * d + k] - coords[i * d + k] + 3) * mul;
+    mul *= 7;
+  }
+  return code;
+}
+
+// K_pre(i, j) = R_i Kbar(offset) R_j^T for every interaction-list pair of a level.
+__global__ void __launch_bounds__(WG) k_kpre(const int* __restrict__ in_start, const int* __restrict__ inter,
+                                             const int* __restrict__ coords, int nb, int d, int q,
+                                             const double* __restrict__ tab, const double* __restrict__ R,
+                                             const int64_t* __restrict__ roff, const int* __restrict__ r,
+                                             double* __restrict__ K, const int64_t* __restrict__ koff) {
+  __shared__ double sh[SW_ROWS * SW_MAXC];
+  const int t = blockIdx.x;
+  const int i = find_row(in_start, nb, t);
+  const int j = inter[t];
+  const int ri = r[i], rj = r[j];
+  const double* Ri = R + roff[i];
+  const double* Rj = R + roff[j];
+  const double* Kb = tab + (int64_t)offset_code(coords, d, i, j) * q * q;
+  double* out = K + koff[t];
+  sandwich(ri, q, q, rj, [&](int x, int y) { return Ri[x + (int64_t)y * ri]; },
+           [&](int x, int y) { return Kb[x + (int64_t)y * q]; },
+           [&](int x, int y) { return Rj[y + (int64_t)x * rj]; },
+           [&](int x, int y, double v) { out[x + (int64_t)y * ri] = v; }, sh);
+}
+
+// K(i, j) = WU_i[:, :k_i]^T K_pre(i, j) WV_j[:, :k_j].
+__global__ void __launch_bounds__(WG) k_krot(const int* __restrict__ in_start, const int* __restrict__ inter, int nb,
+                                             const double* __restrict__ Kpre, const int64_t* __restrict__ kpoff,
+                                             const int* __restrict__ r, const double* __restrict__ WU,
+                                             const double* __restrict__ WV, const int64_t* __restrict__ woff,
+                                             const int* __restrict__ k, double* __restrict__ K,
+                                             const int64_t* __restrict__ koff) {
+  __shared__ double sh[SW_ROWS * SW_MAXC];
+  const int t = blockIdx.x;
+  const int i = find_row(in_start, nb, t);
+  const int j = inter[t];
+  const int ri = r[i], rj = r[j], ki = k[i], kj = k[j];
+  const double* A = WU + woff[i];
+  const double* B = Kpre + kpoff[t];
+  const double* C = WV + woff[j];
+  double* out = K + koff[t];
+  sandwich(ki, ri, rj, kj, [&](int x, int y) { return A[y + (int64_t)x * ri]; },
+           [&](int x, int y) { return B[x + (int64_t)y * ri]; },
+           [&](int x, int y) { return C[x + (int64_t)y * rj]; },
+           [&](int x, int y, double v) { out[x + (int64_t)y * ki] = v; }, sh);
+}
+
+// P(i) = W_i[:, :k_i]^T Ppre(i) W_parent[:, :k_parent]; Ppre(i) is r_i x r_p with leading dim pld[i].
+__global__ void __launch_bounds__(WG) k_prot(const int* __restrict__ parent, int nb,
+                                             const double* __restrict__ Ppre, const int64_t* __restrict__ ppoff,
+                                             const int* __restrict__ pld, const int* __restrict__ r,
+                                             const int* __restrict__ rpar, const double* __restrict__ W,
+                                             const int64_t* __restrict__ woff, const double* __restrict__ Wp,
+                                             const int64_t* __restrict__ wpoff, const int* __restrict__ k,
+                                             const int* __restrict__ kpar, double* __restrict__ out,
+                                             const int64_t* __restrict__ ooff) {
+  __shared__ double sh[SW_ROWS * SW_MAXC];
+  const int i = blockIdx.x;
+  if (i >= nb) return;
+  const int p = parent[i];
+  const int ri = r[i], rp = rpar[p], ki = k[i], kp = kpar[p];
+  const int ld = pld[i];
+  const double* A = W + woff[i];
+  const double* B = Ppre + ppoff[i];
+  const double* C = Wp + wpoff[p];
+  double* o = out + ooff[i];
+  sandwich(ki, ri, rp, kp, [&](int x, int y) { return A[y + (int64_t)x * ri]; },
+           [&](int x, int y) { return B[x + (int64_t)y * ld]; },
+           [&](int x, int y) { return C[x + (int64_t)y * rp]; },
+           [&](int x, int y, double v) { o[x + (int64_t)y * ki] = v; }, sh);
+}
+
+// Rows of M^T for the weights of box i (U side: K_pre(i,j)^T for j in I(i), then
+// (PU(i) G_p)^T; V side: K_pre(j,i), then (PV(i) GV_p)^T).
+__global__ void __launch_bounds__(WG) k_weight_rows(const int* __restrict__ in_start, const int* __restrict__ inter,
+                                                    const int64_t* __restrict__ in_rev_unused, int nb, int side,
+                                                    const int* __restrict__ rev, const double* __restrict__ Kpre,
+                                                    const int64_t* __restrict__ kpoff, const int* __restrict__ r,
+                                                    const int* __restrict__ parent, const double* __restrict__ Ppre,
+                                                    const int64_t* __restrict__ ppoff, const int* __restrict__ pld,
+                                                    const int* __restrict__ rpar, const double* __restrict__ Gp,
+                                                    const int64_t* __restrict__ gpoff, const int* __restrict__ gpcols,
+                                                    double* __restrict__ M, const int64_t* __restrict__ moff,
+                                                    const int* __restrict__ mrows) {
+  const int i = blockIdx.x;
+  if (i >= nb) return;
+  const int ri = r[i];
+  const int rows = mrows[i];
+  double* out = M + moff[i];   // rows x ri, ld rows
+  int row0 = 0;
+  for (int t = in_start[i]; t < in_start[i + 1]; ++t) {
+    const int j = inter[t];
+    const int rj = r[j];
+    if (side == 0) {
+      const double* B = Kpre + kpoff[t];          // ri x rj
+      for (int e = threadIdx.x; e < rj * ri; e += WG) {
+        const int a = e % rj, c = e / rj;
+        out[(row0 + a) + (int64_t)c * rows] = B[c + (int64_t)a * ri];
+      }
+    } else {
+      const double* B = Kpre + kpoff[rev[t]];     // K_pre(j, i): rj x ri
+      for (int e = threadIdx.x; e < rj * ri; e += WG) {
+        const int a = e % rj, c = e / rj;
+        out[(row0 + a) + (int64_t)c * rows] = B[a + (int64_t)c * rj];
+      }
+    }
+    row0 += rj;
+  }
+  if (parent) {
+    const int p = parent[i];
+    const int rp = rpar[p];
+    const int gc = gpcols[p];
+    const double* Pi = Ppre + ppoff[i];   // ri x rp, ld pld[i]
+    const int ld = pld[i];
+    const double* G = Gp + gpoff[p];      // rp x gc, ld rp
+    for (int e = threadIdx.x; e < gc * ri; e += WG) {
+      const int a = e % gc, c = e / gc;
+      double s = 0;
+      for (int m = 0; m < rp; ++m) s += Pi[c + (int64_t)m * ld] * G[m + (int64_t)a * rp];
+      out[(row0 + a) + (int64_t)c * rows] = s;
+    }
+  }
+}
+
+// -------------------------------------------------- E products for sigma_0
+// Vector layout: x (n) | for l = L..2: z_l (nb_l * q) | y_l (nb_l * q); entries
+// of a box beyond its rank stay zero. E is symmetric (radial kernels), so the
+// power iteration applies E twice.
+// z-type rows at level l: (V^T x^(l))_i - y_i.
+__global__ void k_e_zrows(int nb, int q, const int* __restrict__ r, int leaf,
+                          const int64_t* __restrict__ leaf_start, const double* __restrict__ Q,
+                          const double* __restrict__ x, const int* __restrict__ ch_start,
+                          const double* __restrict__ Ppre, const int64_t* __restrict__ ppoff,
+                          const int* __restrict__ pld, const int* __restrict__ rch,
+                          const double* __restrict__ ych, const double* __restrict__ yl,
+                          double* __restrict__ out) {
+  const int i = blockIdx.x;
+  if (i >= nb) return;
+  const int ri = r[i];
+  for (int m = threadIdx.x; m < ri; m += WG) {
+    double s = 0;
+    if (leaf) {
+      const int64_t st = leaf_start[i], mi = leaf_start[i + 1] - st;
+      const double* Qi = Q + st * q;
+      for (int64_t a = 0; a < mi; ++a) s += Qi[a + (int64_t)m * mi] * x[st + a];
+    } else {
+      for (int c = ch_start[i]; c < ch_start[i + 1]; ++c) {
+        const double* Pc = Ppre + ppoff[c];
+        const int ld = pld[c];
+        for (int a = 0; a < rch[c]; ++a) s += Pc[a + (int64_t)m * ld] * ych[(int64_t)c * q + a];
+      }
+    }
+    out[(int64_t)i * q + m] = s - yl[(int64_t)i * q + m];
+  }
+}
+
+// y-type rows at level l: -z_i + sum_{j in I(i)} K_pre(i,j) y_j + PU(i) z_parent.
+__global__ void k_e_yrows(int nb, int q, const int* __restrict__ r, const int* __restrict__ in_start,
+                          const int* __restrict__ inter, const double* __restrict__ Kpre,
+                          const int64_t* __restrict__ kpoff, const double* __restrict__ zl,
+                          const double* __restrict__ yl, const int* __restrict__ parent,
+                          const double* __restrict__ Ppre, const int64_t* __restrict__ ppoff,
+                          const int* __restrict__ pld, const int* __restrict__ rpar,
+                          const double* __restrict__ zpar, double* __restrict__ out) {
+  const int i = blockIdx.x;
+  if (i >= nb) return;
+  const int ri = r[i];
+  for (int m = threadIdx.x; m < ri; m += WG) {
+    double s = -zl[(int64_t)i * q + m];
+    for (int t = in_start[i]; t < in_start[i + 1]; ++t) {
+      const int j = inter[t];
+      const int rj = r[j];
+      const double* B = Kpre + kpoff[t];
+      for (int a = 0; a < rj; ++a) s += B[m + (int64_t)a * ri] * yl[(int64_t)j * q + a];
+    }
+    if (parent) {
+      const int p = parent[i];
+      const double* Pi = Ppre + ppoff[i];
+      const int ld = pld[i];
+      for (int a = 0; a < rpar[p]; ++a) s += Pi[m + (int64_t)a * ld] * zpar[(int64_t)p * q + a];
+    }
+    out[(int64_t)i * q + m] = s;
+  }
+}
+
+__global__ void k_sumsq_partial(const double* __restrict__ v, int64_t n, double* __restrict__ part) {
+  __shared__ double sh[WG / WAVE];
+  double s = 0;
+  for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += (int64_t)gridDim.x * WG) s += v[i] * v[i];
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ void k_scale(double* __restrict__ v, int64_t n, double a) {
+  const int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x;
+  if (i < n) v[i] *= a;
+}
+
+__global__ void k_fill(double* __restrict__ v, int64_t n, double a) {
+  const int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x;
+  if (i < n) v[i] = a;
+}
+
+}  // namespace ifmm
