@@ -652,8 +652,8 @@ inline void build_r2(Problem& P, double sigma0_override) {
       dbg_dump<double>(P, "SU", z.SU.p, z.s_off.empty() ? 0 : (size_t)(z.s_off.back() + z.k.back()));
       dbg_dump<double>(P, "WU box0", WU[l].p, (size_t)R.r[l][0] * R.r[l][0]);
       dbg_dump<double>(P, "sU box0", SU[l].p, (size_t)R.r[l][0]);
-      if (!z.k_off.empty()) dbg_dump<double>(P, "K", z.K.p, (size_t)(z.k_off.back() + 1));
-      if (l == L) dbg_dump<double>(P, "U", z.U.p, (size_t)(z.u_off.back() + 1));
+      dbg_dump<double>(P, "K", z.K.p, z.K.bytes / sizeof(double));
+      if (l == L) dbg_dump<double>(P, "U", z.U.p, z.U.bytes / sizeof(double));
     }
   }
 }

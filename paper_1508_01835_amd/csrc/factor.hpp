@@ -358,6 +358,7 @@ struct Factorizer {
       P.sync();
       DevBuf nw;
       nw.alloc((size_t)o * sizeof(T) + ((size_t)o * sizeof(T)) / 4, &P.mem);
+      if (debug_on()) IFMM_HIP(hipMemsetAsync(nw.p, 0, nw.bytes, P.stream));
       if (wbase > 0)
         IFMM_HIP(hipMemcpyAsync(nw.p, F.work.p, sizeof(T) * wbase, hipMemcpyDeviceToDevice, P.stream));
       F.work = std::move(nw);
@@ -390,17 +391,22 @@ struct Factorizer {
         sd.push_back(s);
       }
     }
+    chk(L, "comp_gather", nullptr, o);
     run_qr<T>(P, qd, F.d4);
+    chk(L, "comp_qr", nullptr, o);
     run_copy(P, tb, F.d4);
     run_svd<T>(P, sd, F.d4);
+    chk(L, "comp_svd", nullptr, o);
     hipLaunchKernelGGL(k_comp_rank<T>, dim3((unsigned)ceil_div((int64_t)cs.size(), WG)), dim3(WG), 0, P.stream, dc,
                        (int)cs.size(), v, (const T*)W, P.tau, P.rank_max);
     IFMM_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_comp_rt<T>, dim3((unsigned)cs.size()), dim3(WG), 0, P.stream, dc, v, (const T*)L.P(), W);
     IFMM_LAUNCH_CHECK();
+    chk(L, "comp_rt", nullptr, o);
     hipLaunchKernelGGL(k_row_xform<T>, dim3((unsigned)cs.size(), L.c7 + 2), dim3(WG), 0, P.stream, dc, v, L.P(),
                        (const T*)W);
     IFMM_LAUNCH_CHECK();
+    chk(L, "row_xform", nullptr, o);
     hipLaunchKernelGGL(k_col_xform<T>, dim3((unsigned)cs.size(), L.c7), dim3(WG), 0, P.stream, dc, v, L.P(),
                        (const T*)W);
     IFMM_LAUNCH_CHECK();
@@ -411,6 +417,48 @@ struct Factorizer {
                        (int)cs.size(), v);
     IFMM_LAUNCH_CHECK();
     (void)el;
+  }
+
+  // Diagnostics: count non-finite values after a step (IFMM_DEBUG only).
+  int dbg_level = 0, dbg_class = 0;
+  bool dbg_reported = false;
+  void chk(LevelPool<T>& L, const char* what, const DevBuf* fac, int64_t wused) {
+    if (!debug_on() || dbg_reported) return;
+    std::vector<T> h;
+    size_t np = 0, nw = 0, nf = 0;
+    P.download(h, L.pool.p, (size_t)L.size);
+    for (auto x : h) np += std::isfinite((double)x) ? 0 : 1;
+    if (wused > 0) {
+      P.download(h, F.work.p, (size_t)wused);
+      for (auto x : h) nw += std::isfinite((double)x) ? 0 : 1;
+    }
+    if (fac) {
+      P.download(h, fac->p, fac->bytes / sizeof(T));
+      for (auto x : h) nf += std::isfinite((double)x) ? 0 : 1;
+    }
+    if (np || nw || nf) {
+      std::fprintf(stderr, "[ifmm] NON-FINITE after %s (level %d class %d): pool %zu work %zu factors %zu\n", what,
+                   dbg_level, dbg_class, np, nw, nf);
+      dbg_reported = true;
+    }
+  }
+
+  // Diagnostics: smallest |pivot| of the class and non-finite values in the pool.
+  void debug_class(LevelPool<T>& L, ClassFactors<T>& cf, int c) {
+    std::vector<T> fac, pool;
+    P.download(fac, cf.fac.p, cf.fac.bytes / sizeof(T));
+    P.download(pool, L.pool.p, (size_t)L.size);
+    double pmin = INFINITY;
+    int bmin = -1;
+    size_t nf = 0;
+    for (const auto& e : cf.el)
+      for (int k = 0; k < e.p; ++k) {
+        const double v = std::fabs((double)fac[e.lu + k + (int64_t)k * e.p]);
+        if (!(v >= pmin)) { pmin = v; bmin = e.box; }
+      }
+    for (auto x : pool) nf += std::isfinite((double)x) ? 0 : 1;
+    std::fprintf(stderr, "[ifmm] level %d class %d: %zu eliminations, min |pivot| %.3e (box %d), non-finite in pool %zu\n",
+                 L.l, c, cf.el.size(), pmin, bmin, nf);
   }
 
   // ----------------------------------------------------------- one level
@@ -514,6 +562,10 @@ struct Factorizer {
       }
       T* fac = cf.fac.template as<T>();
       T* W = F.work.template as<T>();
+      if (debug_on()) {   // so that the non-finite checks see only computed values
+        IFMM_HIP(hipMemsetAsync(cf.fac.p, 0, cf.fac.bytes, P.stream));
+        IFMM_HIP(hipMemsetAsync(F.work.p, 0, F.work.bytes, P.stream));
+      }
       const ElimDesc* del = P.put(F.d1, el);
       const FNode* dF = P.put(F.d2, Fs);
       // gather pivot blocks and couplings
@@ -545,9 +597,15 @@ struct Factorizer {
           dbg_dump<T>(P, "S_ii", L.P() + e.S, (size_t)e.m * e.m, 8);
         }
       }
+      dbg_level = l;
+      dbg_class = c;
+      chk(L, "gather", &cf.fac, 0);
       run_lu<T>(P, lu, F.d3);
+      chk(L, "lu", &cf.fac, 0);
       run_lu_solve<T>(P, ls, F.d4);
+      chk(L, "lu_solve", &cf.fac, 0);
       run_gemm<T>(P, gb, F.d5);
+      chk(L, "schur", nullptr, wo);
       const LevelView v = L.view(P);
       // near fill: added to existing edges
       hipLaunchKernelGGL(k_near_scatter<T>, dim3((unsigned)el.size(), maxF * maxF), dim3(WG), 0, P.stream, del, dF,
@@ -555,10 +613,13 @@ struct Factorizer {
       IFMM_LAUNCH_CHECK();
       // well-separated fill: recompress the bases of the affected boxes, then redirect
       IFMM_HIP(hipMemcpyAsync(L.drnew.p, L.dr.p, sizeof(int) * lv.nb, hipMemcpyDeviceToDevice, P.stream));
+      chk(L, "near_scatter", nullptr, wo);
       recompress(L, cs, el, del, dF, wo);
+      chk(L, "recompress", nullptr, 0);
       hipLaunchKernelGGL(k_redirect<T>, dim3((unsigned)el.size(), maxF * maxF), dim3(WG), 0, P.stream, del, dF, v,
                          (const T*)F.work.template as<T>(), L.P());
       IFMM_LAUNCH_CHECK();
+      if (debug_on()) debug_class(L, cf, c);
     }
     P.download(L.r, L.dr.p, (size_t)lv.nb);
   }

@@ -31,6 +31,25 @@ __device__ inline T block_sum(T v, T* sh /* >= WG/WAVE */) {
   return s;
 }
 
+template <class T>
+__device__ inline T wave_max(T v) {
+  for (int o = WAVE / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, WAVE));
+  return v;
+}
+
+template <class T>
+__device__ inline T block_max(T v, T* sh /* >= WG/WAVE */) {
+  v = wave_max(v);
+  const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+  __syncthreads();
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  T s = 0;
+  for (int i = 0; i < (int)(blockDim.x / WAVE); ++i) s = fmax(s, sh[i]);
+  __syncthreads();
+  return s;
+}
+
 // =================================================================== GEMM
 // C = alpha * op(A) * op(B) + beta * C, op(A) is M x K, op(B) is K x N.
 struct GemmDesc {
@@ -292,19 +311,26 @@ __global__ void __launch_bounds__(WG) k_qr(const QrDesc* __restrict__ ds) {
   __shared__ T red[WG / WAVE];
   const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE, nw = WG / WAVE;
   for (int j = 0; j < kq; ++j) {
-    T s = 0;
-    for (int i = j + threadIdx.x; i < M; i += WG) { T x = A[i + j * lda]; s += x * x; }
-    s = block_sum(s, red);
+    // reflector H = I - tau v v^T with v_j = 1 and beta = -sign(x0) ||x||; the
+    // norm is taken on the column scaled by its largest entry so that tiny or
+    // huge columns neither underflow nor overflow
+    T amax = 0;
+    for (int i = j + threadIdx.x; i < M; i += WG) amax = fmax(amax, fabs(A[i + j * lda]));
+    amax = block_max(amax, red);
     const T x0 = A[j + j * lda];
-    const T nrm = sqrt(s);
     T tj = 0, al = x0;
-    if (nrm > (T)0) {
+    if (amax > (T)0) {
+      const T inv = (T)1 / amax;
+      T s = 0;
+      for (int i = j + threadIdx.x; i < M; i += WG) { const T x = A[i + j * lda] * inv; s += x * x; }
+      s = block_sum(s, red);
+      const T nrm = amax * sqrt(s);
       al = x0 >= (T)0 ? -nrm : nrm;
-      const T v0 = x0 - al;
-      const T vn2 = s - x0 * x0 + v0 * v0;
-      tj = vn2 > (T)0 ? (T)2 / vn2 : (T)0;
+      tj = (al - x0) / al;
+      const T scal = (T)1 / (x0 - al);
+      for (int i = j + 1 + threadIdx.x; i < M; i += WG) A[i + j * lda] *= scal;
       __syncthreads();
-      if (threadIdx.x == 0) A[j + j * lda] = v0;
+      if (threadIdx.x == 0) A[j + j * lda] = (T)1;
     }
     if (threadIdx.x == 0) { tau[j] = tj; alph[j] = al; }
     __syncthreads();
@@ -399,6 +425,16 @@ __global__ void __launch_bounds__(WG) k_jacobi_svd(const SvdDesc* __restrict__ d
   __shared__ int order[SVD_MAXN];
   const T tol = (T)tol_d;
   const int Np = N + (N & 1);   // even number of players; player N (if odd) is a bye
+  // scale by the largest entry so that products of tiny entries do not underflow
+  __shared__ T red[WG / WAVE];
+  T amax = 0;
+  for (int64_t e = threadIdx.x; e < (int64_t)M * N; e += WG) amax = fmax(amax, fabs(B[e % M + (e / M) * ldb]));
+  amax = block_max(amax, red);
+  if (amax > (T)0 && amax != (T)1) {
+    const T inv = (T)1 / amax;
+    for (int64_t e = threadIdx.x; e < (int64_t)M * N; e += WG) B[e % M + (e / M) * ldb] *= inv;
+  }
+  __syncthreads();
   if (N > 1) {
     for (int sweep = 0; sweep < max_sweeps; ++sweep) {
       if (threadIdx.x == 0) rotated = 0;
@@ -447,7 +483,7 @@ __global__ void __launch_bounds__(WG) k_jacobi_svd(const SvdDesc* __restrict__ d
     const T s = nrm[src];
     const T inv = s > (T)0 ? (T)1 / s : (T)0;
     for (int i = lane; i < M; i += WAVE) U[i + c * ldu] = B[i + src * ldb] * inv;
-    if (lane == 0) S[c] = s;
+    if (lane == 0) S[c] = amax > (T)0 ? s * amax : (T)0;
   }
 }
 

@@ -1,0 +1,48 @@
+"""The C-ABI library loads and exports every symbol include/ifmm.h declares (no GPU needed)."""
+import os
+import re
+
+from paper_1508_01835_amd import ifmm as binding
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    src = open(os.path.join(ROOT, "include", "ifmm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ifmm_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_symbols()
+    for n in ["ifmm_build", "ifmm_factorize", "ifmm_solve", "ifmm_matvec", "ifmm_gmres", "ifmm_destroy"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = binding.load_library()
+    for n in declared_symbols():
+        assert hasattr(lib, n), n
+    assert set(binding.EXPORTS) == set(declared_symbols())
+
+
+def test_status_strings_and_defaults():
+    import ctypes
+    lib = binding.load_library()
+    assert lib.ifmm_strerror(0) == b"ok"
+    assert b"argument" in lib.ifmm_strerror(1)
+    opt = binding.Options()
+    lib.ifmm_default_options(ctypes.byref(opt))
+    assert opt.precision == 64 and opt.leaf_max == 64 and opt.rank_max == 0
+
+
+def test_null_arguments_rejected_without_gpu_work():
+    import ctypes
+    lib = binding.load_library()
+    h = ctypes.c_void_p()
+    k = binding.Kernel(0, 0.01, 1.0)
+    rc = lib.ifmm_build(None, 10, 2, k, 3, 3, 1e-6, None, ctypes.byref(h))
+    assert rc == 1 and not h.value
+    assert lib.ifmm_factorize(None) == 1
+    assert lib.ifmm_solve(None, None, None, 1, 1) == 1
+    assert lib.ifmm_destroy(None) == 0
