@@ -33,8 +33,10 @@ inline void build_tree(Problem& P, const double* d_points, int depth, int leaf_m
     lo[k] = INFINITY;
     hi[k] = -INFINITY;
     for (int b = 0; b < nblk; ++b) {
-      lo[k] = std::min(lo[k], hp[(size_t)b * 2 * d + k]);
-      hi[k] = std::max(hi[k], hp[(size_t)b * 2 * d + d + k]);
+      const double a = hp[(size_t)b * 2 * d + k], c = hp[(size_t)b * 2 * d + d + k];
+      if (std::isnan(a) || std::isnan(c)) fail(IFMM_ERR_ARG, "non-finite point coordinates");
+      lo[k] = std::min(lo[k], a);
+      hi[k] = std::max(hi[k], c);
     }
     if (!std::isfinite(lo[k]) || !std::isfinite(hi[k])) fail(IFMM_ERR_ARG, "non-finite point coordinates");
   }

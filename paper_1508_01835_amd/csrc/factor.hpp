@@ -9,6 +9,7 @@
 // device-to-host read of the ranks per class).
 #pragma once
 
+#include "blocked.hpp"
 #include "build.hpp"
 #include "factor_kernels.hpp"
 
@@ -70,6 +71,7 @@ struct FactorStore : FactorStoreBase {
   std::vector<int64_t> coff_level;
   // scratch reused across calls
   DevBuf work, d1, d2, d3, d4, d5;
+  LuScratch lus;
   DevBuf sx;                                       // solve vectors
   DevBuf sc;                                       // c_P store
   int s_nrhs = 0;
@@ -573,15 +575,14 @@ struct Factorizer {
                          (const T*)L.P(), fac);
       IFMM_LAUNCH_CHECK();
       // LU with partial pivoting of every pivot block; W = E_PP^-1 E_PF
-      std::vector<LuDesc> lu;
-      LuSolveBatch ls;
+      std::vector<LuJob> lu;
+      std::vector<TrsJob> ls;
       GemmBatch gb;
       for (const auto& e : el) {
-        LuDesc q;
-        q.A = fac + e.lu; q.piv = cf.piv.template as<int>() + e.piv; q.n = e.p; q.lda = std::max(e.p, 1);
-        q.tag = l * 1000000 + e.box; q.pad = 0;
-        if (e.p > 0) lu.push_back(q);
-        ls.add(fac + e.lu, std::max(e.p, 1), cf.piv.template as<int>() + e.piv, fac + e.w, std::max(e.p, 1), e.p, e.f);
+        if (e.p > 0) {
+          lu.push_back({fac + e.lu, cf.piv.template as<int>() + e.piv, e.p, e.p, l * 1000000 + e.box});
+          if (e.f > 0) ls.push_back({fac + e.lu, cf.piv.template as<int>() + e.piv, fac + e.w, e.p, e.p, e.f, e.p});
+        }
         // Schur fill D = -E_FP W (f x f, inner p)
         gb.add(fac + e.efp, std::max(e.f, 1), 0, fac + e.w, std::max(e.p, 1), 0, W + e.dlt, std::max(e.f, 1), e.f,
                e.f, e.p, -1.0, 0.0);
@@ -600,9 +601,9 @@ struct Factorizer {
       dbg_level = l;
       dbg_class = c;
       chk(L, "gather", &cf.fac, 0);
-      run_lu<T>(P, lu, F.d3);
+      lu_blocked<T>(P, lu, F.lus);
       chk(L, "lu", &cf.fac, 0);
-      run_lu_solve<T>(P, ls, F.d4);
+      lu_solve_blocked<T>(P, ls, F.lus);
       chk(L, "lu_solve", &cf.fac, 0);
       run_gemm<T>(P, gb, F.d5);
       chk(L, "schur", nullptr, wo);
@@ -680,10 +681,9 @@ struct Factorizer {
                        P.ldev[2].coords.template as<int>(), P.d, L.c7, L.dr.template as<int>(), L.dcap.template as<int>(), L.dKt.template as<int64_t>(),
                        doff.template as<int64_t>(), n, (const T*)L.P(), F.top.template as<T>());
     IFMM_LAUNCH_CHECK();
-    std::vector<LuDesc> lu(1);
-    lu[0].A = F.top.template as<T>(); lu[0].piv = F.toppiv.template as<int>(); lu[0].n = n; lu[0].lda = n; lu[0].tag = 999999999;
-    lu[0].pad = 0;
-    run_lu<T>(P, lu, F.d1);
+    std::vector<LuJob> lu(1);
+    lu[0] = {F.top.template as<T>(), F.toppiv.template as<int>(), n, n, 999999999};
+    lu_blocked<T>(P, lu, F.lus);
     flops_lu += 2.0 / 3.0 * (double)n * n * n;
     factor_elems += (int64_t)n * n;
   }

@@ -387,6 +387,7 @@ struct SvdDesc {
 };
 
 constexpr int SVD_MAXN = 1024;
+constexpr int SVD_WG = 1024;   // 16 wavefronts: 16 column pairs rotated at once
 
 template <class T>
 __device__ inline void jacobi_pair(T* __restrict__ B, int64_t ldb, int M, int p, int q, T tol,
@@ -411,7 +412,7 @@ __device__ inline void jacobi_pair(T* __restrict__ B, int64_t ldb, int M, int p,
 }
 
 template <class T>
-__global__ void __launch_bounds__(WG) k_jacobi_svd(const SvdDesc* __restrict__ ds, double tol_d,
+__global__ void __launch_bounds__(SVD_WG) k_jacobi_svd(const SvdDesc* __restrict__ ds, double tol_d,
                                                     int max_sweeps) {
   const SvdDesc d = ds[blockIdx.x];
   T* __restrict__ B = static_cast<T*>(d.B);
@@ -419,20 +420,20 @@ __global__ void __launch_bounds__(WG) k_jacobi_svd(const SvdDesc* __restrict__ d
   T* __restrict__ S = static_cast<T*>(d.S);
   const int M = d.M, N = d.N;
   const int64_t ldb = d.ldb, ldu = d.ldu;
-  const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE, nw = WG / WAVE;
+  const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE, nw = SVD_WG / WAVE;
   __shared__ int rotated;
   __shared__ T nrm[SVD_MAXN];
   __shared__ int order[SVD_MAXN];
   const T tol = (T)tol_d;
   const int Np = N + (N & 1);   // even number of players; player N (if odd) is a bye
   // scale by the largest entry so that products of tiny entries do not underflow
-  __shared__ T red[WG / WAVE];
+  __shared__ T red[SVD_WG / WAVE];
   T amax = 0;
-  for (int64_t e = threadIdx.x; e < (int64_t)M * N; e += WG) amax = fmax(amax, fabs(B[e % M + (e / M) * ldb]));
+  for (int64_t e = threadIdx.x; e < (int64_t)M * N; e += SVD_WG) amax = fmax(amax, fabs(B[e % M + (e / M) * ldb]));
   amax = block_max(amax, red);
   if (amax > (T)0 && amax != (T)1) {
     const T inv = (T)1 / amax;
-    for (int64_t e = threadIdx.x; e < (int64_t)M * N; e += WG) B[e % M + (e / M) * ldb] *= inv;
+    for (int64_t e = threadIdx.x; e < (int64_t)M * N; e += SVD_WG) B[e % M + (e / M) * ldb] *= inv;
   }
   __syncthreads();
   if (N > 1) {

@@ -166,7 +166,7 @@ inline void run_svd(Problem& P, const std::vector<SvdDesc>& v, DevBuf& scratch) 
   if (v.empty()) return;
   const SvdDesc* d = P.put(scratch, v);
   const double tol = 4.0 * Prec<T>::u;
-  hipLaunchKernelGGL(k_jacobi_svd<T>, dim3((unsigned)v.size()), dim3(WG), 0, P.stream, d, tol, 60);
+  hipLaunchKernelGGL(k_jacobi_svd<T>, dim3((unsigned)v.size()), dim3(SVD_WG), 0, P.stream, d, tol, 60);
   IFMM_LAUNCH_CHECK();
 }
 

@@ -182,9 +182,10 @@ inline void solve_impl(Problem& P, FactorStore<T>& F, SolvePlan<T>& S, const dou
       hipLaunchKernelGGL(k_fwd_init<T>, dim3(sc.n), dim3(WG), 0, P.stream, sc.d.template as<SolveDesc>(), (const T*)Xl,
                          S.M[l], nrhs, C);
       IFMM_LAUNCH_CHECK();
-      LuSolveBatch lb;
-      for (const auto& d : sc.h) lb.add(d.lu, std::max(d.p, 1), d.piv, C + d.coff * nrhs, std::max(d.p, 1), d.p, nrhs);
-      run_lu_solve<T>(P, lb, scr);
+      std::vector<TrsJob> jobs;
+      for (const auto& d : sc.h)
+        if (d.p > 0) jobs.push_back({d.lu, d.piv, C + d.coff * nrhs, d.p, d.p, nrhs, d.p});
+      lu_solve_blocked<T>(P, jobs, F.lus);
       hipLaunchKernelGGL(k_fwd_update<T>, dim3(sc.n, std::max(sc.maxF, 1)), dim3(WG), 0, P.stream,
                          sc.d.template as<SolveDesc>(), sc.nodes.template as<SolveNode>(), Xl, S.M[l], Yl, S.M[l - 1], nrhs,
                          (const T*)C);
@@ -192,9 +193,9 @@ inline void solve_impl(Problem& P, FactorStore<T>& F, SolvePlan<T>& S, const dou
     }
   }
   if (F.ntop > 0) {
-    LuSolveBatch lb;
-    lb.add(F.top.template as<T>(), F.ntop, F.toppiv.template as<int>(), X + base[1], S.M[1], F.ntop, nrhs);
-    run_lu_solve<T>(P, lb, scr);
+    std::vector<TrsJob> jobs(1);
+    jobs[0] = {F.top.template as<T>(), F.toppiv.template as<int>(), X + base[1], F.ntop, F.ntop, nrhs, (int)S.M[1]};
+    lu_solve_blocked<T>(P, jobs, F.lus);
   }
   for (int l = 2; l <= L; ++l) {
     T* Xl = X + base[l];

@@ -39,6 +39,8 @@ struct HTree {
 };
 
 // ------------------------------------------------------------------ kernels
+// Per-block minimum and maximum of every coordinate; a coordinate that is not
+// finite turns the block's minimum into NaN so the host rejects the input.
 __global__ void k_bbox_partial(const double* __restrict__ p, int64_t n, int d,
                                double* __restrict__ part /* blocks x 2d */) {
   __shared__ double smin[WG], smax[WG];
@@ -46,6 +48,7 @@ __global__ void k_bbox_partial(const double* __restrict__ p, int64_t n, int d,
     double lo = INFINITY, hi = -INFINITY;
     for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += (int64_t)gridDim.x * WG) {
       const double x = p[i * d + k];
+      if (!isfinite(x)) { lo = NAN; hi = NAN; break; }
       lo = fmin(lo, x);
       hi = fmax(hi, x);
     }
@@ -54,8 +57,10 @@ __global__ void k_bbox_partial(const double* __restrict__ p, int64_t n, int d,
     __syncthreads();
     for (int s = WG / 2; s > 0; s >>= 1) {
       if ((int)threadIdx.x < s) {
-        smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + s]);
-        smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + s]);
+        const double a = smin[threadIdx.x], b = smin[threadIdx.x + s];
+        const double c = smax[threadIdx.x], e = smax[threadIdx.x + s];
+        smin[threadIdx.x] = (a != a || b != b) ? NAN : fmin(a, b);
+        smax[threadIdx.x] = (c != c || e != e) ? NAN : fmax(c, e);
       }
       __syncthreads();
     }
