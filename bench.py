@@ -1,0 +1,202 @@
+"""Benchmark of the IFMM hot path on one MI355X.
+
+Workload (the 3D preconditioner configuration): N = 65536 points uniform in
+[0,1]^3, inverse multiquadric kernel c = 0.005 with 1.0 on the diagonal,
+octree depth 5, Chebyshev order 3 (27 nodes per box), eps = 1e-6, FP64
+factors, used as the preconditioner of FP64 GMRES for 16 N(0,1) right-hand
+sides to relative residual 1e-10. Inputs are seeded synthetic arrays
+(workloads.py) already resident in HBM when the timed region starts.
+
+One step = the whole path: tree + H2 operators + sigma_0 + weights (build),
+level-by-level factorization, and preconditioned GMRES (factor solves and H2
+matvecs) for the 16 right-hand sides.
+
+Printed on one JSON line: value = points processed per second by the whole
+step (Mpts/s); the factorization-only rate, GMRES time-to-1e-10 with FP32 and
+with FP64 factors, p50/p99 single-RHS solve latency, the roofline of the
+dominant kernel family (HIP events inside the library, IFMM_KTIMING=1) and
+the CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+os.environ.setdefault("IFMM_KTIMING", "1")
+
+PEAKS = {  # MI355X published peaks
+    "hbm_GBs": 8000.0,
+    "fp64_TFs": 78.6,      # FP64 vector and FP64 matrix (dense)
+    "fp32_vec_TFs": 157.3,
+    "fp32_mfma_TFs": 157.3,
+}
+FAMILIES = ["schur_gemm", "pivot_lu", "trsm_w", "qr", "jacobi_svd", "edge_update", "solve", "matvec", "other"]
+MEMORY_BOUND = {"solve", "matvec", "edge_update"}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline():
+    """The oracle, as it stands, on a bounded sample of the same workload."""
+    import numpy as np
+
+    import workloads as W
+    from oracle.gmres import gmres_right
+    from oracle.ifmm import IFMM as Oracle
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        cores = 1
+    n, depth, nrhs = 1024, 3, 16          # same 2 points per leaf box as the full workload
+    pts = W.uniform_cube(n, 3, 2001)
+    rhs = W.normal_rhs(n, nrhs, 2002)
+    t0 = time.perf_counter()
+    o = Oracle(pts, "imq", 0.005, 1.0, depth, 3, 1e-6)
+    o.factorize()
+    for k in range(nrhs):
+        gmres_right(o.matvec, o.solve, rhs[:, k], tol=1e-10, maxit=200)
+    t = time.perf_counter() - t0
+    return {"value": n / t / 1e6, "unit": "Mpts/s", "cores": int(cores), "kind": "oracle",
+            "sample": "N=1024 uniform in [0,1]^3, depth 3 (2 points per leaf as in the full workload), "
+                      "order 3, eps 1e-6, build + factorize + GMRES to 1e-10 for 16 RHS; %.1f s" % t}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--n", type=int, default=65536)
+    ap.add_argument("--depth", type=int, default=5)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_1508_01835_amd import IFMM
+
+    wl = W.uniform3d_65536(n=args.n, depth=args.depth)
+    dev = torch.device("cuda:0")
+    pts = torch.tensor(wl.points, device=dev)
+    B = torch.tensor(np.ascontiguousarray(wl.rhs), device=dev)
+    n = wl.n
+
+    def step(precision=64, eps=wl.eps):
+        g = IFMM(pts, wl.kernel, wl.kparam, wl.shift, wl.depth, wl.order, eps, precision=precision)
+        g.factorize()
+        X, it, rr = g.gmres(B, tol=1e-10, maxit=200)
+        return g, it, rr
+
+    for _ in range(args.warmup):
+        g, it, rr = step()
+        g.close()
+    torch.cuda.synchronize()
+    handles = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        g, it, rr = step()
+        handles.append((g, it, rr))
+    torch.cuda.synchronize()
+    T = time.perf_counter() - t0
+    stats = [h[0].stats() for h in handles]
+    iters = max(h[1] for h in handles)
+    relres = max(h[2] for h in handles)
+    if relres > 1e-10:
+        log("GMRES did not reach 1e-10: %.3e" % relres)
+
+    # kernel families over the timed region (sum over the timed handles)
+    fam_ms = [sum(s["kfam_ms"][f] for s in stats) for f in range(len(FAMILIES))]
+    fam_fl = [sum(s["kfam_flops"][f] for s in stats) for f in range(len(FAMILIES))]
+    fam_by = [sum(s["kfam_bytes"][f] for s in stats) for f in range(len(FAMILIES))]
+    fam_nl = [sum(s["kfam_launches"][f] for s in stats) for f in range(len(FAMILIES))]
+    dom = int(np.argmax(fam_ms))
+    name = FAMILIES[dom]
+    if name in MEMORY_BOUND and fam_by[dom] > 0:
+        achieved = fam_by[dom] / (fam_ms[dom] * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": PEAKS["hbm_GBs"], "unit": "GB/s"}
+    else:
+        achieved = fam_fl[dom] / (fam_ms[dom] * 1e-3) / 1e12
+        # the factorization kernels run on the FP64 vector units (fma), not on MFMA
+        roof = {"bound": "alu", "achieved": achieved, "peak": PEAKS["fp64_TFs"], "unit": "TFLOP/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    roof["kernel"] = name
+    roof["launches_per_step"] = fam_nl[dom] / args.steps
+    roof["avg_launch_ms"] = fam_ms[dom] / max(fam_nl[dom], 1)
+    breakdown = {FAMILIES[f]: round(fam_ms[f] / args.steps, 2) for f in range(len(FAMILIES)) if fam_ms[f] > 0}
+
+    g0 = handles[0][0]
+    st0 = stats[0]
+    factor_ms = float(np.mean([s["t_factor_ms"] for s in stats]))
+    build_ms = float(np.mean([s["t_build_ms"] for s in stats]))
+    # solve latency, single RHS, resident FP64 factors (outside the timed region)
+    b1 = B[:, 0].contiguous()
+    lat = []
+    for _ in range(30):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        g0.solve(b1)
+        torch.cuda.synchronize()
+        lat.append((time.perf_counter() - t) * 1e3)
+    lat = np.array(lat[3:])
+    for h in handles:
+        h[0].close()
+
+    # GMRES time-to-1e-10: FP32 factors (eps 1e-5) vs FP64 factors (eps 1e-6), same GPU
+    ttr = {}
+    for prec, eps in ((32, 1e-5), (64, 1e-6)):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        g, it2, rr2 = step(prec, eps)
+        torch.cuda.synchronize()
+        ttr["fp%d" % prec] = {"seconds": time.perf_counter() - t, "iters": it2, "relres": rr2, "eps": eps}
+        g.close()
+
+    out = {
+        "metric": "IFMM factor Mpts/s, GMRES time-to-1e-10 FP32 vs FP64; p50/p99 solve latency",
+        "value": n * args.steps / T / 1e6,
+        "unit": "Mpts/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": T / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "uniform3d_65536: N=65536 uniform [0,1]^3, IMQ c=0.005 + 1.0 I, depth 5, "
+                               "Chebyshev order 3, eps 1e-6, GMRES 16 RHS to 1e-10",
+                   "n": n, "depth": wl.depth, "cheb_order": wl.order, "eps": wl.eps, "nrhs": 16},
+        "factor_mpts_s": n / (factor_ms * 1e-3) / 1e6,
+        "factor_ms": factor_ms,
+        "build_ms": build_ms,
+        "gmres_iters": iters,
+        "gmres_relres": relres,
+        "time_to_1e-10_s": ttr,
+        "solve_latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                             "nrhs": 1},
+        "max_rank": st0["max_rank"],
+        "kernel_ms_per_step": breakdown,
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

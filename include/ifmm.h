@@ -95,6 +95,17 @@ typedef struct {
   int error_level, error_box; /* where IFMM_ERR_SINGULAR / NUMERICAL arose, else -1 */
   int gmres_iters;            /* of the last ifmm_gmres call (max over columns) */
   double gmres_relres;        /* of the last ifmm_gmres call (max over columns) */
+  /* Device time by kernel family, measured with HIP events on the handle's
+     stream when the environment variable IFMM_KTIMING=1 is set at build time
+     (otherwise zero); totals since the handle was built. Families:
+     0 Schur-complement GEMM, 1 pivot LU (panels, swaps, trailing GEMM),
+     2 triangular solves W = E_PP^-1 E_PF, 3 Householder QR of the
+     recompression matrices, 4 Jacobi SVD, 5 basis changes of the edges and
+     redirection, 6 forward/backward substitution, 7 H2 matvec, 8 other. */
+  double kfam_ms[16];
+  double kfam_flops[16];      /* algorithmic flops attributed to the family */
+  double kfam_bytes[16];      /* algorithmic bytes attributed to the family */
+  int64_t kfam_launches[16];
 } ifmm_stats;
 
 typedef struct ifmm_problem* ifmm_handle;

@@ -214,11 +214,13 @@ inline void lu_blocked(Problem& P, const std::vector<LuJob>& jobs, LuScratch& S)
     }
     if (pd.empty()) break;
     const PanelDesc* dp = P.put(S.pd, pd);
+    P.kbegin();
     hipLaunchKernelGGL(k_lu_panel<T>, dim3((unsigned)pd.size()), dim3(WG), 0, P.stream, dp, P.d_info);
     IFMM_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_lu_swap_trsm<T>, dim3((unsigned)pd.size(), (unsigned)ceil_div(maxcols, WG)), dim3(WG), 0,
                        P.stream, dp);
     IFMM_LAUNCH_CHECK();
+    P.kend();
     run_gemm<T>(P, gb, S.gd);
   }
 }
@@ -249,8 +251,10 @@ inline void lu_solve_blocked(Problem& P, const std::vector<TrsJob>& jobs, LuScra
   const unsigned gy = (unsigned)ceil_div(cmax, WG);
   {
     const TrsDesc* dd = P.put(S.pd, all);
+    P.kbegin();
     hipLaunchKernelGGL(k_apply_piv<T>, dim3((unsigned)all.size(), gy), dim3(WG), 0, P.stream, dd);
     IFMM_LAUNCH_CHECK();
+    P.kend();
   }
   const int nblk = (int)ceil_div(nmax, LU_NB);
   for (int pass = 0; pass < 2; ++pass) {          // 0: forward with L, 1: backward with U
@@ -279,8 +283,10 @@ inline void lu_solve_blocked(Problem& P, const std::vector<TrsJob>& jobs, LuScra
       }
       if (v.empty()) continue;
       const TrsDesc* dv = P.put(S.pd, v);
+      P.kbegin();
       hipLaunchKernelGGL(k_trs_diag<T>, dim3((unsigned)v.size(), gy), dim3(WG), 0, P.stream, dv, pass);
       IFMM_LAUNCH_CHECK();
+      P.kend();
       run_gemm<T>(P, gb, S.gd);
     }
   }

@@ -394,11 +394,24 @@ struct Factorizer {
       }
     }
     chk(L, "comp_gather", nullptr, o);
+    double fq = 0, fs = 0, bq = 0;
+    for (const auto& c : cs) {
+      const double mj = L.m[c.box], n = c.ncols, k = c.kq;
+      fq += 2.0 * (2.0 * n * mj * mj - 2.0 / 3.0 * mj * mj * mj);   // Householder R of MU^T and MV^T
+      bq += 2.0 * sizeof(T) * (n * mj + k * mj);
+      fs += 2.0 * (4.0 * mj * k * k + 8.0 * k * k * k);             // SVD (U and singular values)
+    }
+    P.kset(KF_QR, fq, bq);
     run_qr<T>(P, qd, F.d4);
     chk(L, "comp_qr", nullptr, o);
+    P.kset(-1);
     run_copy(P, tb, F.d4);
+    P.kset(KF_SVD, fs, 0);
     run_svd<T>(P, sd, F.d4);
+    P.kset(-1);
     chk(L, "comp_svd", nullptr, o);
+    P.kset(KF_XFORM);
+    P.kbegin();
     hipLaunchKernelGGL(k_comp_rank<T>, dim3((unsigned)ceil_div((int64_t)cs.size(), WG)), dim3(WG), 0, P.stream, dc,
                        (int)cs.size(), v, (const T*)W, P.tau, P.rank_max);
     IFMM_LAUNCH_CHECK();
@@ -418,6 +431,8 @@ struct Factorizer {
     hipLaunchKernelGGL(k_commit_ranks, dim3((unsigned)ceil_div((int64_t)cs.size(), WG)), dim3(WG), 0, P.stream, dc,
                        (int)cs.size(), v);
     IFMM_LAUNCH_CHECK();
+    P.kend();
+    P.kset(-1);
     (void)el;
   }
 
@@ -601,11 +616,23 @@ struct Factorizer {
       dbg_level = l;
       dbg_class = c;
       chk(L, "gather", &cf.fac, 0);
+      double flu = 0, ftr = 0, fsc = 0, bsc = 0;
+      for (const auto& e : el) {
+        const double p = e.p, f = e.f;
+        flu += 2.0 / 3.0 * p * p * p;
+        ftr += 2.0 * p * p * f;
+        fsc += 2.0 * f * f * p;
+        bsc += sizeof(T) * (2.0 * f * p + f * f);   // read E_FP and W once, write D once
+      }
+      P.kset(KF_LU, flu, 0);
       lu_blocked<T>(P, lu, F.lus);
       chk(L, "lu", &cf.fac, 0);
+      P.kset(KF_TRSM, ftr, 0);
       lu_solve_blocked<T>(P, ls, F.lus);
       chk(L, "lu_solve", &cf.fac, 0);
+      P.kset(KF_SCHUR, fsc, bsc);
       run_gemm<T>(P, gb, F.d5);
+      P.kset(-1);
       chk(L, "schur", nullptr, wo);
       const LevelView v = L.view(P);
       // near fill: added to existing edges
@@ -683,7 +710,9 @@ struct Factorizer {
     IFMM_LAUNCH_CHECK();
     std::vector<LuJob> lu(1);
     lu[0] = {F.top.template as<T>(), F.toppiv.template as<int>(), n, n, 999999999};
+    P.kset(KF_LU, 2.0 / 3.0 * (double)n * n * n, 0);
     lu_blocked<T>(P, lu, F.lus);
+    P.kset(-1);
     flops_lu += 2.0 / 3.0 * (double)n * n * n;
     factor_elems += (int64_t)n * n;
   }

@@ -96,6 +96,10 @@ int ifmm_build(const double* points, int64_t n, int dim, ifmm_kernel k, int dept
     h = new ifmm_problem();
     Problem& P = h->P;
     P.mem.budget = o.hbm_budget_bytes;
+    {
+      const char* kt = std::getenv("IFMM_KTIMING");
+      P.kt.on = kt && kt[0] == '1';
+    }
     P.stream = static_cast<hipStream_t>(o.stream);
     P.n = n;
     P.d = dim;
@@ -181,7 +185,11 @@ static void matvec_any(Problem& P, const double* x, double* y, int nrhs, int64_t
   hipLaunchKernelGGL(k_perm_gather, g, dim3(WG), 0, P.stream, x, ld, P.perm.as<int>(), n, nrhs,
                      P.mv_x.as<double>(), n);
   IFMM_LAUNCH_CHECK();
+  P.kset(KF_MATVEC, 0, 0);
+  P.kbegin();
   matvec_tree(P, P.mv_x.as<double>(), P.mv_y.as<double>(), nrhs);
+  P.kend();
+  P.kset(-1);
   hipLaunchKernelGGL(k_perm_scatter, g, dim3(WG), 0, P.stream, (const double*)P.mv_y.as<double>(), n,
                      P.perm.as<int>(), n, nrhs, y, ld);
   IFMM_LAUNCH_CHECK();
@@ -242,6 +250,14 @@ int ifmm_query(ifmm_handle h, ifmm_stats* s) {
     for (int l = 0; l <= P.L && l < 32; ++l) P.st.boxes[l] = l < (int)P.T.lev.size() ? P.T.lev[l].nb : 0;
     P.st.device_bytes = P.mem.cur;
     P.st.device_bytes_peak = P.mem.peak;
+    P.sync();
+    P.kt.collect();
+    for (int f = 0; f < KF_COUNT && f < 16; ++f) {
+      P.st.kfam_ms[f] = P.kt.ms[f];
+      P.st.kfam_flops[f] = P.kt.flops[f];
+      P.st.kfam_bytes[f] = P.kt.bytes[f];
+      P.st.kfam_launches[f] = P.kt.launches[f];
+    }
     *s = P.st;
   });
 }

@@ -34,7 +34,62 @@ struct FactorStoreBase {
   virtual ~FactorStoreBase() = default;
 };
 
+// Kernel-family timing with HIP events on the handle's stream (enabled by
+// IFMM_KTIMING=1): duration, launch count and algorithmic flops / bytes.
+enum KFam {
+  KF_SCHUR = 0, KF_LU, KF_TRSM, KF_QR, KF_SVD, KF_XFORM, KF_SOLVE, KF_MATVEC, KF_OTHER, KF_COUNT
+};
+
+struct KTimer {
+  bool on = false;
+  struct Rec { int fam; hipEvent_t a, b; double flops, bytes; int64_t launches; };
+  std::vector<Rec> open;
+  double ms[KF_COUNT] = {}, flops[KF_COUNT] = {}, bytes[KF_COUNT] = {};
+  int64_t launches[KF_COUNT] = {};
+  void begin(hipStream_t s, int fam, double fl, double by, int64_t nl = 1) {
+    if (!on) return;
+    Rec r{fam, nullptr, nullptr, fl, by, nl};
+    IFMM_HIP(hipEventCreate(&r.a));
+    IFMM_HIP(hipEventCreate(&r.b));
+    IFMM_HIP(hipEventRecord(r.a, s));
+    open.push_back(r);
+  }
+  void end(hipStream_t s) {
+    if (!on || open.empty()) return;
+    IFMM_HIP(hipEventRecord(open.back().b, s));
+  }
+  // Fold completed records into the totals (call after a stream sync).
+  void collect() {
+    for (auto& r : open) {
+      float t = 0;
+      if (hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) {
+        ms[r.fam] += t;
+        flops[r.fam] += r.flops;
+        bytes[r.fam] += r.bytes;
+        launches[r.fam] += r.launches;
+      }
+      (void)hipEventDestroy(r.a);
+      (void)hipEventDestroy(r.b);
+    }
+    open.clear();
+  }
+  void reset() {
+    collect();
+    for (int i = 0; i < KF_COUNT; ++i) { ms[i] = flops[i] = bytes[i] = 0; launches[i] = 0; }
+  }
+};
+
 struct Problem {
+  KTimer kt;
+  int kcur = -1;              // family charged by the next launches (-1: none)
+  double kfl = 0, kby = 0;    // algorithmic flops / bytes still to attribute
+  void kset(int fam, double fl = 0, double by = 0) { kcur = fam; kfl = fl; kby = by; }
+  void kbegin() {
+    if (kt.on && kcur >= 0) { kt.begin(stream, kcur, kfl, kby); kfl = kby = 0; }
+  }
+  void kend() {
+    if (kt.on && kcur >= 0) kt.end(stream);
+  }
   // configuration
   int64_t n = 0;
   int d = 0, L = 0, order = 0, q = 0, precision = 64;
@@ -140,8 +195,10 @@ template <class T>
 inline void run_gemm(Problem& P, GemmBatch& gb, DevBuf& scratch) {
   if (gb.v.empty()) return;
   const GemmDesc* d = P.put(scratch, gb.v);
+  P.kbegin();
   hipLaunchKernelGGL(k_gemm<T>, dim3(gb.tiles), dim3(WG), 0, P.stream, d, (int)gb.v.size());
   IFMM_LAUNCH_CHECK();
+  P.kend();
 }
 
 template <class Ts, class Td>
@@ -157,8 +214,10 @@ template <class T>
 inline void run_qr(Problem& P, const std::vector<QrDesc>& v, DevBuf& scratch) {
   if (v.empty()) return;
   const QrDesc* d = P.put(scratch, v);
+  P.kbegin();
   hipLaunchKernelGGL(k_qr<T>, dim3((unsigned)v.size()), dim3(WG), 0, P.stream, d);
   IFMM_LAUNCH_CHECK();
+  P.kend();
 }
 
 template <class T>
@@ -166,8 +225,10 @@ inline void run_svd(Problem& P, const std::vector<SvdDesc>& v, DevBuf& scratch) 
   if (v.empty()) return;
   const SvdDesc* d = P.put(scratch, v);
   const double tol = 4.0 * Prec<T>::u;
+  P.kbegin();
   hipLaunchKernelGGL(k_jacobi_svd<T>, dim3((unsigned)v.size()), dim3(SVD_WG), 0, P.stream, d, tol, 60);
   IFMM_LAUNCH_CHECK();
+  P.kend();
 }
 
 template <class T>

@@ -97,6 +97,7 @@ struct SolvePlan {
   std::vector<std::vector<Cls>> cls;
   std::vector<int64_t> M;        // vector size per level (level 1 = the top vector)
   int64_t cstore = 0;
+  double factor_elems = 0;       // elements of the factors one solve reads
   bool built = false;
 };
 
@@ -129,6 +130,7 @@ inline SolvePlan<T>& solve_plan(Problem& P, FactorStore<T>& F, SolvePlan<T>& S) 
         d.xoff = sl.xoff[e.box];
         d.coff = co;
         co += e.p;
+        S.factor_elems += (double)e.p * e.p + 2.0 * e.p * e.f;
         for (int a = 0; a < e.nF; ++a) {
           const FNode& n = cf.F[e.F0 + a];
           SolveNode sn{};
@@ -157,6 +159,10 @@ inline void solve_impl(Problem& P, FactorStore<T>& F, SolvePlan<T>& S, const dou
                        int64_t ld) {
   const int L = P.L;
   solve_plan(P, F, S);
+  {
+    const double fe = S.factor_elems + (double)F.ntop * F.ntop;
+    P.kset(KF_SOLVE, 2.0 * fe * nrhs, fe * sizeof(T));
+  }
   // vectors: level L..1
   std::vector<int64_t> base(L + 1, 0);
   int64_t tot = 0;
@@ -179,17 +185,21 @@ inline void solve_impl(Problem& P, FactorStore<T>& F, SolvePlan<T>& S, const dou
     T* Yl = X + base[l - 1];
     for (auto& sc : S.cls[l]) {
       if (!sc.n) continue;
+      P.kbegin();
       hipLaunchKernelGGL(k_fwd_init<T>, dim3(sc.n), dim3(WG), 0, P.stream, sc.d.template as<SolveDesc>(), (const T*)Xl,
                          S.M[l], nrhs, C);
       IFMM_LAUNCH_CHECK();
+      P.kend();
       std::vector<TrsJob> jobs;
       for (const auto& d : sc.h)
         if (d.p > 0) jobs.push_back({d.lu, d.piv, C + d.coff * nrhs, d.p, d.p, nrhs, d.p});
       lu_solve_blocked<T>(P, jobs, F.lus);
+      P.kbegin();
       hipLaunchKernelGGL(k_fwd_update<T>, dim3(sc.n, std::max(sc.maxF, 1)), dim3(WG), 0, P.stream,
                          sc.d.template as<SolveDesc>(), sc.nodes.template as<SolveNode>(), Xl, S.M[l], Yl, S.M[l - 1], nrhs,
                          (const T*)C);
       IFMM_LAUNCH_CHECK();
+      P.kend();
     }
   }
   if (F.ntop > 0) {
@@ -203,14 +213,17 @@ inline void solve_impl(Problem& P, FactorStore<T>& F, SolvePlan<T>& S, const dou
     for (int c = (int)S.cls[l].size() - 1; c >= 0; --c) {
       auto& sc = S.cls[l][c];
       if (!sc.n) continue;
+      P.kbegin();
       hipLaunchKernelGGL(k_bwd<T>, dim3(sc.n), dim3(WG), 0, P.stream, sc.d.template as<SolveDesc>(),
                          sc.nodes.template as<SolveNode>(), Xl, S.M[l], (const T*)Yl, S.M[l - 1], nrhs, (const T*)C);
       IFMM_LAUNCH_CHECK();
+      P.kend();
     }
   }
   hipLaunchKernelGGL((k_perm_convert<T, double>), g, dim3(WG), 0, P.stream, (const T*)(X + base[L]), P.n,
                      P.perm.template as<int>(), P.n, nrhs, x, ld, 0);
   IFMM_LAUNCH_CHECK();
+  P.kset(-1);
 }
 
 }  // namespace ifmm

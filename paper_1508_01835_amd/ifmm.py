@@ -41,7 +41,11 @@ class Stats(ctypes.Structure):
                 ("schur_flops", ctypes.c_double), ("factor_bytes", ctypes.c_int64),
                 ("device_bytes", ctypes.c_int64), ("device_bytes_peak", ctypes.c_int64),
                 ("error_level", ctypes.c_int), ("error_box", ctypes.c_int),
-                ("gmres_iters", ctypes.c_int), ("gmres_relres", ctypes.c_double)]
+                ("gmres_iters", ctypes.c_int), ("gmres_relres", ctypes.c_double),
+                ("kfam_ms", ctypes.c_double * 16), ("kfam_flops", ctypes.c_double * 16),
+                ("kfam_bytes", ctypes.c_double * 16), ("kfam_launches", ctypes.c_int64 * 16)]
+
+KFAMILIES = ["schur_gemm", "pivot_lu", "trsm_w", "qr", "jacobi_svd", "edge_update", "solve", "matvec", "other"]
 
 
 EXPORTS = ["ifmm_default_options", "ifmm_build", "ifmm_factorize", "ifmm_solve", "ifmm_matvec",
