@@ -292,4 +292,205 @@ inline void lu_solve_blocked(Problem& P, const std::vector<TrsJob>& jobs, LuScra
   }
 }
 
+// ============================================================ blocked QR
+// Householder QR in panels of QR_NB columns with the compact WY form
+// H_j0 ... H_j0+nb-1 = I - V T V^T: the panel kernel factorizes the panel and
+// writes V (unit lower trapezoidal, explicit zeros above) and T; the trailing
+// columns are updated by A2 <- A2 - V (T^T (V^T A2)) with the batched GEMM.
+// Only R is produced (the recompression needs the left singular vectors of
+// R^T, not Q).
+constexpr int QR_NB = 32;
+
+struct QrPanel {
+  void* A;
+  void* V;      // (M - j0) x nb, leading dimension M - j0
+  void* Tm;     // nb x nb
+  void* alph;   // N diagonal entries of R (per matrix)
+  int M, N, lda, j0, nb, pad;
+};
+
+template <class T>
+__global__ void __launch_bounds__(WG) k_qr_panel(const QrPanel* __restrict__ ds) {
+  const QrPanel d = ds[blockIdx.x];
+  T* __restrict__ A = static_cast<T*>(d.A);
+  T* __restrict__ V = static_cast<T*>(d.V);
+  T* __restrict__ Tm = static_cast<T*>(d.Tm);
+  T* __restrict__ alph = static_cast<T*>(d.alph);
+  const int M = d.M, j0 = d.j0, nb = d.nb;
+  const int64_t lda = d.lda;
+  const int mv = M - j0;
+  __shared__ T tau[QR_NB];
+  __shared__ T red[WG / WAVE];
+  __shared__ T G[QR_NB * QR_NB];
+  const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE, nw = WG / WAVE;
+  for (int jj = 0; jj < nb; ++jj) {
+    const int j = j0 + jj;
+    T amax = 0;
+    for (int i = j + threadIdx.x; i < M; i += WG) amax = fmax(amax, fabs(A[i + j * lda]));
+    amax = block_max(amax, red);
+    const T x0 = A[j + j * lda];
+    T tj = 0, al = x0;
+    if (amax > (T)0) {
+      // exact power-of-two scaling by 1 / amax: a reciprocal of a subnormal
+      // amax would overflow
+      const int sh = -ilogb((double)amax);
+      T s = 0;
+      for (int i = j + threadIdx.x; i < M; i += WG) { const T x = ldexp(A[i + j * lda], sh); s += x * x; }
+      s = block_sum(s, red);
+      const T x0s = ldexp(x0, sh);
+      const T als = x0s >= (T)0 ? -sqrt(s) : sqrt(s);
+      al = ldexp(als, -sh);
+      tj = (als - x0s) / als;
+      const T scal = (T)1 / (x0s - als);
+      for (int i = j + 1 + threadIdx.x; i < M; i += WG) A[i + j * lda] = ldexp(A[i + j * lda], sh) * scal;
+      __syncthreads();
+      if (threadIdx.x == 0) A[j + j * lda] = (T)1;
+    }
+    if (threadIdx.x == 0) { tau[jj] = tj; alph[j] = al; }
+    __syncthreads();
+    if (tj != (T)0) {
+      for (int c = j + 1 + wv; c < j0 + nb; c += nw) {
+        T dot = 0;
+        for (int i = j + lane; i < M; i += WAVE) dot += A[i + j * lda] * A[i + c * lda];
+        dot = wave_sum(dot) * tj;
+        for (int i = j + lane; i < M; i += WAVE) A[i + c * lda] -= dot * A[i + j * lda];
+      }
+    }
+    __syncthreads();
+  }
+  // V with explicit unit diagonal and zeros above it
+  for (int64_t e = threadIdx.x; e < (int64_t)mv * nb; e += WG) {
+    const int i = (int)(e % mv), c = (int)(e / mv);
+    T v = 0;
+    if (i == c) v = tau[c] != (T)0 ? (T)1 : (T)0;
+    else if (i > c) v = tau[c] != (T)0 ? A[(j0 + i) + (int64_t)(j0 + c) * lda] : (T)0;
+    V[i + (int64_t)c * mv] = v;
+  }
+  __syncthreads();
+  // G = V^T V, then T: T_jj = tau_j, T[0:j, j] = -tau_j T[0:j, 0:j] G[0:j, j]
+  for (int pr = wv; pr < nb * nb; pr += nw) {
+    const int a = pr % nb, b = pr / nb;
+    if (a >= b) continue;
+    T s = 0;
+    for (int i = lane; i < mv; i += WAVE) s += V[i + (int64_t)a * mv] * V[i + (int64_t)b * mv];
+    s = wave_sum(s);
+    if (lane == 0) G[a + b * QR_NB] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int j = 0; j < nb; ++j) {
+      for (int i = 0; i < nb; ++i) Tm[i + j * nb] = (T)0;
+      Tm[j + j * nb] = tau[j];
+      for (int i = 0; i < j; ++i) {
+        T s = 0;
+        for (int k = i; k < j; ++k) s += Tm[i + k * nb] * G[k + j * QR_NB];
+        Tm[i + j * nb] = -tau[j] * s;
+      }
+    }
+  }
+}
+
+// R (kq x N, leading dimension ldr) from the factorized A and its diagonal.
+struct QrOut {
+  const void* A;
+  const void* alph;
+  void* R;
+  int M, N, lda, ldr;
+};
+
+template <class T>
+__global__ void k_qr_extract(const QrOut* __restrict__ ds) {
+  const QrOut d = ds[blockIdx.x];
+  const T* A = static_cast<const T*>(d.A);
+  const T* al = static_cast<const T*>(d.alph);
+  T* R = static_cast<T*>(d.R);
+  const int kq = d.M < d.N ? d.M : d.N;
+  for (int64_t e = threadIdx.x; e < (int64_t)kq * d.N; e += WG) {
+    const int i = (int)(e % kq), c = (int)(e / kq);
+    T v = 0;
+    if (i == c) v = al[i];
+    else if (i < c) v = A[i + (int64_t)c * d.lda];
+    R[i + (int64_t)c * d.ldr] = v;
+  }
+}
+
+struct QrJob {
+  void* A;
+  void* R;
+  int M, N, lda, ldr;
+};
+
+struct QrScratch {
+  DevBuf w, pd, gd, od;
+};
+
+template <class T>
+inline void qr_blocked(Problem& P, const std::vector<QrJob>& jobs, QrScratch& S) {
+  if (jobs.empty()) return;
+  // workspace per job: alph (N), V ((M) x QR_NB), T (QR_NB^2), W1, W2 (QR_NB x N)
+  std::vector<int64_t> off(jobs.size());
+  int64_t tot = 0;
+  int nmax = 0;
+  for (size_t b = 0; b < jobs.size(); ++b) {
+    const auto& j = jobs[b];
+    off[b] = tot;
+    tot += j.N + (int64_t)j.M * QR_NB + QR_NB * QR_NB + 2 * (int64_t)QR_NB * j.N + 8;
+    nmax = std::max(nmax, std::min(j.M, j.N));
+  }
+  if ((size_t)tot * sizeof(T) > S.w.bytes) {
+    P.sync();
+    S.w.alloc((size_t)tot * sizeof(T) * 5 / 4 + 64, &P.mem);
+  }
+  T* W = S.w.template as<T>();
+  for (int j0 = 0; j0 < nmax; j0 += QR_NB) {
+    std::vector<QrPanel> pv;
+    GemmBatch g1, g2, g3;
+    for (size_t b = 0; b < jobs.size(); ++b) {
+      const auto& j = jobs[b];
+      const int kq = std::min(j.M, j.N);
+      if (j0 >= kq) continue;
+      const int nb = std::min(QR_NB, kq - j0);
+      T* al = W + off[b];
+      T* Vb = al + j.N;
+      T* Tb = Vb + (int64_t)j.M * QR_NB;
+      T* W1 = Tb + QR_NB * QR_NB;
+      T* W2 = W1 + (int64_t)QR_NB * j.N;
+      QrPanel q;
+      q.A = j.A; q.V = Vb; q.Tm = Tb; q.alph = al;
+      q.M = j.M; q.N = j.N; q.lda = j.lda; q.j0 = j0; q.nb = nb; q.pad = 0;
+      pv.push_back(q);
+      const int rest = j.N - j0 - nb;
+      if (rest > 0) {
+        T* A2 = static_cast<T*>(j.A) + j0 + (int64_t)(j0 + nb) * j.lda;
+        const int mv = j.M - j0;
+        g1.add(Vb, mv, 1, A2, j.lda, 0, W1, nb, nb, rest, mv, 1.0, 0.0);          // W1 = V^T A2
+        g2.add(Tb, nb, 1, W1, nb, 0, W2, nb, nb, rest, nb, 1.0, 0.0);            // W2 = T^T W1
+        g3.add(Vb, mv, 0, W2, nb, 0, A2, j.lda, mv, rest, nb, -1.0, 1.0);        // A2 -= V W2
+      }
+    }
+    if (pv.empty()) break;
+    const QrPanel* dp = P.put(S.pd, pv);
+    P.kbegin();
+    hipLaunchKernelGGL(k_qr_panel<T>, dim3((unsigned)pv.size()), dim3(WG), 0, P.stream, dp);
+    IFMM_LAUNCH_CHECK();
+    P.kend();
+    run_gemm<T>(P, g1, S.gd);
+    run_gemm<T>(P, g2, S.gd);
+    run_gemm<T>(P, g3, S.gd);
+  }
+  std::vector<QrOut> ov;
+  for (size_t b = 0; b < jobs.size(); ++b) {
+    const auto& j = jobs[b];
+    if (!j.R || std::min(j.M, j.N) == 0) continue;
+    ov.push_back({j.A, W + off[b], j.R, j.M, j.N, j.lda, j.ldr});
+  }
+  if (!ov.empty()) {
+    const QrOut* d = P.put(S.od, ov);
+    P.kbegin();
+    hipLaunchKernelGGL(k_qr_extract<T>, dim3((unsigned)ov.size()), dim3(WG), 0, P.stream, d);
+    IFMM_LAUNCH_CHECK();
+    P.kend();
+  }
+}
+
 }  // namespace ifmm

@@ -533,7 +533,7 @@ inline void build_r2(Problem& P, double sigma0_override) {
         qd.push_back(dd);
         // B = R^T (r_i x kq)
         tb.add(Rw.as<double>() + woff[l][i], kq, Bw.as<double>() + woff[l][i], r[i], r[i], kq, 4);
-        SvdDesc s;
+        SvdDesc s{};
         s.B = Bw.as<double>() + woff[l][i];
         s.U = W.as<double>() + woff[l][i];
         s.S = S.as<double>() + soff[l][i];

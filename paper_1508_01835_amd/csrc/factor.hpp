@@ -72,6 +72,7 @@ struct FactorStore : FactorStoreBase {
   // scratch reused across calls
   DevBuf work, d1, d2, d3, d4, d5;
   LuScratch lus;
+  QrScratch qrs;
   DevBuf sx;                                       // solve vectors
   DevBuf sc;                                       // c_P store
   int s_nrhs = 0;
@@ -354,6 +355,8 @@ struct Factorizer {
       c.sv = take(c.kq);
       c.tr = take((int64_t)L.cap[c.box] * L.cap[c.box]);
       c.tt = take((int64_t)L.cap[c.box] * L.cap[c.box]);
+      c.pu = take(mj + 2);
+      c.pv = take(mj + 2);
       flops_comp += 2.0 * 2.0 * c.ncols * mj * mj + 2.0 * 12.0 * (double)mj * c.kq * c.kq;
     }
     if ((size_t)o * sizeof(T) > F.work.bytes) {
@@ -372,7 +375,7 @@ struct Factorizer {
                        (const T*)L.P(), W);
     IFMM_LAUNCH_CHECK();
     std::vector<QrDesc> qd;
-    CopyBatch<T, T> tb;
+    std::vector<QrcpDesc> pd;
     std::vector<SvdDesc> sd;
     for (const auto& c : cs) {
       const int mj = L.m[c.box];
@@ -383,37 +386,99 @@ struct Factorizer {
         q.Q = nullptr;
         q.M = c.ncols; q.N = mj; q.lda = c.ncols; q.ldr = c.kq; q.ldq = 1; q.pad = 0;
         qd.push_back(q);
-        // B = R^T (m_j x kq), reusing the MU / MV storage
-        tb.add(W + (side ? c.rv : c.ru), c.kq, W + (side ? c.mv : c.mu), mj, mj, c.kq, 4);
-        SvdDesc s;
+        // truncated pivoted QR of R; Y = R'^T (m_j x k) into the MU / MV storage
+        int* perm = reinterpret_cast<int*>(W + (side ? c.pv : c.pu));
+        QrcpDesc r;
+        r.R = W + (side ? c.rv : c.ru);
+        r.Y = W + (side ? c.mv : c.mu);
+        r.perm = perm;
+        r.kout = perm + mj;
+        r.m = c.kq; r.n = mj; r.ldr = c.kq; r.ldy = mj;
+        pd.push_back(r);
+        SvdDesc s{};
         s.B = W + (side ? c.mv : c.mu);
         s.U = W + (side ? c.vv : c.uu);
         s.S = W + (side ? c.sv : c.su);
+        s.nlive = perm + mj;
+        s.perm = perm;
         s.M = mj; s.N = c.kq; s.ldb = mj; s.ldu = mj;
         sd.push_back(s);
       }
     }
     chk(L, "comp_gather", nullptr, o);
-    double fq = 0, fs = 0, bq = 0;
+    double fq = 0, fs = 0, bq = 0, fp = 0;
     for (const auto& c : cs) {
       const double mj = L.m[c.box], n = c.ncols, k = c.kq;
       fq += 2.0 * (2.0 * n * mj * mj - 2.0 / 3.0 * mj * mj * mj);   // Householder R of MU^T and MV^T
       bq += 2.0 * sizeof(T) * (n * mj + k * mj);
+      fp += 2.0 * (2.0 * k * mj * mj - 2.0 / 3.0 * k * k * k);     // pivoted QR of R (untruncated count)
       fs += 2.0 * (4.0 * mj * k * k + 8.0 * k * k * k);             // SVD (U and singular values)
     }
     P.kset(KF_QR, fq, bq);
-    run_qr<T>(P, qd, F.d4);
+    {
+      std::vector<QrJob> qj;
+      qj.reserve(qd.size());
+      for (const auto& q : qd) qj.push_back({q.A, q.R, q.M, q.N, q.lda, q.ldr});
+      qr_blocked<T>(P, qj, F.qrs);
+    }
     chk(L, "comp_qr", nullptr, o);
-    P.kset(-1);
-    run_copy(P, tb, F.d4);
+    auto nan_report = [&](const char* what, bool y) {
+      if (!trace_on()) return;
+      for (const auto& c : cs) {
+        const int mj = L.m[c.box];
+        for (int side = 0; side < 2; ++side) {
+          std::vector<T> h;
+          const int64_t off = y ? (side ? c.mv : c.mu) : (side ? c.rv : c.ru);
+          P.download(h, W + off, (size_t)mj * c.kq);
+          size_t bad = 0;
+          double mx = 0;
+          for (auto x : h) { if (!std::isfinite((double)x)) ++bad; else mx = std::max(mx, std::fabs((double)x)); }
+          if (bad)
+            std::fprintf(stderr, "[ifmm-trace] nan %s level=%d box=%d side=%d mj=%d kq=%d ncols=%d bad=%zu max=%.3e\n",
+                         what, P.trace_level, c.box, side, mj, c.kq, c.ncols, bad, mx);
+        }
+      }
+    };
+    nan_report("after_qr", false);
+    P.kset(KF_QR, fp, 0);
+    run_qrcp<T>(P, pd, F.d4, 1e-7 * P.tau);
+    chk(L, "comp_qrcp", nullptr, o);
+    nan_report("after_qrcp", true);
     P.kset(KF_SVD, fs, 0);
-    run_svd<T>(P, sd, F.d4);
+    run_svd<T>(P, sd, F.d4, 1e-6 * P.tau);
     P.kset(-1);
     chk(L, "comp_svd", nullptr, o);
     P.kset(KF_XFORM);
     P.kbegin();
     hipLaunchKernelGGL(k_comp_rank<T>, dim3((unsigned)ceil_div((int64_t)cs.size(), WG)), dim3(WG), 0, P.stream, dc,
                        (int)cs.size(), v, (const T*)W, P.tau, P.rank_max);
+    IFMM_LAUNCH_CHECK();
+    if (trace_on()) {   // boxes whose common rank exceeds the resolved directions of one side
+      std::vector<int> rn;
+      P.download(rn, L.drnew.p, (size_t)L.nb);
+      for (const auto& c : cs) {
+        const int mj = L.m[c.box], k = rn[c.box];
+        std::vector<T> su, sv;
+        std::vector<int> pu, pv;
+        P.download(su, W + c.su, (size_t)c.kq);
+        P.download(sv, W + c.sv, (size_t)c.kq);
+        P.download(pu, reinterpret_cast<int*>(W + c.pu) + mj, 1);
+        P.download(pv, reinterpret_cast<int*>(W + c.pv) + mj, 1);
+        int ku = 0, kv = 0, gu = 0, gv = 0;
+        for (int a = 0; a < c.kq; ++a) {
+          ku += su[a] > P.tau; kv += sv[a] > P.tau;
+          gu += su[a] > 2e-6 * P.tau; gv += sv[a] > 2e-6 * P.tau;
+        }
+        if (k > gu || k > gv || ku != kv)
+          std::fprintf(stderr,
+                       "[ifmm-trace] rank level=%d box=%d elim=%d mj=%d ncols=%d kq=%d k=%d ku=%d kv=%d gu=%d gv=%d "
+                       "liveu=%d livev=%d su[k-1]/tau=%.3e sv[k-1]/tau=%.3e\n",
+                       P.trace_level, c.box, c.elim, mj, c.ncols, c.kq, k, ku, kv, gu, gv, pu[0], pv[0],
+                       k > 0 ? (double)su[k - 1] / P.tau : 0.0, k > 0 ? (double)sv[k - 1] / P.tau : 0.0);
+      }
+    }
+    hipLaunchKernelGGL(k_comp_complete<T>, dim3((unsigned)cs.size(), 2), dim3(WG), 0, P.stream, dc, v, W,
+                       2e-6 * P.tau);
     IFMM_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_comp_rt<T>, dim3((unsigned)cs.size()), dim3(WG), 0, P.stream, dc, v, (const T*)L.P(), W);
     IFMM_LAUNCH_CHECK();
@@ -740,6 +805,7 @@ struct Factorizer {
     auto cur = std::make_unique<LevelPool<T>>();
     setup_leaf(*cur);
     for (int l = Lv; l >= 2; --l) {
+      P.trace_level = l;
       eliminate_level(*cur);
       plan_solve(*cur);
       P.st.max_rank[l] = 0;

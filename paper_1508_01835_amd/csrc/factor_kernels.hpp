@@ -156,6 +156,7 @@ struct CompDesc {
   int64_t uu, vv;              // workspace offsets of the left singular vectors (m_j x kq, ld m_j)
   int64_t su, sv;              // workspace offsets of the singular values (kq)
   int64_t tr, tt;              // workspace offsets of r_j (k x r, ld cap) and t_j
+  int64_t pu, pv;              // workspace offsets of the pivoted-QR row permutations (m_j ints + count)
   int kq, pad;
 };
 
@@ -211,6 +212,80 @@ __global__ void k_comp_rank(const CompDesc* __restrict__ cs, int nc, LevelView l
   if (rank_max > 0 && k > rank_max) k = rank_max;
   if (k > lv.cap[c.box]) k = lv.cap[c.box];
   lv.rnew[c.box] = k;
+}
+
+// The common rank k may exceed the number of resolved singular directions of
+// one side (singular values at or below good_level, the level under which the
+// SVD neither orthogonalises nor keeps columns). Such columns are replaced by
+// an orthonormal completion: each new column is the unit vector e_i with the
+// largest component outside the columns kept so far (1 - sum_a U[i, a]^2 is
+// largest), orthogonalised twice against them and normalised; its singular
+// value is 0. blockIdx.y = side (0: U, 1: V).
+template <class T>
+__global__ void __launch_bounds__(WG) k_comp_complete(const CompDesc* __restrict__ cs, LevelView lv,
+                                                      T* __restrict__ work, double good_level) {
+  __shared__ T v[1024];
+  __shared__ T coef[1024];
+  __shared__ T red[WG / WAVE];
+  __shared__ T bv[WG / WAVE];
+  __shared__ int bi[WG / WAVE];
+  __shared__ int pick;
+  const CompDesc c = cs[blockIdx.x];
+  const int mj = lv.m[c.box], k = lv.rnew[c.box];
+  T* U = work + (blockIdx.y ? c.vv : c.uu);
+  T* S = work + (blockIdx.y ? c.sv : c.su);
+  const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+  int g = 0;
+  while (g < k && (double)S[g] > good_level) ++g;
+  for (int col = g; col < k; ++col) {
+    // the unit vector least represented in the kept columns
+    T best = (T)-1;
+    int besti = 0;
+    for (int i = threadIdx.x; i < mj; i += WG) {
+      T s = 0;
+      for (int a = 0; a < col; ++a) { const T x = U[i + (int64_t)a * mj]; s += x * x; }
+      if ((T)1 - s > best) { best = (T)1 - s; besti = i; }
+    }
+    for (int o = WAVE / 2; o > 0; o >>= 1) {
+      const T ob = __shfl_xor(best, o, WAVE);
+      const int oi = __shfl_xor(besti, o, WAVE);
+      if (ob > best || (ob == best && oi < besti)) { best = ob; besti = oi; }
+    }
+    if (lane == 0) { bv[w] = best; bi[w] = besti; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      T b = bv[0];
+      int i0 = bi[0];
+      for (int q = 1; q < WG / WAVE; ++q)
+        if (bv[q] > b || (bv[q] == b && bi[q] < i0)) { b = bv[q]; i0 = bi[q]; }
+      pick = i0;
+    }
+    __syncthreads();
+    const int j = pick;
+    for (int i = threadIdx.x; i < mj; i += WG) v[i] = i == j ? (T)1 : (T)0;
+    __syncthreads();
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int a = threadIdx.x; a < col; a += WG) {
+        T s = 0;
+        for (int i = 0; i < mj; ++i) s += U[i + (int64_t)a * mj] * v[i];
+        coef[a] = s;
+      }
+      __syncthreads();
+      for (int i = threadIdx.x; i < mj; i += WG) {
+        T s = v[i];
+        for (int a = 0; a < col; ++a) s -= U[i + (int64_t)a * mj] * coef[a];
+        v[i] = s;
+      }
+      __syncthreads();
+    }
+    T s2 = 0;
+    for (int i = threadIdx.x; i < mj; i += WG) s2 += v[i] * v[i];
+    const T nrm = sqrt(block_sum(s2, red));
+    const T inv = nrm > (T)0 ? (T)1 / nrm : (T)0;
+    for (int i = threadIdx.x; i < mj; i += WG) U[i + (int64_t)col * mj] = v[i] * inv;
+    if (threadIdx.x == 0) S[col] = (T)0;
+    __syncthreads();
+  }
 }
 
 // r_j = Uhat^T U_j and t_j = Vhat^T V_j (k x r_old, ld cap_j).

@@ -1,5 +1,5 @@
 // Batched, variable-size dense linear algebra on gfx950: GEMM, LU with partial
-// pivoting and its solve, Householder QR, one-sided Jacobi SVD, block copies.
+// pivoting and its solve, Householder QR, block copies.
 // Every batch is described by an array of descriptors in device memory; one
 // workgroup (or a set of tiles) serves one descriptor.
 #pragma once
@@ -312,7 +312,8 @@ __global__ void __launch_bounds__(WG) k_qr(const QrDesc* __restrict__ ds) {
   const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE, nw = WG / WAVE;
   for (int j = 0; j < kq; ++j) {
     // reflector H = I - tau v v^T with v_j = 1 and beta = -sign(x0) ||x||; the
-    // norm is taken on the column scaled by its largest entry so that tiny or
+    // norm is taken on the column scaled by the power of two nearest its
+    // largest entry (exact, and finite for subnormal columns) so that tiny or
     // huge columns neither underflow nor overflow
     T amax = 0;
     for (int i = j + threadIdx.x; i < M; i += WG) amax = fmax(amax, fabs(A[i + j * lda]));
@@ -320,15 +321,16 @@ __global__ void __launch_bounds__(WG) k_qr(const QrDesc* __restrict__ ds) {
     const T x0 = A[j + j * lda];
     T tj = 0, al = x0;
     if (amax > (T)0) {
-      const T inv = (T)1 / amax;
+      const int sh = -ilogb((double)amax);
       T s = 0;
-      for (int i = j + threadIdx.x; i < M; i += WG) { const T x = A[i + j * lda] * inv; s += x * x; }
+      for (int i = j + threadIdx.x; i < M; i += WG) { const T x = ldexp(A[i + j * lda], sh); s += x * x; }
       s = block_sum(s, red);
-      const T nrm = amax * sqrt(s);
-      al = x0 >= (T)0 ? -nrm : nrm;
-      tj = (al - x0) / al;
-      const T scal = (T)1 / (x0 - al);
-      for (int i = j + 1 + threadIdx.x; i < M; i += WG) A[i + j * lda] *= scal;
+      const T x0s = ldexp(x0, sh);
+      const T als = x0s >= (T)0 ? -sqrt(s) : sqrt(s);
+      al = ldexp(als, -sh);
+      tj = (als - x0s) / als;
+      const T scal = (T)1 / (x0s - als);
+      for (int i = j + 1 + threadIdx.x; i < M; i += WG) A[i + j * lda] = ldexp(A[i + j * lda], sh) * scal;
       __syncthreads();
       if (threadIdx.x == 0) A[j + j * lda] = (T)1;
     }
@@ -371,120 +373,6 @@ __global__ void __launch_bounds__(WG) k_qr(const QrDesc* __restrict__ ds) {
       }
       __syncthreads();
     }
-  }
-}
-
-// ======================================================= one-sided Jacobi SVD
-// Orthogonalises the columns of B (M x N, ldb) in place by plane rotations
-// (Hestenes). On exit U (M x N, ldu) holds the normalised columns sorted by
-// decreasing norm and S (N) the norms = singular values of the input. A column
-// of zero norm is left as zeros in U.
-struct SvdDesc {
-  void* B;
-  void* U;
-  void* S;
-  int M, N, ldb, ldu;
-};
-
-constexpr int SVD_MAXN = 1024;
-constexpr int SVD_WG = 1024;   // 16 wavefronts: 16 column pairs rotated at once
-
-template <class T>
-__device__ inline void jacobi_pair(T* __restrict__ B, int64_t ldb, int M, int p, int q, T tol,
-                                   int lane, int* rotated) {
-  T a = 0, b = 0, g = 0;
-  for (int i = lane; i < M; i += WAVE) {
-    const T x = B[i + p * ldb], y = B[i + q * ldb];
-    a += x * x; b += y * y; g += x * y;
-  }
-  a = wave_sum(a); b = wave_sum(b); g = wave_sum(g);
-  if (g == (T)0 || !(fabs(g) > tol * sqrt(a * b))) return;
-  const T zeta = (b - a) / ((T)2 * g);
-  const T t = (zeta >= (T)0 ? (T)1 : (T)-1) / (fabs(zeta) + sqrt((T)1 + zeta * zeta));
-  const T c = (T)1 / sqrt((T)1 + t * t);
-  const T s = c * t;
-  for (int i = lane; i < M; i += WAVE) {
-    const T x = B[i + p * ldb], y = B[i + q * ldb];
-    B[i + p * ldb] = c * x - s * y;
-    B[i + q * ldb] = s * x + c * y;
-  }
-  if (lane == 0) *rotated = 1;
-}
-
-template <class T>
-__global__ void __launch_bounds__(SVD_WG) k_jacobi_svd(const SvdDesc* __restrict__ ds, double tol_d,
-                                                    int max_sweeps) {
-  const SvdDesc d = ds[blockIdx.x];
-  T* __restrict__ B = static_cast<T*>(d.B);
-  T* __restrict__ U = static_cast<T*>(d.U);
-  T* __restrict__ S = static_cast<T*>(d.S);
-  const int M = d.M, N = d.N;
-  const int64_t ldb = d.ldb, ldu = d.ldu;
-  const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE, nw = SVD_WG / WAVE;
-  __shared__ int rotated;
-  __shared__ T nrm[SVD_MAXN];
-  __shared__ int order[SVD_MAXN];
-  const T tol = (T)tol_d;
-  const int Np = N + (N & 1);   // even number of players; player N (if odd) is a bye
-  // scale by the largest entry so that products of tiny entries do not underflow
-  __shared__ T red[SVD_WG / WAVE];
-  T amax = 0;
-  for (int64_t e = threadIdx.x; e < (int64_t)M * N; e += SVD_WG) amax = fmax(amax, fabs(B[e % M + (e / M) * ldb]));
-  amax = block_max(amax, red);
-  if (amax > (T)0 && amax != (T)1) {
-    const T inv = (T)1 / amax;
-    for (int64_t e = threadIdx.x; e < (int64_t)M * N; e += SVD_WG) B[e % M + (e / M) * ldb] *= inv;
-  }
-  __syncthreads();
-  if (N > 1) {
-    for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-      if (threadIdx.x == 0) rotated = 0;
-      __syncthreads();
-      // round-robin tournament: player 0 fixed, others rotate
-      for (int round = 0; round < Np - 1; ++round) {
-        for (int pr = wv; pr < Np / 2; pr += nw) {
-          int x, y;
-          if (pr == 0) { x = 0; y = 1 + (round % (Np - 1)); }
-          else {
-            x = 1 + ((round + pr) % (Np - 1));
-            y = 1 + ((round + Np - 1 - pr) % (Np - 1));
-          }
-          if (x < N && y < N) {
-            const int p = x < y ? x : y, q = x < y ? y : x;
-            jacobi_pair(B, ldb, M, p, q, tol, lane, &rotated);
-          }
-        }
-        __syncthreads();
-      }
-      if (!rotated) break;
-      __syncthreads();
-    }
-  }
-  for (int c = wv; c < N; c += nw) {
-    T s = 0;
-    for (int i = lane; i < M; i += WAVE) { T x = B[i + c * ldb]; s += x * x; }
-    s = wave_sum(s);
-    if (lane == 0) nrm[c] = sqrt(s);
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int c = 0; c < N; ++c) order[c] = c;
-    for (int a = 0; a < N; ++a) {   // selection sort, decreasing norm, stable
-      int best = a;
-      for (int b = a + 1; b < N; ++b)
-        if (nrm[order[b]] > nrm[order[best]]) best = b;
-      const int tmp = order[best];
-      for (int b = best; b > a; --b) order[b] = order[b - 1];
-      order[a] = tmp;
-    }
-  }
-  __syncthreads();
-  for (int c = wv; c < N; c += nw) {
-    const int src = order[c];
-    const T s = nrm[src];
-    const T inv = s > (T)0 ? (T)1 / s : (T)0;
-    for (int i = lane; i < M; i += WAVE) U[i + c * ldu] = B[i + src * ldb] * inv;
-    if (lane == 0) S[c] = amax > (T)0 ? s * amax : (T)0;
   }
 }
 

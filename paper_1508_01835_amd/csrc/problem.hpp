@@ -2,6 +2,7 @@
 // truncated initial operators of E (R2, float64), the factors, timers.
 #pragma once
 
+#include <chrono>
 #include <memory>
 
 #include "h2.hpp"
@@ -127,6 +128,9 @@ struct Problem {
 
   // statistics
   ifmm_stats st{};
+  int trace_level = 0;             // level being factorized (IFMM_TRACE output)
+  DevBuf trace_buf;
+  DevBuf svd_state;                // block-Jacobi SVD: scales and convergence flags
   int* d_info = nullptr;           // device error word (first failing tag)
   DevBuf info_buf;
 
@@ -174,6 +178,13 @@ inline bool debug_on() {
   return on;
 }
 
+// Per-launch trace of the dense batched kernels (IFMM_TRACE=1): synchronises
+// after each launch and prints sizes and duration to stderr.
+inline bool trace_on() {
+  static const bool on = std::getenv("IFMM_TRACE") != nullptr;
+  return on;
+}
+
 template <class T>
 inline void dbg_dump(Problem& P, const char* name, const void* d, size_t count, size_t show = 6) {
   if (!debug_on() || count == 0) return;
@@ -216,17 +227,6 @@ inline void run_qr(Problem& P, const std::vector<QrDesc>& v, DevBuf& scratch) {
   const QrDesc* d = P.put(scratch, v);
   P.kbegin();
   hipLaunchKernelGGL(k_qr<T>, dim3((unsigned)v.size()), dim3(WG), 0, P.stream, d);
-  IFMM_LAUNCH_CHECK();
-  P.kend();
-}
-
-template <class T>
-inline void run_svd(Problem& P, const std::vector<SvdDesc>& v, DevBuf& scratch) {
-  if (v.empty()) return;
-  const SvdDesc* d = P.put(scratch, v);
-  const double tol = 4.0 * Prec<T>::u;
-  P.kbegin();
-  hipLaunchKernelGGL(k_jacobi_svd<T>, dim3((unsigned)v.size()), dim3(SVD_WG), 0, P.stream, d, tol, 60);
   IFMM_LAUNCH_CHECK();
   P.kend();
 }

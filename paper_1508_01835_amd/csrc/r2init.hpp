@@ -10,7 +10,7 @@
 //    (eq. methods_SVD_rank_spectralnorm), U and V keeping the same count.
 #pragma once
 
-#include "problem.hpp"
+#include "svd.hpp"
 
 namespace ifmm {
 

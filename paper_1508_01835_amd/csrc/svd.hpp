@@ -1,0 +1,527 @@
+// Batched one-sided Jacobi SVD (Hestenes) of variable-size matrices. The
+// recompressions need the left singular vectors and the singular values only:
+// the columns of B are orthogonalised by plane rotations, their norms are the
+// singular values and the normalised columns the left singular vectors.
+//
+// Two schemes, chosen per matrix:
+//  - small: one workgroup per matrix, the matrix copied into LDS (the many
+//    small matrices of the fine levels);
+//  - block: the columns are split in blocks of nb; one round of a round-robin
+//    tournament over the blocks is one launch in which one workgroup takes one
+//    pair of blocks into LDS and orthogonalises its 2 nb columns among
+//    themselves. All pairs of all matrices of a batch run side by side, so a
+//    colour class with only a few large matrices still spreads over the chip.
+//
+// Rotation rule (both schemes), with a, b the squared norms of columns p, q
+// and g their inner product: rotate iff |g| > tol sqrt(a b), with
+// tol = max(4, sqrt(M)) u: the computed cosine carries a rounding error that
+// grows like sqrt(M) u, and chasing cosines below that only re-rotates noise
+// (the threshold of LAPACK's one-sided Jacobi). Columns of norm below defl
+// (absolute) are frozen: they lie far under the truncation threshold and are
+// discarded by the caller.
+#pragma once
+
+#include "problem.hpp"
+
+namespace ifmm {
+
+struct SvdDesc {
+  void* B;              // M x N, ldb; overwritten
+  void* U;              // M x N, ldu: normalised columns by decreasing norm (zero norm: zeros)
+  void* S;              // N: the singular values, decreasing
+  const int* nlive;     // optional (device): only the first *nlive columns of B are nonzero
+  const int* perm;      // optional (device, M): row i of B is row perm[i] of U
+  int M, N, ldb, ldu;
+};
+
+__device__ inline int svd_cols(const SvdDesc& d) { return d.nlive ? max(0, min(d.N, *d.nlive)) : d.N; }
+
+constexpr int SVD_MAXN = 1024;
+constexpr int SVD_WG = 1024;                // 16 wavefronts: 16 column pairs at once
+constexpr size_t SVD_LDS_MAX = 144 * 1024;  // dynamic LDS per workgroup (gfx950: 160 KB)
+
+// Rotates columns p and q of B (ld) when the rule above asks for it; one
+// wavefront. Returns whether it rotated (uniform over the wavefront).
+template <class T>
+__device__ inline bool jacobi_rot(T* __restrict__ B, int64_t ld, int M, int p, int q, T tol, T defl2, int lane) {
+  T a = 0, b = 0, g = 0;
+  for (int i = lane; i < M; i += WAVE) {
+    const T x = B[i + p * ld], y = B[i + q * ld];
+    a += x * x; b += y * y; g += x * y;
+  }
+  a = wave_sum(a); b = wave_sum(b); g = wave_sum(g);
+  if (a < defl2 || b < defl2) return false;
+  if (!(fabs(g) > tol * sqrt(a * b))) return false;
+  const T zeta = (b - a) / ((T)2 * g);
+  const T t = (zeta >= (T)0 ? (T)1 : (T)-1) / (fabs(zeta) + sqrt((T)1 + zeta * zeta));
+  const T c = (T)1 / sqrt((T)1 + t * t);
+  const T s = c * t;
+  for (int i = lane; i < M; i += WAVE) {
+    const T x = B[i + p * ld], y = B[i + q * ld];
+    B[i + p * ld] = c * x - s * y;
+    B[i + q * ld] = s * x + c * y;
+  }
+  return true;
+}
+
+// Pair (x, y) of player slot pr in round r of a round-robin tournament over
+// np (even) players: player 0 stays, the others rotate.
+__device__ inline void rr_pair(int np, int r, int pr, int& x, int& y) {
+  if (pr == 0) { x = 0; y = 1 + (r % (np - 1)); }
+  else {
+    x = 1 + ((r + pr) % (np - 1));
+    y = 1 + ((r + np - 1 - pr) % (np - 1));
+  }
+}
+
+// Cyclic sweeps over the nc columns of B (ld) until a sweep rotates nothing or
+// max_sweeps; whole workgroup. Returns the sweeps done, *any = whether any
+// rotation happened.
+template <class T>
+__device__ inline int jacobi_sweeps(T* __restrict__ B, int64_t ld, int M, int nc, T tol, T defl2, int max_sweeps,
+                                    int* any, int* flag) {
+  const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE, nw = blockDim.x / WAVE;
+  const int np = nc + (nc & 1);
+  int sweeps = 0;
+  if (nc < 2) return 0;
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    sweeps = sweep + 1;
+    if (threadIdx.x == 0) *flag = 0;
+    __syncthreads();
+    bool rot = false;
+    for (int r = 0; r < np - 1; ++r) {
+      for (int pr = wv; pr < np / 2; pr += nw) {
+        int x, y;
+        rr_pair(np, r, pr, x, y);
+        if (x < nc && y < nc) rot |= jacobi_rot(B, ld, M, min(x, y), max(x, y), tol, defl2, lane);
+      }
+      __syncthreads();
+    }
+    if (rot && lane == 0) *flag = 1;
+    __syncthreads();
+    const int f = *flag;
+    __syncthreads();
+    if (!f) break;
+    *any = 1;
+  }
+  return sweeps;
+}
+
+// Column norms, order by decreasing norm (ties by index), U = B / norm,
+// S = norm * 2^-sh over the N live columns (rows placed through perm when
+// given); columns N..Nout-1 of U and S are zero. Whole workgroup; N <= SVD_MAXN.
+template <class T>
+__device__ inline void svd_finish(const T* __restrict__ B, int64_t ldb, int M, int N, int Nout, T* __restrict__ U,
+                                  int64_t ldu, T* __restrict__ S, int sh, const int* __restrict__ perm, T* nrm,
+                                  int* order) {
+  const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE, nw = blockDim.x / WAVE;
+  for (int c = wv; c < N; c += nw) {
+    T s = 0;
+    for (int i = lane; i < M; i += WAVE) { const T x = B[i + c * ldb]; s += x * x; }
+    s = wave_sum(s);
+    if (lane == 0) nrm[c] = sqrt(s);
+  }
+  __syncthreads();
+  // rank of each column in decreasing order of norm; a NaN norm ranks last
+  // (as -1) so that the ranks stay a permutation
+  for (int c = threadIdx.x; c < N; c += blockDim.x) {
+    const T v = nrm[c] == nrm[c] ? nrm[c] : (T)-1;
+    int rk = 0;
+    for (int j = 0; j < N; ++j) {
+      const T w = nrm[j] == nrm[j] ? nrm[j] : (T)-1;
+      rk += (w > v) || (w == v && j < c);
+    }
+    order[rk] = c;
+  }
+  __syncthreads();
+  for (int c = wv; c < N; c += nw) {
+    const int src = order[c];
+    const T s = nrm[src];
+    for (int i = lane; i < M; i += WAVE)
+      U[(perm ? perm[i] : i) + c * ldu] = s > (T)0 ? B[i + src * ldb] / s : (T)0;
+    if (lane == 0) S[c] = ldexp(s, -sh);
+  }
+  for (int c = N + wv; c < Nout; c += nw) {
+    for (int i = lane; i < M; i += WAVE) U[i + c * ldu] = (T)0;
+    if (lane == 0) S[c] = (T)0;
+  }
+}
+
+// B scaled into D (ldd) by 2^sh, the power of two that brings the largest
+// entry into [1, 2) (exact; finite also for subnormal entries); whole
+// workgroup. Returns sh (0 for a zero matrix).
+template <class T>
+__device__ inline int svd_scale(const T* B, int64_t ldb, int M, int N, T* D, int64_t ldd, T* red) {
+  T m = 0;
+  for (int64_t e = threadIdx.x; e < (int64_t)M * N; e += blockDim.x) m = fmax(m, fabs(B[e % M + (e / M) * ldb]));
+  const T amax = block_max(m, red);
+  const int sh = amax > (T)0 ? -ilogb((double)amax) : 0;
+  for (int64_t e = threadIdx.x; e < (int64_t)M * N; e += blockDim.x)
+    D[e % M + (e / M) * ldd] = ldexp(B[e % M + (e / M) * ldb], sh);
+  return sh;
+}
+
+// ------------------------------------------------------------- small scheme
+template <class T>
+__global__ void __launch_bounds__(SVD_WG) k_svd_small(const SvdDesc* __restrict__ ds, double u, int max_sweeps, double defl, int use_lds,
+                                                   int* __restrict__ sweeps_out) {
+  extern __shared__ unsigned char svd_dyn[];
+  __shared__ T red[SVD_WG / WAVE];
+  __shared__ T nrm[SVD_MAXN];
+  __shared__ int order[SVD_MAXN];
+  __shared__ int flag;
+  const SvdDesc d = ds[blockIdx.x];
+  T* Bg = static_cast<T*>(d.B);
+  const int M = d.M, N = svd_cols(d);
+  // the matrix is rotated in LDS when it fits, in place otherwise
+  T* B = use_lds ? reinterpret_cast<T*>(svd_dyn) : Bg;
+  const int64_t ldb = use_lds ? (int64_t)M : (int64_t)d.ldb;
+  const int sh = svd_scale(Bg, d.ldb, M, N, B, ldb, red);
+  __syncthreads();
+  const T defl_s = (T)ldexp(defl, sh);
+  const T tol = (T)(u * fmax(4.0, sqrt((double)M)));
+  int any = 0;
+  const int sw = jacobi_sweeps(B, ldb, M, N, tol, defl_s * defl_s, max_sweeps, &any, &flag);
+  if (sweeps_out && threadIdx.x == 0) atomicMax(sweeps_out, sw);
+  svd_finish(B, ldb, M, N, d.N, static_cast<T*>(d.U), d.ldu, static_cast<T*>(d.S), sh, d.perm, nrm, order);
+}
+
+// ------------------------------------------------------------- block scheme
+// Per matrix: shs[s] = the scaling exponent sh; flags[2s] = rotations in the
+// current sweep, flags[2s + 1] = converged.
+template <class T>
+__global__ void __launch_bounds__(SVD_WG) k_svd_prep(const SvdDesc* __restrict__ ds, int* __restrict__ shs,
+                                                  int* __restrict__ flags) {
+  __shared__ T red[SVD_WG / WAVE];
+  const SvdDesc d = ds[blockIdx.x];
+  T* B = static_cast<T*>(d.B);
+  const int N = svd_cols(d);
+  const int sh = svd_scale(B, d.ldb, d.M, N, B, d.ldb, red);
+  if (threadIdx.x == 0) {
+    shs[blockIdx.x] = sh;
+    flags[2 * blockIdx.x] = 0;
+    flags[2 * blockIdx.x + 1] = N < 2 ? 1 : 0;
+  }
+}
+
+// One tournament round: blockIdx.y = matrix, blockIdx.x = pair of column blocks.
+template <class T>
+__global__ void __launch_bounds__(SVD_WG) k_svd_round(const SvdDesc* __restrict__ ds,
+                                                   const int* __restrict__ shs, int* __restrict__ flags, int nb,
+                                                   int round, double u, double defl, int inner_sweeps) {
+  extern __shared__ unsigned char svd_dyn[];
+  __shared__ int flag;
+  const int s = blockIdx.y;
+  if (flags[2 * s + 1]) return;
+  const SvdDesc d = ds[s];
+  const int M = d.M, N = svd_cols(d);
+  const int nblk = (N + nb - 1) / nb, np = nblk + (nblk & 1);
+  if (round >= np - 1 || (int)blockIdx.x >= np / 2) return;
+  int x, y;
+  rr_pair(np, round, blockIdx.x, x, y);
+  const int c0[2] = {x < nblk ? x * nb : 0, y < nblk ? y * nb : 0};
+  const int w[2] = {x < nblk ? min(nb, N - x * nb) : 0, y < nblk ? min(nb, N - y * nb) : 0};
+  const int nc = w[0] + w[1];
+  if (nc < 2) return;
+  T* __restrict__ Bg = static_cast<T*>(d.B);
+  T* __restrict__ L = reinterpret_cast<T*>(svd_dyn);
+  for (int64_t e = threadIdx.x; e < (int64_t)M * nc; e += blockDim.x) {
+    const int c = (int)(e / M), i = (int)(e % M);
+    const int gc = c < w[0] ? c0[0] + c : c0[1] + (c - w[0]);
+    L[e] = Bg[i + (int64_t)gc * d.ldb];
+  }
+  __syncthreads();
+  const T defl_s = (T)ldexp(defl, shs[s]);
+  const T tol = (T)(u * fmax(4.0, sqrt((double)M)));
+  int any = 0;
+  jacobi_sweeps(L, (int64_t)M, M, nc, tol, defl_s * defl_s, inner_sweeps, &any, &flag);
+  if (!any) return;   // nothing rotated: global memory already holds these columns
+  for (int64_t e = threadIdx.x; e < (int64_t)M * nc; e += blockDim.x) {
+    const int c = (int)(e / M), i = (int)(e % M);
+    const int gc = c < w[0] ? c0[0] + c : c0[1] + (c - w[0]);
+    Bg[i + (int64_t)gc * d.ldb] = L[e];
+  }
+  if (threadIdx.x == 0) atomicAdd(&flags[2 * s], 1);
+}
+
+// End of a sweep: a matrix whose sweep rotated nothing has converged.
+__global__ void k_svd_sweep_end(int* __restrict__ flags, int n, int sweep, int* __restrict__ sweeps_out) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n || flags[2 * s + 1]) return;
+  if (flags[2 * s] == 0) {
+    flags[2 * s + 1] = 1;
+    if (sweeps_out) atomicMax(sweeps_out, sweep + 1);
+  }
+  flags[2 * s] = 0;
+}
+
+template <class T>
+__global__ void __launch_bounds__(SVD_WG) k_svd_block_finish(const SvdDesc* __restrict__ ds,
+                                                          const int* __restrict__ shs) {
+  __shared__ T nrm[SVD_MAXN];
+  __shared__ int order[SVD_MAXN];
+  const SvdDesc d = ds[blockIdx.x];
+  svd_finish(static_cast<const T*>(d.B), d.ldb, d.M, svd_cols(d), d.N, static_cast<T*>(d.U), d.ldu,
+             static_cast<T*>(d.S), shs[blockIdx.x], d.perm, nrm, order);
+}
+
+// ------------------------------------------- truncated column-pivoted QR
+// Preconditioner of the Jacobi SVD of B = R^T (Drmac-Veselic: Jacobi on the
+// transposed triangular factor of a column-pivoted QR converges in a few
+// sweeps). R is m x n (ld) with m <= n. Householder QR with column pivoting
+// (largest remaining partial column norm; partial norms downdated and
+// recomputed on cancellation) stops at the first step s where the Frobenius
+// norm of the unfactorised block R[s:, s:] is at most max(delta,
+// 4 u ||R||_F), so that B = P Y Q^T + E with ||E||_F below that level,
+// Y = R'[0:k, :]^T (n x k) and P the column permutation. Since the left
+// singular vectors of B are P times those of Y, the Jacobi SVD of Y (rows
+// placed through perm) replaces that of B.
+// Output: Y (n x m area, ld ldy; columns >= k not written), perm (n), *kout;
+// R is overwritten.
+struct QrcpDesc {
+  void* R;
+  void* Y;
+  int* perm;
+  int* kout;
+  int m, n, ldr, ldy;
+};
+
+template <class T>
+__global__ void __launch_bounds__(SVD_WG) k_qrcp(const QrcpDesc* __restrict__ ds, double delta) {
+  __shared__ T vn1[SVD_MAXN], vn2[SVD_MAXN];
+  __shared__ int pv[SVD_MAXN];
+  __shared__ T hv[SVD_MAXN];
+  __shared__ T redv[SVD_WG / WAVE], reds[SVD_WG / WAVE];
+  __shared__ int redi[SVD_WG / WAVE];
+  __shared__ T sh_tau, sh_stop;
+  __shared__ int sh_piv;
+  const QrcpDesc d = ds[blockIdx.x];
+  T* __restrict__ R = static_cast<T*>(d.R);
+  const int m = d.m, n = d.n;
+  const int64_t ld = d.ldr;
+  const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE, nw = SVD_WG / WAVE;
+  // exact power-of-two scaling of R so that squares of small entries do not underflow
+  T am = 0;
+  for (int64_t e = threadIdx.x; e < (int64_t)m * n; e += SVD_WG) am = fmax(am, fabs(R[e % m + (e / m) * ld]));
+  am = block_max(am, redv);
+  const int sh = am > (T)0 ? -ilogb((double)am) : 0;
+  for (int c = wv; c < n; c += nw) {
+    T s = 0;
+    for (int i = lane; i < m; i += WAVE) {
+      const T x = ldexp(R[i + c * ld], sh);
+      R[i + c * ld] = x;
+      s += x * x;
+    }
+    s = wave_sum(s);
+    if (lane == 0) { vn1[c] = vn2[c] = sqrt(s); pv[c] = c; }
+  }
+  __syncthreads();
+  delta = ldexp(delta, sh);
+  const T tol3z = sqrt((T)Prec<T>::u);
+  const int kmax = min(m, n);
+  int k = 0;
+  for (int s = 0; s < kmax; ++s) {
+    // pivot = the largest remaining partial norm (first on ties); remaining Frobenius norm
+    T best = (T)-1, ss = 0;
+    int bi = s;
+    for (int j = s + threadIdx.x; j < n; j += SVD_WG) {
+      const T x = vn1[j];
+      ss += x * x;
+      if (x > best) { best = x; bi = j; }
+    }
+    for (int o = WAVE / 2; o > 0; o >>= 1) {
+      const T ob = __shfl_xor(best, o, WAVE);
+      const int oi = __shfl_xor(bi, o, WAVE);
+      if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+      ss += __shfl_xor(ss, o, WAVE);
+    }
+    if (lane == 0) { redv[wv] = best; redi[wv] = bi; reds[wv] = ss; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      T b = redv[0], t = reds[0];
+      int i0 = redi[0];
+      for (int w = 1; w < nw; ++w) {
+        if (redv[w] > b || (redv[w] == b && redi[w] < i0)) { b = redv[w]; i0 = redi[w]; }
+        t += reds[w];
+      }
+      if (s == 0) sh_stop = fmax((T)delta, (T)4 * (T)Prec<T>::u * sqrt(t));
+      sh_piv = sqrt(t) <= sh_stop ? -1 : i0;
+    }
+    __syncthreads();
+    const int piv = sh_piv;
+    if (piv < 0) break;
+    if (piv != s) {
+      for (int i = threadIdx.x; i < m; i += SVD_WG) {
+        const T a = R[i + (int64_t)s * ld];
+        R[i + (int64_t)s * ld] = R[i + (int64_t)piv * ld];
+        R[i + (int64_t)piv * ld] = a;
+      }
+      if (threadIdx.x == 0) {
+        T t = vn1[s]; vn1[s] = vn1[piv]; vn1[piv] = t;
+        t = vn2[s]; vn2[s] = vn2[piv]; vn2[piv] = t;
+        const int q = pv[s]; pv[s] = pv[piv]; pv[piv] = q;
+      }
+    }
+    __syncthreads();
+    // Householder reflector H = I - tau v v^T with v_s = 1 zeroing R[s+1:, s]
+    // x0 is read before the reduction's barriers: thread 0 overwrites R[s, s] after them
+    const T x0 = R[s + (int64_t)s * ld];
+    T x2 = 0;
+    for (int i = s + 1 + threadIdx.x; i < m; i += SVD_WG) { const T x = R[i + (int64_t)s * ld]; x2 += x * x; }
+    x2 = block_sum(x2, redv);
+    T tau = 0, beta = x0, scale = 0;
+    if (x2 > (T)0) {
+      beta = x0 >= (T)0 ? -sqrt(x0 * x0 + x2) : sqrt(x0 * x0 + x2);
+      tau = (beta - x0) / beta;
+      scale = (T)1 / (x0 - beta);
+    }
+    for (int i = s + threadIdx.x; i < m; i += SVD_WG) {
+      hv[i] = i == s ? (T)1 : R[i + (int64_t)s * ld] * scale;
+      R[i + (int64_t)s * ld] = i == s ? beta : (T)0;
+    }
+    if (threadIdx.x == 0) sh_tau = tau;
+    __syncthreads();
+    tau = sh_tau;
+    // apply to the trailing columns, one wavefront per column, and downdate its partial norm
+    for (int j = s + 1 + wv; j < n; j += nw) {
+      T w = 0;
+      for (int i = s + lane; i < m; i += WAVE) w += hv[i] * R[i + (int64_t)j * ld];
+      w = wave_sum(w) * tau;
+      T rs = 0, rest = 0;
+      for (int i = s + lane; i < m; i += WAVE) {
+        const T x = R[i + (int64_t)j * ld] - w * hv[i];
+        R[i + (int64_t)j * ld] = x;
+        if (i == s) rs = x;
+        else rest += x * x;
+      }
+      rs = wave_sum(rs);     // only the lane holding row s contributes
+      rest = wave_sum(rest);
+      if (lane == 0 && vn1[j] != (T)0) {
+        const T r = fabs(rs) / vn1[j];
+        const T t = fmax((T)0, ((T)1 + r) * ((T)1 - r));
+        const T q = vn1[j] / vn2[j];
+        if (t * q * q <= tol3z) { vn1[j] = sqrt(rest); vn2[j] = vn1[j]; }
+        else vn1[j] *= sqrt(t);
+      }
+    }
+    __syncthreads();
+    k = s + 1;
+  }
+  // Y = R'[0:k, :]^T, upper trapezoidal rows become lower trapezoidal columns
+  T* __restrict__ Y = static_cast<T*>(d.Y);
+  for (int64_t e = threadIdx.x; e < (int64_t)n * k; e += SVD_WG) {
+    const int i = (int)(e % n), c = (int)(e / n);
+    Y[i + (int64_t)c * d.ldy] = i >= c ? ldexp(R[c + (int64_t)i * ld], -sh) : (T)0;
+  }
+  for (int i = threadIdx.x; i < n; i += SVD_WG) d.perm[i] = pv[i];
+  if (threadIdx.x == 0) *d.kout = k;
+}
+
+template <class T>
+inline void run_qrcp(Problem& P, const std::vector<QrcpDesc>& v, DevBuf& scratch, double delta) {
+  if (v.empty()) return;
+  for (const auto& q : v)
+    if (q.n > SVD_MAXN || q.m > SVD_MAXN || q.m > q.n) fail(IFMM_ERR_INTERNAL, "QRCP shape out of range");
+  const QrcpDesc* d = P.put(scratch, v);
+  P.kbegin();
+  hipLaunchKernelGGL(k_qrcp<T>, dim3((unsigned)v.size()), dim3(SVD_WG), 0, P.stream, d, delta);
+  IFMM_LAUNCH_CHECK();
+  P.kend();
+}
+
+// ------------------------------------------------------------------ launcher
+// defl: singular directions below this absolute level are not resolved (they
+// fall far under the truncation threshold and are discarded).
+template <class T>
+inline void run_svd(Problem& P, const std::vector<SvdDesc>& v, DevBuf& scratch, double defl = 0.0) {
+  if (v.empty()) return;
+  static bool attr = false;
+  if (!attr) {
+    IFMM_HIP(hipFuncSetAttribute((const void*)k_svd_small<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)SVD_LDS_MAX));
+    IFMM_HIP(hipFuncSetAttribute((const void*)k_svd_round<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)SVD_LDS_MAX));
+    attr = true;
+  }
+  std::vector<SvdDesc> small, big;
+  size_t lds = 0;
+  int bigM = 0, bigBlocks = 0;
+  for (const auto& s : v) {
+    if (s.N > SVD_MAXN) fail(IFMM_ERR_INTERNAL, "SVD wider than SVD_MAXN");
+    const size_t b = (size_t)s.M * s.N * sizeof(T);
+    if (b <= SVD_LDS_MAX) { small.push_back(s); lds = std::max(lds, b); }
+    else { big.push_back(s); bigM = std::max(bigM, s.M); }
+  }
+  // column block width of the block scheme: two blocks of M_max rows in LDS
+  int nb = 16;
+  while (nb > 2 && (size_t)bigM * 2 * nb * sizeof(T) > SVD_LDS_MAX) nb /= 2;
+  for (const auto& s : big) bigBlocks = std::max(bigBlocks, (s.N + nb - 1) / nb);
+  const double u = Prec<T>::u;
+  const int max_sweeps = 60;
+  const size_t ns = small.size();
+  small.insert(small.end(), big.begin(), big.end());
+  const SvdDesc* d = P.put(scratch, small);
+  const bool tr = trace_on();
+  int* sw = nullptr;
+  std::chrono::steady_clock::time_point t0;
+  if (tr) {
+    P.trace_buf.reserve(64, &P.mem);
+    sw = P.trace_buf.as<int>();
+    IFMM_HIP(hipMemsetAsync(sw, 0, sizeof(int), P.stream));
+    P.sync();
+    t0 = std::chrono::steady_clock::now();
+  }
+  P.kbegin();
+  if (ns)
+    hipLaunchKernelGGL(k_svd_small<T>, dim3((unsigned)ns), dim3(SVD_WG), lds, P.stream, d, u, max_sweeps, defl, 1,
+                       sw);
+  IFMM_LAUNCH_CHECK();
+  int outer = 0;
+  if (!big.empty()) {
+    const int nbig = (int)big.size();
+    const SvdDesc* db = d + ns;
+    P.svd_state.reserve(sizeof(int) * 3 * nbig + 64, &P.mem);
+    int* shs = P.svd_state.as<int>();
+    int* flags = shs + nbig;
+    hipLaunchKernelGGL(k_svd_prep<T>, dim3(nbig), dim3(SVD_WG), 0, P.stream, db, shs, flags);
+    IFMM_LAUNCH_CHECK();
+    const int np = bigBlocks + (bigBlocks & 1);
+    const size_t lds_b = (size_t)bigM * 2 * nb * sizeof(T);
+    std::vector<int> hf;
+    for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+      for (int r = 0; r < np - 1; ++r) {
+        hipLaunchKernelGGL(k_svd_round<T>, dim3((unsigned)(np / 2), (unsigned)nbig), dim3(SVD_WG), lds_b, P.stream,
+                           db, (const int*)shs, flags, nb, r, u, defl, 1);
+        IFMM_LAUNCH_CHECK();
+      }
+      hipLaunchKernelGGL(k_svd_sweep_end, dim3((unsigned)ceil_div(nbig, 256)), dim3(256), 0, P.stream, flags, nbig,
+                         sweep, sw);
+      IFMM_LAUNCH_CHECK();
+      outer = sweep + 1;
+      if (sweep >= 3 && (sweep % 2 == 1)) {   // poll the converged flags now and then
+        P.download(hf, flags, (size_t)2 * nbig);
+        bool all = true;
+        for (int s = 0; s < nbig; ++s) all = all && hf[2 * s + 1];
+        if (all) break;
+      }
+    }
+    hipLaunchKernelGGL(k_svd_block_finish<T>, dim3(nbig), dim3(SVD_WG), 0, P.stream, db, (const int*)shs);
+    IFMM_LAUNCH_CHECK();
+  }
+  P.kend();
+  if (tr) {
+    P.sync();
+    const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    std::vector<int> h;
+    P.download(h, sw, 1);
+    int mm = 0, mn = 0;
+    double work = 0;
+    for (const auto& s : v) { mm = std::max(mm, s.M); mn = std::max(mn, s.N); work += 3.0 * s.M * (double)s.N * s.N; }
+    std::fprintf(stderr,
+                 "[ifmm-trace] svd level=%d count=%zu small=%zu maxM=%d maxN=%d sweep_work=%.3e sweeps=%d outer=%d "
+                 "nb=%d ms=%.3f\n",
+                 P.trace_level, v.size(), ns, mm, mn, work, h[0], outer, nb, ms);
+  }
+}
+
+}  // namespace ifmm
