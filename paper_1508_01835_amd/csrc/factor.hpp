@@ -42,12 +42,16 @@ struct LevelPool {
   }
 };
 
-// Stored factors of one colour class (read once per solve).
+// Stored factors of one colour class (read once per solve). With b_P =
+// [b(x~_i); 0] (the z rows of the right-hand side stay zero), the
+// substitution of one elimination needs only
+//   A = (E_PP^-1)[0:m, 0:m], G = E_FP (E_PP^-1)[:, 0:m], W_x = (E_PP^-1 E_PF)[0:m, :]
+// forward: c = A b(x~_i), b_F -= G b(x~_i); backward: x~_i = c - W_x x_F.
+// H = [A; G] and W_x live in sol; the LU, E_PF and E_FP blocks are transient.
 template <class T>
 struct ClassFactors {
-  DevBuf fac;                  // LU, W, E_FP blocks
-  DevBuf piv;                  // pivots
-  std::vector<ElimDesc> el;    // offsets relative to fac / piv
+  DevBuf sol;                  // H and W_x of every elimination
+  std::vector<ElimDesc> el;    // h / wx offsets relative to sol
   std::vector<FNode> F;
 };
 
@@ -64,19 +68,13 @@ template <class T>
 struct FactorStore : FactorStoreBase {
   std::vector<std::vector<ClassFactors<T>>> cls;   // by level, by class
   std::vector<SolveLevel<T>> sl;                   // by level
-  DevBuf top;                                      // LU of the y^(2) system
-  DevBuf toppiv;
+  DevBuf topinv;                                   // inverse of the y^(2) system
   int ntop = 0;
-  int64_t cstore = 0;                              // elements of the c_P store per rhs
-  std::vector<int64_t> coff_level;
+  DevBuf arena, pivs;                              // transient blocks of the class being eliminated
   // scratch reused across calls
   DevBuf work, d1, d2, d3, d4, d5;
   LuScratch lus;
   QrScratch qrs;
-  DevBuf sx;                                       // solve vectors
-  DevBuf sc;                                       // c_P store
-  int s_nrhs = 0;
-  std::vector<int64_t> xbase;                      // per level offset into sx
 };
 
 // --------------------------------------------------------------- fill kernels
@@ -528,7 +526,7 @@ struct Factorizer {
   // Diagnostics: smallest |pivot| of the class and non-finite values in the pool.
   void debug_class(LevelPool<T>& L, ClassFactors<T>& cf, int c) {
     std::vector<T> fac, pool;
-    P.download(fac, cf.fac.p, cf.fac.bytes / sizeof(T));
+    P.download(fac, F.arena.p, F.arena.bytes / sizeof(T));
     P.download(pool, L.pool.p, (size_t)L.size);
     double pmin = INFINITY;
     int bmin = -1;
@@ -541,6 +539,34 @@ struct Factorizer {
     for (auto x : pool) nf += std::isfinite((double)x) ? 0 : 1;
     std::fprintf(stderr, "[ifmm] level %d class %d: %zu eliminations, min |pivot| %.3e (box %d), non-finite in pool %zu\n",
                  L.l, c, cf.el.size(), pmin, bmin, nf);
+  }
+
+  // H = [A; G] and W_x of every elimination of a class (see ClassFactors):
+  // X = E_PP^-1 [I_m; 0] by the LU solve, G = E_FP X, A = X[0:m, :],
+  // W_x = W[0:m, :].
+  void solve_blocks(const std::vector<ElimDesc>& el, T* fac, int* piv, T* sol) {
+    CopyBatch<T, T> init, cp;
+    std::vector<TrsJob> xs;
+    GemmBatch gg;
+    double fl = 0;
+    for (const auto& e : el) {
+      if (e.m == 0 || e.p == 0) continue;
+      init.add(nullptr, e.p, fac + e.xi, e.p, e.p, e.m, 2, 1.0);
+      xs.push_back({fac + e.lu, piv + e.piv, fac + e.xi, e.p, e.p, e.m, e.p});
+      if (e.f > 0) {
+        gg.add(fac + e.efp, e.f, 0, fac + e.xi, e.p, 0, sol + e.h + e.m, e.m + e.f, e.f, e.m, e.p, 1.0, 0.0);
+        cp.add(fac + e.w, e.p, sol + e.wx, e.m, e.m, e.f, 0);
+      }
+      cp.add(fac + e.xi, e.p, sol + e.h, e.m + e.f, e.m, e.m, 0);
+      fl += 2.0 * e.p * (double)e.p * e.m + 2.0 * e.f * (double)e.p * e.m;
+    }
+    run_copy(P, init, F.d4);
+    P.kset(KF_TRSM, 0, 0);
+    lu_solve_blocked<T>(P, xs, F.lus);
+    P.kset(KF_SCHUR, fl, 0);
+    run_gemm<T>(P, gg, F.d5);
+    P.kset(-1);
+    run_copy(P, cp, F.d4);
   }
 
   // ----------------------------------------------------------- one level
@@ -560,7 +586,7 @@ struct Factorizer {
       std::vector<FNode>& Fs = cf.F;
       el.clear();
       Fs.clear();
-      int64_t fo = 0, po = 0, wo = 0;
+      int64_t fo = 0, po = 0, wo = 0, so = 0;
       int maxF = 0;
       std::vector<CompDesc> cs;
       for (int i : boxes) {
@@ -608,6 +634,9 @@ struct Factorizer {
         e.lu = fo; fo += ((int64_t)e.p * e.p + 1) & ~int64_t(1);
         e.w = fo; fo += ((int64_t)e.p * e.f + 1) & ~int64_t(1);
         e.efp = fo; fo += ((int64_t)e.f * e.p + 1) & ~int64_t(1);
+        e.xi = fo; fo += ((int64_t)e.p * e.m + 1) & ~int64_t(1);
+        e.h = so; so += ((int64_t)(e.m + e.f) * e.m + 1) & ~int64_t(1);
+        e.wx = so; so += ((int64_t)e.m * e.f + 1) & ~int64_t(1);
         e.piv = po; po += e.p;
         e.dlt = wo; wo += ((int64_t)e.f * e.f + 1) & ~int64_t(1);
         e.S = L.St[(size_t)i * L.c3 + offset3(lv, i, i)];
@@ -633,19 +662,24 @@ struct Factorizer {
         }
         flops_lu += 2.0 / 3.0 * e.p * (double)e.p * e.p + 2.0 * e.p * (double)e.p * e.f;
         flops_schur += 2.0 * e.f * (double)e.f * e.p;
-        factor_elems += (int64_t)e.p * e.p + 2 * (int64_t)e.p * e.f;
+        flops_other += 2.0 * e.p * (double)e.p * e.m + 2.0 * e.f * (double)e.p * e.m;
+        factor_elems += (int64_t)(e.m + e.f) * e.m + (int64_t)e.m * e.f;
         el.push_back(e);
       }
-      cf.fac.alloc(sizeof(T) * std::max<int64_t>(fo, 2), &P.mem);
-      cf.piv.alloc(sizeof(int) * std::max<int64_t>(po, 1), &P.mem);
-      if ((size_t)wo * sizeof(T) > F.work.bytes) {
-        P.sync();
+      if ((size_t)fo * sizeof(T) > F.arena.bytes || (size_t)po * sizeof(int) > F.pivs.bytes ||
+          (size_t)wo * sizeof(T) > F.work.bytes)
+        P.sync();   // kernels of the previous class may still use the buffers being replaced
+      F.arena.reserve(sizeof(T) * std::max<int64_t>(fo, 2), &P.mem);
+      F.pivs.reserve(sizeof(int) * std::max<int64_t>(po, 1), &P.mem);
+      cf.sol.alloc(sizeof(T) * std::max<int64_t>(so, 2), &P.mem);
+      if ((size_t)wo * sizeof(T) > F.work.bytes)
         F.work.alloc((size_t)wo * sizeof(T) + (size_t)wo * sizeof(T) / 4 + 64, &P.mem);
-      }
-      T* fac = cf.fac.template as<T>();
+      T* fac = F.arena.template as<T>();
+      int* piv = F.pivs.template as<int>();
+      T* sol = cf.sol.template as<T>();
       T* W = F.work.template as<T>();
       if (debug_on()) {   // so that the non-finite checks see only computed values
-        IFMM_HIP(hipMemsetAsync(cf.fac.p, 0, cf.fac.bytes, P.stream));
+        IFMM_HIP(hipMemsetAsync(F.arena.p, 0, F.arena.bytes, P.stream));
         IFMM_HIP(hipMemsetAsync(F.work.p, 0, F.work.bytes, P.stream));
       }
       const ElimDesc* del = P.put(F.d1, el);
@@ -660,8 +694,8 @@ struct Factorizer {
       GemmBatch gb;
       for (const auto& e : el) {
         if (e.p > 0) {
-          lu.push_back({fac + e.lu, cf.piv.template as<int>() + e.piv, e.p, e.p, l * 1000000 + e.box});
-          if (e.f > 0) ls.push_back({fac + e.lu, cf.piv.template as<int>() + e.piv, fac + e.w, e.p, e.p, e.f, e.p});
+          lu.push_back({fac + e.lu, piv + e.piv, e.p, e.p, l * 1000000 + e.box});
+          if (e.f > 0) ls.push_back({fac + e.lu, piv + e.piv, fac + e.w, e.p, e.p, e.f, e.p});
         }
         // Schur fill D = -E_FP W (f x f, inner p)
         gb.add(fac + e.efp, std::max(e.f, 1), 0, fac + e.w, std::max(e.p, 1), 0, W + e.dlt, std::max(e.f, 1), e.f,
@@ -680,7 +714,7 @@ struct Factorizer {
       }
       dbg_level = l;
       dbg_class = c;
-      chk(L, "gather", &cf.fac, 0);
+      chk(L, "gather", &F.arena, 0);
       double flu = 0, ftr = 0, fsc = 0, bsc = 0;
       for (const auto& e : el) {
         const double p = e.p, f = e.f;
@@ -691,14 +725,16 @@ struct Factorizer {
       }
       P.kset(KF_LU, flu, 0);
       lu_blocked<T>(P, lu, F.lus);
-      chk(L, "lu", &cf.fac, 0);
+      chk(L, "lu", &F.arena, 0);
       P.kset(KF_TRSM, ftr, 0);
       lu_solve_blocked<T>(P, ls, F.lus);
-      chk(L, "lu_solve", &cf.fac, 0);
+      chk(L, "lu_solve", &F.arena, 0);
       P.kset(KF_SCHUR, fsc, bsc);
       run_gemm<T>(P, gb, F.d5);
       P.kset(-1);
       chk(L, "schur", nullptr, wo);
+      solve_blocks(el, fac, piv, sol);
+      chk(L, "solve_blocks", &F.arena, 0);
       const LevelView v = L.view(P);
       // near fill: added to existing edges
       hipLaunchKernelGGL(k_near_scatter<T>, dim3((unsigned)el.size(), maxF * maxF), dim3(WG), 0, P.stream, del, dF,
@@ -765,20 +801,32 @@ struct Factorizer {
     for (int i = 0; i < lv.nb; ++i) off[i + 1] = off[i] + L.r[i];
     const int n = (int)off[lv.nb];
     F.ntop = n;
-    F.top.alloc(sizeof(T) * std::max<int64_t>((int64_t)n * n, 1), &P.mem);
-    F.toppiv.alloc(sizeof(int) * std::max(n, 1), &P.mem);
+    F.topinv.alloc(sizeof(T) * std::max<int64_t>((int64_t)n * n, 1), &P.mem);
     if (n == 0) return;
+    DevBuf top, toppiv;
+    top.alloc(sizeof(T) * (size_t)n * n, &P.mem);
+    toppiv.alloc(sizeof(int) * (size_t)n, &P.mem);
     DevBuf doff = up(P, off);
     hipLaunchKernelGGL(k_top_gather<T>, dim3((unsigned)(lv.nb * lv.nb)), dim3(WG), 0, P.stream, lv.nb,
                        P.ldev[2].coords.template as<int>(), P.d, L.c7, L.dr.template as<int>(), L.dcap.template as<int>(), L.dKt.template as<int64_t>(),
-                       doff.template as<int64_t>(), n, (const T*)L.P(), F.top.template as<T>());
+                       doff.template as<int64_t>(), n, (const T*)L.P(), top.template as<T>());
     IFMM_LAUNCH_CHECK();
     std::vector<LuJob> lu(1);
-    lu[0] = {F.top.template as<T>(), F.toppiv.template as<int>(), n, n, 999999999};
+    lu[0] = {top.template as<T>(), toppiv.template as<int>(), n, n, 999999999};
     P.kset(KF_LU, 2.0 / 3.0 * (double)n * n * n, 0);
     lu_blocked<T>(P, lu, F.lus);
+    // the explicit inverse turns the top substitution into one matrix-vector product
+    CopyBatch<T, T> id;
+    id.add(nullptr, n, F.topinv.template as<T>(), n, n, n, 2, 1.0);
+    run_copy(P, id, F.d4);
+    std::vector<TrsJob> inv(1);
+    inv[0] = {top.template as<T>(), toppiv.template as<int>(), F.topinv.template as<T>(), n, n, n, n};
+    P.kset(KF_TRSM, 2.0 * (double)n * n * n, 0);
+    lu_solve_blocked<T>(P, inv, F.lus);
     P.kset(-1);
+    P.sync();   // top and toppiv are released on return
     flops_lu += 2.0 / 3.0 * (double)n * n * n;
+    flops_other += 2.0 * (double)n * n * n;
     factor_elems += (int64_t)n * n;
   }
 

@@ -18,8 +18,9 @@ struct FNode {
 
 struct ElimDesc {
   int box, m, r, p, f, nF, F0, pad;
-  int64_t lu, w, efp, piv, dlt;   // factor arena (lu, w, efp), int arena (piv), workspace (dlt)
-  int64_t S, U, V;                // pool offsets of S(i,i), U_i, V_i (ld m_i)
+  int64_t lu, w, efp, xi, piv, dlt;   // class arena (lu, w, efp, xi), int arena (piv), workspace (dlt)
+  int64_t h, wx;                      // solve store: H = [A; G] ((m + f) x m), W_x (m x f)
+  int64_t S, U, V;                    // pool offsets of S(i,i), U_i, V_i (ld m_i)
 };
 
 // Level tables shared by the kernels (device pointers).

@@ -1,228 +1,382 @@
-// Substitution with the stored factors (Alg. 1, solve for y^(2) and
-// substitute back down the tree): forward over the eliminations in their
-// order, c_P = E_PP^-1 b_P and b_F -= E_FP c_P; the dense top solve; backward
-// in reverse order, x_P = c_P - W x_F. Memory bound: every factor block is
-// read once per call for all right-hand sides together.
+// Substitution with the stored factors (Alg. 1: solve for y^(2), then
+// substitute back down the tree) as batched matrix-vector products.
+//
+// Vector store V: one row per unknown of every level (x~ of level L, then the
+// x~ of each coarser level = the y of the level below, down to the y^(2) of
+// level 2), then the c rows (c = A b(x~_i) of every elimination). The nrhs
+// right-hand sides of a row are contiguous, so one pass over a factor block
+// serves all of them.
+//
+//  forward, level L..2, colour classes in order, one launch per class: a
+//    workgroup takes 256 rows of H = [A; G] of one elimination; rows of A
+//    write c, rows of G subtract from the F rows (x~ of later-coloured and y
+//    of earlier-coloured neighbours, disjoint between the eliminations of a
+//    class);
+//  top: y^(2) = T^-1 b(y^(2));
+//  backward, level 2..L, classes in reverse: x~_i = c - W_x x_F.
+// The top and backward products are split over column chunks: partial sums,
+// then a reduction in a fixed order (deterministic), two launches each.
+//
+// Memory bound: every stored factor element is read once per call. The plan
+// (task tables) is uploaded once per factorization; a call only launches.
 #pragma once
 
 #include "factor.hpp"
 
 namespace ifmm {
 
-struct SolveDesc {
-  const void* lu;
-  const int* piv;
-  const void* w;
-  const void* efp;
-  int m, r, p, f, nF, F0;
-  int64_t xoff;    // offset of x~_i in the level's vector
-  int64_t coff;    // offset of c_P in the c store, in units of nrhs
+constexpr int SV_KCH = 512;   // columns of one partial-sum chunk
+constexpr int SV_KT = 64;     // columns staged in LDS at a time
+
+struct SvNode {
+  int64_t pos;    // V row of the node's first unknown
+  int off, dim;   // rows [off, off + dim) of the elimination's F
 };
 
-struct SolveNode {
-  int type, dim, off, pad;
-  int64_t voff;    // offset in the level's x~ vector (type 0) or in the y vector (type 1)
+struct FwTask {
+  const void* H;
+  int64_t ld;
+  int m, rows;            // rows = m + f
+  int node0, nnode;
+  int64_t in_pos, c_pos;  // V rows of x~_i and of c
+  int chunk0, pad;        // first workgroup of the task in its launch
 };
 
-// c_P = [b(x~_i); 0]
-template <class T>
-__global__ void k_fwd_init(const SolveDesc* __restrict__ ds, const T* __restrict__ X, int64_t ldx, int nrhs,
-                           T* __restrict__ C) {
-  const SolveDesc d = ds[blockIdx.x];
-  T* c = C + d.coff * nrhs;
-  for (int t = threadIdx.x; t < d.p * nrhs; t += WG) {
-    const int i = t % d.p, rr = t / d.p;
-    c[t] = i < d.m ? X[d.xoff + i + (int64_t)rr * ldx] : (T)0;
+// out = c + alpha A x, A rows x cols (ld), x gathered through the nodes.
+struct BwTask {
+  const void* A;
+  int64_t ld;
+  int rows, cols;
+  int node0, nnode;
+  int64_t out_pos, c_pos;  // c_pos < 0: c = 0
+  int64_t part;            // first partial-sum row
+  int chunk0, nrc, nkc, chunk0b;
+  double alpha;
+};
+
+template <class TK>
+__device__ inline int sv_find(const TK* __restrict__ ts, int nt, int b) {
+  int lo = 0, hi = nt - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (ts[mid].chunk0 <= b) lo = mid; else hi = mid - 1;
   }
+  return lo;
 }
 
-// b_F -= E_FP c_P, one block per (elimination, node of F).
-template <class T>
-__global__ void k_fwd_update(const SolveDesc* __restrict__ ds, const SolveNode* __restrict__ ns,
-                             T* __restrict__ X, int64_t ldx, T* __restrict__ Y, int64_t ldy, int nrhs,
-                             const T* __restrict__ C) {
-  const SolveDesc d = ds[blockIdx.x];
-  if ((int)blockIdx.y >= d.nF) return;
-  const SolveNode n = ns[d.F0 + blockIdx.y];
-  const T* efp = static_cast<const T*>(d.efp);
-  const T* c = C + d.coff * nrhs;
-  T* dst = n.type == 0 ? X + n.voff : Y + n.voff;
-  const int64_t ld = n.type == 0 ? ldx : ldy;
-  for (int t = threadIdx.x; t < n.dim * nrhs; t += WG) {
-    const int i = t % n.dim, rr = t / n.dim;
-    T s = 0;
-    for (int k = 0; k < d.p; ++k) s += efp[(n.off + i) + (int64_t)k * d.f] * c[k + (int64_t)rr * d.p];
-    dst[i + (int64_t)rr * ld] -= s;
-  }
+// node of a task owning row (column) k; the nodes of a task are in increasing off
+__device__ inline int64_t sv_pos(const SvNode* __restrict__ nodes, int node0, int nnode, int k) {
+  int a = node0;
+  while (a + 1 < node0 + nnode && nodes[a + 1].off <= k) ++a;
+  return nodes[a].pos + (k - nodes[a].off);
 }
 
-// x~_i = (c_P - W x_F)[0:m]
-template <class T>
-__global__ void k_bwd(const SolveDesc* __restrict__ ds, const SolveNode* __restrict__ ns, T* __restrict__ X,
-                      int64_t ldx, const T* __restrict__ Y, int64_t ldy, int nrhs, const T* __restrict__ C) {
-  const SolveDesc d = ds[blockIdx.x];
-  const T* w = static_cast<const T*>(d.w);
-  const T* c = C + d.coff * nrhs;
-  for (int t = threadIdx.x; t < d.m * nrhs; t += WG) {
-    const int i = t % d.m, rr = t / d.m;
-    T s = c[i + (int64_t)rr * d.p];
-    for (int a = 0; a < d.nF; ++a) {
-      const SolveNode n = ns[d.F0 + a];
-      const T* src = n.type == 0 ? X + n.voff + (int64_t)rr * ldx : Y + n.voff + (int64_t)rr * ldy;
-      for (int u = 0; u < n.dim; ++u) s -= w[i + (int64_t)(n.off + u) * d.p] * src[u];
+template <class T, int NR>
+__global__ void __launch_bounds__(WG) k_sv_fwd(const FwTask* __restrict__ ts, int nt,
+                                               const SvNode* __restrict__ nodes, T* __restrict__ V, int nrhs,
+                                               int r0) {
+  __shared__ T xb[SV_KT * NR];
+  const FwTask t = ts[sv_find(ts, nt, blockIdx.x)];
+  const int i = ((int)blockIdx.x - t.chunk0) * WG + threadIdx.x;
+  const T* __restrict__ H = static_cast<const T*>(t.H);
+  T acc[NR];
+  for (int r = 0; r < NR; ++r) acc[r] = 0;
+  for (int k0 = 0; k0 < t.m; k0 += SV_KT) {
+    const int kn = min(SV_KT, t.m - k0);
+    __syncthreads();
+    for (int e = threadIdx.x; e < kn * NR; e += WG) {
+      const int k = e / NR, r = e % NR;
+      xb[e] = r0 + r < nrhs ? V[(t.in_pos + k0 + k) * nrhs + r0 + r] : (T)0;
     }
-    X[d.xoff + i + (int64_t)rr * ldx] = s;
+    __syncthreads();
+    if (i < t.rows)
+      for (int k = 0; k < kn; ++k) {
+        const T h = H[i + (int64_t)(k0 + k) * t.ld];
+        for (int r = 0; r < NR; ++r) acc[r] += h * xb[k * NR + r];
+      }
+  }
+  if (i >= t.rows) return;
+  if (i < t.m) {
+    for (int r = 0; r < NR; ++r)
+      if (r0 + r < nrhs) V[(t.c_pos + i) * nrhs + r0 + r] = acc[r];
+    return;
+  }
+  const int64_t pos = sv_pos(nodes, t.node0, t.nnode, i - t.m);
+  for (int r = 0; r < NR; ++r)
+    if (r0 + r < nrhs) V[pos * nrhs + r0 + r] -= acc[r];
+}
+
+// partial sums of rows rc*WG.. over columns kc*SV_KCH..; Part row-major with NR
+template <class T, int NR>
+__global__ void __launch_bounds__(WG) k_sv_part(const BwTask* __restrict__ ts, int nt,
+                                                const SvNode* __restrict__ nodes, const T* __restrict__ V, int nrhs,
+                                                int r0, T* __restrict__ Part) {
+  __shared__ T xb[SV_KT * NR];
+  const BwTask t = ts[sv_find(ts, nt, blockIdx.x)];
+  const int local = (int)blockIdx.x - t.chunk0;
+  const int rc = local % t.nrc, kc = local / t.nrc;
+  const int i = rc * WG + threadIdx.x;
+  const int kb = kc * SV_KCH, ke = min(t.cols, kb + SV_KCH);
+  const T* __restrict__ A = static_cast<const T*>(t.A);
+  T acc[NR];
+  for (int r = 0; r < NR; ++r) acc[r] = 0;
+  for (int k0 = kb; k0 < ke; k0 += SV_KT) {
+    const int kn = min(SV_KT, ke - k0);
+    __syncthreads();
+    for (int e = threadIdx.x; e < kn * NR; e += WG) {
+      const int k = e / NR, r = e % NR;
+      const int64_t pos = sv_pos(nodes, t.node0, t.nnode, k0 + k);
+      xb[e] = r0 + r < nrhs ? V[pos * nrhs + r0 + r] : (T)0;
+    }
+    __syncthreads();
+    if (i < t.rows)
+      for (int k = 0; k < kn; ++k) {
+        const T a = A[i + (int64_t)(k0 + k) * t.ld];
+        for (int r = 0; r < NR; ++r) acc[r] += a * xb[k * NR + r];
+      }
+  }
+  if (i < t.rows)
+    for (int r = 0; r < NR; ++r) Part[(t.part + (int64_t)kc * t.rows + i) * NR + r] = acc[r];
+}
+
+// out = c + alpha * (sum of the partial sums in chunk order)
+template <class T, int NR>
+__global__ void __launch_bounds__(WG) k_sv_reduce(const BwTask* __restrict__ ts, int nt, T* __restrict__ V, int nrhs,
+                                                  int r0, const T* __restrict__ Part) {
+  int lo = 0, hi = nt - 1;
+  const int b = blockIdx.x;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (ts[mid].chunk0b <= b) lo = mid; else hi = mid - 1;
+  }
+  const BwTask t = ts[lo];
+  const int i = (b - t.chunk0b) * WG + threadIdx.x;
+  if (i >= t.rows) return;
+  for (int r = 0; r < NR; ++r) {
+    if (r0 + r >= nrhs) break;
+    T s = 0;
+    for (int kc = 0; kc < t.nkc; ++kc) s += Part[(t.part + (int64_t)kc * t.rows + i) * NR + r];
+    const T c = t.c_pos >= 0 ? V[(t.c_pos + i) * nrhs + r0 + r] : (T)0;
+    V[(t.out_pos + i) * nrhs + r0 + r] = c + (T)t.alpha * s;
   }
 }
 
 template <class Ts, class Td>
-__global__ void k_perm_convert(const Ts* __restrict__ src, int64_t lds, const int* __restrict__ perm, int64_t n,
-                               int nrhs, Td* __restrict__ dst, int64_t ldd, int to_tree) {
+__global__ void k_sv_perm(const Ts* __restrict__ src, int64_t lds, const int* __restrict__ perm, int64_t n,
+                          int nrhs, Td* __restrict__ dst, int64_t ldd, int to_tree) {
   const int64_t e = (int64_t)blockIdx.x * WG + threadIdx.x;
   if (e >= n * nrhs) return;
-  const int64_t t = e % n;
-  const int r = (int)(e / n);
-  if (to_tree) dst[t + r * ldd] = (Td)src[(int64_t)perm[t] + r * lds];
-  else dst[(int64_t)perm[t] + r * ldd] = (Td)src[t + r * lds];
+  if (to_tree) {   // dst: V rows (row-major over right-hand sides); src: caller order, column-major
+    const int64_t t = e / nrhs;
+    const int r = (int)(e % nrhs);
+    dst[e] = (Td)src[(int64_t)perm[t] + r * lds];
+  } else {         // src: V rows; dst: caller order, column-major
+    const int64_t t = e % n;
+    const int r = (int)(e / n);
+    dst[(int64_t)perm[t] + r * ldd] = (Td)src[t * nrhs + r];
+  }
+}
+
+template <class T>
+__global__ void k_sv_zero(T* __restrict__ v, int64_t n) {
+  const int64_t e = (int64_t)blockIdx.x * WG + threadIdx.x;
+  if (e < n) v[e] = (T)0;
 }
 
 template <class T>
 struct SolvePlan {
-  // per level, per class: device descriptors
-  struct Cls {
-    DevBuf d, nodes;
-    std::vector<SolveDesc> h;
-    int n = 0, maxF = 0;
+  struct Launch {
+    int kind;                 // 0: forward, 1: partial sums + reduction
+    int ntasks, nwg, nwg2;
+    DevBuf tasks;             // FwTask or BwTask
   };
-  std::vector<std::vector<Cls>> cls;
-  std::vector<int64_t> M;        // vector size per level (level 1 = the top vector)
-  int64_t cstore = 0;
-  double factor_elems = 0;       // elements of the factors one solve reads
+  std::vector<Launch> seq;    // in execution order
+  DevBuf nodes;               // SvNode, all launches
+  int64_t rows = 0;           // V rows
+  int64_t nL = 0;             // rows of the leaf level
+  int64_t part_rows = 0;      // largest partial-sum need of one launch
+  double factor_elems = 0;    // elements of the stored factors one solve reads
+  int64_t launches = 0;
   bool built = false;
+  DevBuf V, Part;             // per-call storage (grown on demand)
 };
 
 template <class T>
 inline SolvePlan<T>& solve_plan(Problem& P, FactorStore<T>& F, SolvePlan<T>& S) {
   if (S.built) return S;
   const int L = P.L;
-  S.cls.clear();
-  S.cls.resize(L + 1);
-  S.M.assign(L + 1, 0);
-  int64_t co = 0;
+  // V row bases: level L first, then coarser levels, then the y^(2) rows, then c
+  std::vector<int64_t> base(L + 1, 0), M(L + 1, 0);
+  for (int l = L; l >= 2; --l) { M[l] = F.sl[l].M; M[l - 1] = F.sl[l].Mup; }
+  int64_t r = 0;
+  for (int l = L; l >= 1; --l) { base[l] = r; r += M[l]; }
+  int64_t cpos = r;
+  for (int l = L; l >= 2; --l)
+    for (const auto& cf : F.cls[l])
+      for (const auto& e : cf.el) cpos += e.m;
+  S.rows = cpos;
+  S.nL = M[L];
+  std::vector<SvNode> nodes;
+  std::vector<typename SolvePlan<T>::Launch> fw, bw;
+  std::vector<std::vector<BwTask>> bwt;
+  int64_t cp = r;
+  S.factor_elems = 0;
+  S.part_rows = 0;
+  auto node_list = [&](const ClassFactors<T>& cf, const ElimDesc& e, int l) {
+    const int n0 = (int)nodes.size();
+    for (int a = 0; a < e.nF; ++a) {
+      const FNode& n = cf.F[e.F0 + a];
+      SvNode s{};
+      s.pos = n.type == 0 ? base[l] + F.sl[l].xoff[n.box] : base[l - 1] + F.sl[l].yoff[n.box];
+      s.off = n.off;
+      s.dim = n.dim;
+      nodes.push_back(s);
+    }
+    return n0;
+  };
   for (int l = L; l >= 2; --l) {
-    const SolveLevel<T>& sl = F.sl[l];
-    S.M[l] = sl.M;
-    S.M[l - 1] = sl.Mup;
-    S.cls[l].resize(F.cls[l].size());
-    for (size_t c = 0; c < F.cls[l].size(); ++c) {
-      const ClassFactors<T>& cf = F.cls[l][c];
-      auto& sc = S.cls[l][c];
-      if (cf.el.empty()) continue;
-      std::vector<SolveNode> nodes;
+    for (const auto& cf : F.cls[l]) {
+      std::vector<FwTask> ft;
+      std::vector<BwTask> bt;
+      int wg = 0, wgp = 0, wgr = 0;
+      int64_t part = 0;
       for (const auto& e : cf.el) {
-        SolveDesc d{};
-        d.lu = cf.fac.template as<T>() + e.lu;
-        d.piv = cf.piv.template as<int>() + e.piv;
-        d.w = cf.fac.template as<T>() + e.w;
-        d.efp = cf.fac.template as<T>() + e.efp;
-        d.m = e.m; d.r = e.r; d.p = e.p; d.f = e.f; d.nF = e.nF;
-        d.F0 = (int)nodes.size();
-        d.xoff = sl.xoff[e.box];
-        d.coff = co;
-        co += e.p;
-        S.factor_elems += (double)e.p * e.p + 2.0 * e.p * e.f;
-        for (int a = 0; a < e.nF; ++a) {
-          const FNode& n = cf.F[e.F0 + a];
-          SolveNode sn{};
-          sn.type = n.type;
-          sn.dim = n.dim;
-          sn.off = n.off;
-          sn.voff = n.type == 0 ? sl.xoff[n.box] : sl.yoff[n.box];
-          nodes.push_back(sn);
-        }
-        sc.maxF = std::max(sc.maxF, e.nF);
-        sc.h.push_back(d);
+        if (e.m == 0) continue;
+        const int n0 = node_list(cf, e, l);
+        const T* sol = cf.sol.template as<T>();
+        FwTask f{};
+        f.H = sol + e.h;
+        f.ld = e.m + e.f;
+        f.m = e.m;
+        f.rows = e.m + e.f;
+        f.node0 = n0;
+        f.nnode = e.nF;
+        f.in_pos = base[l] + F.sl[l].xoff[e.box];
+        f.c_pos = cp;
+        f.chunk0 = wg;
+        wg += (int)ceil_div((int64_t)f.rows, WG);
+        ft.push_back(f);
+        BwTask b{};
+        b.A = sol + e.wx;
+        b.ld = e.m;
+        b.rows = e.m;
+        b.cols = e.f;
+        b.node0 = n0;
+        b.nnode = e.nF;
+        b.out_pos = f.in_pos;
+        b.c_pos = cp;
+        b.alpha = -1.0;
+        b.nrc = (int)ceil_div((int64_t)e.m, WG);
+        b.nkc = std::max(1, (int)ceil_div((int64_t)e.f, SV_KCH));
+        b.part = part;
+        part += (int64_t)b.nkc * e.m;
+        b.chunk0 = wgp;
+        wgp += b.nrc * b.nkc;
+        b.chunk0b = wgr;
+        wgr += b.nrc;
+        bt.push_back(b);
+        cp += e.m;
+        S.factor_elems += (double)(e.m + e.f) * e.m + (double)e.m * e.f;
       }
-      sc.n = (int)sc.h.size();
-      P.upload(sc.d, sc.h);
-      P.upload(sc.nodes, nodes);
+      if (ft.empty()) continue;
+      typename SolvePlan<T>::Launch a;
+      a.kind = 0; a.ntasks = (int)ft.size(); a.nwg = wg; a.nwg2 = 0;
+      P.upload(a.tasks, ft);
+      fw.push_back(std::move(a));
+      typename SolvePlan<T>::Launch b;
+      b.kind = 1; b.ntasks = (int)bt.size(); b.nwg = wgp; b.nwg2 = wgr;
+      P.upload(b.tasks, bt);
+      bw.push_back(std::move(b));
+      S.part_rows = std::max(S.part_rows, part);
     }
   }
-  S.cstore = co;
+  S.seq.clear();
+  for (auto& a : fw) S.seq.push_back(std::move(a));
+  if (F.ntop > 0) {
+    SvNode s{};
+    s.pos = base[1];
+    s.off = 0;
+    s.dim = F.ntop;
+    const int n0 = (int)nodes.size();
+    nodes.push_back(s);
+    BwTask b{};
+    b.A = F.topinv.template as<T>();
+    b.ld = F.ntop;
+    b.rows = b.cols = F.ntop;
+    b.node0 = n0;
+    b.nnode = 1;
+    b.out_pos = base[1];
+    b.c_pos = -1;
+    b.alpha = 1.0;
+    b.nrc = (int)ceil_div((int64_t)F.ntop, WG);
+    b.nkc = (int)ceil_div((int64_t)F.ntop, SV_KCH);
+    b.part = 0;
+    b.chunk0 = 0;
+    b.chunk0b = 0;
+    typename SolvePlan<T>::Launch a;
+    a.kind = 1; a.ntasks = 1; a.nwg = b.nrc * b.nkc; a.nwg2 = b.nrc;
+    std::vector<BwTask> one(1, b);
+    P.upload(a.tasks, one);
+    S.seq.push_back(std::move(a));
+    S.part_rows = std::max(S.part_rows, (int64_t)b.nkc * F.ntop);
+    S.factor_elems += (double)F.ntop * F.ntop;
+  }
+  for (auto it = bw.rbegin(); it != bw.rend(); ++it) S.seq.push_back(std::move(*it));
+  P.upload(S.nodes, nodes);
+  S.launches = 3;
+  for (const auto& a : S.seq) S.launches += a.kind == 0 ? 1 : 2;
   S.built = true;
   return S;
 }
 
-// x = IFMM^-1 b, b and x in caller order (float64), nrhs columns.
+template <class T, int NR>
+inline void solve_pass(Problem& P, SolvePlan<T>& S, T* V, int nrhs, int r0) {
+  T* Part = S.Part.template as<T>();
+  const SvNode* nodes = S.nodes.template as<SvNode>();
+  for (auto& a : S.seq) {
+    if (a.kind == 0) {
+      hipLaunchKernelGGL((k_sv_fwd<T, NR>), dim3((unsigned)a.nwg), dim3(WG), 0, P.stream,
+                         a.tasks.template as<FwTask>(), a.ntasks, nodes, V, nrhs, r0);
+    } else {
+      hipLaunchKernelGGL((k_sv_part<T, NR>), dim3((unsigned)a.nwg), dim3(WG), 0, P.stream,
+                         a.tasks.template as<BwTask>(), a.ntasks, nodes, (const T*)V, nrhs, r0, Part);
+      hipLaunchKernelGGL((k_sv_reduce<T, NR>), dim3((unsigned)a.nwg2), dim3(WG), 0, P.stream,
+                         a.tasks.template as<BwTask>(), a.ntasks, V, nrhs, r0, (const T*)Part);
+    }
+    IFMM_LAUNCH_CHECK();
+  }
+}
+
+// x = IFMM^-1 b, b and x in caller order (float64, column-major, ld), nrhs columns.
 template <class T>
 inline void solve_impl(Problem& P, FactorStore<T>& F, SolvePlan<T>& S, const double* b, double* x, int nrhs,
                        int64_t ld) {
-  const int L = P.L;
   solve_plan(P, F, S);
-  {
-    const double fe = S.factor_elems + (double)F.ntop * F.ntop;
-    P.kset(KF_SOLVE, 2.0 * fe * nrhs, fe * sizeof(T));
-  }
-  // vectors: level L..1
-  std::vector<int64_t> base(L + 1, 0);
-  int64_t tot = 0;
-  for (int l = L; l >= 1; --l) {
-    base[l] = tot;
-    tot += S.M[l] * nrhs;
-  }
-  F.sx.reserve(sizeof(T) * std::max<int64_t>(tot, 1), &P.mem);
-  F.sc.reserve(sizeof(T) * std::max<int64_t>(S.cstore * nrhs, 1), &P.mem);
-  T* X = F.sx.template as<T>();
-  T* C = F.sc.template as<T>();
-  IFMM_HIP(hipMemsetAsync(X, 0, sizeof(T) * std::max<int64_t>(tot, 1), P.stream));
-  dim3 g((unsigned)std::max<int64_t>(1, ceil_div(P.n * nrhs, WG)));
-  hipLaunchKernelGGL((k_perm_convert<double, T>), g, dim3(WG), 0, P.stream, b, ld, P.perm.template as<int>(), P.n, nrhs,
-                     X + base[L], P.n, 1);
+  const int NRmax = 16;
+  const int nr = nrhs >= NRmax ? NRmax : nrhs;
+  S.V.reserve(sizeof(T) * (size_t)std::max<int64_t>(S.rows * nrhs, 1), &P.mem);
+  S.Part.reserve(sizeof(T) * (size_t)std::max<int64_t>(S.part_rows * NRmax, 1), &P.mem);
+  T* V = S.V.template as<T>();
+  P.kset(KF_SOLVE, 2.0 * S.factor_elems * nrhs, S.factor_elems * sizeof(T));
+  P.kbegin();
+  const int64_t ne = P.n * nrhs;
+  hipLaunchKernelGGL((k_sv_perm<double, T>), dim3((unsigned)std::max<int64_t>(1, ceil_div(ne, WG))), dim3(WG), 0,
+                     P.stream, b, ld, P.perm.template as<int>(), P.n, nrhs, V, (int64_t)0, 1);
+  const int64_t nz = (S.rows - S.nL) * nrhs;
+  if (nz > 0)
+    hipLaunchKernelGGL(k_sv_zero<T>, dim3((unsigned)ceil_div(nz, WG)), dim3(WG), 0, P.stream, V + S.nL * nrhs, nz);
   IFMM_LAUNCH_CHECK();
-  DevBuf scr;
-  for (int l = L; l >= 2; --l) {
-    T* Xl = X + base[l];
-    T* Yl = X + base[l - 1];
-    for (auto& sc : S.cls[l]) {
-      if (!sc.n) continue;
-      P.kbegin();
-      hipLaunchKernelGGL(k_fwd_init<T>, dim3(sc.n), dim3(WG), 0, P.stream, sc.d.template as<SolveDesc>(), (const T*)Xl,
-                         S.M[l], nrhs, C);
-      IFMM_LAUNCH_CHECK();
-      P.kend();
-      std::vector<TrsJob> jobs;
-      for (const auto& d : sc.h)
-        if (d.p > 0) jobs.push_back({d.lu, d.piv, C + d.coff * nrhs, d.p, d.p, nrhs, d.p});
-      lu_solve_blocked<T>(P, jobs, F.lus);
-      P.kbegin();
-      hipLaunchKernelGGL(k_fwd_update<T>, dim3(sc.n, std::max(sc.maxF, 1)), dim3(WG), 0, P.stream,
-                         sc.d.template as<SolveDesc>(), sc.nodes.template as<SolveNode>(), Xl, S.M[l], Yl, S.M[l - 1], nrhs,
-                         (const T*)C);
-      IFMM_LAUNCH_CHECK();
-      P.kend();
-    }
+  for (int r0 = 0; r0 < nrhs; r0 += nr) {
+    if (nr == 1) solve_pass<T, 1>(P, S, V, nrhs, r0);
+    else if (nr == 2) solve_pass<T, 2>(P, S, V, nrhs, r0);
+    else if (nr <= 4) solve_pass<T, 4>(P, S, V, nrhs, r0);
+    else if (nr <= 8) solve_pass<T, 8>(P, S, V, nrhs, r0);
+    else solve_pass<T, 16>(P, S, V, nrhs, r0);
   }
-  if (F.ntop > 0) {
-    std::vector<TrsJob> jobs(1);
-    jobs[0] = {F.top.template as<T>(), F.toppiv.template as<int>(), X + base[1], F.ntop, F.ntop, nrhs, (int)S.M[1]};
-    lu_solve_blocked<T>(P, jobs, F.lus);
-  }
-  for (int l = 2; l <= L; ++l) {
-    T* Xl = X + base[l];
-    T* Yl = X + base[l - 1];
-    for (int c = (int)S.cls[l].size() - 1; c >= 0; --c) {
-      auto& sc = S.cls[l][c];
-      if (!sc.n) continue;
-      P.kbegin();
-      hipLaunchKernelGGL(k_bwd<T>, dim3(sc.n), dim3(WG), 0, P.stream, sc.d.template as<SolveDesc>(),
-                         sc.nodes.template as<SolveNode>(), Xl, S.M[l], (const T*)Yl, S.M[l - 1], nrhs, (const T*)C);
-      IFMM_LAUNCH_CHECK();
-      P.kend();
-    }
-  }
-  hipLaunchKernelGGL((k_perm_convert<T, double>), g, dim3(WG), 0, P.stream, (const T*)(X + base[L]), P.n,
-                     P.perm.template as<int>(), P.n, nrhs, x, ld, 0);
+  hipLaunchKernelGGL((k_sv_perm<T, double>), dim3((unsigned)std::max<int64_t>(1, ceil_div(ne, WG))), dim3(WG), 0,
+                     P.stream, (const T*)V, (int64_t)0, P.perm.template as<int>(), P.n, nrhs, x, ld, 0);
   IFMM_LAUNCH_CHECK();
+  P.kend();
   P.kset(-1);
 }
 
