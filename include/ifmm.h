@@ -101,7 +101,11 @@ typedef struct {
      0 Schur-complement GEMM, 1 pivot LU (panels, swaps, trailing GEMM),
      2 triangular solves W = E_PP^-1 E_PF, 3 Householder QR of the
      recompression matrices, 4 Jacobi SVD, 5 basis changes of the edges and
-     redirection, 6 forward/backward substitution, 7 H2 matvec, 8 other. */
+     redirection, 6 forward/backward substitution, 7 H2 matvec, 8 other.
+     Families 9-14 hold one kernel each, every launch timed on its own (the
+     kernel is not counted in the families above): 9 block-Jacobi round,
+     10 Householder QR panel, 11 truncated pivoted QR, 12 one-workgroup
+     Jacobi SVD, 13 row basis change, 14 column basis change. */
   double kfam_ms[16];
   double kfam_flops[16];      /* algorithmic flops attributed to the family */
   double kfam_bytes[16];      /* algorithmic bytes attributed to the family */

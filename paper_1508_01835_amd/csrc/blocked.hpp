@@ -442,6 +442,7 @@ inline void qr_blocked(Problem& P, const std::vector<QrJob>& jobs, QrScratch& S)
     S.w.alloc((size_t)tot * sizeof(T) * 5 / 4 + 64, &P.mem);
   }
   T* W = S.w.template as<T>();
+  double panel_total = 0;
   for (int j0 = 0; j0 < nmax; j0 += QR_NB) {
     std::vector<QrPanel> pv;
     GemmBatch g1, g2, g3;
@@ -470,10 +471,13 @@ inline void qr_blocked(Problem& P, const std::vector<QrJob>& jobs, QrScratch& S)
     }
     if (pv.empty()) break;
     const QrPanel* dp = P.put(S.pd, pv);
-    P.kbegin();
+    double fl = 0;   // Householder panel: 2 (M - j0) nb^2 - 2/3 nb^3
+    for (const auto& q : pv) fl += 2.0 * (q.M - q.j0) * (double)q.nb * q.nb - 2.0 / 3.0 * (double)q.nb * q.nb * q.nb;
+    panel_total += fl;
+    P.kone_begin(KF_QR_PANEL, fl);
     hipLaunchKernelGGL(k_qr_panel<T>, dim3((unsigned)pv.size()), dim3(WG), 0, P.stream, dp);
     IFMM_LAUNCH_CHECK();
-    P.kend();
+    P.kone_end();
     run_gemm<T>(P, g1, S.gd);
     run_gemm<T>(P, g2, S.gd);
     run_gemm<T>(P, g3, S.gd);
@@ -491,6 +495,8 @@ inline void qr_blocked(Problem& P, const std::vector<QrJob>& jobs, QrScratch& S)
     IFMM_LAUNCH_CHECK();
     P.kend();
   }
+  // the panels' share of the caller's QR flops is counted in their own family
+  if (P.kt.on && P.kcur >= 0) P.kt.flops[P.kcur] -= panel_total;
 }
 
 }  // namespace ifmm

@@ -404,13 +404,11 @@ struct Factorizer {
       }
     }
     chk(L, "comp_gather", nullptr, o);
-    double fq = 0, fs = 0, bq = 0, fp = 0;
+    double fq = 0, bq = 0;
     for (const auto& c : cs) {
       const double mj = L.m[c.box], n = c.ncols, k = c.kq;
       fq += 2.0 * (2.0 * n * mj * mj - 2.0 / 3.0 * mj * mj * mj);   // Householder R of MU^T and MV^T
       bq += 2.0 * sizeof(T) * (n * mj + k * mj);
-      fp += 2.0 * (2.0 * k * mj * mj - 2.0 / 3.0 * k * k * k);     // pivoted QR of R (untruncated count)
-      fs += 2.0 * (4.0 * mj * k * k + 8.0 * k * k * k);             // SVD (U and singular values)
     }
     P.kset(KF_QR, fq, bq);
     {
@@ -438,11 +436,11 @@ struct Factorizer {
       }
     };
     nan_report("after_qr", false);
-    P.kset(KF_QR, fp, 0);
+    P.kset(-1);
     run_qrcp<T>(P, pd, F.d4, 1e-7 * P.tau);
     chk(L, "comp_qrcp", nullptr, o);
     nan_report("after_qrcp", true);
-    P.kset(KF_SVD, fs, 0);
+    P.kset(KF_SVD, 0, 0);   // flops are attributed to the SVD kernels themselves
     run_svd<T>(P, sd, F.d4, 1e-6 * P.tau);
     P.kset(-1);
     chk(L, "comp_svd", nullptr, o);
@@ -481,13 +479,33 @@ struct Factorizer {
     hipLaunchKernelGGL(k_comp_rt<T>, dim3((unsigned)cs.size()), dim3(WG), 0, P.stream, dc, v, (const T*)L.P(), W);
     IFMM_LAUNCH_CHECK();
     chk(L, "comp_rt", nullptr, o);
+    P.kend();
+    // flops of the basis changes 2 k r cols per edge, with the new rank k
+    // bounded by the old rank r (the new ranks are still on the device)
+    double frow = 0, fcol = 0;
+    for (const auto& c : cs) {
+      const int j = c.box;
+      const double r = L.r[j];
+      for (int code = 0; code < L.c7; ++code) {
+        if (L.Kt[(size_t)j * L.c7 + code] < 0) continue;
+        const int q = L.B7[(size_t)j * L.c7 + code];
+        frow += 2.0 * r * r * L.r[q];
+        fcol += 2.0 * r * r * L.r[q];
+      }
+      if (L.l > 2) frow += 2.0 * 2.0 * r * r * L.rpar[j];
+    }
+    P.kone_begin(KF_ROW_XFORM, frow);
     hipLaunchKernelGGL(k_row_xform<T>, dim3((unsigned)cs.size(), L.c7 + 2), dim3(WG), 0, P.stream, dc, v, L.P(),
                        (const T*)W);
     IFMM_LAUNCH_CHECK();
+    P.kone_end();
     chk(L, "row_xform", nullptr, o);
+    P.kone_begin(KF_COL_XFORM, fcol);
     hipLaunchKernelGGL(k_col_xform<T>, dim3((unsigned)cs.size(), L.c7), dim3(WG), 0, P.stream, dc, v, L.P(),
                        (const T*)W);
     IFMM_LAUNCH_CHECK();
+    P.kone_end();
+    P.kbegin();
     hipLaunchKernelGGL(k_comp_commit<T>, dim3((unsigned)cs.size()), dim3(WG), 0, P.stream, dc, v, L.P(),
                        (const T*)W);
     IFMM_LAUNCH_CHECK();

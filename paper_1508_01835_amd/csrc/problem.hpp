@@ -37,21 +37,33 @@ struct FactorStoreBase {
 
 // Kernel-family timing with HIP events on the handle's stream (enabled by
 // IFMM_KTIMING=1): duration, launch count and algorithmic flops / bytes.
+// Families 0-8 group the launches of one phase; families 9-14 hold exactly
+// one kernel each, every launch timed on its own (per-launch averages).
 enum KFam {
-  KF_SCHUR = 0, KF_LU, KF_TRSM, KF_QR, KF_SVD, KF_XFORM, KF_SOLVE, KF_MATVEC, KF_OTHER, KF_COUNT
+  KF_SCHUR = 0, KF_LU, KF_TRSM, KF_QR, KF_SVD, KF_XFORM, KF_SOLVE, KF_MATVEC, KF_OTHER,
+  KF_SVD_ROUND, KF_QR_PANEL, KF_QRCP, KF_SVD_SMALL, KF_ROW_XFORM, KF_COL_XFORM, KF_COUNT
 };
 
 struct KTimer {
   bool on = false;
   struct Rec { int fam; hipEvent_t a, b; double flops, bytes; int64_t launches; };
   std::vector<Rec> open;
+  std::vector<hipEvent_t> pool;   // events of collected records, reused
   double ms[KF_COUNT] = {}, flops[KF_COUNT] = {}, bytes[KF_COUNT] = {};
   int64_t launches[KF_COUNT] = {};
+  ~KTimer() {
+    for (auto& r : open) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
+  hipEvent_t event() {
+    hipEvent_t e;
+    if (!pool.empty()) { e = pool.back(); pool.pop_back(); return e; }
+    IFMM_HIP(hipEventCreate(&e));
+    return e;
+  }
   void begin(hipStream_t s, int fam, double fl, double by, int64_t nl = 1) {
     if (!on) return;
-    Rec r{fam, nullptr, nullptr, fl, by, nl};
-    IFMM_HIP(hipEventCreate(&r.a));
-    IFMM_HIP(hipEventCreate(&r.b));
+    Rec r{fam, event(), event(), fl, by, nl};
     IFMM_HIP(hipEventRecord(r.a, s));
     open.push_back(r);
   }
@@ -69,8 +81,8 @@ struct KTimer {
         bytes[r.fam] += r.bytes;
         launches[r.fam] += r.launches;
       }
-      (void)hipEventDestroy(r.a);
-      (void)hipEventDestroy(r.b);
+      pool.push_back(r.a);
+      pool.push_back(r.b);
     }
     open.clear();
   }
@@ -90,6 +102,14 @@ struct Problem {
   }
   void kend() {
     if (kt.on && kcur >= 0) kt.end(stream);
+  }
+  // One launch timed on its own in a single-kernel family (not nested in an
+  // open kbegin / kend range).
+  void kone_begin(int fam, double fl, double by = 0) {
+    if (kt.on) kt.begin(stream, fam, fl, by);
+  }
+  void kone_end() {
+    if (kt.on) kt.end(stream);
   }
   // configuration
   int64_t n = 0;

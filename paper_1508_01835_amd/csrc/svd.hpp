@@ -423,10 +423,13 @@ inline void run_qrcp(Problem& P, const std::vector<QrcpDesc>& v, DevBuf& scratch
   for (const auto& q : v)
     if (q.n > SVD_MAXN || q.m > SVD_MAXN || q.m > q.n) fail(IFMM_ERR_INTERNAL, "QRCP shape out of range");
   const QrcpDesc* d = P.put(scratch, v);
-  P.kbegin();
+  // Householder QR flops of the untruncated factorization (m <= n): 2 n m^2 - 2/3 m^3
+  double fl = 0;
+  for (const auto& q : v) fl += 2.0 * q.n * (double)q.m * q.m - 2.0 / 3.0 * (double)q.m * q.m * q.m;
+  P.kone_begin(KF_QRCP, fl);
   hipLaunchKernelGGL(k_qrcp<T>, dim3((unsigned)v.size()), dim3(SVD_WG), 0, P.stream, d, delta);
   IFMM_LAUNCH_CHECK();
-  P.kend();
+  P.kone_end();
 }
 
 // ------------------------------------------------------------------ launcher
@@ -458,6 +461,10 @@ inline void run_svd(Problem& P, const std::vector<SvdDesc>& v, DevBuf& scratch, 
   for (const auto& s : big) bigBlocks = std::max(bigBlocks, (s.N + nb - 1) / nb);
   const double u = Prec<T>::u;
   const int max_sweeps = 60;
+  // algorithmic flops of an SVD with left vectors (LAWN 41 style): 4 M N^2 + 8 N^3
+  double fl_small = 0, fl_big = 0;
+  for (const auto& s : small) fl_small += 4.0 * s.M * (double)s.N * s.N + 8.0 * (double)s.N * s.N * s.N;
+  for (const auto& s : big) fl_big += 4.0 * s.M * (double)s.N * s.N + 8.0 * (double)s.N * s.N * s.N;
   const size_t ns = small.size();
   small.insert(small.end(), big.begin(), big.end());
   const SvdDesc* d = P.put(scratch, small);
@@ -471,12 +478,16 @@ inline void run_svd(Problem& P, const std::vector<SvdDesc>& v, DevBuf& scratch, 
     P.sync();
     t0 = std::chrono::steady_clock::now();
   }
-  P.kbegin();
-  if (ns)
+  if (ns) {
+    P.kone_begin(KF_SVD_SMALL, fl_small);
     hipLaunchKernelGGL(k_svd_small<T>, dim3((unsigned)ns), dim3(SVD_WG), lds, P.stream, d, u, max_sweeps, defl, 1,
                        sw);
-  IFMM_LAUNCH_CHECK();
+    IFMM_LAUNCH_CHECK();
+    P.kone_end();
+  }
+  P.kbegin();
   int outer = 0;
+  int64_t nrounds = 0;
   if (!big.empty()) {
     const int nbig = (int)big.size();
     const SvdDesc* db = d + ns;
@@ -489,11 +500,16 @@ inline void run_svd(Problem& P, const std::vector<SvdDesc>& v, DevBuf& scratch, 
     const size_t lds_b = (size_t)bigM * 2 * nb * sizeof(T);
     std::vector<int> hf;
     for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+      P.kend();
       for (int r = 0; r < np - 1; ++r) {
+        P.kone_begin(KF_SVD_ROUND, 0);
         hipLaunchKernelGGL(k_svd_round<T>, dim3((unsigned)(np / 2), (unsigned)nbig), dim3(SVD_WG), lds_b, P.stream,
                            db, (const int*)shs, flags, nb, r, u, defl, 1);
         IFMM_LAUNCH_CHECK();
+        P.kone_end();
+        ++nrounds;
       }
+      P.kbegin();
       hipLaunchKernelGGL(k_svd_sweep_end, dim3((unsigned)ceil_div(nbig, 256)), dim3(256), 0, P.stream, flags, nbig,
                          sweep, sw);
       IFMM_LAUNCH_CHECK();
@@ -509,6 +525,8 @@ inline void run_svd(Problem& P, const std::vector<SvdDesc>& v, DevBuf& scratch, 
     IFMM_LAUNCH_CHECK();
   }
   P.kend();
+  // the block scheme's algorithmic flops, shared evenly by its round launches
+  if (P.kt.on && nrounds > 0) P.kt.flops[KF_SVD_ROUND] += fl_big;
   if (tr) {
     P.sync();
     const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();

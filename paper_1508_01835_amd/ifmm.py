@@ -45,7 +45,11 @@ class Stats(ctypes.Structure):
                 ("kfam_ms", ctypes.c_double * 16), ("kfam_flops", ctypes.c_double * 16),
                 ("kfam_bytes", ctypes.c_double * 16), ("kfam_launches", ctypes.c_int64 * 16)]
 
-KFAMILIES = ["schur_gemm", "pivot_lu", "trsm_w", "qr", "jacobi_svd", "edge_update", "solve", "matvec", "other"]
+KFAMILIES = ["schur_gemm", "pivot_lu", "trsm_w", "qr", "jacobi_svd", "edge_update", "solve", "matvec", "other",
+             "svd_round", "qr_panel", "qrcp", "svd_small", "row_xform", "col_xform"]
+# families holding exactly one kernel (per-launch timing), with its name
+KERNEL_OF_FAMILY = {"svd_round": "k_svd_round", "qr_panel": "k_qr_panel", "qrcp": "k_qrcp",
+                    "svd_small": "k_svd_small", "row_xform": "k_row_xform", "col_xform": "k_col_xform"}
 
 
 EXPORTS = ["ifmm_default_options", "ifmm_build", "ifmm_factorize", "ifmm_solve", "ifmm_matvec",
