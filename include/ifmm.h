@@ -120,9 +120,8 @@ void ifmm_default_options(ifmm_options* opt);
 
 /*
  * ifmm_build - tree, H2 operators and the initial extended system
- * (Alg. 1, lines constructing the octree and initialising the operators;
- * Sec. 3 opening: Chebyshev interpolation followed by an SVD; Sec. 2.4:
- * sigma_0(E) and the rank rule).
+ * (Alg. 1: octree and initial operators; Sec. 3 opening: Chebyshev
+ * interpolation followed by an SVD; Sec. 2.4: sigma_0(E) and the rank rule).
  *   points      device, n x dim row-major float64; copied, not retained
  *   n           number of points (>= 1)
  *   dim         1, 2 or 3
@@ -144,6 +143,21 @@ int ifmm_build(const double* points, int64_t n, int dim, ifmm_kernel k, int dept
  * P2P_kj to K_merge). Stores the factors for any number of later solves.
  */
 int ifmm_factorize(ifmm_handle h);
+
+/*
+ * ifmm_factorize_batch - ifmm_factorize of count independent handles at once
+ * (each problem factorized as in Alg. 1 and 2). Host worker threads take the
+ * problems largest first; each problem's launches go to its own handle's
+ * stream, so problems on distinct streams overlap on the device. Results are
+ * identical to factorizing each handle alone.
+ *   hs        host array of count handles (distinct; non-NULL)
+ *   count     >= 0
+ *   nthreads  host worker threads (>= 1; capped at count)
+ *   status    host array of count, may be NULL: per-problem status code
+ * Returns IFMM_OK when every problem succeeded, else the first failing
+ * problem's code (its message is in ifmm_last_error of the calling thread).
+ */
+int ifmm_factorize_batch(ifmm_handle* hs, int count, int nthreads, int* status);
 
 /*
  * ifmm_solve - x = IFMM^-1 b for nrhs right-hand sides (Alg. 1, substitution).

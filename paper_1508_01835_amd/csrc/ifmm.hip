@@ -1,5 +1,9 @@
 // C ABI of the IFMM library (include/ifmm.h). Every entry point converts
 // failures into status codes; nothing throws across the boundary.
+#include <algorithm>
+#include <atomic>
+#include <thread>
+
 #include "gmres.hpp"
 
 using namespace ifmm;
@@ -129,8 +133,12 @@ int ifmm_build(const double* points, int64_t n, int dim, ifmm_kernel k, int dept
   return rc;
 }
 
-int ifmm_factorize(ifmm_handle h) {
-  return guarded([&] {
+}  // extern "C"
+
+namespace {
+
+void factorize_handle(ifmm_handle h) {
+  {
     if (!h) fail(IFMM_ERR_ARG, "null handle");
     Problem& P = h->P;
     P.factorized = false;
@@ -151,7 +159,58 @@ int ifmm_factorize(ifmm_handle h) {
     }
     P.st.t_factor_ms = now_ms() - t0;
     P.factorized = true;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int ifmm_factorize(ifmm_handle h) {
+  return guarded([&] { factorize_handle(h); });
+}
+
+int ifmm_factorize_batch(ifmm_handle* hs, int count, int nthreads, int* status) {
+  std::vector<int> rc;
+  int first = IFMM_OK;
+  std::string first_msg;
+  const int vrc = guarded([&] {
+    if (count < 0 || (count > 0 && !hs)) fail(IFMM_ERR_ARG, "null handle array or negative count");
+    if (nthreads < 1) fail(IFMM_ERR_ARG, "nthreads must be >= 1");
+    for (int i = 0; i < count; ++i) {
+      if (!hs[i]) fail(IFMM_ERR_ARG, "null handle in the batch");
+      for (int j = 0; j < i; ++j)
+        if (hs[j] == hs[i]) fail(IFMM_ERR_ARG, "a handle appears twice in the batch");
+    }
+    // largest problems first, so that the last ones to finish are small
+    std::vector<int> order(count);
+    for (int i = 0; i < count; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return hs[a]->P.n > hs[b]->P.n; });
+    rc.assign(count, IFMM_OK);
+    std::vector<std::string> msg(count);
+    std::atomic<int> next{0};
+    auto worker = [&] {
+      for (;;) {
+        const int t = next.fetch_add(1);
+        if (t >= count) break;
+        const int i = order[t];
+        rc[i] = guarded([&] { factorize_handle(hs[i]); });
+        if (rc[i] != IFMM_OK) msg[i] = g_last_error;
+      }
+    };
+    const int nt = std::max(1, std::min(nthreads, count));
+    std::vector<std::thread> pool;
+    for (int w = 1; w < nt; ++w) pool.emplace_back(worker);
+    worker();
+    for (auto& th : pool) th.join();
+    for (int i = 0; i < count; ++i)
+      if (rc[i] != IFMM_OK) { first = rc[i]; first_msg = msg[i]; break; }
   });
+  if (vrc != IFMM_OK) return vrc;
+  if (status)
+    for (int i = 0; i < count; ++i) status[i] = rc[i];
+  if (first != IFMM_OK) g_last_error = first_msg;
+  return first;
 }
 
 static void solve_any(Problem& P, const double* b, double* x, int nrhs, int64_t ld) {

@@ -438,14 +438,14 @@ inline void run_qrcp(Problem& P, const std::vector<QrcpDesc>& v, DevBuf& scratch
 template <class T>
 inline void run_svd(Problem& P, const std::vector<SvdDesc>& v, DevBuf& scratch, double defl = 0.0) {
   if (v.empty()) return;
-  static bool attr = false;
-  if (!attr) {
+  static const bool attr = [] {   // once per process (thread-safe initialisation)
     IFMM_HIP(hipFuncSetAttribute((const void*)k_svd_small<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                  (int)SVD_LDS_MAX));
     IFMM_HIP(hipFuncSetAttribute((const void*)k_svd_round<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                  (int)SVD_LDS_MAX));
-    attr = true;
-  }
+    return true;
+  }();
+  (void)attr;
   std::vector<SvdDesc> small, big;
   size_t lds = 0;
   int bigM = 0, bigBlocks = 0;

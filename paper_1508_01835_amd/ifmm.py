@@ -52,8 +52,8 @@ KERNEL_OF_FAMILY = {"svd_round": "k_svd_round", "qr_panel": "k_qr_panel", "qrcp"
                     "svd_small": "k_svd_small", "row_xform": "k_row_xform", "col_xform": "k_col_xform"}
 
 
-EXPORTS = ["ifmm_default_options", "ifmm_build", "ifmm_factorize", "ifmm_solve", "ifmm_matvec",
-           "ifmm_gmres", "ifmm_query", "ifmm_destroy", "ifmm_strerror", "ifmm_last_error"]
+EXPORTS = ["ifmm_default_options", "ifmm_build", "ifmm_factorize", "ifmm_factorize_batch", "ifmm_solve",
+           "ifmm_matvec", "ifmm_gmres", "ifmm_query", "ifmm_destroy", "ifmm_strerror", "ifmm_last_error"]
 
 
 def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
@@ -66,6 +66,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                ctypes.c_int, ctypes.c_double, ctypes.POINTER(Options),
                                ctypes.POINTER(ctypes.c_void_p)]
     lib.ifmm_factorize.argtypes = [ctypes.c_void_p]
+    lib.ifmm_factorize_batch.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.c_int,
+                                         ctypes.POINTER(ctypes.c_int)]
     lib.ifmm_solve.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int64]
     lib.ifmm_matvec.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int64]
     lib.ifmm_gmres.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
@@ -77,8 +79,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.ifmm_strerror.restype = ctypes.c_char_p
     lib.ifmm_last_error.argtypes = []
     lib.ifmm_last_error.restype = ctypes.c_char_p
-    for name in ["ifmm_build", "ifmm_factorize", "ifmm_solve", "ifmm_matvec", "ifmm_gmres", "ifmm_query",
-                 "ifmm_destroy"]:
+    for name in ["ifmm_build", "ifmm_factorize", "ifmm_factorize_batch", "ifmm_solve", "ifmm_matvec", "ifmm_gmres",
+                 "ifmm_query", "ifmm_destroy"]:
         getattr(lib, name).restype = ctypes.c_int
     return lib
 
@@ -136,7 +138,7 @@ class IFMM:
         opt.stream = ctypes.c_void_p(self.stream.cuda_stream)
         k = Kernel(KERNELS[kernel], float(param), float(shift))
         h = ctypes.c_void_p()
-        torch.cuda.synchronize()
+        torch.cuda.current_stream().synchronize()   # the points are ready before the handle's stream reads them
         _check(lib().ifmm_build(ctypes.c_void_p(pts.data_ptr()), self.n, self.dim, k, depth, order, float(eps),
                                 ctypes.byref(opt), ctypes.byref(h)))
         self.h = h
@@ -145,9 +147,17 @@ class IFMM:
     def factorize(self) -> None:
         _check(lib().ifmm_factorize(self.h))
 
+    def _inputs_ready(self) -> None:
+        """Inputs are written on the caller's current stream; the library reads them on the handle's."""
+        import torch
+        cur = torch.cuda.current_stream()
+        if cur.cuda_stream != self.stream.cuda_stream:
+            cur.synchronize()
+
     def solve(self, b):
         B = _colmajor(b, self.n)
         X = B.clone()
+        self._inputs_ready()
         _check(lib().ifmm_solve(self.h, ctypes.c_void_p(B.data_ptr()), ctypes.c_void_p(X.data_ptr()),
                                 B.shape[0], self.n))
         out = X.t()
@@ -156,6 +166,7 @@ class IFMM:
     def matvec(self, x):
         Xc = _colmajor(x, self.n)
         Y = Xc.new_empty(Xc.shape)
+        self._inputs_ready()
         _check(lib().ifmm_matvec(self.h, ctypes.c_void_p(Xc.data_ptr()), ctypes.c_void_p(Y.data_ptr()),
                                  Xc.shape[0], self.n))
         out = Y.t()
@@ -167,6 +178,7 @@ class IFMM:
         it = ctypes.c_int()
         rr = ctypes.c_double()
         p = prec.h if prec is not None else self.h
+        self._inputs_ready()
         _check(lib().ifmm_gmres(self.h, p, ctypes.c_void_p(B.data_ptr()), ctypes.c_void_p(X.data_ptr()),
                                 B.shape[0], self.n, float(tol), int(maxit), ctypes.byref(it), ctypes.byref(rr)))
         out = X.t()
@@ -197,3 +209,16 @@ class IFMM:
             self.close()
         except Exception:
             pass
+
+
+def factorize_batch(handles, nthreads: int = 8) -> list:
+    """Factorize independent handles concurrently (ifmm_factorize_batch); per-problem status codes.
+
+    Give each handle its own stream (IFMM(..., stream=torch.cuda.Stream())) so that the problems overlap on
+    the device. Raises IFMMError if any problem failed."""
+    n = len(handles)
+    arr = (ctypes.c_void_p * max(n, 1))(*[h.h for h in handles])
+    st = (ctypes.c_int * max(n, 1))()
+    rc = lib().ifmm_factorize_batch(arr, n, int(nthreads), st)
+    _check(rc)
+    return [st[i] for i in range(n)]
