@@ -129,6 +129,33 @@ def run_batch(args):
     print(json.dumps(out))
 
 
+def run_serve(args):
+    """Serving loop: Poisson arrivals, 25% factorize (+ one solve) with N log-uniform in [4096, 32768]
+    (uniform cube or 8 Gaussian clusters, half each), 75% solves of 1..64 right-hand sides on a resident
+    factor; IMQ c = 0.01 + 1.0 I, Chebyshev order 3, eps 1e-5, FP32 factors, FP64 GMRES to 1e-10."""
+    import torch
+
+    from paper_1508_01835_amd.serve import Server, synthetic_requests
+
+    warm = synthetic_requests(3, rate=100.0, n_lo=2048, n_hi=2048, seed=5000)
+    Server(hbm_budget_bytes=args.serve_budget).run(warm)
+    torch.cuda.synchronize()
+    reqs = synthetic_requests(args.serve_count, rate=args.rate, n_lo=4096, n_hi=32768, seed=5001)
+    res = Server(hbm_budget_bytes=args.serve_budget).run(reqs)
+    out = {
+        "metric": "IFMM serving p99 request latency (continuous batching, FP32 factors + FP64 GMRES 1e-10)",
+        "value": res["p99_ms"], "unit": "ms", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": res["wall_s"] * 1e3, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": "serve%d: Poisson %.1f req/s, 25%% factorize N log-uniform [4096, 32768] "
+                               "(cube / 8 clusters), 75%% solve nrhs 1..64, IMQ c=0.01 + 1.0 I, order 3, "
+                               "eps 1e-5" % (args.serve_count, args.rate),
+                   "hbm_budget_bytes": args.serve_budget},
+        "serve": res,
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -137,7 +164,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n", type=int, default=65536)
     ap.add_argument("--depth", type=int, default=5)
-    ap.add_argument("--workload", choices=["uniform3d", "batch"], default="uniform3d")
+    ap.add_argument("--workload", choices=["uniform3d", "batch", "serve"], default="uniform3d")
+    ap.add_argument("--serve-count", type=int, default=200)
+    ap.add_argument("--rate", type=float, default=1.0)
+    ap.add_argument("--serve-budget", type=int, default=64 << 30)
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--threads", type=int, default=8)
     args = ap.parse_args()
@@ -146,6 +176,9 @@ def main():
         sys.exit(2)
     if args.workload == "batch":
         run_batch(args)
+        return
+    if args.workload == "serve":
+        run_serve(args)
         return
 
     import numpy as np

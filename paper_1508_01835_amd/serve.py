@@ -1,0 +1,240 @@
+"""Serving loop on one GPU: resident IFMM factors, continuous batching of solves.
+
+Two request kinds:
+  * factorize: points (+ one right-hand side): build a handle with FP32
+    factors, factorize it, keep it resident, then solve its right-hand side;
+  * solve: right-hand sides for a resident factor: FP64 GMRES to the
+    tolerance, preconditioned by the FP32 factors (Sec. 3.2 of the paper:
+    the IFMM as a preconditioner).
+
+Scheduling (host side; every step of a request runs in the HIP library):
+  * admission: a factorization starts only when the device bytes of the
+    resident factors plus its estimate fit the budget; least-recently-used
+    factors with no pending work are evicted to make room;
+  * factorizations run one at a time on a worker thread, each on its own
+    stream, overlapping the solves;
+  * continuous batching: when the solve lane is free it takes the factor of
+    the oldest pending solve and runs all pending solves of that factor as one
+    multi-column GMRES call. Columns are independent GMRES runs, so a request
+    gets the same result alone or in a mix;
+  * latency = completion - arrival, per request.
+"""
+from __future__ import annotations
+
+import threading
+import time
+from collections import OrderedDict
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from .ifmm import IFMM
+
+
+@dataclass
+class Request:
+    rid: int
+    arrival: float                       # seconds from the start of the run
+    kind: str                            # "factorize" or "solve"
+    points: np.ndarray | None = None     # factorize: n x 3
+    cluster: bool = False
+    nrhs: int = 1                        # solve: right-hand sides
+    seed: int = 0
+    # filled in by the server
+    factor: int = -1
+    t_done: float = -1.0
+    iters: int = 0
+    relres: float = 0.0
+    x: np.ndarray | None = None
+
+
+@dataclass
+class _Factor:
+    fid: int
+    handle: IFMM
+    n: int
+    bytes: int
+    last_use: float
+    pending: list = field(default_factory=list)
+
+
+class Server:
+    def __init__(self, hbm_budget_bytes: int, kernel=("imq", 0.01, 1.0), order: int = 3, eps: float = 1e-5,
+                 leaf_max: int = 64, tol: float = 1e-10, maxit: int = 200, keep_results: bool = False):
+        import torch
+        self.torch = torch
+        self.budget = int(hbm_budget_bytes)
+        self.kernel, self.order, self.eps, self.leaf_max = kernel, order, eps, leaf_max
+        self.tol, self.maxit, self.keep = tol, maxit, keep_results
+        self.factors: "OrderedDict[int, _Factor]" = OrderedDict()
+        self.bytes_per_point = 4.0e4      # first estimate; replaced by what factorizations use
+        self.solve_stream = torch.cuda.Stream()
+        self.stats = {"factorized_points": 0, "factor_busy_s": 0.0, "solve_busy_s": 0.0, "evicted": 0,
+                      "gmres_calls": 0, "rhs": 0}
+
+    # ------------------------------------------------------------ factors
+    def _resident_bytes(self) -> int:
+        return sum(f.bytes for f in self.factors.values())
+
+    def _make_room(self, need: int, busy: set) -> bool:
+        while self._resident_bytes() + need > self.budget:
+            victims = [f for f in self.factors.values() if not f.pending and f.fid not in busy]
+            if not victims:
+                return False
+            v = min(victims, key=lambda f: f.last_use)
+            v.handle.close()
+            del self.factors[v.fid]
+            self.stats["evicted"] += 1
+        return True
+
+    def _factorize(self, req: Request, stream, out: dict) -> None:
+        torch = self.torch
+        t0 = time.perf_counter()
+        try:
+            with torch.cuda.stream(stream):
+                pts = torch.tensor(req.points, device="cuda")
+                k, c, s = self.kernel
+                h = IFMM(pts, k, c, s, 0, self.order, self.eps, precision=32, leaf_max=self.leaf_max,
+                         stream=stream)
+                h.factorize()
+            out["handle"] = h
+        except Exception as e:   # reported with the request
+            out["error"] = e
+        out["seconds"] = time.perf_counter() - t0
+
+    # ------------------------------------------------------------ solves
+    def _solve_batch(self, f: _Factor, reqs: list, now) -> None:
+        torch = self.torch
+        cols = [np.random.default_rng(r.seed).standard_normal((f.n, r.nrhs)) for r in reqs]
+        B = torch.tensor(np.concatenate(cols, axis=1), device="cuda")
+        t0 = time.perf_counter()
+        with torch.cuda.stream(f.handle.stream):
+            X, it, rr = f.handle.gmres(B, tol=self.tol, maxit=self.maxit)
+        self.stats["solve_busy_s"] += time.perf_counter() - t0
+        self.stats["gmres_calls"] += 1
+        self.stats["rhs"] += B.shape[1]
+        t_done = now()
+        Xh = X.cpu().numpy() if self.keep else None
+        c0 = 0
+        for r in reqs:
+            r.t_done, r.iters, r.relres = t_done, it, rr
+            if Xh is not None:
+                r.x = Xh[:, c0:c0 + r.nrhs].copy()
+            c0 += r.nrhs
+        f.last_use = t_done
+
+    # ------------------------------------------------------------ loop
+    def run(self, requests: list) -> dict:
+        requests = sorted(requests, key=lambda r: r.arrival)
+        t_start = time.perf_counter()
+
+        def now():
+            return time.perf_counter() - t_start
+
+        rng = np.random.default_rng(5001)
+        arrived = 0
+        fq: list = []                 # factorize requests waiting for admission
+        orphans: list = []            # solve requests that arrived with no resident factor
+        worker = None                 # (thread, request, out, stream)
+        done = 0
+        total = len(requests)
+        while done < total:
+            t = now()
+            while arrived < total and requests[arrived].arrival <= t:
+                r = requests[arrived]
+                arrived += 1
+                if r.kind == "factorize":
+                    fq.append(r)
+                else:
+                    orphans.append(r)
+            # solve requests pick a resident factor (uniformly) when one exists
+            if orphans and self.factors:
+                ids = list(self.factors.keys())
+                for r in orphans:
+                    r.factor = ids[int(rng.integers(len(ids)))]
+                    self.factors[r.factor].pending.append(r)
+                orphans = []
+            # finished factorization: make it resident, queue its own solve
+            if worker is not None and not worker[0].is_alive():
+                th, r, out, stream = worker
+                worker = None
+                self.stats["factor_busy_s"] += out["seconds"]
+                if "error" in out:
+                    r.t_done, r.relres = now(), float("nan")
+                    done += 1
+                else:
+                    h = out["handle"]
+                    st = h.stats()
+                    f = _Factor(r.rid, h, h.n, int(st["device_bytes"]), now())
+                    self.bytes_per_point = max(self.bytes_per_point * 0.5, 1.2 * f.bytes / f.n)
+                    self.factors[r.rid] = f
+                    self.stats["factorized_points"] += f.n
+                    r.factor = r.rid
+                    f.pending.append(r)
+            # start the next admitted factorization
+            if worker is None and fq:
+                r = fq[0]
+                need = int(self.bytes_per_point * r.points.shape[0])
+                if self._make_room(need, set()) or not self.factors:
+                    fq.pop(0)
+                    out: dict = {}
+                    stream = self.torch.cuda.Stream()
+                    th = threading.Thread(target=self._factorize, args=(r, stream, out))
+                    th.start()
+                    worker = (th, r, out, stream)
+            # solve lane: the factor of the oldest pending solve, all its pending solves at once
+            pend = [f for f in self.factors.values() if f.pending]
+            if pend:
+                f = min(pend, key=lambda f: min(q.arrival for q in f.pending))
+                reqs, f.pending = f.pending, []
+                self._solve_batch(f, reqs, now)
+                done += len(reqs)
+                continue
+            if worker is None and not fq and arrived < total:
+                time.sleep(max(0.0, min(0.002, requests[arrived].arrival - now())))
+            elif worker is not None:
+                worker[0].join(timeout=0.002)
+        wall = now()
+        for f in self.factors.values():
+            f.handle.close()
+        self.factors.clear()
+        lat = np.array([r.t_done - r.arrival for r in requests])
+        fl = np.array([r.t_done - r.arrival for r in requests if r.kind == "factorize"])
+        sl = np.array([r.t_done - r.arrival for r in requests if r.kind == "solve"])
+        res = {
+            "requests": total, "wall_s": wall, "req_per_s": total / wall,
+            "rhs_per_s": self.stats["rhs"] / wall,
+            "factorized_mpts_per_s": self.stats["factorized_points"] / max(self.stats["factor_busy_s"], 1e-9) / 1e6,
+            "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+            "factorize_p50_ms": float(np.percentile(fl, 50) * 1e3) if fl.size else None,
+            "solve_p50_ms": float(np.percentile(sl, 50) * 1e3) if sl.size else None,
+            "solve_p99_ms": float(np.percentile(sl, 99) * 1e3) if sl.size else None,
+            "max_relres": float(max(r.relres for r in requests)),
+            "max_iters": int(max(r.iters for r in requests)),
+        }
+        res.update(self.stats)
+        return res
+
+
+def synthetic_requests(count: int, rate: float, n_lo: int, n_hi: int, seed: int = 5001,
+                       factorize_frac: float = 0.25, nrhs_max: int = 64) -> list:
+    """Poisson arrivals; a fraction of factorize requests (N log-uniform in [n_lo, n_hi], uniform cube or 8
+    Gaussian clusters of width 0.05, half each), the rest solve requests with nrhs uniform in 1..nrhs_max.
+    The first request is a factorization so that solves have a factor to go to."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for k in range(count):
+        t += float(rng.exponential(1.0 / rate))
+        if k == 0 or rng.random() < factorize_frac:
+            n = int(round(np.exp(rng.uniform(np.log(n_lo), np.log(n_hi)))))
+            cl = bool(rng.random() < 0.5)
+            if cl:
+                cen = rng.random((8, 3))
+                pts = cen[rng.integers(0, 8, n)] + 0.05 * rng.standard_normal((n, 3))
+            else:
+                pts = rng.random((n, 3))
+            out.append(Request(k, t, "factorize", points=pts, cluster=cl, nrhs=1, seed=seed * 1000 + k))
+        else:
+            out.append(Request(k, t, "solve", nrhs=int(rng.integers(1, nrhs_max + 1)), seed=seed * 1000 + k))
+    return out
