@@ -259,7 +259,12 @@ def main():
         t = time.perf_counter()
         g, it2, rr2 = step(prec, eps)
         torch.cuda.synchronize()
-        ttr["fp%d" % prec] = {"seconds": time.perf_counter() - t, "iters": it2, "relres": rr2, "eps": eps}
+        sec = time.perf_counter() - t
+        sg = g.stats()
+        ttr["fp%d" % prec] = {"seconds": sec, "iters": it2, "relres": rr2, "eps": eps,
+                              "build_ms": sg["t_build_ms"], "factor_ms": sg["t_factor_ms"],
+                              "kernel_ms": {FAMILIES[f]: round(sg["kfam_ms"][f], 1) for f in range(len(FAMILIES))
+                                            if sg["kfam_ms"][f] > 0}}
         g.close()
 
     out = {

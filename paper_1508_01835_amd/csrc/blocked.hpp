@@ -300,6 +300,7 @@ inline void lu_solve_blocked(Problem& P, const std::vector<TrsJob>& jobs, LuScra
 // Only R is produced (the recompression needs the left singular vectors of
 // R^T, not Q).
 constexpr int QR_NB = 32;
+constexpr int QR_WG = 1024;   // threads of the panel kernel (16 wavefronts)
 
 struct QrPanel {
   void* A;
@@ -310,7 +311,7 @@ struct QrPanel {
 };
 
 template <class T>
-__global__ void __launch_bounds__(WG) k_qr_panel(const QrPanel* __restrict__ ds) {
+__global__ void __launch_bounds__(QR_WG) k_qr_panel(const QrPanel* __restrict__ ds) {
   const QrPanel d = ds[blockIdx.x];
   T* __restrict__ A = static_cast<T*>(d.A);
   T* __restrict__ V = static_cast<T*>(d.V);
@@ -320,13 +321,13 @@ __global__ void __launch_bounds__(WG) k_qr_panel(const QrPanel* __restrict__ ds)
   const int64_t lda = d.lda;
   const int mv = M - j0;
   __shared__ T tau[QR_NB];
-  __shared__ T red[WG / WAVE];
+  __shared__ T red[QR_WG / WAVE];
   __shared__ T G[QR_NB * QR_NB];
-  const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE, nw = WG / WAVE;
+  const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE, nw = QR_WG / WAVE;
   for (int jj = 0; jj < nb; ++jj) {
     const int j = j0 + jj;
     T amax = 0;
-    for (int i = j + threadIdx.x; i < M; i += WG) amax = fmax(amax, fabs(A[i + j * lda]));
+    for (int i = j + threadIdx.x; i < M; i += QR_WG) amax = fmax(amax, fabs(A[i + j * lda]));
     amax = block_max(amax, red);
     const T x0 = A[j + j * lda];
     T tj = 0, al = x0;
@@ -335,14 +336,14 @@ __global__ void __launch_bounds__(WG) k_qr_panel(const QrPanel* __restrict__ ds)
       // amax would overflow
       const int sh = -ilogb((double)amax);
       T s = 0;
-      for (int i = j + threadIdx.x; i < M; i += WG) { const T x = ldexp(A[i + j * lda], sh); s += x * x; }
+      for (int i = j + threadIdx.x; i < M; i += QR_WG) { const T x = ldexp(A[i + j * lda], sh); s += x * x; }
       s = block_sum(s, red);
       const T x0s = ldexp(x0, sh);
       const T als = x0s >= (T)0 ? -sqrt(s) : sqrt(s);
       al = ldexp(als, -sh);
       tj = (als - x0s) / als;
       const T scal = (T)1 / (x0s - als);
-      for (int i = j + 1 + threadIdx.x; i < M; i += WG) A[i + j * lda] = ldexp(A[i + j * lda], sh) * scal;
+      for (int i = j + 1 + threadIdx.x; i < M; i += QR_WG) A[i + j * lda] = ldexp(A[i + j * lda], sh) * scal;
       __syncthreads();
       if (threadIdx.x == 0) A[j + j * lda] = (T)1;
     }
@@ -359,7 +360,7 @@ __global__ void __launch_bounds__(WG) k_qr_panel(const QrPanel* __restrict__ ds)
     __syncthreads();
   }
   // V with explicit unit diagonal and zeros above it
-  for (int64_t e = threadIdx.x; e < (int64_t)mv * nb; e += WG) {
+  for (int64_t e = threadIdx.x; e < (int64_t)mv * nb; e += QR_WG) {
     const int i = (int)(e % mv), c = (int)(e / mv);
     T v = 0;
     if (i == c) v = tau[c] != (T)0 ? (T)1 : (T)0;
@@ -475,7 +476,7 @@ inline void qr_blocked(Problem& P, const std::vector<QrJob>& jobs, QrScratch& S)
     for (const auto& q : pv) fl += 2.0 * (q.M - q.j0) * (double)q.nb * q.nb - 2.0 / 3.0 * (double)q.nb * q.nb * q.nb;
     panel_total += fl;
     P.kone_begin(KF_QR_PANEL, fl);
-    hipLaunchKernelGGL(k_qr_panel<T>, dim3((unsigned)pv.size()), dim3(WG), 0, P.stream, dp);
+    hipLaunchKernelGGL(k_qr_panel<T>, dim3((unsigned)pv.size()), dim3(QR_WG), 0, P.stream, dp);
     IFMM_LAUNCH_CHECK();
     P.kone_end();
     run_gemm<T>(P, g1, S.gd);

@@ -480,31 +480,51 @@ struct Factorizer {
     IFMM_LAUNCH_CHECK();
     chk(L, "comp_rt", nullptr, o);
     P.kend();
-    // flops of the basis changes 2 k r cols per edge, with the new rank k
-    // bounded by the old rank r (the new ranks are still on the device)
+    // one task per existing edge (the host holds the edge tables); flops of the
+    // basis changes 2 k r cols per edge, with the new rank k bounded by the old
+    // rank r (the new ranks are still on the device)
+    std::vector<int2> tasks;
+    size_t nrow = 0;
     double frow = 0, fcol = 0;
-    for (const auto& c : cs) {
-      const int j = c.box;
-      const double r = L.r[j];
-      for (int code = 0; code < L.c7; ++code) {
-        if (L.Kt[(size_t)j * L.c7 + code] < 0) continue;
-        const int q = L.B7[(size_t)j * L.c7 + code];
-        frow += 2.0 * r * r * L.r[q];
-        fcol += 2.0 * r * r * L.r[q];
+    for (int pass = 0; pass < 2; ++pass) {
+      for (size_t ci = 0; ci < cs.size(); ++ci) {
+        const int j = cs[ci].box;
+        const double r = L.r[j];
+        for (int code = 0; code < L.c7; ++code) {
+          const int q = L.B7[(size_t)j * L.c7 + code];
+          if (q < 0) continue;
+          if (pass == 0 && L.Kt[(size_t)j * L.c7 + code] >= 0) {
+            tasks.push_back(make_int2((int)ci, code));
+            frow += 2.0 * r * r * L.r[q];
+          }
+          if (pass == 1 && L.Kt[(size_t)q * L.c7 + (L.c7 - 1 - code)] >= 0) {
+            tasks.push_back(make_int2((int)ci, code));
+            fcol += 2.0 * r * r * L.r[q];
+          }
+        }
+        if (pass == 0 && L.l > 2) {
+          tasks.push_back(make_int2((int)ci, L.c7));
+          tasks.push_back(make_int2((int)ci, L.c7 + 1));
+          frow += 2.0 * 2.0 * r * r * L.rpar[j];
+        }
       }
-      if (L.l > 2) frow += 2.0 * 2.0 * r * r * L.rpar[j];
+      if (pass == 0) nrow = tasks.size();
     }
-    P.kone_begin(KF_ROW_XFORM, frow);
-    hipLaunchKernelGGL(k_row_xform<T>, dim3((unsigned)cs.size(), L.c7 + 2), dim3(WG), 0, P.stream, dc, v, L.P(),
-                       (const T*)W);
-    IFMM_LAUNCH_CHECK();
-    P.kone_end();
+    const int2* dt = P.put(F.d5, tasks);
+    if (nrow > 0) {
+      P.kone_begin(KF_ROW_XFORM, frow);
+      hipLaunchKernelGGL(k_row_xform<T>, dim3((unsigned)nrow), dim3(WG), 0, P.stream, dc, dt, v, L.P(), (const T*)W);
+      IFMM_LAUNCH_CHECK();
+      P.kone_end();
+    }
     chk(L, "row_xform", nullptr, o);
-    P.kone_begin(KF_COL_XFORM, fcol);
-    hipLaunchKernelGGL(k_col_xform<T>, dim3((unsigned)cs.size(), L.c7), dim3(WG), 0, P.stream, dc, v, L.P(),
-                       (const T*)W);
-    IFMM_LAUNCH_CHECK();
-    P.kone_end();
+    if (tasks.size() > nrow) {
+      P.kone_begin(KF_COL_XFORM, fcol);
+      hipLaunchKernelGGL(k_col_xform<T>, dim3((unsigned)(tasks.size() - nrow)), dim3(WG), 0, P.stream, dc,
+                         dt + nrow, v, L.P(), (const T*)W);
+      IFMM_LAUNCH_CHECK();
+      P.kone_end();
+    }
     P.kbegin();
     hipLaunchKernelGGL(k_comp_commit<T>, dim3((unsigned)cs.size()), dim3(WG), 0, P.stream, dc, v, L.P(),
                        (const T*)W);

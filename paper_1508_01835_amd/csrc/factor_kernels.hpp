@@ -312,18 +312,23 @@ __global__ void __launch_bounds__(WG) k_comp_rt(const CompDesc* __restrict__ cs,
   }
 }
 
-constexpr int XF_CHUNK = 8;    // columns (rows) of an edge transformed at a time
+constexpr int XF_CHUNK = 32;        // columns (rows) of an edge transformed at a time, at most
+constexpr int XF_LDS = 32 * 1024;   // bytes of LDS for the staged edge slice
 
 // Row transform of every y-y edge of an affected box j and of its transfers:
 // K(j, q) <- r_j K(j, q), PU(j) <- r_j PU(j), PV(j) <- t_j PV(j)
 // (eqs. K_jq_update, U_parent_j_update, V_parent_j_update).
-// blockIdx.x: affected box; blockIdx.y: offset code (c7 = PU, c7 + 1 = PV).
+// One workgroup per existing edge: tasks[t] = (recompression, offset code),
+// code c7 = PU, c7 + 1 = PV.
+// A slice of up to XF_CHUNK columns of the edge is staged in LDS; each thread
+// computes one output row of the slice, reading its row of the transform once.
 template <class T>
-__global__ void __launch_bounds__(WG) k_row_xform(const CompDesc* __restrict__ cs, LevelView lv, T* __restrict__ pool,
-                                                  const T* __restrict__ work) {
-  const CompDesc c = cs[blockIdx.x];
+__global__ void __launch_bounds__(WG) k_row_xform(const CompDesc* __restrict__ cs, const int2* __restrict__ tasks,
+                                                  LevelView lv, T* __restrict__ pool, const T* __restrict__ work) {
+  const int2 tk = tasks[blockIdx.x];
+  const CompDesc c = cs[tk.x];
   const int j = c.box;
-  const int code = blockIdx.y;
+  const int code = tk.y;
   int64_t off;
   int cols;
   const T* X;
@@ -339,32 +344,49 @@ __global__ void __launch_bounds__(WG) k_row_xform(const CompDesc* __restrict__ c
     X = work + (code == lv.c7 ? c.tr : c.tt);
   }
   const int r = lv.r[j], k = lv.rnew[j], cap = lv.cap[j];
-  __shared__ T sh[XF_CHUNK * 1024];   // rank <= 1024
+  if (r == 0 || cols == 0) {
+    for (int t = threadIdx.x; t < k * cols; t += WG) pool[off + t % k + (int64_t)(t / k) * cap] = (T)0;
+    return;
+  }
+  __shared__ T sh[XF_LDS / sizeof(T)];
+  const int wmax = min(XF_CHUNK, (int)(XF_LDS / sizeof(T)) / r);   // r <= 1024: at least 8 columns (FP64)
   T* E = pool + off;
-  for (int c0 = 0; c0 < cols; c0 += XF_CHUNK) {
-    const int nc = (cols - c0) < XF_CHUNK ? (cols - c0) : XF_CHUNK;
+  for (int c0 = 0; c0 < cols; c0 += wmax) {
+    const int nc = min(wmax, cols - c0);
     for (int t = threadIdx.x; t < r * nc; t += WG) {
       const int i = t % r, cc = t / r;
       sh[i + cc * r] = E[i + (int64_t)(c0 + cc) * cap];
     }
     __syncthreads();
-    for (int t = threadIdx.x; t < k * nc; t += WG) {
-      const int i = t % k, cc = t / k;
-      T s = 0;
-      for (int b = 0; b < r; ++b) s += X[i + (int64_t)b * cap] * sh[b + cc * r];
-      E[i + (int64_t)(c0 + cc) * cap] = s;
+    for (int i = threadIdx.x; i < k; i += WG) {
+      T acc[XF_CHUNK];
+#pragma unroll
+      for (int cc = 0; cc < XF_CHUNK; ++cc) acc[cc] = 0;
+      for (int b = 0; b < r; ++b) {
+        const T x = X[i + (int64_t)b * cap];
+#pragma unroll
+        for (int cc = 0; cc < XF_CHUNK; ++cc)
+          if (cc < nc) acc[cc] += x * sh[b + cc * r];
+      }
+#pragma unroll
+      for (int cc = 0; cc < XF_CHUNK; ++cc)
+        if (cc < nc) E[i + (int64_t)(c0 + cc) * cap] = acc[cc];
     }
     __syncthreads();
   }
 }
 
 // Column transform: K(q, j) <- K(q, j) t_j^T for every edge into y_j (eq. K_qj_update).
+// One workgroup per existing edge: tasks[t] = (recompression, offset code of q from j).
+// A slice of up to XF_CHUNK rows of the edge is staged in LDS; each thread
+// computes one output column of the slice, reading its row of t_j once.
 template <class T>
-__global__ void __launch_bounds__(WG) k_col_xform(const CompDesc* __restrict__ cs, LevelView lv, T* __restrict__ pool,
-                                                  const T* __restrict__ work) {
-  const CompDesc c = cs[blockIdx.x];
+__global__ void __launch_bounds__(WG) k_col_xform(const CompDesc* __restrict__ cs, const int2* __restrict__ tasks,
+                                                  LevelView lv, T* __restrict__ pool, const T* __restrict__ work) {
+  const int2 tk = tasks[blockIdx.x];
+  const CompDesc c = cs[tk.x];
   const int j = c.box;
-  const int code = blockIdx.y;
+  const int code = tk.y;
   const int qb = lv.B7[(int64_t)j * lv.c7 + code];
   if (qb < 0) return;
   const int back = lv.c7 - 1 - code;   // offset of j seen from q
@@ -373,20 +395,33 @@ __global__ void __launch_bounds__(WG) k_col_xform(const CompDesc* __restrict__ c
   const int rows = lv.rnew[qb], r = lv.r[j], k = lv.rnew[j];
   const int ldq = lv.cap[qb], capj = lv.cap[j];
   const T* X = work + c.tt;
-  __shared__ T sh[XF_CHUNK * 1024];   // rank <= 1024
   T* E = pool + off;
-  for (int r0 = 0; r0 < rows; r0 += XF_CHUNK) {
-    const int nr = (rows - r0) < XF_CHUNK ? (rows - r0) : XF_CHUNK;
+  if (r == 0 || rows == 0) {
+    for (int t = threadIdx.x; t < rows * k; t += WG) E[t % rows + (int64_t)(t / rows) * ldq] = (T)0;
+    return;
+  }
+  __shared__ T sh[XF_LDS / sizeof(T)];
+  const int hmax = min(XF_CHUNK, (int)(XF_LDS / sizeof(T)) / r);
+  for (int r0 = 0; r0 < rows; r0 += hmax) {
+    const int nr = min(hmax, rows - r0);
     for (int t = threadIdx.x; t < nr * r; t += WG) {
       const int i = t % nr, b = t / nr;
-      sh[i + b * XF_CHUNK] = E[(r0 + i) + (int64_t)b * ldq];
+      sh[i + b * hmax] = E[(r0 + i) + (int64_t)b * ldq];
     }
     __syncthreads();
-    for (int t = threadIdx.x; t < nr * k; t += WG) {
-      const int i = t % nr, a = t / nr;
-      T s = 0;
-      for (int b = 0; b < r; ++b) s += sh[i + b * XF_CHUNK] * X[a + (int64_t)b * capj];
-      E[(r0 + i) + (int64_t)a * ldq] = s;
+    for (int a = threadIdx.x; a < k; a += WG) {
+      T acc[XF_CHUNK];
+#pragma unroll
+      for (int ii = 0; ii < XF_CHUNK; ++ii) acc[ii] = 0;
+      for (int b = 0; b < r; ++b) {
+        const T x = X[a + (int64_t)b * capj];
+#pragma unroll
+        for (int ii = 0; ii < XF_CHUNK; ++ii)
+          if (ii < nr) acc[ii] += sh[ii + b * hmax] * x;
+      }
+#pragma unroll
+      for (int ii = 0; ii < XF_CHUNK; ++ii)
+        if (ii < nr) E[(r0 + ii) + (int64_t)a * ldq] = acc[ii];
     }
     __syncthreads();
   }

@@ -8,9 +8,11 @@
 //    small matrices of the fine levels);
 //  - block: the columns are split in blocks of nb; one round of a round-robin
 //    tournament over the blocks is one launch in which one workgroup takes one
-//    pair of blocks into LDS and orthogonalises its 2 nb columns among
-//    themselves. All pairs of all matrices of a batch run side by side, so a
-//    colour class with only a few large matrices still spreads over the chip.
+//    pair of blocks into LDS and rotates its column pairs: in round 0 all
+//    pairs of its 2 nb columns, in later rounds only the pairs across the two
+//    blocks, so that a sweep visits every column pair once. All pairs of all
+//    matrices of a batch run side by side, so a colour class with only a few
+//    large matrices still spreads over the chip.
 //
 // Rotation rule (both schemes), with a, b the squared norms of columns p, q
 // and g their inner product: rotate iff |g| > tol sqrt(a b), with
@@ -234,7 +236,28 @@ __global__ void __launch_bounds__(SVD_WG) k_svd_round(const SvdDesc* __restrict_
   const T defl_s = (T)ldexp(defl, shs[s]);
   const T tol = (T)(u * fmax(4.0, sqrt((double)M)));
   int any = 0;
-  jacobi_sweeps(L, (int64_t)M, M, nc, tol, defl_s * defl_s, inner_sweeps, &any, &flag);
+  if (round == 0) {
+    // every block takes part in round 0: its pairs inside the block are visited here, once per sweep
+    jacobi_sweeps(L, (int64_t)M, M, nc, tol, defl_s * defl_s, inner_sweeps, &any, &flag);
+  } else if (w[0] > 0 && w[1] > 0) {
+    // only the pairs across the two blocks: in step t wavefront a pairs column a of the first block with
+    // column (a + t) mod R of the second, so no column is used twice in a step and every cross pair once
+    const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE, nw = blockDim.x / WAVE;
+    const int R = max(w[0], w[1]);
+    if (threadIdx.x == 0) flag = 0;
+    __syncthreads();
+    bool rot = false;
+    for (int t = 0; t < R; ++t) {
+      for (int a = wv; a < w[0]; a += nw) {
+        const int b = (a + t) % R;
+        if (b < w[1]) rot |= jacobi_rot(L, (int64_t)M, M, a, w[0] + b, tol, defl_s * defl_s, lane);
+      }
+      __syncthreads();
+    }
+    if (rot && lane == 0) flag = 1;
+    __syncthreads();
+    any = flag;
+  }
   if (!any) return;   // nothing rotated: global memory already holds these columns
   for (int64_t e = threadIdx.x; e < (int64_t)M * nc; e += blockDim.x) {
     const int c = (int)(e / M), i = (int)(e % M);
