@@ -23,6 +23,9 @@ struct LevelPool {
   std::vector<int> m, cap, r, rpar;
   std::vector<int64_t> Kt, St, XYt, YXt, Uo, Vo, SUo, SVo, PUo, PVo;
   std::vector<int> B7;
+  // per box, the offset codes of its existing edges K(j, q) (row) and K(q, j)
+  // (column), CSR; built on first use, the edge tables of a level are fixed
+  std::vector<int> erow_start, erow, ecol_start, ecol;
   int64_t size = 0;
   DevBuf pool;
   DevBuf dm, dcap, dr, drnew, dKt, dB7, dSt, dXYt, dYXt, dUo, dVo, dSUo, dSVo, dPUo, dPVo, drpar, dparent;
@@ -483,6 +486,20 @@ struct Factorizer {
     // one task per existing edge (the host holds the edge tables); flops of the
     // basis changes 2 k r cols per edge, with the new rank k bounded by the old
     // rank r (the new ranks are still on the device)
+    if (L.erow_start.empty()) {
+      L.erow_start.assign(L.nb + 1, 0);
+      L.ecol_start.assign(L.nb + 1, 0);
+      for (int j = 0; j < L.nb; ++j) {
+        for (int code = 0; code < L.c7; ++code) {
+          const int q = L.B7[(size_t)j * L.c7 + code];
+          if (q < 0) continue;
+          if (L.Kt[(size_t)j * L.c7 + code] >= 0) L.erow.push_back(code);
+          if (L.Kt[(size_t)q * L.c7 + (L.c7 - 1 - code)] >= 0) L.ecol.push_back(code);
+        }
+        L.erow_start[j + 1] = (int)L.erow.size();
+        L.ecol_start[j + 1] = (int)L.ecol.size();
+      }
+    }
     std::vector<int2> tasks;
     size_t nrow = 0;
     double frow = 0, fcol = 0;
@@ -490,17 +507,12 @@ struct Factorizer {
       for (size_t ci = 0; ci < cs.size(); ++ci) {
         const int j = cs[ci].box;
         const double r = L.r[j];
-        for (int code = 0; code < L.c7; ++code) {
-          const int q = L.B7[(size_t)j * L.c7 + code];
-          if (q < 0) continue;
-          if (pass == 0 && L.Kt[(size_t)j * L.c7 + code] >= 0) {
-            tasks.push_back(make_int2((int)ci, code));
-            frow += 2.0 * r * r * L.r[q];
-          }
-          if (pass == 1 && L.Kt[(size_t)q * L.c7 + (L.c7 - 1 - code)] >= 0) {
-            tasks.push_back(make_int2((int)ci, code));
-            fcol += 2.0 * r * r * L.r[q];
-          }
+        const std::vector<int>& st = pass == 0 ? L.erow_start : L.ecol_start;
+        const std::vector<int>& ls = pass == 0 ? L.erow : L.ecol;
+        for (int e = st[j]; e < st[j + 1]; ++e) {
+          const int code = ls[e];
+          tasks.push_back(make_int2((int)ci, code));
+          (pass == 0 ? frow : fcol) += 2.0 * r * r * L.r[L.B7[(size_t)j * L.c7 + code]];
         }
         if (pass == 0 && L.l > 2) {
           tasks.push_back(make_int2((int)ci, L.c7));
@@ -617,8 +629,10 @@ struct Factorizer {
     for (int c = 0; c < lv.ncolour; ++c) {
       const auto& boxes = lv.classes[c];
       if (boxes.empty()) continue;
-      // ranks are exact on the host at the start of every class
+      // ranks are exact on the host at the start of every class; the stream is
+      // idle, so the descriptors of the previous class can be recycled
       P.download(L.r, L.dr.p, (size_t)lv.nb);
+      P.arena_reset();
       ClassFactors<T>& cf = F.cls[l][c];
       std::vector<ElimDesc>& el = cf.el;
       std::vector<FNode>& Fs = cf.F;
@@ -793,6 +807,7 @@ struct Factorizer {
 
   // ---------------------------------------------------- merge into l - 1
   void merge(LevelPool<T>& C, LevelPool<T>& Pp) {
+    P.arena_reset();
     const int l = C.l, lp = l - 1;
     const HLevel& lv = P.T.lev[lp];
     std::vector<int> m(lv.nb, 0), choff(C.nb, 0);
@@ -834,6 +849,7 @@ struct Factorizer {
   }
 
   void top(LevelPool<T>& L) {
+    P.arena_reset();
     const HLevel& lv = P.T.lev[2];
     std::vector<int64_t> off(lv.nb + 1, 0);
     for (int i = 0; i < lv.nb; ++i) off[i + 1] = off[i] + L.r[i];

@@ -141,6 +141,7 @@ void factorize_handle(ifmm_handle h) {
   {
     if (!h) fail(IFMM_ERR_ARG, "null handle");
     Problem& P = h->P;
+    P.arena_reset();
     P.factorized = false;
     P.fac.reset();
     IFMM_HIP(hipMemsetAsync(P.d_info, 0xff, sizeof(int) * 4, P.stream));

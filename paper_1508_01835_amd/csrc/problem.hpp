@@ -175,19 +175,53 @@ struct Problem {
     sync();
     std::memcpy(v.data(), h, count * sizeof(T));
   }
-  // Upload descriptors into a reusable device buffer (no sync beyond the copy).
+  // Descriptor arena: launch descriptors are appended to pinned host chunks
+  // and copied to matching device chunks on the stream, with no
+  // synchronisation. A descriptor stays valid until arena_reset(), which the
+  // factorization calls where the stream is idle anyway (start of a colour
+  // class, of a merge, of the top system, of every API call).
+  struct ArenaChunk {
+    DevBuf dev;
+    void* host = nullptr;
+    size_t bytes = 0;
+  };
+  std::vector<ArenaChunk> arena;
+  size_t arena_cur = 0, arena_off = 0;
+  void arena_reset() {
+    sync();
+    arena_cur = 0;
+    arena_off = 0;
+  }
   template <class D>
-  const D* put(DevBuf& b, const std::vector<D>& v) {
-    const size_t bytes = v.size() * sizeof(D);
-    if (bytes + 16 > b.bytes) sync();   // kernels still reading the old buffer must finish
-    b.reserve(bytes + 16, &mem);
-    if (bytes) {
-      void* h = stage.get(bytes);
-      std::memcpy(h, v.data(), bytes);
-      IFMM_HIP(hipMemcpyAsync(b.p, h, bytes, hipMemcpyHostToDevice, stream));
-      sync();
+  const D* put(DevBuf& unused, const std::vector<D>& v) {
+    (void)unused;
+    const size_t bytes = (v.size() * sizeof(D) + 255) & ~size_t(255);
+    if (arena.empty() || arena_off + bytes > arena[arena_cur].bytes) {
+      if (!arena.empty() && arena_off > 0) { ++arena_cur; arena_off = 0; }
+      while (arena_cur < arena.size() && arena[arena_cur].bytes < bytes) ++arena_cur;
+      if (arena_cur >= arena.size()) {
+        ArenaChunk c;
+        c.bytes = std::max<size_t>(bytes, size_t(8) << 20);
+        c.dev.alloc(c.bytes, &mem);
+        IFMM_HIP(hipHostMalloc(&c.host, c.bytes, hipHostMallocDefault));
+        arena.push_back(std::move(c));
+        arena_cur = arena.size() - 1;
+      }
     }
-    return b.as<D>();
+    ArenaChunk& c = arena[arena_cur];
+    char* h = static_cast<char*>(c.host) + arena_off;
+    char* d = static_cast<char*>(c.dev.p) + arena_off;
+    if (!v.empty()) {
+      std::memcpy(h, v.data(), v.size() * sizeof(D));
+      IFMM_HIP(hipMemcpyAsync(d, h, v.size() * sizeof(D), hipMemcpyHostToDevice, stream));
+    }
+    arena_off += bytes;
+    return reinterpret_cast<const D*>(d);
+  }
+  ~Problem() {
+    if (stream) (void)hipStreamSynchronize(stream);
+    for (auto& c : arena)
+      if (c.host) (void)hipHostFree(c.host);
   }
 };
 
