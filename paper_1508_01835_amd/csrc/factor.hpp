@@ -26,6 +26,7 @@ struct LevelPool {
   // per box, the offset codes of its existing edges K(j, q) (row) and K(q, j)
   // (column), CSR; built on first use, the edge tables of a level are fixed
   std::vector<int> erow_start, erow, ecol_start, ecol;
+  DevBuf derow_start, derow, decol_start, decol;
   int64_t size = 0;
   DevBuf pool;
   DevBuf dm, dcap, dr, drnew, dKt, dB7, dSt, dXYt, dYXt, dUo, dVo, dSUo, dSVo, dPUo, dPVo, drpar, dparent;
@@ -499,41 +500,46 @@ struct Factorizer {
         L.erow_start[j + 1] = (int)L.erow.size();
         L.ecol_start[j + 1] = (int)L.ecol.size();
       }
+      P.upload(L.derow_start, L.erow_start);
+      P.upload(L.derow, L.erow);
+      P.upload(L.decol_start, L.ecol_start);
+      P.upload(L.decol, L.ecol);
     }
-    std::vector<int2> tasks;
-    size_t nrow = 0;
+    // per recompression the first workgroup of its edges; flops estimated as
+    // 2 r_j^2 (edges of j) rbar with the level's mean rank rbar (exact counts
+    // would need a pass over every edge on the host)
+    const int extra = L.l > 2 ? 2 : 0;
+    std::vector<int> prow(cs.size() + 1, 0), pcol(cs.size() + 1, 0);
+    double rbar = 0;
+    for (int x : L.r) rbar += x;
+    rbar = L.nb ? rbar / L.nb : 0.0;
     double frow = 0, fcol = 0;
-    for (int pass = 0; pass < 2; ++pass) {
-      for (size_t ci = 0; ci < cs.size(); ++ci) {
-        const int j = cs[ci].box;
-        const double r = L.r[j];
-        const std::vector<int>& st = pass == 0 ? L.erow_start : L.ecol_start;
-        const std::vector<int>& ls = pass == 0 ? L.erow : L.ecol;
-        for (int e = st[j]; e < st[j + 1]; ++e) {
-          const int code = ls[e];
-          tasks.push_back(make_int2((int)ci, code));
-          (pass == 0 ? frow : fcol) += 2.0 * r * r * L.r[L.B7[(size_t)j * L.c7 + code]];
-        }
-        if (pass == 0 && L.l > 2) {
-          tasks.push_back(make_int2((int)ci, L.c7));
-          tasks.push_back(make_int2((int)ci, L.c7 + 1));
-          frow += 2.0 * 2.0 * r * r * L.rpar[j];
-        }
-      }
-      if (pass == 0) nrow = tasks.size();
+    for (size_t ci = 0; ci < cs.size(); ++ci) {
+      const int j = cs[ci].box;
+      const int nr = L.erow_start[j + 1] - L.erow_start[j], nc = L.ecol_start[j + 1] - L.ecol_start[j];
+      prow[ci + 1] = prow[ci] + nr + extra;
+      pcol[ci + 1] = pcol[ci] + nc;
+      const double r = L.r[j];
+      frow += 2.0 * r * r * (nr * rbar + (extra ? 2.0 * L.rpar[j] : 0.0));
+      fcol += 2.0 * r * r * nc * rbar;
     }
-    const int2* dt = P.put(F.d5, tasks);
-    if (nrow > 0) {
+    std::vector<int> pre(prow.begin(), prow.end() - 1);
+    pre.insert(pre.end(), pcol.begin(), pcol.end() - 1);
+    const int* dpre = P.put(F.d5, pre);
+    XfTasks xr{dpre, (int)cs.size(), extra, L.derow_start.template as<int>(), L.derow.template as<int>()};
+    XfTasks xc{dpre + cs.size(), (int)cs.size(), 0, L.decol_start.template as<int>(), L.decol.template as<int>()};
+    if (prow.back() > 0) {
       P.kone_begin(KF_ROW_XFORM, frow);
-      hipLaunchKernelGGL(k_row_xform<T>, dim3((unsigned)nrow), dim3(WG), 0, P.stream, dc, dt, v, L.P(), (const T*)W);
+      hipLaunchKernelGGL(k_row_xform<T>, dim3((unsigned)prow.back()), dim3(WG), 0, P.stream, dc, xr, v, L.P(),
+                         (const T*)W);
       IFMM_LAUNCH_CHECK();
       P.kone_end();
     }
     chk(L, "row_xform", nullptr, o);
-    if (tasks.size() > nrow) {
+    if (pcol.back() > 0) {
       P.kone_begin(KF_COL_XFORM, fcol);
-      hipLaunchKernelGGL(k_col_xform<T>, dim3((unsigned)(tasks.size() - nrow)), dim3(WG), 0, P.stream, dc,
-                         dt + nrow, v, L.P(), (const T*)W);
+      hipLaunchKernelGGL(k_col_xform<T>, dim3((unsigned)pcol.back()), dim3(WG), 0, P.stream, dc, xc, v, L.P(),
+                         (const T*)W);
       IFMM_LAUNCH_CHECK();
       P.kone_end();
     }

@@ -318,14 +318,37 @@ constexpr int XF_LDS = 32 * 1024;   // bytes of LDS for the staged edge slice
 // Row transform of every y-y edge of an affected box j and of its transfers:
 // K(j, q) <- r_j K(j, q), PU(j) <- r_j PU(j), PV(j) <- t_j PV(j)
 // (eqs. K_jq_update, U_parent_j_update, V_parent_j_update).
-// One workgroup per existing edge: tasks[t] = (recompression, offset code),
-// code c7 = PU, c7 + 1 = PV.
+// Edges of the affected boxes, one workgroup each: pre[ci] is the first
+// workgroup of recompression ci (prefix over the recompressions of the number
+// of edges of their box, + 2 for PU / PV above level 2); estart / elist list
+// the offset codes of a box's existing edges (CSR over the level's boxes).
+struct XfTasks {
+  const int* pre;
+  int ncs, extra;            // extra: 2 for the parent transfers (row transform above level 2), else 0
+  const int* estart;
+  const int* elist;
+};
+
+__device__ inline int2 xf_task(const XfTasks& x, const CompDesc* __restrict__ cs, int c7) {
+  int lo = 0, hi = x.ncs - 1;
+  const int b = blockIdx.x;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (x.pre[mid] <= b) lo = mid; else hi = mid - 1;
+  }
+  const int j = cs[lo].box;
+  const int local = b - x.pre[lo];
+  const int ne = x.estart[j + 1] - x.estart[j];
+  return make_int2(lo, local < ne ? x.elist[x.estart[j] + local] : c7 + (local - ne));
+}
+
+// One workgroup per existing edge (code c7 = PU, c7 + 1 = PV).
 // A slice of up to XF_CHUNK columns of the edge is staged in LDS; each thread
 // computes one output row of the slice, reading its row of the transform once.
 template <class T>
-__global__ void __launch_bounds__(WG) k_row_xform(const CompDesc* __restrict__ cs, const int2* __restrict__ tasks,
-                                                  LevelView lv, T* __restrict__ pool, const T* __restrict__ work) {
-  const int2 tk = tasks[blockIdx.x];
+__global__ void __launch_bounds__(WG) k_row_xform(const CompDesc* __restrict__ cs, XfTasks xt, LevelView lv,
+                                                  T* __restrict__ pool, const T* __restrict__ work) {
+  const int2 tk = xf_task(xt, cs, lv.c7);
   const CompDesc c = cs[tk.x];
   const int j = c.box;
   const int code = tk.y;
@@ -377,13 +400,13 @@ __global__ void __launch_bounds__(WG) k_row_xform(const CompDesc* __restrict__ c
 }
 
 // Column transform: K(q, j) <- K(q, j) t_j^T for every edge into y_j (eq. K_qj_update).
-// One workgroup per existing edge: tasks[t] = (recompression, offset code of q from j).
+// One workgroup per existing edge K(q, j) (code: offset of q from j).
 // A slice of up to XF_CHUNK rows of the edge is staged in LDS; each thread
 // computes one output column of the slice, reading its row of t_j once.
 template <class T>
-__global__ void __launch_bounds__(WG) k_col_xform(const CompDesc* __restrict__ cs, const int2* __restrict__ tasks,
-                                                  LevelView lv, T* __restrict__ pool, const T* __restrict__ work) {
-  const int2 tk = tasks[blockIdx.x];
+__global__ void __launch_bounds__(WG) k_col_xform(const CompDesc* __restrict__ cs, XfTasks xt, LevelView lv,
+                                                  T* __restrict__ pool, const T* __restrict__ work) {
+  const int2 tk = xf_task(xt, cs, lv.c7);
   const CompDesc c = cs[tk.x];
   const int j = c.box;
   const int code = tk.y;
