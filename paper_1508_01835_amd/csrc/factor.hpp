@@ -528,18 +528,30 @@ struct Factorizer {
     const int* dpre = P.put(F.d5, pre);
     XfTasks xr{dpre, (int)cs.size(), extra, L.derow_start.template as<int>(), L.derow.template as<int>()};
     XfTasks xc{dpre + cs.size(), (int)cs.size(), 0, L.decol_start.template as<int>(), L.decol.template as<int>()};
+    // small ranks (fine levels): one wavefront per edge, many edges resident per CU
+    int rmax = 0;
+    for (const auto& c : cs) rmax = std::max(rmax, L.r[c.box]);
+    const bool small = rmax <= XF_SMALL_R;
     if (prow.back() > 0) {
       P.kone_begin(KF_ROW_XFORM, frow);
-      hipLaunchKernelGGL(k_row_xform<T>, dim3((unsigned)prow.back()), dim3(WG), 0, P.stream, dc, xr, v, L.P(),
-                         (const T*)W);
+      if (small)
+        hipLaunchKernelGGL((k_row_xform<T, 64, 8192>), dim3((unsigned)prow.back()), dim3(64), 0, P.stream, dc, xr, v,
+                           L.P(), (const T*)W);
+      else
+        hipLaunchKernelGGL((k_row_xform<T, WG, XF_LDS>), dim3((unsigned)prow.back()), dim3(WG), 0, P.stream, dc, xr,
+                           v, L.P(), (const T*)W);
       IFMM_LAUNCH_CHECK();
       P.kone_end();
     }
     chk(L, "row_xform", nullptr, o);
     if (pcol.back() > 0) {
       P.kone_begin(KF_COL_XFORM, fcol);
-      hipLaunchKernelGGL(k_col_xform<T>, dim3((unsigned)pcol.back()), dim3(WG), 0, P.stream, dc, xc, v, L.P(),
-                         (const T*)W);
+      if (small)
+        hipLaunchKernelGGL((k_col_xform<T, 64, 8192>), dim3((unsigned)pcol.back()), dim3(64), 0, P.stream, dc, xc, v,
+                           L.P(), (const T*)W);
+      else
+        hipLaunchKernelGGL((k_col_xform<T, WG, XF_LDS>), dim3((unsigned)pcol.back()), dim3(WG), 0, P.stream, dc, xc,
+                           v, L.P(), (const T*)W);
       IFMM_LAUNCH_CHECK();
       P.kone_end();
     }

@@ -313,7 +313,8 @@ __global__ void __launch_bounds__(WG) k_comp_rt(const CompDesc* __restrict__ cs,
 }
 
 constexpr int XF_CHUNK = 32;        // columns (rows) of an edge transformed at a time, at most
-constexpr int XF_LDS = 32 * 1024;   // bytes of LDS for the staged edge slice
+constexpr int XF_LDS = 32 * 1024;   // bytes of LDS for the staged edge slice (256-thread variant)
+constexpr int XF_SMALL_R = 32;      // ranks up to this use 64-thread workgroups with 8 KB of LDS
 
 // Row transform of every y-y edge of an affected box j and of its transfers:
 // K(j, q) <- r_j K(j, q), PU(j) <- r_j PU(j), PV(j) <- t_j PV(j)
@@ -345,8 +346,8 @@ __device__ inline int2 xf_task(const XfTasks& x, const CompDesc* __restrict__ cs
 // One workgroup per existing edge (code c7 = PU, c7 + 1 = PV).
 // A slice of up to XF_CHUNK columns of the edge is staged in LDS; each thread
 // computes one output row of the slice, reading its row of the transform once.
-template <class T>
-__global__ void __launch_bounds__(WG) k_row_xform(const CompDesc* __restrict__ cs, XfTasks xt, LevelView lv,
+template <class T, int BS, int LDSB>
+__global__ void __launch_bounds__(BS) k_row_xform(const CompDesc* __restrict__ cs, XfTasks xt, LevelView lv,
                                                   T* __restrict__ pool, const T* __restrict__ work) {
   const int2 tk = xf_task(xt, cs, lv.c7);
   const CompDesc c = cs[tk.x];
@@ -368,20 +369,20 @@ __global__ void __launch_bounds__(WG) k_row_xform(const CompDesc* __restrict__ c
   }
   const int r = lv.r[j], k = lv.rnew[j], cap = lv.cap[j];
   if (r == 0 || cols == 0) {
-    for (int t = threadIdx.x; t < k * cols; t += WG) pool[off + t % k + (int64_t)(t / k) * cap] = (T)0;
+    for (int t = threadIdx.x; t < k * cols; t += BS) pool[off + t % k + (int64_t)(t / k) * cap] = (T)0;
     return;
   }
-  __shared__ T sh[XF_LDS / sizeof(T)];
-  const int wmax = min(XF_CHUNK, (int)(XF_LDS / sizeof(T)) / r);   // r <= 1024: at least 8 columns (FP64)
+  __shared__ T sh[LDSB / sizeof(T)];
+  const int wmax = min(XF_CHUNK, (int)(LDSB / sizeof(T)) / r);   // r <= 1024: at least 8 columns (FP64)
   T* E = pool + off;
   for (int c0 = 0; c0 < cols; c0 += wmax) {
     const int nc = min(wmax, cols - c0);
-    for (int t = threadIdx.x; t < r * nc; t += WG) {
+    for (int t = threadIdx.x; t < r * nc; t += BS) {
       const int i = t % r, cc = t / r;
       sh[i + cc * r] = E[i + (int64_t)(c0 + cc) * cap];
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < k; i += WG) {
+    for (int i = threadIdx.x; i < k; i += BS) {
       T acc[XF_CHUNK];
 #pragma unroll
       for (int cc = 0; cc < XF_CHUNK; ++cc) acc[cc] = 0;
@@ -403,8 +404,8 @@ __global__ void __launch_bounds__(WG) k_row_xform(const CompDesc* __restrict__ c
 // One workgroup per existing edge K(q, j) (code: offset of q from j).
 // A slice of up to XF_CHUNK rows of the edge is staged in LDS; each thread
 // computes one output column of the slice, reading its row of t_j once.
-template <class T>
-__global__ void __launch_bounds__(WG) k_col_xform(const CompDesc* __restrict__ cs, XfTasks xt, LevelView lv,
+template <class T, int BS, int LDSB>
+__global__ void __launch_bounds__(BS) k_col_xform(const CompDesc* __restrict__ cs, XfTasks xt, LevelView lv,
                                                   T* __restrict__ pool, const T* __restrict__ work) {
   const int2 tk = xf_task(xt, cs, lv.c7);
   const CompDesc c = cs[tk.x];
@@ -420,19 +421,19 @@ __global__ void __launch_bounds__(WG) k_col_xform(const CompDesc* __restrict__ c
   const T* X = work + c.tt;
   T* E = pool + off;
   if (r == 0 || rows == 0) {
-    for (int t = threadIdx.x; t < rows * k; t += WG) E[t % rows + (int64_t)(t / rows) * ldq] = (T)0;
+    for (int t = threadIdx.x; t < rows * k; t += BS) E[t % rows + (int64_t)(t / rows) * ldq] = (T)0;
     return;
   }
-  __shared__ T sh[XF_LDS / sizeof(T)];
-  const int hmax = min(XF_CHUNK, (int)(XF_LDS / sizeof(T)) / r);
+  __shared__ T sh[LDSB / sizeof(T)];
+  const int hmax = min(XF_CHUNK, (int)(LDSB / sizeof(T)) / r);
   for (int r0 = 0; r0 < rows; r0 += hmax) {
     const int nr = min(hmax, rows - r0);
-    for (int t = threadIdx.x; t < nr * r; t += WG) {
+    for (int t = threadIdx.x; t < nr * r; t += BS) {
       const int i = t % nr, b = t / nr;
       sh[i + b * hmax] = E[(r0 + i) + (int64_t)b * ldq];
     }
     __syncthreads();
-    for (int a = threadIdx.x; a < k; a += WG) {
+    for (int a = threadIdx.x; a < k; a += BS) {
       T acc[XF_CHUNK];
 #pragma unroll
       for (int ii = 0; ii < XF_CHUNK; ++ii) acc[ii] = 0;
