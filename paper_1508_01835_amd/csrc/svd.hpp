@@ -43,16 +43,19 @@ constexpr int SVD_WG = 1024;                // 16 wavefronts: 16 column pairs at
 constexpr size_t SVD_LDS_MAX = 144 * 1024;  // dynamic LDS per workgroup (gfx950: 160 KB)
 
 // Rotates columns p and q of B (ld) when the rule above asks for it; one
-// wavefront. Returns whether it rotated (uniform over the wavefront).
+// wavefront. nrm2 holds the squared column norms: only the inner product is
+// reduced across the wavefront, and the two norms are updated exactly for the
+// rotation that zeroes it (a' = a - t g, b' = b + t g); callers recompute them
+// at every sweep (meeting) start, as LAPACK's one-sided Jacobi does. Returns
+// whether it rotated (uniform over the wavefront).
 template <class T>
-__device__ inline bool jacobi_rot(T* __restrict__ B, int64_t ld, int M, int p, int q, T tol, T defl2, int lane) {
-  T a = 0, b = 0, g = 0;
-  for (int i = lane; i < M; i += WAVE) {
-    const T x = B[i + p * ld], y = B[i + q * ld];
-    a += x * x; b += y * y; g += x * y;
-  }
-  a = wave_sum(a); b = wave_sum(b); g = wave_sum(g);
+__device__ inline bool jacobi_rot(T* __restrict__ B, int64_t ld, int M, int p, int q, T tol, T defl2, int lane,
+                                  T* nrm2) {
+  const T a = nrm2[p], b = nrm2[q];
   if (a < defl2 || b < defl2) return false;
+  T g = 0;
+  for (int i = lane; i < M; i += WAVE) g += B[i + p * ld] * B[i + q * ld];
+  g = wave_sum(g);
   if (!(fabs(g) > tol * sqrt(a * b))) return false;
   const T zeta = (b - a) / ((T)2 * g);
   const T t = (zeta >= (T)0 ? (T)1 : (T)-1) / (fabs(zeta) + sqrt((T)1 + zeta * zeta));
@@ -63,7 +66,24 @@ __device__ inline bool jacobi_rot(T* __restrict__ B, int64_t ld, int M, int p, i
     B[i + p * ld] = c * x - s * y;
     B[i + q * ld] = s * x + c * y;
   }
+  if (lane == 0) {
+    nrm2[p] = fmax((T)0, a - t * g);
+    nrm2[q] = b + t * g;
+  }
   return true;
+}
+
+// Squared norms of the nc columns of B into nrm2; whole workgroup.
+template <class T>
+__device__ inline void col_norms2(const T* __restrict__ B, int64_t ld, int M, int nc, T* nrm2) {
+  const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE, nw = blockDim.x / WAVE;
+  for (int c = wv; c < nc; c += nw) {
+    T s = 0;
+    for (int i = lane; i < M; i += WAVE) { const T x = B[i + c * ld]; s += x * x; }
+    s = wave_sum(s);
+    if (lane == 0) nrm2[c] = s;
+  }
+  __syncthreads();
 }
 
 // Pair (x, y) of player slot pr in round r of a round-robin tournament over
@@ -81,7 +101,7 @@ __device__ inline void rr_pair(int np, int r, int pr, int& x, int& y) {
 // rotation happened.
 template <class T>
 __device__ inline int jacobi_sweeps(T* __restrict__ B, int64_t ld, int M, int nc, T tol, T defl2, int max_sweeps,
-                                    int* any, int* flag) {
+                                    int* any, int* flag, T* nrm2) {
   const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE, nw = blockDim.x / WAVE;
   const int np = nc + (nc & 1);
   int sweeps = 0;
@@ -89,13 +109,13 @@ __device__ inline int jacobi_sweeps(T* __restrict__ B, int64_t ld, int M, int nc
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     sweeps = sweep + 1;
     if (threadIdx.x == 0) *flag = 0;
-    __syncthreads();
+    col_norms2(B, ld, M, nc, nrm2);
     bool rot = false;
     for (int r = 0; r < np - 1; ++r) {
       for (int pr = wv; pr < np / 2; pr += nw) {
         int x, y;
         rr_pair(np, r, pr, x, y);
-        if (x < nc && y < nc) rot |= jacobi_rot(B, ld, M, min(x, y), max(x, y), tol, defl2, lane);
+        if (x < nc && y < nc) rot |= jacobi_rot(B, ld, M, min(x, y), max(x, y), tol, defl2, lane, nrm2);
       }
       __syncthreads();
     }
@@ -183,7 +203,7 @@ __global__ void __launch_bounds__(SVD_WG) k_svd_small(const SvdDesc* __restrict_
   const T defl_s = (T)ldexp(defl, sh);
   const T tol = (T)(u * fmax(4.0, sqrt((double)M)));
   int any = 0;
-  const int sw = jacobi_sweeps(B, ldb, M, N, tol, defl_s * defl_s, max_sweeps, &any, &flag);
+  const int sw = jacobi_sweeps(B, ldb, M, N, tol, defl_s * defl_s, max_sweeps, &any, &flag, nrm);
   if (sweeps_out && threadIdx.x == 0) atomicMax(sweeps_out, sw);
   svd_finish(B, ldb, M, N, d.N, static_cast<T*>(d.U), d.ldu, static_cast<T*>(d.S), sh, d.perm, nrm, order);
 }
@@ -191,14 +211,22 @@ __global__ void __launch_bounds__(SVD_WG) k_svd_small(const SvdDesc* __restrict_
 // ------------------------------------------------------------- block scheme
 // Per matrix: shs[s] = the scaling exponent sh; flags[2s] = rotations in the
 // current sweep, flags[2s + 1] = converged.
+// Block bookkeeping per matrix (nbm = largest block count of the batch):
+// bst[0, nbm): round stamp of the last change of each block's columns;
+// bst[nbm + x nbm + y]: stamp of the last meeting of blocks x and y (y = x:
+// block x alone) that rotated nothing, -1 if none since. A meeting is skipped
+// when both blocks are unchanged since their last such meeting: the pairs it
+// would check are still within the threshold.
 template <class T>
 __global__ void __launch_bounds__(SVD_WG) k_svd_prep(const SvdDesc* __restrict__ ds, int* __restrict__ shs,
-                                                  int* __restrict__ flags) {
+                                                  int* __restrict__ flags, int* __restrict__ bst, int nbm) {
   __shared__ T red[SVD_WG / WAVE];
   const SvdDesc d = ds[blockIdx.x];
   T* B = static_cast<T*>(d.B);
   const int N = svd_cols(d);
   const int sh = svd_scale(B, d.ldb, d.M, N, B, d.ldb, red);
+  int* st = bst + (int64_t)blockIdx.x * (nbm + nbm * nbm);
+  for (int e = threadIdx.x; e < nbm + nbm * nbm; e += SVD_WG) st[e] = -1;
   if (threadIdx.x == 0) {
     shs[blockIdx.x] = sh;
     flags[2 * blockIdx.x] = 0;
@@ -210,9 +238,11 @@ __global__ void __launch_bounds__(SVD_WG) k_svd_prep(const SvdDesc* __restrict__
 template <class T>
 __global__ void __launch_bounds__(SVD_WG) k_svd_round(const SvdDesc* __restrict__ ds,
                                                    const int* __restrict__ shs, int* __restrict__ flags, int nb,
-                                                   int round, double u, double defl, int inner_sweeps) {
+                                                   int round, double u, double defl, int inner_sweeps,
+                                                   int* __restrict__ bst, int nbm, int stamp) {
   extern __shared__ unsigned char svd_dyn[];
   __shared__ int flag;
+  __shared__ T nrm2[64];
   const int s = blockIdx.y;
   if (flags[2 * s + 1]) return;
   const SvdDesc d = ds[s];
@@ -225,6 +255,11 @@ __global__ void __launch_bounds__(SVD_WG) k_svd_round(const SvdDesc* __restrict_
   const int w[2] = {x < nblk ? min(nb, N - x * nb) : 0, y < nblk ? min(nb, N - y * nb) : 0};
   const int nc = w[0] + w[1];
   if (nc < 2) return;
+  if (round > 0 && (w[0] == 0 || w[1] == 0)) return;   // a block alone has no cross pairs
+  int* st = bst + (int64_t)s * (nbm + nbm * nbm);
+  const int bx = x < nblk ? x : y, by = y < nblk ? y : x;   // a bye meets its partner alone
+  int* clean = st + nbm + bx * nbm + by;
+  if (*clean >= 0 && st[bx] < *clean && st[by] < *clean) return;
   T* __restrict__ Bg = static_cast<T*>(d.B);
   T* __restrict__ L = reinterpret_cast<T*>(svd_dyn);
   for (int64_t e = threadIdx.x; e < (int64_t)M * nc; e += blockDim.x) {
@@ -238,19 +273,19 @@ __global__ void __launch_bounds__(SVD_WG) k_svd_round(const SvdDesc* __restrict_
   int any = 0;
   if (round == 0) {
     // every block takes part in round 0: its pairs inside the block are visited here, once per sweep
-    jacobi_sweeps(L, (int64_t)M, M, nc, tol, defl_s * defl_s, inner_sweeps, &any, &flag);
+    jacobi_sweeps(L, (int64_t)M, M, nc, tol, defl_s * defl_s, inner_sweeps, &any, &flag, nrm2);
   } else if (w[0] > 0 && w[1] > 0) {
     // only the pairs across the two blocks: in step t wavefront a pairs column a of the first block with
     // column (a + t) mod R of the second, so no column is used twice in a step and every cross pair once
     const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE, nw = blockDim.x / WAVE;
     const int R = max(w[0], w[1]);
     if (threadIdx.x == 0) flag = 0;
-    __syncthreads();
+    col_norms2(L, (int64_t)M, M, nc, nrm2);
     bool rot = false;
     for (int t = 0; t < R; ++t) {
       for (int a = wv; a < w[0]; a += nw) {
         const int b = (a + t) % R;
-        if (b < w[1]) rot |= jacobi_rot(L, (int64_t)M, M, a, w[0] + b, tol, defl_s * defl_s, lane);
+        if (b < w[1]) rot |= jacobi_rot(L, (int64_t)M, M, a, w[0] + b, tol, defl_s * defl_s, lane, nrm2);
       }
       __syncthreads();
     }
@@ -258,13 +293,21 @@ __global__ void __launch_bounds__(SVD_WG) k_svd_round(const SvdDesc* __restrict_
     __syncthreads();
     any = flag;
   }
-  if (!any) return;   // nothing rotated: global memory already holds these columns
+  if (!any) {   // nothing rotated: global memory already holds these columns
+    if (threadIdx.x == 0) *clean = stamp;
+    return;
+  }
   for (int64_t e = threadIdx.x; e < (int64_t)M * nc; e += blockDim.x) {
     const int c = (int)(e / M), i = (int)(e % M);
     const int gc = c < w[0] ? c0[0] + c : c0[1] + (c - w[0]);
     Bg[i + (int64_t)gc * d.ldb] = L[e];
   }
-  if (threadIdx.x == 0) atomicAdd(&flags[2 * s], 1);
+  if (threadIdx.x == 0) {
+    atomicAdd(&flags[2 * s], 1);
+    st[bx] = stamp;
+    st[by] = stamp;
+    *clean = -1;
+  }
 }
 
 // End of a sweep: a matrix whose sweep rotated nothing has converged.
@@ -514,10 +557,12 @@ inline void run_svd(Problem& P, const std::vector<SvdDesc>& v, DevBuf& scratch, 
   if (!big.empty()) {
     const int nbig = (int)big.size();
     const SvdDesc* db = d + ns;
-    P.svd_state.reserve(sizeof(int) * 3 * nbig + 64, &P.mem);
+    const int nbm = bigBlocks + (bigBlocks & 1);
+    P.svd_state.reserve(sizeof(int) * ((size_t)3 * nbig + (size_t)nbig * (nbm + nbm * nbm)) + 64, &P.mem);
     int* shs = P.svd_state.as<int>();
     int* flags = shs + nbig;
-    hipLaunchKernelGGL(k_svd_prep<T>, dim3(nbig), dim3(SVD_WG), 0, P.stream, db, shs, flags);
+    int* bst = flags + 2 * nbig;
+    hipLaunchKernelGGL(k_svd_prep<T>, dim3(nbig), dim3(SVD_WG), 0, P.stream, db, shs, flags, bst, nbm);
     IFMM_LAUNCH_CHECK();
     const int np = bigBlocks + (bigBlocks & 1);
     const size_t lds_b = (size_t)bigM * 2 * nb * sizeof(T);
@@ -527,7 +572,7 @@ inline void run_svd(Problem& P, const std::vector<SvdDesc>& v, DevBuf& scratch, 
       for (int r = 0; r < np - 1; ++r) {
         P.kone_begin(KF_SVD_ROUND, 0);
         hipLaunchKernelGGL(k_svd_round<T>, dim3((unsigned)(np / 2), (unsigned)nbig), dim3(SVD_WG), lds_b, P.stream,
-                           db, (const int*)shs, flags, nb, r, u, defl, 1);
+                           db, (const int*)shs, flags, nb, r, u, defl, 1, bst, nbm, sweep * 4096 + r);
         IFMM_LAUNCH_CHECK();
         P.kone_end();
         ++nrounds;
