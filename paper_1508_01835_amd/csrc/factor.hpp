@@ -609,28 +609,22 @@ struct Factorizer {
                  L.l, c, cf.el.size(), pmin, bmin, nf);
   }
 
-  // H = [A; G] and W_x of every elimination of a class (see ClassFactors):
-  // X = E_PP^-1 [I_m; 0] by the LU solve, G = E_FP X, A = X[0:m, :],
-  // W_x = W[0:m, :].
-  void solve_blocks(const std::vector<ElimDesc>& el, T* fac, int* piv, T* sol) {
-    CopyBatch<T, T> init, cp;
-    std::vector<TrsJob> xs;
+  // H = [A; G] and W_x of every elimination of a class (see ClassFactors),
+  // from X = E_PP^-1[:, 0:m] (the first m columns of the inverse): G = E_FP X,
+  // A = X[0:m, :], W_x = W[0:m, :].
+  void solve_blocks(const std::vector<ElimDesc>& el, T* fac, T* sol) {
+    CopyBatch<T, T> cp;
     GemmBatch gg;
     double fl = 0;
     for (const auto& e : el) {
       if (e.m == 0 || e.p == 0) continue;
-      init.add(nullptr, e.p, fac + e.xi, e.p, e.p, e.m, 2, 1.0);
-      xs.push_back({fac + e.lu, piv + e.piv, fac + e.xi, e.p, e.p, e.m, e.p});
       if (e.f > 0) {
         gg.add(fac + e.efp, e.f, 0, fac + e.xi, e.p, 0, sol + e.h + e.m, e.m + e.f, e.f, e.m, e.p, 1.0, 0.0);
         cp.add(fac + e.w, e.p, sol + e.wx, e.m, e.m, e.f, 0);
       }
       cp.add(fac + e.xi, e.p, sol + e.h, e.m + e.f, e.m, e.m, 0);
-      fl += 2.0 * e.p * (double)e.p * e.m + 2.0 * e.f * (double)e.p * e.m;
+      fl += 2.0 * e.f * (double)e.p * e.m;
     }
-    run_copy(P, init, F.d4);
-    P.kset(KF_TRSM, 0, 0);
-    lu_solve_blocked<T>(P, xs, F.lus);
     P.kset(KF_SCHUR, fl, 0);
     run_gemm<T>(P, gg, F.d5);
     P.kset(-1);
@@ -703,8 +697,9 @@ struct Factorizer {
         maxF = std::max(maxF, e.nF);
         e.lu = fo; fo += ((int64_t)e.p * e.p + 1) & ~int64_t(1);
         e.w = fo; fo += ((int64_t)e.p * e.f + 1) & ~int64_t(1);
+        e.epf = fo; fo += ((int64_t)e.p * e.f + 1) & ~int64_t(1);
         e.efp = fo; fo += ((int64_t)e.f * e.p + 1) & ~int64_t(1);
-        e.xi = fo; fo += ((int64_t)e.p * e.m + 1) & ~int64_t(1);
+        e.xi = fo; fo += ((int64_t)e.p * e.p + 1) & ~int64_t(1);
         e.h = so; so += ((int64_t)(e.m + e.f) * e.m + 1) & ~int64_t(1);
         e.wx = so; so += ((int64_t)e.m * e.f + 1) & ~int64_t(1);
         e.piv = po; po += e.p;
@@ -732,7 +727,7 @@ struct Factorizer {
         }
         flops_lu += 2.0 / 3.0 * e.p * (double)e.p * e.p + 2.0 * e.p * (double)e.p * e.f;
         flops_schur += 2.0 * e.f * (double)e.f * e.p;
-        flops_other += 2.0 * e.p * (double)e.p * e.m + 2.0 * e.f * (double)e.p * e.m;
+        flops_other += 2.0 * e.p * (double)e.p * e.p + 2.0 * e.f * (double)e.p * e.m;
         factor_elems += (int64_t)(e.m + e.f) * e.m + (int64_t)e.m * e.f;
         el.push_back(e);
       }
@@ -758,14 +753,20 @@ struct Factorizer {
       hipLaunchKernelGGL(k_gather<T>, dim3((unsigned)el.size(), maxF + 1), dim3(WG), 0, P.stream, del, dF,
                          (const T*)L.P(), fac);
       IFMM_LAUNCH_CHECK();
-      // LU with partial pivoting of every pivot block; W = E_PP^-1 E_PF
+      // LU with partial pivoting of every pivot block, E_PP^-1 by the LU solve of
+      // the identity, then W = E_PP^-1 E_PF as one product (instead of a
+      // triangular solve with |F| right-hand sides)
       std::vector<LuJob> lu;
       std::vector<TrsJob> ls;
-      GemmBatch gb;
+      CopyBatch<T, T> eye;
+      GemmBatch gb, gw;
       for (const auto& e : el) {
         if (e.p > 0) {
           lu.push_back({fac + e.lu, piv + e.piv, e.p, e.p, l * 1000000 + e.box});
-          if (e.f > 0) ls.push_back({fac + e.lu, piv + e.piv, fac + e.w, e.p, e.p, e.f, e.p});
+          eye.add(nullptr, e.p, fac + e.xi, e.p, e.p, e.p, 2, 1.0);
+          ls.push_back({fac + e.lu, piv + e.piv, fac + e.xi, e.p, e.p, e.p, e.p});
+          if (e.f > 0)
+            gw.add(fac + e.xi, e.p, 0, fac + e.epf, e.p, 0, fac + e.w, e.p, e.p, e.f, e.p, 1.0, 0.0);
         }
         // Schur fill D = -E_FP W (f x f, inner p)
         gb.add(fac + e.efp, std::max(e.f, 1), 0, fac + e.w, std::max(e.p, 1), 0, W + e.dlt, std::max(e.f, 1), e.f,
@@ -789,21 +790,23 @@ struct Factorizer {
       for (const auto& e : el) {
         const double p = e.p, f = e.f;
         flu += 2.0 / 3.0 * p * p * p;
-        ftr += 2.0 * p * p * f;
+        ftr += 2.0 * p * p * p + 2.0 * p * p * f;
         fsc += 2.0 * f * f * p;
         bsc += sizeof(T) * (2.0 * f * p + f * f);   // read E_FP and W once, write D once
       }
       P.kset(KF_LU, flu, 0);
       lu_blocked<T>(P, lu, F.lus);
       chk(L, "lu", &F.arena, 0);
+      run_copy(P, eye, F.d4);
       P.kset(KF_TRSM, ftr, 0);
       lu_solve_blocked<T>(P, ls, F.lus);
+      run_gemm<T>(P, gw, F.d5);
       chk(L, "lu_solve", &F.arena, 0);
       P.kset(KF_SCHUR, fsc, bsc);
       run_gemm<T>(P, gb, F.d5);
       P.kset(-1);
       chk(L, "schur", nullptr, wo);
-      solve_blocks(el, fac, piv, sol);
+      solve_blocks(el, fac, sol);
       chk(L, "solve_blocks", &F.arena, 0);
       const LevelView v = L.view(P);
       // near fill: added to existing edges

@@ -18,7 +18,7 @@ struct FNode {
 
 struct ElimDesc {
   int box, m, r, p, f, nF, F0, pad;
-  int64_t lu, w, efp, xi, piv, dlt;   // class arena (lu, w, efp, xi), int arena (piv), workspace (dlt)
+  int64_t lu, w, epf, efp, xi, piv, dlt;   // class arena (lu, w, epf, efp, xi), int arena (piv), workspace (dlt)
   int64_t h, wx;                      // solve store: H = [A; G] ((m + f) x m), W_x (m x f)
   int64_t S, U, V;                    // pool offsets of S(i,i), U_i, V_i (ld m_i)
 };
@@ -78,7 +78,7 @@ __global__ void __launch_bounds__(WG) k_gather(const ElimDesc* __restrict__ es, 
   if (a > e.nF) return;
   const int m = e.m, r = e.r, p = e.p, f = e.f;
   T* EPP = arena + e.lu;
-  T* EPF = arena + e.w;
+  T* EPF = arena + e.epf;
   T* EFP = arena + e.efp;
   if (a == e.nF) {
     for (int t = threadIdx.x; t < p * p; t += WG) {
