@@ -324,41 +324,58 @@ __global__ void __launch_bounds__(QR_WG) k_qr_panel(const QrPanel* __restrict__ 
   __shared__ T red[QR_WG / WAVE];
   __shared__ T G[QR_NB * QR_NB];
   const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE, nw = QR_WG / WAVE;
+  // The panel is scaled once by the exact power of two that brings its largest
+  // entry into [1, 2), so that squares of tiny or huge entries neither underflow
+  // nor overflow (a reciprocal of a subnormal maximum would overflow); the
+  // Householder vectors are scale-free, the R entries are scaled back at the end.
+  T am = 0;
+  for (int64_t e = threadIdx.x; e < (int64_t)mv * nb; e += QR_WG)
+    am = fmax(am, fabs(A[(j0 + e % mv) + (j0 + e / mv) * lda]));
+  am = block_max(am, red);
+  const int sh = am > (T)0 ? -ilogb((double)am) : 0;
+  for (int64_t e = threadIdx.x; e < (int64_t)mv * nb; e += QR_WG) {
+    T* a = &A[(j0 + e % mv) + (j0 + e / mv) * lda];
+    *a = ldexp(*a, sh);
+  }
+  __syncthreads();
   for (int jj = 0; jj < nb; ++jj) {
     const int j = j0 + jj;
-    T amax = 0;
-    for (int i = j + threadIdx.x; i < M; i += QR_WG) amax = fmax(amax, fabs(A[i + j * lda]));
-    amax = block_max(amax, red);
     const T x0 = A[j + j * lda];
+    T s = 0;
+    for (int i = j + 1 + threadIdx.x; i < M; i += QR_WG) { const T x = A[i + j * lda]; s += x * x; }
+    s = block_sum(s, red);
     T tj = 0, al = x0;
-    if (amax > (T)0) {
-      // exact power-of-two scaling by 1 / amax: a reciprocal of a subnormal
-      // amax would overflow
-      const int sh = -ilogb((double)amax);
-      T s = 0;
-      for (int i = j + threadIdx.x; i < M; i += QR_WG) { const T x = ldexp(A[i + j * lda], sh); s += x * x; }
-      s = block_sum(s, red);
-      const T x0s = ldexp(x0, sh);
-      const T als = x0s >= (T)0 ? -sqrt(s) : sqrt(s);
-      al = ldexp(als, -sh);
-      tj = (als - x0s) / als;
-      const T scal = (T)1 / (x0s - als);
-      for (int i = j + 1 + threadIdx.x; i < M; i += QR_WG) A[i + j * lda] = ldexp(A[i + j * lda], sh) * scal;
+    if (s > (T)0) {
+      al = x0 >= (T)0 ? -sqrt(x0 * x0 + s) : sqrt(x0 * x0 + s);
+      tj = (al - x0) / al;
+      const T scal = (T)1 / (x0 - al);
+      for (int i = j + 1 + threadIdx.x; i < M; i += QR_WG) A[i + j * lda] *= scal;
       __syncthreads();
       if (threadIdx.x == 0) A[j + j * lda] = (T)1;
     }
-    if (threadIdx.x == 0) { tau[jj] = tj; alph[j] = al; }
+    if (threadIdx.x == 0) { tau[jj] = tj; alph[j] = ldexp(al, -sh); }
     __syncthreads();
     if (tj != (T)0) {
       for (int c = j + 1 + wv; c < j0 + nb; c += nw) {
-        T dot = 0;
-        for (int i = j + lane; i < M; i += WAVE) dot += A[i + j * lda] * A[i + c * lda];
-        dot = wave_sum(dot) * tj;
-        for (int i = j + lane; i < M; i += WAVE) A[i + c * lda] -= dot * A[i + j * lda];
+        T d0 = 0, d1 = 0;   // two chains for more loads in flight
+        int i = j + lane;
+        for (; i + WAVE < M; i += 2 * WAVE) {
+          d0 += A[i + j * lda] * A[i + c * lda];
+          d1 += A[i + WAVE + j * lda] * A[i + WAVE + c * lda];
+        }
+        if (i < M) d0 += A[i + j * lda] * A[i + c * lda];
+        const T dot = wave_sum(d0 + d1) * tj;
+        for (int i2 = j + lane; i2 < M; i2 += WAVE) A[i2 + c * lda] -= dot * A[i2 + j * lda];
       }
     }
     __syncthreads();
   }
+  // R entries of the panel rows, strictly right of the diagonal, back to their scale
+  for (int e = threadIdx.x; e < nb * nb; e += QR_WG) {
+    const int r = e % nb, c = e / nb;
+    if (r < c) A[(j0 + r) + (j0 + c) * lda] = ldexp(A[(j0 + r) + (j0 + c) * lda], -sh);
+  }
+  __syncthreads();
   // V with explicit unit diagonal and zeros above it
   for (int64_t e = threadIdx.x; e < (int64_t)mv * nb; e += QR_WG) {
     const int i = (int)(e % mv), c = (int)(e / mv);
