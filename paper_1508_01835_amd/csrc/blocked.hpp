@@ -106,11 +106,12 @@ __global__ void __launch_bounds__(WG) k_lu_swap_trsm(const PanelDesc* __restrict
     if (i < nb) x[i] = A[(k0 + i) + c * ld];
 #pragma unroll
   for (int i = 0; i < LU_NB; ++i) {
-    if (i >= nb) break;
-    const T xi = x[i];
+    if (i < nb) {
+      const T xi = x[i];
 #pragma unroll
-    for (int r = i + 1; r < LU_NB; ++r)
-      if (r < nb) x[r] -= A[(k0 + r) + (int64_t)(k0 + i) * ld] * xi;
+      for (int r = i + 1; r < LU_NB; ++r)
+        if (r < nb) x[r] -= A[(k0 + r) + (int64_t)(k0 + i) * ld] * xi;
+    }
   }
 #pragma unroll
   for (int i = 0; i < LU_NB; ++i)
@@ -127,7 +128,7 @@ struct TrsDesc {
 
 // B <- P B (all n interchanges), one thread per column.
 template <class T>
-__global__ void k_apply_piv(const TrsDesc* __restrict__ ds) {
+__global__ void __launch_bounds__(WG) k_apply_piv(const TrsDesc* __restrict__ ds) {
   const TrsDesc d = ds[blockIdx.x];
   const int c = blockIdx.y * WG + threadIdx.x;
   if (c >= d.ncols) return;
@@ -141,7 +142,7 @@ __global__ void k_apply_piv(const TrsDesc* __restrict__ ds) {
 // Diagonal block solve: lower unit (upper = 0) or upper non-unit (upper = 1)
 // on rows k0..k0+nb-1 of every column.
 template <class T>
-__global__ void k_trs_diag(const TrsDesc* __restrict__ ds, int upper) {
+__global__ void __launch_bounds__(WG) k_trs_diag(const TrsDesc* __restrict__ ds, int upper) {
   const TrsDesc d = ds[blockIdx.x];
   const int c = blockIdx.y * WG + threadIdx.x;
   if (c >= d.ncols) return;
@@ -156,21 +157,23 @@ __global__ void k_trs_diag(const TrsDesc* __restrict__ ds, int upper) {
   if (!upper) {
 #pragma unroll
     for (int i = 0; i < LU_NB; ++i) {
-      if (i >= nb) break;
-      const T xi = x[i];
+      if (i < nb) {
+        const T xi = x[i];
 #pragma unroll
-      for (int r = i + 1; r < LU_NB; ++r)
-        if (r < nb) x[r] -= L[(k0 + r) + (int64_t)(k0 + i) * ld] * xi;
+        for (int r = i + 1; r < LU_NB; ++r)
+          if (r < nb) x[r] -= L[(k0 + r) + (int64_t)(k0 + i) * ld] * xi;
+      }
     }
   } else {
 #pragma unroll
     for (int i = LU_NB - 1; i >= 0; --i) {
-      if (i >= nb) continue;
-      const T xi = x[i] / L[(k0 + i) + (int64_t)(k0 + i) * ld];
-      x[i] = xi;
+      if (i < nb) {
+        const T xi = x[i] / L[(k0 + i) + (int64_t)(k0 + i) * ld];
+        x[i] = xi;
 #pragma unroll
-      for (int r = 0; r < LU_NB; ++r)
-        if (r < i) x[r] -= L[(k0 + r) + (int64_t)(k0 + i) * ld] * xi;
+        for (int r = 0; r < LU_NB; ++r)
+          if (r < i) x[r] -= L[(k0 + r) + (int64_t)(k0 + i) * ld] * xi;
+      }
     }
   }
 #pragma unroll

@@ -448,26 +448,52 @@ __global__ void __launch_bounds__(SVD_WG) k_qrcp(const QrcpDesc* __restrict__ ds
     if (threadIdx.x == 0) sh_tau = tau;
     __syncthreads();
     tau = sh_tau;
-    // apply to the trailing columns, one wavefront per column, and downdate its partial norm
-    for (int j = s + 1 + wv; j < n; j += nw) {
-      T w = 0;
-      for (int i = s + lane; i < m; i += WAVE) w += hv[i] * R[i + (int64_t)j * ld];
-      w = wave_sum(w) * tau;
-      T rs = 0, rest = 0;
+    // apply to the trailing columns, four per wavefront at a time (their
+    // reductions overlap), and downdate their partial norms; lane 0 holds row
+    // s, and the rest of a column is reduced only when its norm is recomputed
+    for (int jc = s + 1 + wv * 4; jc < n; jc += nw * 4) {
+      T w[4] = {0, 0, 0, 0};
       for (int i = s + lane; i < m; i += WAVE) {
-        const T x = R[i + (int64_t)j * ld] - w * hv[i];
-        R[i + (int64_t)j * ld] = x;
-        if (i == s) rs = x;
-        else rest += x * x;
+        const T h = hv[i];
+#pragma unroll
+        for (int g = 0; g < 4; ++g)
+          if (jc + g < n) w[g] += h * R[i + (int64_t)(jc + g) * ld];
       }
-      rs = wave_sum(rs);     // only the lane holding row s contributes
-      rest = wave_sum(rest);
-      if (lane == 0 && vn1[j] != (T)0) {
-        const T r = fabs(rs) / vn1[j];
-        const T t = fmax((T)0, ((T)1 + r) * ((T)1 - r));
-        const T q = vn1[j] / vn2[j];
-        if (t * q * q <= tol3z) { vn1[j] = sqrt(rest); vn2[j] = vn1[j]; }
-        else vn1[j] *= sqrt(t);
+#pragma unroll
+      for (int g = 0; g < 4; ++g) w[g] = wave_sum(w[g]) * tau;
+      T rs[4] = {0, 0, 0, 0}, rest[4] = {0, 0, 0, 0};
+      for (int i = s + lane; i < m; i += WAVE) {
+        const T h = hv[i];
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+          if (jc + g < n) {
+            const T x = R[i + (int64_t)(jc + g) * ld] - w[g] * h;
+            R[i + (int64_t)(jc + g) * ld] = x;
+            if (i == s) rs[g] = x;
+            else rest[g] += x * x;
+          }
+        }
+      }
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const int j = jc + g;
+        if (j < n) {
+          int need = 0;   // 1: recompute the partial norm, 2: downdate it by t
+          T t = 0;
+          if (lane == 0 && vn1[j] != (T)0) {
+            const T r = fabs(rs[g]) / vn1[j];
+            t = fmax((T)0, ((T)1 + r) * ((T)1 - r));
+            const T q = vn1[j] / vn2[j];
+            need = t * q * q <= tol3z ? 1 : 2;
+          }
+          need = __shfl(need, 0, WAVE);
+          if (need == 1) {
+            const T tot = wave_sum(rest[g]);
+            if (lane == 0) { vn1[j] = sqrt(tot); vn2[j] = vn1[j]; }
+          } else if (need == 2 && lane == 0) {
+            vn1[j] *= sqrt(t);
+          }
+        }
       }
     }
     __syncthreads();
