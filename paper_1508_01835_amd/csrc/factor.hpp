@@ -77,6 +77,7 @@ struct FactorStore : FactorStoreBase {
   DevBuf arena, pivs;                              // transient blocks of the class being eliminated
   // scratch reused across calls
   DevBuf work, d1, d2, d3, d4, d5;
+  DevBuf rtmp;                                     // redirect: U^T D products of x~-x~ pairs
   LuScratch lus;
   QrScratch qrs;
 };
@@ -631,6 +632,69 @@ struct Factorizer {
     run_copy(P, cp, F.d4);
   }
 
+  // Redirect the compressed well-separated fill through K (eq. K_kj_update,
+  // Alg. 3): for every ordered pair (a, b) of F of an elimination whose boxes
+  // are not adjacent (and not both y), K(a, b) += op_a(D(a, b)) op_b with
+  // op = Uhat^T on an x~ row side and Vhat on an x~ column side, as batched
+  // products: x~-x~ pairs through T = Uhat_a^T D(a, b), then K += T Vhat_b; an
+  // x~-y or y-x~ pair in one product. The new ranks are read once per class.
+  void redirect(LevelPool<T>& L, const std::vector<ElimDesc>& el, const std::vector<FNode>& Fs,
+                const HLevel& lv) {
+    P.download(L.r, L.dr.p, (size_t)L.nb);
+    T* Wk = F.work.template as<T>();
+    T* pool = L.P();
+    GemmBatch g1, g2;
+    struct Pend { const T* D; int ldD, ma, mb, ka, kb; int64_t dst, ua, vb; int ld; };
+    std::vector<Pend> xx;
+    int64_t tmp = 0;
+    double fl = 0;
+    for (const auto& e : el) {
+      for (int ia = 0; ia < e.nF; ++ia) {
+        const FNode& A = Fs[e.F0 + ia];
+        for (int ib = 0; ib < e.nF; ++ib) {
+          const FNode& B = Fs[e.F0 + ib];
+          if (A.type == 1 && B.type == 1) continue;
+          if (adjacent(lv, P.d, A.box, B.box)) continue;
+          const int code = offset7(lv, P.d, A.box, B.box);
+          if (code < 0) continue;
+          const int64_t dst = L.Kt[(size_t)A.box * L.c7 + code];
+          if (dst < 0) continue;
+          const int ka = A.type == 0 ? L.r[A.box] : A.dim;
+          const int kb = B.type == 0 ? L.r[B.box] : B.dim;
+          if (ka == 0 || kb == 0 || A.dim == 0 || B.dim == 0) continue;
+          const T* D = Wk + e.dlt + A.off + (int64_t)B.off * e.f;
+          const int ld = L.cap[A.box];
+          if (A.type == 0 && B.type == 0) {
+            xx.push_back({D, e.f, A.dim, B.dim, ka, kb, dst, L.Uo[A.box], L.Vo[B.box], ld});
+            tmp += ((int64_t)ka * B.dim + 1) & ~int64_t(1);
+            fl += 2.0 * ka * A.dim * B.dim + 2.0 * ka * B.dim * kb;
+          } else if (A.type == 0) {   // Uhat_a^T D
+            g1.add(pool + L.Uo[A.box], A.dim, 1, D, e.f, 0, pool + dst, ld, ka, kb, A.dim, 1.0, 1.0);
+            fl += 2.0 * ka * A.dim * kb;
+          } else {                    // D Vhat_b
+            g1.add(D, e.f, 0, pool + L.Vo[B.box], B.dim, 0, pool + dst, ld, ka, kb, B.dim, 1.0, 1.0);
+            fl += 2.0 * ka * B.dim * kb;
+          }
+        }
+      }
+    }
+    if (!xx.empty()) {
+      if ((size_t)tmp * sizeof(T) > F.rtmp.bytes) P.sync();
+      F.rtmp.reserve(sizeof(T) * (size_t)std::max<int64_t>(tmp, 2), &P.mem);
+      T* Tb = F.rtmp.template as<T>();
+      int64_t o = 0;
+      for (const auto& x : xx) {
+        g1.add(pool + x.ua, x.ma, 1, x.D, x.ldD, 0, Tb + o, x.ka, x.ka, x.mb, x.ma, 1.0, 0.0);
+        g2.add(Tb + o, x.ka, 0, pool + x.vb, x.mb, 0, pool + x.dst, x.ld, x.ka, x.kb, x.mb, 1.0, 1.0);
+        o += ((int64_t)x.ka * x.mb + 1) & ~int64_t(1);
+      }
+    }
+    P.kset(KF_XFORM, fl, 0);
+    run_gemm<T>(P, g1, F.d5);
+    run_gemm<T>(P, g2, F.d5);
+    P.kset(-1);
+  }
+
   // ----------------------------------------------------------- one level
   void eliminate_level(LevelPool<T>& L) {
     const int l = L.l;
@@ -818,9 +882,21 @@ struct Factorizer {
       chk(L, "near_scatter", nullptr, wo);
       recompress(L, cs, el, del, dF, wo);
       chk(L, "recompress", nullptr, 0);
-      hipLaunchKernelGGL(k_redirect<T>, dim3((unsigned)el.size(), maxF * maxF), dim3(WG), 0, P.stream, del, dF, v,
-                         (const T*)F.work.template as<T>(), L.P());
-      IFMM_LAUNCH_CHECK();
+      {   // coarse levels (large ranks): batched products; fine levels: one workgroup per pair on the device
+        int rmax = 0;
+        for (int x : L.cap) rmax = std::max(rmax, x);
+        if (rmax > XF_SMALL_R) {
+          redirect(L, el, Fs, lv);
+        } else {
+          P.kset(KF_XFORM);
+          P.kbegin();
+          hipLaunchKernelGGL(k_redirect<T>, dim3((unsigned)el.size(), maxF * maxF), dim3(WG), 0, P.stream, del, dF, v,
+                             (const T*)F.work.template as<T>(), L.P());
+          IFMM_LAUNCH_CHECK();
+          P.kend();
+          P.kset(-1);
+        }
+      }
       if (debug_on()) debug_class(L, cf, c);
     }
     P.download(L.r, L.dr.p, (size_t)lv.nb);
