@@ -29,6 +29,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 os.environ.setdefault("IFMM_KTIMING", "1")
 
+# HBM bytes per launch of a roofline kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE counter runs, scaled by
+# what the counters read for a 512 MiB device copy (profiles/k_qr_panel_uniform3d_65536.txt); valid for the
+# kernel version the counters were taken on
+MEASURED_TRAFFIC = {"k_qr_panel<double>": 1.203e9}
+
 PEAKS = {  # MI355X published peaks
     "hbm_GBs": 8000.0,
     "fp64_TFs": 78.6,      # FP64 vector and FP64 matrix (dense)
@@ -164,6 +169,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n", type=int, default=65536)
     ap.add_argument("--depth", type=int, default=5)
+    ap.add_argument("--quick", action="store_true",
+                    help="timed steps only: no latency, time-to-tolerance or CPU runs (for counter runs)")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="end with a 512 MiB device-to-device copy, the reference for HBM byte counters")
     ap.add_argument("--workload", choices=["uniform3d", "batch", "serve"], default="uniform3d")
     ap.add_argument("--serve-count", type=int, default=200)
     ap.add_argument("--rate", type=float, default=1.0)
@@ -228,13 +237,28 @@ def main():
     # FP64 arithmetic on the vector ALUs (FMA): 256 CUs x 2.4 GHz x 128 flop/clk = 78.6 TFLOP/s
     achieved = fam_fl[dom] / (fam_ms[dom] * 1e-3) / 1e12
     roof = {"bound": "alu", "achieved": achieved, "peak": PEAKS["fp64_TFs"], "unit": "TFLOP/s",
-            "frac": achieved / PEAKS["fp64_TFs"], "traffic": None,
+            "frac": achieved / PEAKS["fp64_TFs"],
+            "traffic": MEASURED_TRAFFIC.get(KERNEL_OF_FAMILY[name] + "<double>"),
             "kernel": KERNEL_OF_FAMILY[name] + "<double>",
             "launches_per_step": fam_nl[dom] / args.steps,
             "avg_launch_ms": fam_ms[dom] / max(fam_nl[dom], 1),
             "flops_per_launch": fam_fl[dom] / max(fam_nl[dom], 1)}
     breakdown = {FAMILIES[f]: round(fam_ms[f] / args.steps, 2) for f in range(len(FAMILIES)) if fam_ms[f] > 0}
 
+    if args.quick:
+        for h in handles:
+            h[0].close()
+        out = {"metric": "IFMM factor Mpts/s (quick run)", "value": n * args.steps / T / 1e6, "unit": "Mpts/s",
+               "ms_per_step": T / args.steps * 1e3, "kernel_ms_per_step": breakdown, "roofline": roof}
+        if args.calib_copy:
+            src = torch.ones(64 << 20, dtype=torch.float64, device=dev)   # 512 MiB
+            dst = torch.empty_like(src)
+            torch.cuda.synchronize()
+            dst.copy_(src)
+            torch.cuda.synchronize()
+            out["calib_copy_bytes"] = src.numel() * 8
+        print(json.dumps(out))
+        return
     g0 = handles[0][0]
     st0 = stats[0]
     factor_ms = float(np.mean([s["t_factor_ms"] for s in stats]))
