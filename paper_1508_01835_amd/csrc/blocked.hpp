@@ -313,102 +313,302 @@ struct QrPanel {
   int M, N, lda, j0, nb, pad;
 };
 
+// Sum of 32 per-lane values over the 64 lanes of a wavefront, reduce-scattered:
+// each exchange halves the values a lane keeps, so the whole reduction takes
+// 32 shuffles instead of 32 x 6. On return lanes 2c and 2c+1 hold the sum of
+// value c.
 template <class T>
-__global__ void __launch_bounds__(QR_WG) k_qr_panel(const QrPanel* __restrict__ ds) {
-  const QrPanel d = ds[blockIdx.x];
+__device__ inline T wave_sum32_scatter(const T (&v)[32], int lane) {
+  T a[16];
+  {
+    const bool hi = lane & 32;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const T keep = hi ? v[k + 16] : v[k], send = hi ? v[k] : v[k + 16];
+      a[k] = keep + __shfl_xor(send, 32, WAVE);
+    }
+  }
+  T b[8];
+  {
+    const bool hi = lane & 16;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const T keep = hi ? a[k + 8] : a[k], send = hi ? a[k] : a[k + 8];
+      b[k] = keep + __shfl_xor(send, 16, WAVE);
+    }
+  }
+  T c[4];
+  {
+    const bool hi = lane & 8;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const T keep = hi ? b[k + 4] : b[k], send = hi ? b[k] : b[k + 4];
+      c[k] = keep + __shfl_xor(send, 8, WAVE);
+    }
+  }
+  T e[2];
+  {
+    const bool hi = lane & 4;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const T keep = hi ? c[k + 2] : c[k], send = hi ? c[k] : c[k + 2];
+      e[k] = keep + __shfl_xor(send, 4, WAVE);
+    }
+  }
+  const bool hi = lane & 2;
+  T f = (hi ? e[1] : e[0]) + __shfl_xor(hi ? e[0] : e[1], 2, WAVE);
+  return f + __shfl_xor(f, 1, WAVE);
+}
+
+// Raw buffer access (gfx9 buffer resource: base, byte extent, 32-bit data
+// format word). One 32-bit per-lane byte offset serves every column of a
+// panel; the column offset is wave-uniform and goes in a scalar register, so a
+// row's 32 loads need no per-column address registers. Accesses past the
+// extent read zero and drop writes.
+__device__ inline __amdgpu_buffer_rsrc_t buf_rsrc(void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(base, (short)0, (int)bytes, 0x00020000);
+}
+template <class T>
+__device__ inline T buf_ld(__amdgpu_buffer_rsrc_t r, int vo, int so);
+template <>
+__device__ inline double buf_ld<double>(__amdgpu_buffer_rsrc_t r, int vo, int so) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
+}
+template <>
+__device__ inline float buf_ld<float>(__amdgpu_buffer_rsrc_t r, int vo, int so) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
+}
+__device__ inline void buf_st(double v, __amdgpu_buffer_rsrc_t r, int vo, int so) {
+  using B = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(B, v), r, vo, so, 0);
+}
+__device__ inline void buf_st(float v, __amdgpu_buffer_rsrc_t r, int vo, int so) {
+  using B = decltype(__builtin_amdgcn_raw_buffer_load_b32(r, 0, 0, 0));
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(B, v), r, vo, so, 0);
+}
+
+// One panel of QR_NB columns per workgroup. Each thread owns the panel rows
+// i = tid + k QR_WG and reads a row's panel columns together (independent
+// loads from one per-lane offset), so the panel streams at bandwidth instead of
+// one dependent column walk per wavefront. Per Householder column j:
+//   the norm of the column below the diagonal (one block reduction; after the
+//   first column it is accumulated by the previous update pass);
+//   v = scaled column, and the products of v with every panel column in one
+//   pass: those right of j are the trailing-update coefficients, those left
+//   of j are the entries V^T v of the Gram matrix that builds T;
+//   the rank-one update of the columns right of j.
+// T follows from the Gram entries row by row (row i of T needs only row i).
+// FULL: the panel has exactly QR_NB columns, so no column test is needed and
+// the update stores whole chunks (finished columns get a zero coefficient and
+// are rewritten unchanged). Otherwise columns past the panel are skipped one by
+// one.
+template <class T, bool FULL>
+__device__ __forceinline__ void qr_panel_run(const QrPanel& d) {
+  constexpr int NW = QR_WG / WAVE;
+  constexpr int QC = 4;   // columns loaded together per row
   T* __restrict__ A = static_cast<T*>(d.A);
   T* __restrict__ V = static_cast<T*>(d.V);
   T* __restrict__ Tm = static_cast<T*>(d.Tm);
   T* __restrict__ alph = static_cast<T*>(d.alph);
-  const int M = d.M, j0 = d.j0, nb = d.nb;
+  const int j0 = d.j0;
+  const int nb = FULL ? QR_NB : d.nb;
   const int64_t lda = d.lda;
-  const int mv = M - j0;
+  const int mv = d.M - j0;
   __shared__ T tau[QR_NB];
-  __shared__ T red[QR_WG / WAVE];
-  __shared__ T G[QR_NB * QR_NB];
-  const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE, nw = QR_WG / WAVE;
+  __shared__ T red[NW];
+  __shared__ T part[NW][QR_NB];
+  __shared__ T dots[QR_NB];        // tau_j times the products of v_j with the panel columns right of j
+  __shared__ T G[QR_NB * QR_NB];   // G[k + j QR_NB] = V(:,k)^T V(:,j), k < j
+  __shared__ T Ts[QR_NB * QR_NB];
+  const int tid = threadIdx.x, lane = tid % WAVE, wv = tid / WAVE;
+  T* P = A + j0 + (int64_t)j0 * lda;   // panel: P[i + c lda], i < mv, c < nb
+  const int ldb = (int)lda * (int)sizeof(T);   // the host checks QR_NB lda sizeof(T) < 2^31
+  const __amdgpu_buffer_rsrc_t rs = buf_rsrc(P, (uint32_t)(((int64_t)(nb - 1) * lda + mv) * sizeof(T)));
+  // element (i, c); past a partial panel, columns alias its last one (loaded, never stored)
+  auto ld = [&](int c, int i) {
+    return buf_ld<T>(rs, i * (int)sizeof(T), (FULL || c < nb ? c : nb - 1) * ldb);
+  };
+  auto st = [&](int c, int i, T v) { buf_st(v, rs, i * (int)sizeof(T), c * ldb); };
+
   // The panel is scaled once by the exact power of two that brings its largest
   // entry into [1, 2), so that squares of tiny or huge entries neither underflow
-  // nor overflow (a reciprocal of a subnormal maximum would overflow); the
-  // Householder vectors are scale-free, the R entries are scaled back at the end.
+  // nor overflow; the Householder vectors are scale-free, the R entries are
+  // scaled back at the end.
   T am = 0;
-  for (int64_t e = threadIdx.x; e < (int64_t)mv * nb; e += QR_WG)
-    am = fmax(am, fabs(A[(j0 + e % mv) + (j0 + e / mv) * lda]));
+  for (int i = tid; i < mv; i += QR_WG) {
+#pragma unroll
+    for (int q = 0; q < QR_NB; q += QC) {
+      if (FULL || q < nb) {
+        T x[QC];
+#pragma unroll
+        for (int k = 0; k < QC; ++k) x[k] = ld(q + k, i);
+#pragma unroll
+        for (int k = 0; k < QC; ++k) am = fmax(am, fabs(x[k]));
+      }
+    }
+  }
   am = block_max(am, red);
   const int sh = am > (T)0 ? -ilogb((double)am) : 0;
-  for (int64_t e = threadIdx.x; e < (int64_t)mv * nb; e += QR_WG) {
-    T* a = &A[(j0 + e % mv) + (j0 + e / mv) * lda];
-    *a = ldexp(*a, sh);
-  }
-  __syncthreads();
-  for (int jj = 0; jj < nb; ++jj) {
-    const int j = j0 + jj;
-    const T x0 = A[j + j * lda];
-    T s = 0;
-    for (int i = j + 1 + threadIdx.x; i < M; i += QR_WG) { const T x = A[i + j * lda]; s += x * x; }
-    s = block_sum(s, red);
-    T tj = 0, al = x0;
-    if (s > (T)0) {
-      al = x0 >= (T)0 ? -sqrt(x0 * x0 + s) : sqrt(x0 * x0 + s);
-      tj = (al - x0) / al;
-      const T scal = (T)1 / (x0 - al);
-      for (int i = j + 1 + threadIdx.x; i < M; i += QR_WG) A[i + j * lda] *= scal;
-      __syncthreads();
-      if (threadIdx.x == 0) A[j + j * lda] = (T)1;
-    }
-    if (threadIdx.x == 0) { tau[jj] = tj; alph[j] = ldexp(al, -sh); }
-    __syncthreads();
-    if (tj != (T)0) {
-      for (int c = j + 1 + wv; c < j0 + nb; c += nw) {
-        T d0 = 0, d1 = 0;   // two chains for more loads in flight
-        int i = j + lane;
-        for (; i + WAVE < M; i += 2 * WAVE) {
-          d0 += A[i + j * lda] * A[i + c * lda];
-          d1 += A[i + WAVE + j * lda] * A[i + WAVE + c * lda];
+  if (sh != 0)
+    for (int i = tid; i < mv; i += QR_WG) {
+#pragma unroll
+      for (int q = 0; q < QR_NB; q += QC) {
+        if (FULL || q < nb) {
+          T x[QC];
+#pragma unroll
+          for (int k = 0; k < QC; ++k) x[k] = ld(q + k, i);
+#pragma unroll
+          for (int k = 0; k < QC; ++k)
+            if (FULL || q + k < nb) st(q + k, i, ldexp(x[k], sh));
         }
-        if (i < M) d0 += A[i + j * lda] * A[i + c * lda];
-        const T dot = wave_sum(d0 + d1) * tj;
-        for (int i2 = j + lane; i2 < M; i2 += WAVE) A[i2 + c * lda] -= dot * A[i2 + j * lda];
       }
+    }
+  __syncthreads();
+
+  // partial sum of squares of the next column below its diagonal, taken while
+  // the previous rank-one update writes that column
+  T s_next = 0;
+  bool have_next = false;
+  for (int jj = 0; jj < nb; ++jj) {
+    const T x0 = ld(jj, jj);
+    T s = s_next;
+    if (!have_next) {
+      s = 0;
+      for (int i = tid; i < mv; i += QR_WG)
+        if (i > jj) { const T x = ld(jj, i); s += x * x; }
+    }
+    have_next = false;
+    s_next = 0;
+    s = block_sum(s, red);
+    if (!(s > (T)0)) {   // nothing below the diagonal: the reflector is the identity
+      if (tid == 0) { tau[jj] = 0; alph[j0 + jj] = ldexp(x0, -sh); }
+      continue;
+    }
+    const T al = x0 >= (T)0 ? -sqrt(x0 * x0 + s) : sqrt(x0 * x0 + s);
+    const T tj = (al - x0) / al;
+    const T scal = (T)1 / (x0 - al);
+    if (tid == 0) { tau[jj] = tj; alph[j0 + jj] = ldexp(al, -sh); }
+    // v (unit at row jj) and its products with every panel column
+    T acc[QR_NB];
+#pragma unroll
+    for (int c = 0; c < QR_NB; ++c) acc[c] = 0;
+    for (int i = tid; i < mv; i += QR_WG) {
+      if (i < jj) continue;
+      const T v = i == jj ? (T)1 : ld(jj, i) * scal;
+      st(jj, i, v);
+#pragma unroll
+      for (int q = 0; q < QR_NB; q += QC) {
+        if (FULL || q < nb) {
+          T x[QC];
+#pragma unroll
+          for (int k = 0; k < QC; ++k) x[k] = ld(q + k, i);
+#pragma unroll
+          for (int k = 0; k < QC; ++k) acc[q + k] += v * x[k];
+        }
+      }
+    }
+    const T r = wave_sum32_scatter(acc, lane);
+    if ((lane & 1) == 0) part[wv][lane >> 1] = r;
+    __syncthreads();
+    if (tid < QR_NB) {
+      T t = 0;
+      for (int w = 0; w < NW; ++w) t += part[w][tid];
+      dots[tid] = tid > jj ? tj * t : (T)0;
+      if (tid < jj) G[tid + jj * QR_NB] = t;
+    }
+    __syncthreads();
+    if (jj + 1 < nb) {
+      // the loads of a chunk pair are in flight together before their stores
+      constexpr int HC = 2 * QC;
+      const int nx = jj + 1;
+      for (int i = tid; i < mv; i += QR_WG) {
+        if (i < jj) continue;
+        const T v = ld(jj, i);
+#pragma unroll
+        for (int h = 0; h < QR_NB; h += HC) {
+          if (h + HC - 1 > jj && (FULL || h < nb)) {
+            T x[HC];
+#pragma unroll
+            for (int k = 0; k < HC; ++k) x[k] = ld(h + k, i);
+#pragma unroll
+            for (int k = 0; k < HC; ++k) x[k] -= dots[h + k] * v;
+            if (FULL) {
+#pragma unroll
+              for (int q = 0; q < HC; q += QC)
+                if (h + q + QC - 1 > jj) {
+#pragma unroll
+                  for (int k = 0; k < QC; ++k) st(h + q + k, i, x[q + k]);
+                }
+            } else {
+#pragma unroll
+              for (int k = 0; k < HC; ++k)
+                if (h + k > jj && h + k < nb) st(h + k, i, x[k]);
+            }
+            if (nx >= h && nx < h + HC && i > nx) {
+              T y = x[0];
+#pragma unroll
+              for (int k = 1; k < HC; ++k) y = nx == h + k ? x[k] : y;
+              s_next += y * y;
+            }
+          }
+        }
+      }
+      have_next = true;
     }
     __syncthreads();
   }
+  __syncthreads();
   // R entries of the panel rows, strictly right of the diagonal, back to their scale
-  for (int e = threadIdx.x; e < nb * nb; e += QR_WG) {
+  for (int e = tid; e < nb * nb; e += QR_WG) {
     const int r = e % nb, c = e / nb;
-    if (r < c) A[(j0 + r) + (j0 + c) * lda] = ldexp(A[(j0 + r) + (j0 + c) * lda], -sh);
+    if (r < c) st(c, r, ldexp(ld(c, r), -sh));
   }
-  __syncthreads();
-  // V with explicit unit diagonal and zeros above it
-  for (int64_t e = threadIdx.x; e < (int64_t)mv * nb; e += QR_WG) {
-    const int i = (int)(e % mv), c = (int)(e / mv);
-    T v = 0;
-    if (i == c) v = tau[c] != (T)0 ? (T)1 : (T)0;
-    else if (i > c) v = tau[c] != (T)0 ? A[(j0 + i) + (int64_t)(j0 + c) * lda] : (T)0;
-    V[i + (int64_t)c * mv] = v;
-  }
-  __syncthreads();
-  // G = V^T V, then T: T_jj = tau_j, T[0:j, j] = -tau_j T[0:j, 0:j] G[0:j, j]
-  for (int pr = wv; pr < nb * nb; pr += nw) {
-    const int a = pr % nb, b = pr / nb;
-    if (a >= b) continue;
-    T s = 0;
-    for (int i = lane; i < mv; i += WAVE) s += V[i + (int64_t)a * mv] * V[i + (int64_t)b * mv];
-    s = wave_sum(s);
-    if (lane == 0) G[a + b * QR_NB] = s;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int j = 0; j < nb; ++j) {
-      for (int i = 0; i < nb; ++i) Tm[i + j * nb] = (T)0;
-      Tm[j + j * nb] = tau[j];
-      for (int i = 0; i < j; ++i) {
-        T s = 0;
-        for (int k = i; k < j; ++k) s += Tm[i + k * nb] * G[k + j * QR_NB];
-        Tm[i + j * nb] = -tau[j] * s;
+  // V with explicit unit diagonal and zeros above it (own rows only)
+  for (int i = tid; i < mv; i += QR_WG) {
+#pragma unroll
+    for (int q = 0; q < QR_NB; q += QC) {
+      if (FULL || q < nb) {
+        T x[QC];
+#pragma unroll
+        for (int k = 0; k < QC; ++k) x[k] = ld(q + k, i);
+#pragma unroll
+        for (int k = 0; k < QC; ++k) {
+          const int c = q + k;
+          if (FULL || c < nb) {
+            T v = 0;
+            if (tau[c] != (T)0) v = i == c ? (T)1 : (i > c ? x[k] : (T)0);
+            V[i + (int64_t)c * mv] = v;
+          }
+        }
       }
     }
   }
+  // T: T_ii = tau_i, T(i, j) = -tau_j sum_{k=i}^{j-1} T(i, k) G(k, j); row i
+  // depends only on row i, so lane i of the first wavefront builds it
+  if (tid < nb) {
+    const int i = tid;
+    for (int j = 0; j < nb; ++j) {
+      T val = 0;
+      if (j == i) {
+        val = tau[i];
+      } else if (j > i && tau[j] != (T)0) {
+        T sacc = 0;
+        for (int k = i; k < j; ++k) sacc += Ts[i + k * QR_NB] * G[k + j * QR_NB];
+        val = -tau[j] * sacc;
+      }
+      Ts[i + j * QR_NB] = val;
+      Tm[i + j * nb] = val;
+    }
+  }
+}
+
+template <class T>
+__global__ void __launch_bounds__(QR_WG) k_qr_panel(const QrPanel* __restrict__ ds) {
+  const QrPanel d = ds[blockIdx.x];
+  if (d.nb == QR_NB)
+    qr_panel_run<T, true>(d);
+  else
+    qr_panel_run<T, false>(d);
 }
 
 // R (kq x N, leading dimension ldr) from the factorized A and its diagonal.
@@ -454,6 +654,9 @@ inline void qr_blocked(Problem& P, const std::vector<QrJob>& jobs, QrScratch& S)
   int nmax = 0;
   for (size_t b = 0; b < jobs.size(); ++b) {
     const auto& j = jobs[b];
+    // the panel kernel addresses a panel with 32-bit byte offsets
+    if ((int64_t)j.lda * QR_NB * (int64_t)sizeof(T) >= ((int64_t)1 << 31))
+      fail(IFMM_ERR_ARG, "QR of a matrix with leading dimension " + std::to_string(j.lda) + ": above the panel limit");
     off[b] = tot;
     tot += j.N + (int64_t)j.M * QR_NB + QR_NB * QR_NB + 2 * (int64_t)QR_NB * j.N + 8;
     nmax = std::max(nmax, std::min(j.M, j.N));
@@ -491,6 +694,13 @@ inline void qr_blocked(Problem& P, const std::vector<QrJob>& jobs, QrScratch& S)
       }
     }
     if (pv.empty()) break;
+    if (trace_on() && j0 == 0) {
+      int64_t sm = 0;
+      int mx = 0, nx = 0;
+      for (const auto& q : pv) { sm += q.M; mx = std::max(mx, q.M); nx = std::max(nx, q.N); }
+      std::fprintf(stderr, "[ifmm-trace] qr level=%d jobs=%zu maxM=%d meanM=%.0f maxN=%d panels=%d\n",
+                   P.trace_level, pv.size(), mx, (double)sm / pv.size(), nx, (nmax + QR_NB - 1) / QR_NB);
+    }
     const QrPanel* dp = P.put(S.pd, pv);
     double fl = 0;   // Householder panel: 2 (M - j0) nb^2 - 2/3 nb^3
     for (const auto& q : pv) fl += 2.0 * (q.M - q.j0) * (double)q.nb * q.nb - 2.0 / 3.0 * (double)q.nb * q.nb * q.nb;
