@@ -105,7 +105,9 @@ typedef struct {
      Families 9-14 hold one kernel each, every launch timed on its own (the
      kernel is not counted in the families above): 9 block-Jacobi round,
      10 Householder QR panel, 11 truncated pivoted QR, 12 one-workgroup
-     Jacobi SVD, 13 row basis change, 14 column basis change. */
+     Jacobi SVD, 13 row basis change, 14 column basis change. Family 15
+     holds the launches of the step-wise truncated pivoted QR (batches of
+     few problems: one launch per Householder step). */
   double kfam_ms[16];
   double kfam_flops[16];      /* algorithmic flops attributed to the family */
   double kfam_bytes[16];      /* algorithmic bytes attributed to the family */

@@ -78,6 +78,7 @@ struct FactorStore : FactorStoreBase {
   // scratch reused across calls
   DevBuf work, d1, d2, d3, d4, d5;
   DevBuf rtmp;                                     // redirect: U^T D products of x~-x~ pairs
+  DevBuf qcw;                                      // step-wise pivoted QR: norms, pivots, state
   LuScratch lus;
   QrScratch qrs;
 };
@@ -442,7 +443,7 @@ struct Factorizer {
     };
     nan_report("after_qr", false);
     P.kset(-1);
-    run_qrcp<T>(P, pd, F.d4, 1e-7 * P.tau);
+    run_qrcp<T>(P, pd, F.d4, F.qcw, 1e-7 * P.tau);
     chk(L, "comp_qrcp", nullptr, o);
     nan_report("after_qrcp", true);
     P.kset(KF_SVD, 0, 0);   // flops are attributed to the SVD kernels themselves

@@ -38,11 +38,13 @@ struct FactorStoreBase {
 // Kernel-family timing with HIP events on the handle's stream (enabled by
 // IFMM_KTIMING=1): duration, launch count and algorithmic flops / bytes.
 // Families 0-8 group the launches of one phase; families 9-14 hold exactly
-// one kernel each, every launch timed on its own (per-launch averages).
+// one kernel each, every launch timed on its own (per-launch averages);
+// family 15 holds the launches of the step-wise pivoted QR.
 enum KFam {
   KF_SCHUR = 0, KF_LU, KF_TRSM, KF_QR, KF_SVD, KF_XFORM, KF_SOLVE, KF_MATVEC, KF_OTHER,
-  KF_SVD_ROUND, KF_QR_PANEL, KF_QRCP, KF_SVD_SMALL, KF_ROW_XFORM, KF_COL_XFORM, KF_COUNT
+  KF_SVD_ROUND, KF_QR_PANEL, KF_QRCP, KF_SVD_SMALL, KF_ROW_XFORM, KF_COL_XFORM, KF_QRCP_STEP, KF_COUNT
 };
+static_assert(KF_COUNT <= 16, "the query structure holds 16 families");
 
 struct KTimer {
   bool on = false;

@@ -509,11 +509,307 @@ __global__ void __launch_bounds__(SVD_WG) k_qrcp(const QrcpDesc* __restrict__ ds
   if (threadIdx.x == 0) *d.kout = k;
 }
 
+// ------------------------------------------------------------ step-wise QRCP
+// The same factorization for launches with few problems, where one workgroup
+// per problem would leave most of the chip idle: one launch per Householder
+// step, each problem's columns split into blocks of QS_CB owned by one
+// workgroup. Every workgroup of a problem derives the pivot and the reflector
+// from the same data in the same order, so they agree bitwise and none waits
+// for another inside a launch. Columns are not moved: the pivot of step s is
+// recorded in pos[s] and excluded afterwards, and the partial norms are kept
+// twice, read from the copy of step parity s and written to the other one.
+// Pivot ties go to the smallest column index; the columns left at the stop
+// follow in increasing index.
+constexpr int QS_CB = 16;    // columns per workgroup
+constexpr int QS_WG = 256;   // threads per workgroup (four wavefronts, four columns each)
+
+struct QrcpStepDesc {
+  void* R;          // m x n, ld ldr, scaled in place
+  void* Y;          // output as in QrcpDesc
+  int* perm;
+  int* kout;
+  void* vn;         // 4 n: vn1, vn2 of parity 0, then of parity 1
+  void* beta;       // min(m, n): R(s, pos[s])
+  void* thr;        // stop level (set at step 0)
+  int* pos;         // min(m, n): pivot column of step s
+  int* st;          // st[0]: -1 running, else the number of steps taken; st[1]: scale exponent
+  int m, n, ldr, ldy;
+};
+
+struct QsBlock {
+  int prob, c0, c1, first;   // problem, owned columns [c0, c1), first block of its problem
+};
+
+// scale by the exact power of two that brings max |R| into [1, 2); column norms
 template <class T>
-inline void run_qrcp(Problem& P, const std::vector<QrcpDesc>& v, DevBuf& scratch, double delta) {
+__global__ void __launch_bounds__(SVD_WG) k_qrcp_init(const QrcpStepDesc* __restrict__ ds, int* nstopped) {
+  __shared__ T red[SVD_WG / WAVE];
+  const QrcpStepDesc d = ds[blockIdx.x];
+  T* __restrict__ R = static_cast<T*>(d.R);
+  T* __restrict__ vn = static_cast<T*>(d.vn);
+  const int m = d.m, n = d.n;
+  const int64_t ld = d.ldr;
+  const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE, nw = SVD_WG / WAVE;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *nstopped = 0;
+  T am = 0;
+  for (int c = wv; c < n; c += nw)
+    for (int i = lane; i < m; i += WAVE) am = fmax(am, fabs(R[i + c * ld]));
+  am = block_max(am, red);
+  const int sh = am > (T)0 ? -ilogb((double)am) : 0;
+  for (int c = wv; c < n; c += nw) {
+    T s = 0;
+    for (int i = lane; i < m; i += WAVE) {
+      const T x = ldexp(R[i + c * ld], sh);
+      R[i + c * ld] = x;
+      s += x * x;
+    }
+    s = wave_sum(s);
+    if (lane == 0) vn[c] = vn[n + c] = sqrt(s);
+  }
+  if (threadIdx.x == 0) { d.st[0] = -1; d.st[1] = sh; }
+}
+
+template <class T>
+__global__ void __launch_bounds__(QS_WG) k_qrcp_step(const QrcpStepDesc* __restrict__ ds,
+                                                     const QsBlock* __restrict__ blocks, int s, double delta,
+                                                     int* nstopped) {
+  constexpr int NW = QS_WG / WAVE;
+  __shared__ unsigned char done[SVD_MAXN];
+  __shared__ T hv[SVD_MAXN];
+  __shared__ T redv[NW], reds[NW];
+  __shared__ int redi[NW];
+  const QsBlock b = blocks[blockIdx.x];
+  const QrcpStepDesc d = ds[b.prob];
+  const int st0 = d.st[0];
+  if (st0 >= 0 && st0 <= s) return;   // stopped (the last step records k = s + 1 while others still update)
+  const int m = d.m, n = d.n, kmax = min(m, n);
+  if (s >= kmax) return;
+  T* __restrict__ R = static_cast<T*>(d.R);
+  const int64_t ld = d.ldr;
+  const int tid = threadIdx.x, lane = tid % WAVE, wv = tid / WAVE;
+  const T* vn1 = static_cast<const T*>(d.vn) + (s & 1) * 2 * n;
+  const T* vn2 = vn1 + n;
+  T* wn1 = static_cast<T*>(d.vn) + ((s + 1) & 1) * 2 * n;
+  T* wn2 = wn1 + n;
+  for (int c = tid; c < n; c += QS_WG) done[c] = 0;
+  __syncthreads();
+  for (int j = tid; j < s; j += QS_WG) done[d.pos[j]] = 1;
+  __syncthreads();
+  // pivot = the largest remaining partial norm (smallest index on ties); remaining Frobenius norm
+  T best = (T)-1, ss = 0;
+  int bi = n;
+  for (int c = tid; c < n; c += QS_WG) {
+    if (done[c]) continue;
+    const T x = vn1[c];
+    ss += x * x;
+    if (x > best) { best = x; bi = c; }
+  }
+  for (int o = WAVE / 2; o > 0; o >>= 1) {
+    const T ob = __shfl_xor(best, o, WAVE);
+    const int oi = __shfl_xor(bi, o, WAVE);
+    if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+    ss += __shfl_xor(ss, o, WAVE);
+  }
+  if (lane == 0) { redv[wv] = best; redi[wv] = bi; reds[wv] = ss; }
+  __syncthreads();
+  T tot = reds[0];
+  int piv = redi[0];
+  best = redv[0];
+  for (int w = 1; w < NW; ++w) {
+    if (redv[w] > best || (redv[w] == best && redi[w] < piv)) { best = redv[w]; piv = redi[w]; }
+    tot += reds[w];
+  }
+  const int sh = d.st[1];
+  T* thrp = static_cast<T*>(d.thr);
+  const T thr = s == 0 ? fmax((T)ldexp(delta, sh), (T)4 * (T)Prec<T>::u * sqrt(tot)) : *thrp;
+  if (s == 0 && b.first && tid == 0) *thrp = thr;
+  if (sqrt(tot) <= thr || piv >= n) {
+    if (b.first && tid == 0) { d.st[0] = s; atomicAdd(nstopped, 1); }
+    return;
+  }
+  // reflector H = I - tau v v^T with v_s = 1 zeroing the pivot column below row s
+  const T* Rp = R + (int64_t)piv * ld;
+  const T x0 = Rp[s];
+  T x2 = 0;
+  for (int i = s + 1 + tid; i < m; i += QS_WG) { const T x = Rp[i]; x2 += x * x; }
+  x2 = block_sum(x2, redv);
+  T tau = 0, beta = x0, scale = 0;
+  if (x2 > (T)0) {
+    beta = x0 >= (T)0 ? -sqrt(x0 * x0 + x2) : sqrt(x0 * x0 + x2);
+    tau = (beta - x0) / beta;
+    scale = (T)1 / (x0 - beta);
+  }
+  for (int i = s + tid; i < m; i += QS_WG) hv[i] = i == s ? (T)1 : Rp[i] * scale;
+  if (b.first && tid == 0) {
+    d.pos[s] = piv;
+    static_cast<T*>(d.beta)[s] = beta;
+    if (s + 1 == kmax) { d.st[0] = kmax; atomicAdd(nstopped, 1); }
+  }
+  __syncthreads();
+  // apply to the owned remaining columns, four per wavefront at a time, and
+  // downdate their partial norms into the other parity
+  for (int jc = b.c0 + wv * 4; jc < b.c1; jc += NW * 4) {
+    bool live[4];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) live[g] = jc + g < b.c1 && !done[jc + g] && jc + g != piv;
+    T w[4] = {0, 0, 0, 0};
+    for (int i = s + lane; i < m; i += WAVE) {
+      const T h = hv[i];
+#pragma unroll
+      for (int g = 0; g < 4; ++g)
+        if (live[g]) w[g] += h * R[i + (int64_t)(jc + g) * ld];
+    }
+#pragma unroll
+    for (int g = 0; g < 4; ++g) w[g] = wave_sum(w[g]) * tau;
+    T rs[4] = {0, 0, 0, 0}, rest[4] = {0, 0, 0, 0};
+    for (int i = s + lane; i < m; i += WAVE) {
+      const T h = hv[i];
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        if (live[g]) {
+          const T x = R[i + (int64_t)(jc + g) * ld] - w[g] * h;
+          R[i + (int64_t)(jc + g) * ld] = x;
+          if (i == s) rs[g] = x;
+          else rest[g] += x * x;
+        }
+      }
+    }
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      if (!live[g]) continue;
+      const int j = jc + g;
+      int need = 0;   // 1: recompute the partial norm, 2: downdate it by t
+      T t = 0;
+      const T a1 = vn1[j], a2 = vn2[j];
+      if (lane == 0 && a1 != (T)0) {
+        const T r = fabs(rs[g]) / a1;
+        t = fmax((T)0, ((T)1 + r) * ((T)1 - r));
+        const T q = a1 / a2;
+        need = t * q * q <= sqrt((T)Prec<T>::u) ? 1 : 2;
+      }
+      need = __shfl(need, 0, WAVE);
+      if (need == 1) {
+        const T nr = sqrt(wave_sum(rest[g]));
+        if (lane == 0) { wn1[j] = nr; wn2[j] = nr; }
+      } else if (lane == 0) {
+        wn1[j] = need == 2 ? a1 * sqrt(t) : a1;
+        wn2[j] = a2;
+      }
+    }
+  }
+}
+
+// Y = R'[0:k, :]^T in pivot order, then the remaining columns by index; perm; k
+template <class T>
+__global__ void __launch_bounds__(SVD_WG) k_qrcp_finish(const QrcpStepDesc* __restrict__ ds) {
+  __shared__ int order[SVD_MAXN];
+  __shared__ unsigned char done[SVD_MAXN];
+  const QrcpStepDesc d = ds[blockIdx.x];
+  const T* __restrict__ R = static_cast<const T*>(d.R);
+  const T* __restrict__ beta = static_cast<const T*>(d.beta);
+  T* __restrict__ Y = static_cast<T*>(d.Y);
+  const int m = d.m, n = d.n, kmax = min(m, n);
+  const int64_t ld = d.ldr;
+  const int k = d.st[0] >= 0 ? d.st[0] : kmax;
+  const int sh = d.st[1];
+  for (int c = threadIdx.x; c < n; c += SVD_WG) done[c] = 0;
+  __syncthreads();
+  for (int j = threadIdx.x; j < k; j += SVD_WG) { done[d.pos[j]] = 1; order[j] = d.pos[j]; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int q = k;
+    for (int c = 0; c < n; ++c)
+      if (!done[c]) order[q++] = c;
+    *d.kout = k;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += SVD_WG) d.perm[i] = order[i];
+  for (int64_t e = threadIdx.x; e < (int64_t)n * k; e += SVD_WG) {
+    const int i = (int)(e % n), c = (int)(e / n);
+    T v = 0;
+    if (i == c) v = beta[c];
+    else if (i > c) v = R[c + (int64_t)order[i] * ld];
+    Y[i + (int64_t)c * d.ldy] = ldexp(v, -sh);
+  }
+}
+
+// Step-wise path: init, one launch per step (the host reads the count of
+// stopped problems every QS_POLL steps), finish.
+constexpr int QS_POLL = 16;
+
+template <class T>
+inline void run_qrcp_steps(Problem& P, const std::vector<QrcpDesc>& v, DevBuf& scratch, DevBuf& work,
+                           double delta) {
+  const int np = (int)v.size();
+  std::vector<int64_t> toff(np), ioff(np);
+  int64_t tt = 0, ti = 0;
+  int kall = 0;
+  for (int p = 0; p < np; ++p) {
+    const int km = std::min(v[p].m, v[p].n);
+    toff[p] = tt;
+    tt += 4 * (int64_t)v[p].n + km + 1;
+    ioff[p] = ti;
+    ti += km + 2;
+    kall = std::max(kall, km);
+  }
+  const size_t bytes = (size_t)tt * sizeof(T) + (size_t)(ti + 1) * sizeof(int) + 256;
+  if (bytes > work.bytes) {
+    P.sync();
+    work.alloc(bytes + bytes / 4, &P.mem);
+  }
+  T* tw = work.template as<T>();
+  int* iw = reinterpret_cast<int*>(tw + tt);
+  int* nst = iw + ti;
+  std::vector<QrcpStepDesc> dv(np);
+  std::vector<QsBlock> bl;
+  for (int p = 0; p < np; ++p) {
+    const auto& q = v[p];
+    const int km = std::min(q.m, q.n);
+    T* t0 = tw + toff[p];
+    dv[p] = {q.R, q.Y, q.perm, q.kout, t0, t0 + 4 * (int64_t)q.n, t0 + 4 * (int64_t)q.n + km,
+             iw + ioff[p], iw + ioff[p] + km, q.m, q.n, q.ldr, q.ldy};
+    for (int c0 = 0; c0 < q.n; c0 += QS_CB) bl.push_back({p, c0, std::min(q.n, c0 + QS_CB), c0 == 0 ? 1 : 0});
+  }
+  const QrcpStepDesc* dd = P.put(scratch, dv);
+  const QsBlock* db = P.put(scratch, bl);
+  P.kone_begin(KF_QRCP_STEP, 0);
+  hipLaunchKernelGGL(k_qrcp_init<T>, dim3((unsigned)np), dim3(SVD_WG), 0, P.stream, dd, nst);
+  IFMM_LAUNCH_CHECK();
+  P.kone_end();
+  for (int s = 0; s < kall; ++s) {
+    double fl = 0;   // Householder step: products with the trailing block and its rank-one update
+    for (const auto& q : v)
+      if (s < std::min(q.m, q.n)) fl += 4.0 * (q.m - s) * (double)(q.n - s);
+    P.kone_begin(KF_QRCP_STEP, fl);
+    hipLaunchKernelGGL(k_qrcp_step<T>, dim3((unsigned)bl.size()), dim3(QS_WG), 0, P.stream, dd, db, s, delta, nst);
+    IFMM_LAUNCH_CHECK();
+    P.kone_end();
+    if ((s + 1) % QS_POLL == 0 && s + 1 < kall) {
+      std::vector<int> h;
+      P.download(h, nst, 1);
+      if (h[0] >= np) break;
+    }
+  }
+  P.kone_begin(KF_QRCP_STEP, 0);
+  hipLaunchKernelGGL(k_qrcp_finish<T>, dim3((unsigned)np), dim3(SVD_WG), 0, P.stream, dd);
+  IFMM_LAUNCH_CHECK();
+  P.kone_end();
+}
+
+// Launches whose problems would fill less than half of the compute units
+// take the step-wise path.
+template <class T>
+inline void run_qrcp(Problem& P, const std::vector<QrcpDesc>& v, DevBuf& scratch, DevBuf& work, double delta) {
   if (v.empty()) return;
-  for (const auto& q : v)
+  int64_t nblk = 0;
+  for (const auto& q : v) {
     if (q.n > SVD_MAXN || q.m > SVD_MAXN || q.m > q.n) fail(IFMM_ERR_INTERNAL, "QRCP shape out of range");
+    nblk += ceil_div(q.n, QS_CB);
+  }
+  if (v.size() < 128 && nblk <= 2048) {
+    run_qrcp_steps<T>(P, v, scratch, work, delta);
+    return;
+  }
   const QrcpDesc* d = P.put(scratch, v);
   // Householder QR flops of the untruncated factorization (m <= n): 2 n m^2 - 2/3 m^3
   double fl = 0;

@@ -46,7 +46,7 @@ class Stats(ctypes.Structure):
                 ("kfam_bytes", ctypes.c_double * 16), ("kfam_launches", ctypes.c_int64 * 16)]
 
 KFAMILIES = ["schur_gemm", "pivot_lu", "trsm_w", "qr", "jacobi_svd", "edge_update", "solve", "matvec", "other",
-             "svd_round", "qr_panel", "qrcp", "svd_small", "row_xform", "col_xform"]
+             "svd_round", "qr_panel", "qrcp", "svd_small", "row_xform", "col_xform", "qrcp_step"]
 # families holding exactly one kernel (per-launch timing), with its name
 KERNEL_OF_FAMILY = {"svd_round": "k_svd_round", "qr_panel": "k_qr_panel", "qrcp": "k_qrcp",
                     "svd_small": "k_svd_small", "row_xform": "k_row_xform", "col_xform": "k_col_xform"}
