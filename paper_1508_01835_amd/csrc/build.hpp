@@ -125,16 +125,17 @@ inline void build_tree(Problem& P, const double* d_points, int depth, int leaf_m
       cb[i] = b;
     }
     P.upload(ld.cbits, cb);
-    // position of pair (j, i) in j's list, for every pair (i, j)
+    // position of pair (j, i) in j's list, for every pair (i, j): the lists
+    // are symmetric and sorted, so visiting i in increasing order meets the
+    // entries of j's list in order (one cursor per box)
     std::vector<int> rev(lv.inter.size());
+    std::vector<int> cur(lv.in_start.begin(), lv.in_start.end() - 1);
     for (int i = 0; i < lv.nb; ++i)
       for (int t = lv.in_start[i]; t < lv.in_start[i + 1]; ++t) {
         const int j = lv.inter[t];
-        const int* b = &lv.inter[lv.in_start[j]];
-        const int* e = &lv.inter[lv.in_start[j + 1]];
-        const int* f = std::lower_bound(b, e, i);
-        IFMM_CHECK(f != e && *f == i, "interaction lists not symmetric");
-        rev[t] = (int)(f - &lv.inter[0]);
+        const int f = cur[j]++;
+        IFMM_CHECK(f < lv.in_start[j + 1] && lv.inter[f] == i, "interaction lists not symmetric");
+        rev[t] = f;
       }
     P.upload(ld.in_rev, rev);
   }

@@ -2,6 +2,8 @@
 // accounting, small host/device helpers.
 #pragma once
 
+#include <atomic>
+
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -52,6 +54,15 @@ struct MemAccount {
   void sub(int64_t b) { cur -= b; }
 };
 
+// Host time spent in hipMalloc / hipFree, process totals (diagnostics).
+struct AllocClock {
+  static inline std::atomic<int64_t> ns_malloc{0}, ns_free{0}, calls{0};
+  static int64_t now_ns() {
+    return std::chrono::duration_cast<std::chrono::nanoseconds>(
+               std::chrono::steady_clock::now().time_since_epoch()).count();
+  }
+};
+
 // An owning device buffer. Moves only.
 struct DevBuf {
   void* p = nullptr;
@@ -74,7 +85,10 @@ struct DevBuf {
     release();
     if (b == 0) b = 256;
     if (a) a->add((int64_t)b);
+    const int64_t t0 = AllocClock::now_ns();
     hipError_t e = hipMalloc(&p, b);
+    AllocClock::ns_malloc += AllocClock::now_ns() - t0;
+    ++AllocClock::calls;
     if (e != hipSuccess) {
       if (a) a->sub((int64_t)b);
       p = nullptr;
@@ -85,7 +99,9 @@ struct DevBuf {
   }
   void release() {
     if (p) {
+      const int64_t t0 = AllocClock::now_ns();
       (void)hipFree(p);
+      AllocClock::ns_free += AllocClock::now_ns() - t0;
       if (acct) acct->sub((int64_t)bytes);
     }
     p = nullptr;

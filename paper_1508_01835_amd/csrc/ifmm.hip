@@ -327,6 +327,10 @@ int ifmm_destroy(ifmm_handle h) {
     if (!h) return;
     (void)hipStreamSynchronize(h->P.stream);
     delete h;
+    if (trace_on())
+      std::fprintf(stderr, "[ifmm-trace] hipMalloc %lld calls %.1f ms, hipFree %.1f ms (process totals)\n",
+                   (long long)AllocClock::calls.load(), AllocClock::ns_malloc.load() * 1e-6,
+                   AllocClock::ns_free.load() * 1e-6);
   });
 }
 

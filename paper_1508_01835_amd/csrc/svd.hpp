@@ -509,6 +509,44 @@ __global__ void __launch_bounds__(SVD_WG) k_qrcp(const QrcpDesc* __restrict__ ds
   if (threadIdx.x == 0) *d.kout = k;
 }
 
+// Sum of 16 per-lane values over the 64 lanes of a wavefront, reduce-scattered
+// (each exchange halves the values a lane keeps): on return lanes 4c..4c+3
+// hold the sum of value c.
+template <class T>
+__device__ inline T wave_sum16_scatter(const T (&v)[16], int lane) {
+  T a[8];
+  {
+    const bool hi = lane & 32;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const T keep = hi ? v[k + 8] : v[k], send = hi ? v[k] : v[k + 8];
+      a[k] = keep + __shfl_xor(send, 32, WAVE);
+    }
+  }
+  T c[4];
+  {
+    const bool hi = lane & 16;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const T keep = hi ? a[k + 4] : a[k], send = hi ? a[k] : a[k + 4];
+      c[k] = keep + __shfl_xor(send, 16, WAVE);
+    }
+  }
+  T e[2];
+  {
+    const bool hi = lane & 8;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const T keep = hi ? c[k + 2] : c[k], send = hi ? c[k] : c[k + 2];
+      e[k] = keep + __shfl_xor(send, 8, WAVE);
+    }
+  }
+  const bool hi = lane & 4;
+  T f = (hi ? e[1] : e[0]) + __shfl_xor(hi ? e[0] : e[1], 4, WAVE);
+  f += __shfl_xor(f, 2, WAVE);
+  return f + __shfl_xor(f, 1, WAVE);
+}
+
 // ------------------------------------------------------------ step-wise QRCP
 // The same factorization for launches with few problems, where one workgroup
 // per problem would leave most of the chip idle: one launch per Householder
@@ -578,6 +616,8 @@ __global__ void __launch_bounds__(QS_WG) k_qrcp_step(const QrcpStepDesc* __restr
   __shared__ T hv[SVD_MAXN];
   __shared__ T redv[NW], reds[NW];
   __shared__ int redi[NW];
+  __shared__ T part[NW][QS_CB];
+  __shared__ T rsh[QS_CB];          // updated row s of the owned columns
   const QsBlock b = blocks[blockIdx.x];
   const QrcpStepDesc d = ds[b.prob];
   const int st0 = d.st[0];
@@ -646,55 +686,87 @@ __global__ void __launch_bounds__(QS_WG) k_qrcp_step(const QrcpStepDesc* __restr
     if (s + 1 == kmax) { d.st[0] = kmax; atomicAdd(nstopped, 1); }
   }
   __syncthreads();
-  // apply to the owned remaining columns, four per wavefront at a time, and
-  // downdate their partial norms into the other parity
-  for (int jc = b.c0 + wv * 4; jc < b.c1; jc += NW * 4) {
-    bool live[4];
+  // the owned block: rows s.. held in registers, row s + tid + r QS_WG in slot r
+  // (past the last row the slot repeats row m - 1 with a zero reflector entry)
+  constexpr int RPT = SVD_MAXN / QS_WG;
+  const int c0 = b.c0, nc = b.c1 - b.c0, nr = (m - s + QS_WG - 1) / QS_WG;
+  T x[RPT][QS_CB], hr[RPT];
 #pragma unroll
-    for (int g = 0; g < 4; ++g) live[g] = jc + g < b.c1 && !done[jc + g] && jc + g != piv;
-    T w[4] = {0, 0, 0, 0};
-    for (int i = s + lane; i < m; i += WAVE) {
-      const T h = hv[i];
+  for (int r = 0; r < RPT; ++r) {
+    hr[r] = 0;
+    if (r < nr) {
+      const int i = s + tid + r * QS_WG;
+      const int ii = i < m ? i : m - 1;
+      hr[r] = i < m ? hv[i] : (T)0;
 #pragma unroll
-      for (int g = 0; g < 4; ++g)
-        if (live[g]) w[g] += h * R[i + (int64_t)(jc + g) * ld];
+      for (int g = 0; g < QS_CB; ++g) x[r][g] = R[ii + (int64_t)(c0 + (g < nc ? g : 0)) * ld];
     }
+  }
+  // w = tau v^T (block), reduced over the workgroup
+  T acc[QS_CB];
 #pragma unroll
-    for (int g = 0; g < 4; ++g) w[g] = wave_sum(w[g]) * tau;
-    T rs[4] = {0, 0, 0, 0}, rest[4] = {0, 0, 0, 0};
-    for (int i = s + lane; i < m; i += WAVE) {
-      const T h = hv[i];
+  for (int g = 0; g < QS_CB; ++g) {
+    acc[g] = 0;
 #pragma unroll
-      for (int g = 0; g < 4; ++g) {
-        if (live[g]) {
-          const T x = R[i + (int64_t)(jc + g) * ld] - w[g] * h;
-          R[i + (int64_t)(jc + g) * ld] = x;
-          if (i == s) rs[g] = x;
-          else rest[g] += x * x;
+    for (int r = 0; r < RPT; ++r)
+      if (r < nr) acc[g] += hr[r] * x[r][g];
+  }
+  T wsum = wave_sum16_scatter(acc, lane);
+  if ((lane & 3) == 0) part[wv][lane >> 2] = wsum;
+  __syncthreads();
+  T w[QS_CB];
+#pragma unroll
+  for (int g = 0; g < QS_CB; ++g) {
+    T t = 0;
+    for (int q = 0; q < NW; ++q) t += part[q][g];
+    w[g] = t * tau;
+  }
+  // rank-one update of the live columns; new row s and squares below it
+  T rest[QS_CB];
+#pragma unroll
+  for (int g = 0; g < QS_CB; ++g) rest[g] = 0;
+#pragma unroll
+  for (int r = 0; r < RPT; ++r) {
+    if (r < nr) {
+      const int i = s + tid + r * QS_WG;
+      if (i < m) {
+#pragma unroll
+        for (int g = 0; g < QS_CB; ++g) {
+          const int j = c0 + g;
+          if (g < nc && !done[j] && j != piv) {
+            const T y = x[r][g] - w[g] * hr[r];
+            R[i + (int64_t)j * ld] = y;
+            if (i == s) rsh[g] = y;
+            else rest[g] += y * y;
+          }
         }
       }
     }
-#pragma unroll
-    for (int g = 0; g < 4; ++g) {
-      if (!live[g]) continue;
-      const int j = jc + g;
-      int need = 0;   // 1: recompute the partial norm, 2: downdate it by t
-      T t = 0;
+  }
+  wsum = wave_sum16_scatter(rest, lane);
+  __syncthreads();   // every wavefront has read part[] for w
+  if ((lane & 3) == 0) part[wv][lane >> 2] = wsum;
+  __syncthreads();
+  // downdate (or recompute) the partial norms into the other parity
+  if (tid < nc) {
+    const int j = c0 + tid;
+    if (!done[j] && j != piv) {
       const T a1 = vn1[j], a2 = vn2[j];
-      if (lane == 0 && a1 != (T)0) {
-        const T r = fabs(rs[g]) / a1;
-        t = fmax((T)0, ((T)1 + r) * ((T)1 - r));
+      T n1 = a1, n2 = a2;
+      if (a1 != (T)0) {
+        const T r = fabs(rsh[tid]) / a1;
+        const T t = fmax((T)0, ((T)1 + r) * ((T)1 - r));
         const T q = a1 / a2;
-        need = t * q * q <= sqrt((T)Prec<T>::u) ? 1 : 2;
+        if (t * q * q <= sqrt((T)Prec<T>::u)) {
+          T tot2 = 0;
+          for (int q2 = 0; q2 < NW; ++q2) tot2 += part[q2][tid];
+          n1 = n2 = sqrt(tot2);
+        } else {
+          n1 = a1 * sqrt(t);
+        }
       }
-      need = __shfl(need, 0, WAVE);
-      if (need == 1) {
-        const T nr = sqrt(wave_sum(rest[g]));
-        if (lane == 0) { wn1[j] = nr; wn2[j] = nr; }
-      } else if (lane == 0) {
-        wn1[j] = need == 2 ? a1 * sqrt(t) : a1;
-        wn2[j] = a2;
-      }
+      wn1[j] = n1;
+      wn2[j] = n2;
     }
   }
 }

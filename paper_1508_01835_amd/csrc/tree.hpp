@@ -196,8 +196,8 @@ inline void plan_tree(HTree& T, const std::vector<uint64_t>& sorted_keys) {
       lv.colour[i] = c;
       lv.classes[c].push_back(i);
     }
-    BoxLookup look;
-    look.build(lv, d);
+    BoxLookup look;   // coordinate lookup, used at level 2 (no parent lists)
+    if (l == 2) look.build(lv, d);
     int offs1[27][3];
     int no = 0;
     {
@@ -214,6 +214,34 @@ inline void plan_tree(HTree& T, const std::vector<uint64_t>& sorted_keys) {
     lv.in_start.assign(lv.nb + 1, 0);
     lv.nbr.clear();
     lv.inter.clear();
+    if (l > 2) {
+      // N(i) and I(i) are the children of the parent's neighbours that are,
+      // respectively are not, adjacent to i. The parent's list is in Morton
+      // order and children are contiguous in Morton order, so both lists come
+      // out sorted.
+      const HLevel& pl = T.lev[l - 1];
+      lv.nbr.reserve((size_t)lv.nb * no);
+      lv.inter.reserve((size_t)lv.nb * (no * (1 << d) - no));
+      for (int i = 0; i < lv.nb; ++i) {
+        const int* ci = &lv.coords[(size_t)i * d];
+        const int p = lv.parent[i];
+        for (int t = pl.nb_start[p]; t < pl.nb_start[p + 1]; ++t) {
+          const int pn = pl.nbr[t];
+          for (int j = pl.ch_start[pn]; j < pl.ch_start[pn + 1]; ++j) {
+            const int* cj = &lv.coords[(size_t)j * d];
+            bool adj = true;
+            for (int k = 0; k < d; ++k) {
+              const int dd = cj[k] - ci[k];
+              if (dd > 1 || dd < -1) adj = false;
+            }
+            (adj ? lv.nbr : lv.inter).push_back(j);
+          }
+        }
+        lv.nb_start[i + 1] = (int)lv.nbr.size();
+        lv.in_start[i + 1] = (int)lv.inter.size();
+      }
+      continue;
+    }
     std::vector<int> tmp;
     for (int i = 0; i < lv.nb; ++i) {
       const int* ci = &lv.coords[(size_t)i * d];
