@@ -24,7 +24,8 @@
  *     a longer, thread-local description of the last failure.
  *   - Handle life cycle: BUILT (after ifmm_build) -> FACTORIZED (after
  *     ifmm_factorize). ifmm_matvec is legal in both states; ifmm_solve and
- *     ifmm_gmres need FACTORIZED; factorizing again is allowed.
+ *     the preconditioner handle of ifmm_gmres need FACTORIZED; factorizing
+ *     again is allowed.
  */
 #ifndef IFMM_H
 #define IFMM_H
@@ -180,7 +181,9 @@ int ifmm_matvec(ifmm_handle h, const double* x, double* y, int nrhs, int64_t ld)
  * products use op's H2 matvec in float64, the preconditioner is prec's
  * factorization (float32 or float64); orthogonalisation is float64.
  * op and prec must describe the same points (same n); they may be the same
- * handle. Each column is an independent GMRES run.
+ * handle. prec = NULL runs GMRES without a preconditioner (the comparison
+ * runs of Sec. 3.2); op then need not be factorized. Each column is an
+ * independent GMRES run.
  *   b, x        device, n x nrhs, leading dimension ld; x is overwritten
  *   tol         stop when ||b - A~ x|| <= tol ||b|| (per column)
  *   maxit       iteration limit (<= 1000)

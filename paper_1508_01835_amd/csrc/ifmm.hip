@@ -271,17 +271,23 @@ int ifmm_matvec(ifmm_handle h, const double* x, double* y, int nrhs, int64_t ld)
 int ifmm_gmres(ifmm_handle op, ifmm_handle prec, const double* b, double* x, int nrhs, int64_t ld, double tol,
                int maxit, int* iters_out, double* relres_out) {
   return guarded([&] {
-    if (!op || !prec || !b || !x) fail(IFMM_ERR_ARG, "null pointer");
+    if (!op || !b || !x) fail(IFMM_ERR_ARG, "null pointer");
     Problem& A = op->P;
-    Problem& M = prec->P;
-    if (A.n != M.n) fail(IFMM_ERR_ARG, "op and prec have different sizes");
-    if (!M.factorized) fail(IFMM_ERR_STATE, "the preconditioner handle is not factorized");
+    if (prec) {
+      if (A.n != prec->P.n) fail(IFMM_ERR_ARG, "op and prec have different sizes");
+      if (!prec->P.factorized) fail(IFMM_ERR_STATE, "the preconditioner handle is not factorized");
+    }
     if (nrhs < 1 || ld < A.n) fail(IFMM_ERR_ARG, "nrhs must be >= 1 and ld >= n");
     if (maxit < 1 || maxit > 1000) fail(IFMM_ERR_ARG, "maxit must be in [1, 1000]");
     if (!(tol > 0)) fail(IFMM_ERR_ARG, "tol must be > 0");
-    if (M.stream != A.stream) M.sync();
+    if (prec && prec->P.stream != A.stream) prec->P.sync();
     auto applyA = [&](const double* in, double* out) { matvec_any(A, in, out, nrhs, A.n); };
     auto applyM = [&](const double* in, double* out) {
+      if (!prec) {   // no preconditioner: z = v
+        IFMM_HIP(hipMemcpyAsync(out, in, sizeof(double) * (size_t)A.n * nrhs, hipMemcpyDeviceToDevice, A.stream));
+        return;
+      }
+      Problem& M = prec->P;
       solve_any(M, in, out, nrhs, M.n);
       if (M.stream != A.stream) M.sync();
     };

@@ -172,12 +172,15 @@ class IFMM:
         out = Y.t()
         return out[:, 0] if x.dim() == 1 else out
 
-    def gmres(self, b, tol: float = 1e-10, maxit: int = 500, prec: "IFMM | None" = None):
+    def gmres(self, b, tol: float = 1e-10, maxit: int = 500, prec: "IFMM | None" = None,
+              precondition: bool = True):
+        """GMRES on this handle's H2 operator; preconditioner: prec's factorization, else this handle's,
+        none with precondition=False."""
         B = _colmajor(b, self.n)
         X = B.new_zeros(B.shape)
         it = ctypes.c_int()
         rr = ctypes.c_double()
-        p = prec.h if prec is not None else self.h
+        p = None if not precondition else (prec.h if prec is not None else self.h)
         self._inputs_ready()
         _check(lib().ifmm_gmres(self.h, p, ctypes.c_void_p(B.data_ptr()), ctypes.c_void_p(X.data_ptr()),
                                 B.shape[0], self.n, float(tol), int(maxit), ctypes.byref(it), ctypes.byref(rr)))

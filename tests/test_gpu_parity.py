@@ -193,3 +193,28 @@ def test_error_paths():
     with pytest.raises(IFMMError) as e:
         IFMM(to_dev(wl.points), wl.kernel, wl.kparam, wl.shift, 1, 3, 1e-6)
     assert e.value.code == 1
+
+
+def test_paper_kernel_gmres_with_and_without_preconditioner():
+    """The paper's GMRES comparison (Sec. 3.2) at a size the oracle runs: the same H2 operator without a
+    preconditioner and with the IFMM preconditioner (eps 1e-3). Iteration counts follow the oracle's runs
+    of the same method; the preconditioned run needs far fewer."""
+    from oracle.gmres import gmres_right
+    from oracle.ifmm import IFMM as Oracle
+    wl = W.paper_cube(n=2000, d=1e-2, order=3, depth=3, eps=1e-3, seed=6101)
+    b = wl.rhs[:, 0]
+    o = Oracle(wl.points, wl.kernel, wl.kparam, wl.shift, wl.depth, wl.order, wl.eps)
+    o.factorize()
+    g = gpu()(to_dev(wl.points), wl.kernel, wl.kparam, wl.shift, wl.depth, wl.order, wl.eps,
+              sigma0=o.r2.sigma0)
+    xn, itn, rrn = g.gmres(to_dev(b), tol=1e-10, maxit=500, precondition=False)   # before factorize
+    xo_n, ito_n, rro_n, _ = gmres_right(o.matvec, lambda v: v, b, tol=1e-10, maxit=500)
+    g.factorize()
+    xp, itp, rrp = g.gmres(to_dev(b), tol=1e-10, maxit=500)
+    xo_p, ito_p, rro_p, _ = gmres_right(o.matvec, o.solve, b, tol=1e-10, maxit=500)
+    g.close()
+    print("unpreconditioned", itn, ito_n, "preconditioned", itp, ito_p, flush=True)
+    assert max(rrn, rrp, rro_n, rro_p) <= 1e-10
+    assert abs(itn - ito_n) <= 1 and abs(itp - ito_p) <= 1
+    assert itp * 3 <= itn
+    assert rel(xn.cpu().numpy(), xo_n) <= 1e-8 and rel(xp.cpu().numpy(), xo_p) <= 1e-8

@@ -112,6 +112,17 @@ def batch_problem(k: int, n: int) -> np.ndarray:
     return unit_sphere(n, 4100 + k) if k % 2 == 0 else uniform_cube(n, 3, 4100 + k)
 
 
+def paper_cube(n: int = 100000, d: float = 1e-3, order: int = 3, depth: int = 3, eps: float = 1e-3,
+               seed: int = 6001) -> Workload:
+    """The paper's own GMRES workload (Sec. 3.2, Tables 1-2): n points uniform in [-1,1]^3, kernel
+    K(0)=1, r/d below d, d/r above, no diagonal shift, eps 1e-3. The octree depth giving leaves closest to
+    100 points is 3 for n = 1e5 (about 195 per leaf; depth 4 gives about 24). The solution x has
+    N(0,1) entries (seed + 1); the right-hand side is formed from it by the caller's matvec."""
+    pts = 2.0 * uniform_cube(n, 3, seed) - 1.0
+    return Workload("paper_cube_%d_d%g_n%d" % (n, d, order), pts, "paper", d, 0.0, depth, order, eps,
+                    normal_rhs(n, 1, seed + 1))
+
+
 def small_uniform(n: int, dim: int, seed: int, depth: int, order: int, eps: float,
                   kernel: str = "imq", kparam: float = 0.01, shift: float = 1.0,
                   nrhs: int = 1) -> Workload:
