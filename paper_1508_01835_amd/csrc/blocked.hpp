@@ -303,7 +303,7 @@ inline void lu_solve_blocked(Problem& P, const std::vector<TrsJob>& jobs, LuScra
 // Only R is produced (the recompression needs the left singular vectors of
 // R^T, not Q).
 constexpr int QR_NB = 32;
-constexpr int QR_WG = 1024;   // threads of the panel kernel (16 wavefronts)
+constexpr int QR_WG = 512;    // threads of the panel kernel (8 wavefronts, 256 registers each)
 
 struct QrPanel {
   void* A;
@@ -390,22 +390,24 @@ __device__ inline void buf_st(float v, __amdgpu_buffer_rsrc_t r, int vo, int so)
 // One panel of QR_NB columns per workgroup. Each thread owns the panel rows
 // i = tid + k QR_WG and reads a row's panel columns together (independent
 // loads from one per-lane offset), so the panel streams at bandwidth instead of
-// one dependent column walk per wavefront. Per Householder column j:
-//   the norm of the column below the diagonal (one block reduction; after the
-//   first column it is accumulated by the previous update pass);
-//   v = scaled column, and the products of v with every panel column in one
-//   pass: those right of j are the trailing-update coefficients, those left
-//   of j are the entries V^T v of the Gram matrix that builds T;
-//   the rank-one update of the columns right of j.
+// one dependent column walk per wavefront. One pass over the panel per
+// Householder column j does three things:
+//   applies reflector j - 1 to the columns right of it and stores column
+//   j - 1 as v_{j-1};
+//   sums the squares of the updated column j below its diagonal;
+//   sums S_c = sum_{i > j} y_i x_ic, the products of that column with every
+//   panel column.
+// With the broadcast row j, the coefficients of reflector j follow:
+// v_j^T x_c = x_jc + S_c / (x_jj - alpha). For c > j they are the update
+// coefficients; for c < j they are the Gram entries V^T v_j that build T.
 // T follows from the Gram entries row by row (row i of T needs only row i).
 // FULL: the panel has exactly QR_NB columns, so no column test is needed and
-// the update stores whole chunks (finished columns get a zero coefficient and
-// are rewritten unchanged). Otherwise columns past the panel are skipped one by
-// one.
+// stores cover whole chunks (unchanged columns are rewritten as read).
+// Otherwise columns past the panel are read as aliases and never stored.
 template <class T, bool FULL>
 __device__ __forceinline__ void qr_panel_run(const QrPanel& d) {
   constexpr int NW = QR_WG / WAVE;
-  constexpr int QC = 4;   // columns loaded together per row
+  constexpr int QC = 4;   // columns per store chunk
   T* __restrict__ A = static_cast<T*>(d.A);
   T* __restrict__ V = static_cast<T*>(d.V);
   T* __restrict__ Tm = static_cast<T*>(d.Tm);
@@ -415,9 +417,11 @@ __device__ __forceinline__ void qr_panel_run(const QrPanel& d) {
   const int64_t lda = d.lda;
   const int mv = d.M - j0;
   __shared__ T tau[QR_NB];
-  __shared__ T red[NW];
   __shared__ T part[NW][QR_NB];
-  __shared__ T dots[QR_NB];        // tau_j times the products of v_j with the panel columns right of j
+  __shared__ T sred[NW];
+  __shared__ T Stot[QR_NB];        // S_c of the column being prepared
+  __shared__ T stot;               // its squares below the diagonal
+  __shared__ T rowj[QR_NB];        // its diagonal row, after the updates so far
   __shared__ T G[QR_NB * QR_NB];   // G[k + j QR_NB] = V(:,k)^T V(:,j), k < j
   __shared__ T Ts[QR_NB * QR_NB];
   const int tid = threadIdx.x, lane = tid % WAVE, wv = tid / WAVE;
@@ -429,6 +433,39 @@ __device__ __forceinline__ void qr_panel_run(const QrPanel& d) {
     return buf_ld<T>(rs, i * (int)sizeof(T), (FULL || c < nb ? c : nb - 1) * ldb);
   };
   auto st = [&](int c, int i, T v) { buf_st(v, rs, i * (int)sizeof(T), c * ldb); };
+  auto load_row = [&](int i, T (&x)[QR_NB]) {
+#pragma unroll
+    for (int c = 0; c < QR_NB; ++c) x[c] = ld(c, i);
+  };
+  // store the columns >= c0 of row i (FULL: whole chunks from the one holding c0)
+  auto store_row = [&](int i, const T (&x)[QR_NB], int c0) {
+#pragma unroll
+    for (int q = 0; q < QR_NB; q += QC) {
+      if (q + QC - 1 >= c0) {
+#pragma unroll
+        for (int k = 0; k < QC; ++k)
+          if (FULL || (q + k >= c0 && q + k < nb)) st(q + k, i, x[q + k]);
+      }
+    }
+  };
+  // block sums of S[] and s into Stot and stot
+  auto reduce = [&](const T (&S)[QR_NB], T s) {
+    const T r = wave_sum32_scatter(S, lane);
+    s = wave_sum(s);
+    if ((lane & 1) == 0) part[wv][lane >> 1] = r;
+    if (lane == 0) sred[wv] = s;
+    __syncthreads();
+    if (tid < QR_NB) {
+      T t = 0;
+      for (int w = 0; w < NW; ++w) t += part[w][tid];
+      Stot[tid] = t;
+    } else if (tid == QR_NB) {
+      T t = 0;
+      for (int w = 0; w < NW; ++w) t += sred[w];
+      stot = t;
+    }
+    __syncthreads();
+  };
 
   // The panel is scaled once by the exact power of two that brings its largest
   // entry into [1, 2), so that squares of tiny or huge entries neither underflow
@@ -436,126 +473,88 @@ __device__ __forceinline__ void qr_panel_run(const QrPanel& d) {
   // scaled back at the end.
   T am = 0;
   for (int i = tid; i < mv; i += QR_WG) {
+    T x[QR_NB];
+    load_row(i, x);
 #pragma unroll
-    for (int q = 0; q < QR_NB; q += QC) {
-      if (FULL || q < nb) {
-        T x[QC];
-#pragma unroll
-        for (int k = 0; k < QC; ++k) x[k] = ld(q + k, i);
-#pragma unroll
-        for (int k = 0; k < QC; ++k) am = fmax(am, fabs(x[k]));
-      }
-    }
+    for (int c = 0; c < QR_NB; ++c) am = fmax(am, fabs(x[c]));
   }
-  am = block_max(am, red);
+  am = block_max(am, sred);
   const int sh = am > (T)0 ? -ilogb((double)am) : 0;
-  if (sh != 0)
+  // scaling pass, which also prepares column 0
+  {
+    T S[QR_NB], s = 0;
+#pragma unroll
+    for (int c = 0; c < QR_NB; ++c) S[c] = 0;
     for (int i = tid; i < mv; i += QR_WG) {
+      T x[QR_NB];
+      load_row(i, x);
+      if (sh != 0) {
 #pragma unroll
-      for (int q = 0; q < QR_NB; q += QC) {
-        if (FULL || q < nb) {
-          T x[QC];
+        for (int c = 0; c < QR_NB; ++c) x[c] = ldexp(x[c], sh);
+        store_row(i, x, 0);
+      }
+      if (i == 0) {
 #pragma unroll
-          for (int k = 0; k < QC; ++k) x[k] = ld(q + k, i);
+        for (int c = 0; c < QR_NB; ++c) rowj[c] = x[c];
+      } else {
+        const T y = x[0];
+        s += y * y;
 #pragma unroll
-          for (int k = 0; k < QC; ++k)
-            if (FULL || q + k < nb) st(q + k, i, ldexp(x[k], sh));
-        }
+        for (int c = 0; c < QR_NB; ++c) S[c] += y * x[c];
       }
     }
-  __syncthreads();
+    reduce(S, s);
+  }
 
-  // partial sum of squares of the next column below its diagonal, taken while
-  // the previous rank-one update writes that column
-  T s_next = 0;
-  bool have_next = false;
-  for (int jj = 0; jj < nb; ++jj) {
-    const T x0 = ld(jj, jj);
-    T s = s_next;
-    if (!have_next) {
-      s = 0;
-      for (int i = tid; i < mv; i += QR_WG)
-        if (i > jj) { const T x = ld(jj, i); s += x * x; }
+  T scal_prev = 1;
+  for (int j = 0; j < nb; ++j) {
+    // reflector j (every thread computes the same values from the block sums)
+    const T x0 = rowj[j], s = stot;
+    T tj = 0, al = x0, scal = 0;
+    if (s > (T)0) {
+      al = x0 >= (T)0 ? -sqrt(x0 * x0 + s) : sqrt(x0 * x0 + s);
+      tj = (al - x0) / al;
+      scal = (T)1 / (x0 - al);
     }
-    have_next = false;
-    s_next = 0;
-    s = block_sum(s, red);
-    if (!(s > (T)0)) {   // nothing below the diagonal: the reflector is the identity
-      if (tid == 0) { tau[jj] = 0; alph[j0 + jj] = ldexp(x0, -sh); }
-      continue;
-    }
-    const T al = x0 >= (T)0 ? -sqrt(x0 * x0 + s) : sqrt(x0 * x0 + s);
-    const T tj = (al - x0) / al;
-    const T scal = (T)1 / (x0 - al);
-    if (tid == 0) { tau[jj] = tj; alph[j0 + jj] = ldexp(al, -sh); }
-    // v (unit at row jj) and its products with every panel column
-    T acc[QR_NB];
+    // coefficients of the rank-one update (zero up to column j, so those
+    // columns are rewritten unchanged); the pass left column j - 1 unscaled in
+    // its products, hence the factor scal_prev on that Gram entry
+    T coef[QR_NB];
 #pragma unroll
-    for (int c = 0; c < QR_NB; ++c) acc[c] = 0;
+    for (int c = 0; c < QR_NB; ++c) coef[c] = c > j ? tj * (rowj[c] + scal * Stot[c]) : (T)0;
+    const T cnext = j + 1 < nb ? tj * (rowj[j + 1] + scal * Stot[j + 1]) : (T)0;
+    if (tid < j) G[tid + j * QR_NB] = (rowj[tid] + scal * Stot[tid]) * (tid == j - 1 ? scal_prev : (T)1);
+    if (tid == 0) { tau[j] = tj; alph[j0 + j] = ldexp(al, -sh); }
+    scal_prev = scal;
+    __syncthreads();   // rowj, Stot and stot are rewritten below
+    // apply reflector j, store v_j, prepare column j + 1
+    const bool next = j + 1 < nb;
+    T S[QR_NB], sn = 0;
+#pragma unroll
+    for (int c = 0; c < QR_NB; ++c) S[c] = 0;
     for (int i = tid; i < mv; i += QR_WG) {
-      if (i < jj) continue;
-      const T v = i == jj ? (T)1 : ld(jj, i) * scal;
-      st(jj, i, v);
+      if (i < j) continue;
+      T x[QR_NB];
+      load_row(i, x);
+      const T xj = ld(j, i), xn = next ? ld(j + 1, i) : (T)0;
+      const T v = i > j ? xj * scal : (T)1;
 #pragma unroll
-      for (int q = 0; q < QR_NB; q += QC) {
-        if (FULL || q < nb) {
-          T x[QC];
+      for (int c = 0; c < QR_NB; ++c) x[c] -= coef[c] * v;
+      store_row(i, x, j);
+      st(j, i, v);   // after the chunk that rewrote column j unchanged
+      if (next) {
+        if (i == j + 1) {
 #pragma unroll
-          for (int k = 0; k < QC; ++k) x[k] = ld(q + k, i);
+          for (int c = 0; c < QR_NB; ++c) rowj[c] = x[c];
+        } else if (i > j + 1) {
+          const T y = xn - cnext * v;
+          sn += y * y;
 #pragma unroll
-          for (int k = 0; k < QC; ++k) acc[q + k] += v * x[k];
+          for (int c = 0; c < QR_NB; ++c) S[c] += y * x[c];
         }
       }
     }
-    const T r = wave_sum32_scatter(acc, lane);
-    if ((lane & 1) == 0) part[wv][lane >> 1] = r;
-    __syncthreads();
-    if (tid < QR_NB) {
-      T t = 0;
-      for (int w = 0; w < NW; ++w) t += part[w][tid];
-      dots[tid] = tid > jj ? tj * t : (T)0;
-      if (tid < jj) G[tid + jj * QR_NB] = t;
-    }
-    __syncthreads();
-    if (jj + 1 < nb) {
-      // the loads of a chunk pair are in flight together before their stores
-      constexpr int HC = 2 * QC;
-      const int nx = jj + 1;
-      for (int i = tid; i < mv; i += QR_WG) {
-        if (i < jj) continue;
-        const T v = ld(jj, i);
-#pragma unroll
-        for (int h = 0; h < QR_NB; h += HC) {
-          if (h + HC - 1 > jj && (FULL || h < nb)) {
-            T x[HC];
-#pragma unroll
-            for (int k = 0; k < HC; ++k) x[k] = ld(h + k, i);
-#pragma unroll
-            for (int k = 0; k < HC; ++k) x[k] -= dots[h + k] * v;
-            if (FULL) {
-#pragma unroll
-              for (int q = 0; q < HC; q += QC)
-                if (h + q + QC - 1 > jj) {
-#pragma unroll
-                  for (int k = 0; k < QC; ++k) st(h + q + k, i, x[q + k]);
-                }
-            } else {
-#pragma unroll
-              for (int k = 0; k < HC; ++k)
-                if (h + k > jj && h + k < nb) st(h + k, i, x[k]);
-            }
-            if (nx >= h && nx < h + HC && i > nx) {
-              T y = x[0];
-#pragma unroll
-              for (int k = 1; k < HC; ++k) y = nx == h + k ? x[k] : y;
-              s_next += y * y;
-            }
-          }
-        }
-      }
-      have_next = true;
-    }
-    __syncthreads();
+    if (next) reduce(S, sn);
   }
   __syncthreads();
   // R entries of the panel rows, strictly right of the diagonal, back to their scale
@@ -565,21 +564,14 @@ __device__ __forceinline__ void qr_panel_run(const QrPanel& d) {
   }
   // V with explicit unit diagonal and zeros above it (own rows only)
   for (int i = tid; i < mv; i += QR_WG) {
+    T x[QR_NB];
+    load_row(i, x);
 #pragma unroll
-    for (int q = 0; q < QR_NB; q += QC) {
-      if (FULL || q < nb) {
-        T x[QC];
-#pragma unroll
-        for (int k = 0; k < QC; ++k) x[k] = ld(q + k, i);
-#pragma unroll
-        for (int k = 0; k < QC; ++k) {
-          const int c = q + k;
-          if (FULL || c < nb) {
-            T v = 0;
-            if (tau[c] != (T)0) v = i == c ? (T)1 : (i > c ? x[k] : (T)0);
-            V[i + (int64_t)c * mv] = v;
-          }
-        }
+    for (int c = 0; c < QR_NB; ++c) {
+      if (FULL || c < nb) {
+        T v = 0;
+        if (tau[c] != (T)0) v = i == c ? (T)1 : (i > c ? x[c] : (T)0);
+        V[i + (int64_t)c * mv] = v;
       }
     }
   }
