@@ -14,6 +14,34 @@ namespace ifmm {
 
 constexpr int LU_NB = 32;
 
+// Raw buffer access (gfx9 buffer resource: base, byte extent, 32-bit data
+// format word). One 32-bit per-lane byte offset serves every column of a
+// panel; the column offset is wave-uniform and goes in a scalar register, so a
+// row's 32 loads need no per-column address registers. Accesses past the
+// extent read zero and drop writes.
+__device__ inline __amdgpu_buffer_rsrc_t buf_rsrc(void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(base, (short)0, (int)bytes, 0x00020000);
+}
+template <class T>
+__device__ inline T buf_ld(__amdgpu_buffer_rsrc_t r, int vo, int so);
+template <>
+__device__ inline double buf_ld<double>(__amdgpu_buffer_rsrc_t r, int vo, int so) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
+}
+template <>
+__device__ inline float buf_ld<float>(__amdgpu_buffer_rsrc_t r, int vo, int so) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
+}
+__device__ inline void buf_st(double v, __amdgpu_buffer_rsrc_t r, int vo, int so) {
+  using B = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(B, v), r, vo, so, 0);
+}
+__device__ inline void buf_st(float v, __amdgpu_buffer_rsrc_t r, int vo, int so) {
+  using B = decltype(__builtin_amdgcn_raw_buffer_load_b32(r, 0, 0, 0));
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(B, v), r, vo, so, 0);
+}
+
+
 struct PanelDesc {
   void* A;
   int* piv;
@@ -21,64 +49,135 @@ struct PanelDesc {
 };
 
 // Factorize columns k0..k0+nb-1 (rows k0..n-1), swapping rows inside the panel.
-template <class T>
-__global__ void __launch_bounds__(WG) k_lu_panel(const PanelDesc* __restrict__ ds, int* info) {
-  const PanelDesc d = ds[blockIdx.x];
+// Each thread owns the rows i = k0 + tid + k WG. Per column: the pivot (largest
+// magnitude, smallest row on ties) by wavefront shuffles and one exchange
+// through LDS; the swap of the pivot row, which also goes to LDS; then each
+// thread scales its rows' multipliers and updates their remaining panel
+// columns with all loads of a chunk in flight, keeping the magnitude of the
+// next column as its pivot candidate (so the next pivot needs no extra pass).
+template <class T, bool INLDS>
+__device__ __forceinline__ void lu_panel_run(const PanelDesc& d, int* info, T* __restrict__ L) {
+  constexpr int NW = WG / WAVE;
+  constexpr int QC = 8;
   T* __restrict__ A = static_cast<T*>(d.A);
   const int n = d.n, k0 = d.k0, nb = d.nb;
   const int64_t ld = d.lda;
-  __shared__ T smax[WG];
-  __shared__ int sidx[WG];
+  __shared__ T wbest[NW];
+  __shared__ int wbi[NW];
+  __shared__ T prow[LU_NB];   // pivot row after the swap, zero outside the columns to update
+  __shared__ T pdiag;
   __shared__ int sp;
-  __shared__ T spv;
+  const int tid = threadIdx.x, lane = tid % WAVE, wv = tid / WAVE;
+  // the panel's columns from row 0: one per-lane offset for all of a row's columns
+  T* P = A + (int64_t)k0 * ld;
+  const int ldb = (int)ld * (int)sizeof(T);   // the host checks LU_NB lda sizeof(T) < 2^31
+  const __amdgpu_buffer_rsrc_t rs = buf_rsrc(P, (uint32_t)(((int64_t)(nb - 1) * ld + n) * sizeof(T)));
+  // INLDS: the panel rows k0..n-1 live in LDS (column-major, leading dimension n - k0) while it is factorized
+  const int ml = n - k0;
+  auto ldv = [&](int c, int i) -> T {
+    if constexpr (INLDS) return L[(i - k0) + c * ml];
+    else return buf_ld<T>(rs, i * (int)sizeof(T), c * ldb);
+  };
+  auto stv = [&](int c, int i, T v) {
+    if constexpr (INLDS) L[(i - k0) + c * ml] = v;
+    else buf_st(v, rs, i * (int)sizeof(T), c * ldb);
+  };
+  if constexpr (INLDS) {
+    for (int c = 0; c < nb; ++c)
+      for (int i = tid; i < ml; i += WG) L[i + c * ml] = buf_ld<T>(rs, (k0 + i) * (int)sizeof(T), c * ldb);
+    __syncthreads();
+  }
+  T best = (T)-1;
+  int bi = k0;
+  for (int i = k0 + tid; i < n; i += WG) {
+    const T v = fabs(ldv(0, i));
+    if (v > best) { best = v; bi = i; }
+  }
   for (int j = 0; j < nb; ++j) {
     const int col = k0 + j;
-    T best = -1;
-    int bi = col;
-    for (int i = col + threadIdx.x; i < n; i += WG) {
-      const T v = fabs(A[i + col * ld]);
-      if (v > best) { best = v; bi = i; }
+    for (int o = WAVE / 2; o > 0; o >>= 1) {
+      const T ob = __shfl_xor(best, o, WAVE);
+      const int oi = __shfl_xor(bi, o, WAVE);
+      if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
     }
-    smax[threadIdx.x] = best;
-    sidx[threadIdx.x] = bi;
+    if (lane == 0) { wbest[wv] = best; wbi[wv] = bi; }
     __syncthreads();
-    for (int s = WG / 2; s > 0; s >>= 1) {
-      if ((int)threadIdx.x < s) {
-        const T o = smax[threadIdx.x + s];
-        const int oi = sidx[threadIdx.x + s];
-        if (o > smax[threadIdx.x] || (o == smax[threadIdx.x] && oi < sidx[threadIdx.x])) {
-          smax[threadIdx.x] = o;
-          sidx[threadIdx.x] = oi;
-        }
-      }
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-      sp = sidx[0];
-      d.piv[col] = sp;
-      if (!(smax[0] > (T)0) && info) atomicCAS(info, -1, d.tag);
+    if (tid == 0) {
+      T b = wbest[0];
+      int i0 = wbi[0];
+      for (int w = 1; w < NW; ++w)
+        if (wbest[w] > b || (wbest[w] == b && wbi[w] < i0)) { b = wbest[w]; i0 = wbi[w]; }
+      sp = i0;
+      d.piv[col] = i0;
+      if (!(b > (T)0) && info) atomicCAS(info, -1, d.tag);
     }
     __syncthreads();
     const int p = sp;
-    if (p != col)
-      for (int c = k0 + (int)threadIdx.x; c < k0 + nb; c += WG) {
-        const T a = A[col + c * ld];
-        A[col + c * ld] = A[p + c * ld];
-        A[p + c * ld] = a;
+    if (tid < LU_NB) {
+      T b = 0;
+      if (tid < nb) {
+        const T a = ldv(tid, col);
+        b = ldv(tid, p);
+        if (p != col) {
+          stv(tid, col, b);
+          stv(tid, p, a);
+        }
       }
-    __syncthreads();
-    if (threadIdx.x == 0) spv = A[col + col * ld];
-    __syncthreads();
-    const T inv = spv != (T)0 ? (T)1 / spv : (T)0;
-    for (int i = col + 1 + threadIdx.x; i < n; i += WG) A[i + col * ld] *= inv;
-    __syncthreads();
-    const int rows = n - col - 1, cols = k0 + nb - col - 1;
-    for (int e = threadIdx.x; e < rows * cols; e += WG) {
-      const int i = col + 1 + e % rows, c = col + 1 + e / rows;
-      A[i + c * ld] -= A[i + col * ld] * A[col + c * ld];
+      if (tid == j) pdiag = b;
+      prow[tid] = tid > j && tid < nb ? b : (T)0;
     }
     __syncthreads();
+    const T inv = pdiag != (T)0 ? (T)1 / pdiag : (T)0;
+    best = (T)-1;
+    bi = col + 1;
+    for (int i = k0 + tid; i < n; i += WG) {
+      if (i <= col) continue;
+      const T l = ldv(j, i) * inv;
+#pragma unroll
+      for (int q = 0; q < LU_NB; q += QC) {
+        if (q + QC - 1 > j && q < nb) {
+          T x[QC];
+#pragma unroll
+          for (int k = 0; k < QC; ++k) x[k] = ldv(min(q + k, nb - 1), i);
+#pragma unroll
+          for (int k = 0; k < QC; ++k) x[k] -= l * prow[q + k];
+          if (q + QC <= nb) {
+#pragma unroll
+            for (int k = 0; k < QC; ++k) stv(q + k, i, x[k]);
+          } else {
+#pragma unroll
+            for (int k = 0; k < QC; ++k)
+              if (q + k < nb) stv(q + k, i, x[k]);
+          }
+          if (j + 1 >= q && j + 1 < q + QC) {
+            T y = x[0];
+#pragma unroll
+            for (int k = 1; k < QC; ++k) y = j + 1 == q + k ? x[k] : y;
+            const T v = fabs(y);
+            if (v > best) { best = v; bi = i; }
+          }
+        }
+      }
+      stv(j, i, l);   // after the chunk that rewrote column col unchanged
+    }
   }
+  if constexpr (INLDS) {
+    __syncthreads();
+    for (int c = 0; c < nb; ++c)
+      for (int i = tid; i < ml; i += WG) buf_st(L[i + c * ml], rs, (k0 + i) * (int)sizeof(T), c * ldb);
+  }
+}
+
+// lds_rows > 0: every panel of the launch has at most lds_rows rows and is
+// factorized in dynamic LDS (lds_rows x LU_NB elements).
+template <class T>
+__global__ void __launch_bounds__(WG) k_lu_panel(const PanelDesc* __restrict__ ds, int* info, int lds_rows) {
+  extern __shared__ unsigned char lu_dyn[];
+  const PanelDesc d = ds[blockIdx.x];
+  if (lds_rows > 0)
+    lu_panel_run<T, true>(d, info, reinterpret_cast<T*>(lu_dyn));
+  else
+    lu_panel_run<T, false>(d, info, nullptr);
 }
 
 // Apply the panel's row interchanges to the columns outside the panel, then
@@ -192,10 +291,23 @@ struct LuScratch {
   DevBuf pd, gd;
 };
 
+constexpr size_t LU_LDS_MAX = 144 * 1024;   // dynamic LDS of the panel kernel (gfx950: 160 KB per workgroup)
+
 template <class T>
 inline void lu_blocked(Problem& P, const std::vector<LuJob>& jobs, LuScratch& S) {
+  static const bool attr = [] {   // once per process (thread-safe initialisation)
+    IFMM_HIP(hipFuncSetAttribute((const void*)k_lu_panel<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)LU_LDS_MAX));
+    return true;
+  }();
+  (void)attr;
   int nmax = 0;
-  for (const auto& j : jobs) nmax = std::max(nmax, j.n);
+  for (const auto& j : jobs) {
+    nmax = std::max(nmax, j.n);
+    // the panel kernel addresses a panel with 32-bit byte offsets
+    if ((int64_t)j.lda * LU_NB * (int64_t)sizeof(T) >= ((int64_t)1 << 31))
+      fail(IFMM_ERR_ARG, "LU of a matrix with leading dimension " + std::to_string(j.lda) + ": above the panel limit");
+  }
   for (int k0 = 0; k0 < nmax; k0 += LU_NB) {
     std::vector<PanelDesc> pd;
     GemmBatch gb;
@@ -217,8 +329,14 @@ inline void lu_blocked(Problem& P, const std::vector<LuJob>& jobs, LuScratch& S)
     }
     if (pd.empty()) break;
     const PanelDesc* dp = P.put(S.pd, pd);
+    // panels that fit are factorized in LDS (one load and one store of the panel)
+    int rows = 0;
+    for (const auto& q : pd) rows = std::max(rows, q.n - q.k0);
+    const size_t lds = (size_t)rows * LU_NB * sizeof(T);
+    const bool inlds = lds <= LU_LDS_MAX;
     P.kbegin();
-    hipLaunchKernelGGL(k_lu_panel<T>, dim3((unsigned)pd.size()), dim3(WG), 0, P.stream, dp, P.d_info);
+    hipLaunchKernelGGL(k_lu_panel<T>, dim3((unsigned)pd.size()), dim3(WG), inlds ? lds : 0, P.stream, dp, P.d_info,
+                       inlds ? rows : 0);
     IFMM_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_lu_swap_trsm<T>, dim3((unsigned)pd.size(), (unsigned)ceil_div(maxcols, WG)), dim3(WG), 0,
                        P.stream, dp);
@@ -358,33 +476,6 @@ __device__ inline T wave_sum32_scatter(const T (&v)[32], int lane) {
   const bool hi = lane & 2;
   T f = (hi ? e[1] : e[0]) + __shfl_xor(hi ? e[0] : e[1], 2, WAVE);
   return f + __shfl_xor(f, 1, WAVE);
-}
-
-// Raw buffer access (gfx9 buffer resource: base, byte extent, 32-bit data
-// format word). One 32-bit per-lane byte offset serves every column of a
-// panel; the column offset is wave-uniform and goes in a scalar register, so a
-// row's 32 loads need no per-column address registers. Accesses past the
-// extent read zero and drop writes.
-__device__ inline __amdgpu_buffer_rsrc_t buf_rsrc(void* base, uint32_t bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(base, (short)0, (int)bytes, 0x00020000);
-}
-template <class T>
-__device__ inline T buf_ld(__amdgpu_buffer_rsrc_t r, int vo, int so);
-template <>
-__device__ inline double buf_ld<double>(__amdgpu_buffer_rsrc_t r, int vo, int so) {
-  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
-}
-template <>
-__device__ inline float buf_ld<float>(__amdgpu_buffer_rsrc_t r, int vo, int so) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
-}
-__device__ inline void buf_st(double v, __amdgpu_buffer_rsrc_t r, int vo, int so) {
-  using B = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
-  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(B, v), r, vo, so, 0);
-}
-__device__ inline void buf_st(float v, __amdgpu_buffer_rsrc_t r, int vo, int so) {
-  using B = decltype(__builtin_amdgcn_raw_buffer_load_b32(r, 0, 0, 0));
-  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(B, v), r, vo, so, 0);
 }
 
 // One panel of QR_NB columns per workgroup. Each thread owns the panel rows
