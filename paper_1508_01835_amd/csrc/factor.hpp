@@ -9,6 +9,8 @@
 // device-to-host read of the ranks per class).
 #pragma once
 
+#include <thread>
+
 #include "blocked.hpp"
 #include "build.hpp"
 #include "factor_kernels.hpp"
@@ -279,6 +281,25 @@ struct Factorizer {
     P.upload(L.dSVo, L.SVo); P.upload(L.dPUo, L.PUo); P.upload(L.dPVo, L.PVo); P.upload(L.drpar, L.rpar);
   }
 
+  // adjacency of two offsets in {-1, 0, 1}^d (codes as offset3): |o_a - o_b| <= 1 per axis
+  std::vector<uint8_t> adj3_;
+  int c3_ = 0;
+  void build_adj3() {
+    if (!adj3_.empty()) return;
+    c3_ = 1;
+    for (int k = 0; k < P.d; ++k) c3_ *= 3;
+    adj3_.assign((size_t)c3_ * c3_, 0);
+    for (int a = 0; a < c3_; ++a)
+      for (int b = 0; b < c3_; ++b) {
+        bool ok = true;
+        for (int k = 0, x = a, y = b; k < P.d; ++k, x /= 3, y /= 3) {
+          const int dd = x % 3 - y % 3;
+          if (dd > 1 || dd < -1) ok = false;
+        }
+        adj3_[(size_t)a * c3_ + b] = ok ? 1 : 0;
+      }
+  }
+
   int offset3(const HLevel& lv, int i, int j) const {
     int code = 0, mul = 1;
     for (int k = 0; k < P.d; ++k) {
@@ -490,17 +511,37 @@ struct Factorizer {
     // basis changes 2 k r cols per edge, with the new rank k bounded by the old
     // rank r (the new ranks are still on the device)
     if (L.erow_start.empty()) {
+      // boxes split over host threads, chunks concatenated in order
+      const int nt = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+      std::vector<std::vector<int>> rch(nt), cch(nt), rcnt(nt), ccnt(nt);
+      std::vector<std::thread> th;
+      const int per = (L.nb + nt - 1) / nt;
+      for (int t = 0; t < nt; ++t)
+        th.emplace_back([&, t] {
+          const int j0 = t * per, j1 = std::min(L.nb, j0 + per);
+          for (int j = j0; j < j1; ++j) {
+            int nr = 0, nc = 0;
+            for (int code = 0; code < L.c7; ++code) {
+              const int q = L.B7[(size_t)j * L.c7 + code];
+              if (q < 0) continue;
+              if (L.Kt[(size_t)j * L.c7 + code] >= 0) { rch[t].push_back(code); ++nr; }
+              if (L.Kt[(size_t)q * L.c7 + (L.c7 - 1 - code)] >= 0) { cch[t].push_back(code); ++nc; }
+            }
+            rcnt[t].push_back(nr);
+            ccnt[t].push_back(nc);
+          }
+        });
+      for (auto& x : th) x.join();
       L.erow_start.assign(L.nb + 1, 0);
       L.ecol_start.assign(L.nb + 1, 0);
-      for (int j = 0; j < L.nb; ++j) {
-        for (int code = 0; code < L.c7; ++code) {
-          const int q = L.B7[(size_t)j * L.c7 + code];
-          if (q < 0) continue;
-          if (L.Kt[(size_t)j * L.c7 + code] >= 0) L.erow.push_back(code);
-          if (L.Kt[(size_t)q * L.c7 + (L.c7 - 1 - code)] >= 0) L.ecol.push_back(code);
+      int j = 0;
+      for (int t = 0; t < nt; ++t) {
+        L.erow.insert(L.erow.end(), rch[t].begin(), rch[t].end());
+        L.ecol.insert(L.ecol.end(), cch[t].begin(), cch[t].end());
+        for (size_t k = 0; k < rcnt[t].size(); ++k, ++j) {
+          L.erow_start[j + 1] = L.erow_start[j] + rcnt[t][k];
+          L.ecol_start[j + 1] = L.ecol_start[j] + ccnt[t][k];
         }
-        L.erow_start[j + 1] = (int)L.erow.size();
-        L.ecol_start[j + 1] = (int)L.ecol.size();
       }
       P.upload(L.derow_start, L.erow_start);
       P.upload(L.derow, L.erow);
@@ -698,6 +739,7 @@ struct Factorizer {
 
   // ----------------------------------------------------------- one level
   void eliminate_level(LevelPool<T>& L) {
+    build_adj3();
     const int l = L.l;
     const HLevel& lv = P.T.lev[l];
     const int d = P.d;
@@ -718,6 +760,7 @@ struct Factorizer {
       int64_t fo = 0, po = 0, wo = 0, so = 0;
       int maxF = 0;
       std::vector<CompDesc> cs;
+      std::vector<int> fcode;   // offset code (3^d) of each F node of the box relative to it
       for (int i : boxes) {
         ElimDesc e{};
         e.box = i;
@@ -725,8 +768,10 @@ struct Factorizer {
         e.r = L.r[i];
         e.p = e.m + e.r;
         e.F0 = (int)Fs.size();
+        fcode.clear();
         int f = 0;
         auto push = [&](int type, int b) {
+          fcode.push_back(offset3(lv, i, b));
           FNode n{};
           n.type = type;
           n.box = b;
@@ -778,9 +823,10 @@ struct Factorizer {
           if (X.type != 0) continue;
           int nc = L.r[X.box];
           bool any = false;
+          // both are neighbours of i: adjacent iff their offsets from i differ by at most one
+          const uint8_t* adj = &adj3_[(size_t)fcode[a] * c3_];
           for (int b = 0; b < e.nF; ++b) {
-            const FNode& B = Fs[e.F0 + b];
-            if (!adjacent(lv, d, X.box, B.box)) { nc += B.dim; any = true; }
+            if (!adj[fcode[b]]) { nc += Fs[e.F0 + b].dim; any = true; }
           }
           if (!any) continue;
           CompDesc cd{};
