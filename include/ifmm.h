@@ -98,7 +98,8 @@ typedef struct {
   double gmres_relres;        /* of the last ifmm_gmres call (max over columns) */
   /* Device time by kernel family, measured with HIP events on the handle's
      stream when the environment variable IFMM_KTIMING=1 is set at build time
-     (otherwise zero); totals since the handle was built. Families:
+     (IFMM_KTIMING=m<hex>: only the families whose bits are set; otherwise
+     zero); totals since the handle was built. Families:
      0 Schur-complement GEMM, 1 pivot LU (panels, swaps, trailing GEMM),
      2 triangular solves W = E_PP^-1 E_PF, 3 Householder QR of the
      recompression matrices, 4 Jacobi SVD, 5 basis changes of the edges and

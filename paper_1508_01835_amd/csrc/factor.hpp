@@ -750,8 +750,12 @@ struct Factorizer {
       if (boxes.empty()) continue;
       // ranks are exact on the host at the start of every class; the stream is
       // idle, so the descriptors of the previous class can be recycled
-      P.download(L.r, L.dr.p, (size_t)lv.nb);
+      {
+        HostScope hs(P.hprof, "class: wait + read ranks");
+        P.download(L.r, L.dr.p, (size_t)lv.nb);
+      }
       P.arena_reset();
+      HostScope hs_plan(P.hprof, "class: plan");
       ClassFactors<T>& cf = F.cls[l][c];
       std::vector<ElimDesc>& el = cf.el;
       std::vector<FNode>& Fs = cf.F;
@@ -842,6 +846,8 @@ struct Factorizer {
         factor_elems += (int64_t)(e.m + e.f) * e.m + (int64_t)e.m * e.f;
         el.push_back(e);
       }
+      hs_plan.stop();
+      HostScope hs_launch(P.hprof, "class: allocate + launch");
       if ((size_t)fo * sizeof(T) > F.arena.bytes || (size_t)po * sizeof(int) > F.pivs.bytes ||
           (size_t)wo * sizeof(T) > F.work.bytes)
         P.sync();   // kernels of the previous class may still use the buffers being replaced
@@ -927,7 +933,12 @@ struct Factorizer {
       // well-separated fill: recompress the bases of the affected boxes, then redirect
       IFMM_HIP(hipMemcpyAsync(L.drnew.p, L.dr.p, sizeof(int) * lv.nb, hipMemcpyDeviceToDevice, P.stream));
       chk(L, "near_scatter", nullptr, wo);
-      recompress(L, cs, el, del, dF, wo);
+      hs_launch.stop();
+      {
+        HostScope hs(P.hprof, "class: recompress");
+        recompress(L, cs, el, del, dF, wo);
+      }
+      HostScope hs_red(P.hprof, "class: redirect");
       chk(L, "recompress", nullptr, 0);
       {   // coarse levels (large ranks): batched products; fine levels: one workgroup per pair on the device
         int rmax = 0;
@@ -1049,24 +1060,35 @@ struct Factorizer {
     F.cls.resize(Lv + 1);
     F.sl.assign(Lv + 1, SolveLevel<T>());
     auto cur = std::make_unique<LevelPool<T>>();
-    setup_leaf(*cur);
+    {
+      HostScope hs(P.hprof, "setup leaf level");
+      setup_leaf(*cur);
+    }
     for (int l = Lv; l >= 2; --l) {
       P.trace_level = l;
       eliminate_level(*cur);
+      HostScope hs_ps(P.hprof, "plan solve");
       plan_solve(*cur);
+      hs_ps.stop();
       P.st.max_rank[l] = 0;
       double sum = 0;
       for (int x : cur->r) { P.st.max_rank[l] = std::max(P.st.max_rank[l], x); sum += x; }
       P.st.mean_rank[l] = cur->nb ? sum / cur->nb : 0.0;
       if (l > 2) {
+        HostScope hs(P.hprof, "merge");
         auto nxt = std::make_unique<LevelPool<T>>();
         merge(*cur, *nxt);
+        HostScope hs_free(P.hprof, "free child level");
         cur = std::move(nxt);
       } else {
+        HostScope hs(P.hprof, "top");
         top(*cur);
       }
     }
-    P.sync();
+    {
+      HostScope hs(P.hprof, "final wait");
+      P.sync();
+    }
     std::vector<int> info;
     P.download(info, P.d_info, 1);
     if (info[0] != -1) {

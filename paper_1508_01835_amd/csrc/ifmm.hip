@@ -102,7 +102,8 @@ int ifmm_build(const double* points, int64_t n, int dim, ifmm_kernel k, int dept
     P.mem.budget = o.hbm_budget_bytes;
     {
       const char* kt = std::getenv("IFMM_KTIMING");
-      P.kt.on = kt && kt[0] == '1';
+      P.kt.on = kt && (kt[0] == '1' || kt[0] == 'm');
+      if (kt && kt[0] == 'm') P.kt.mask = (uint32_t)std::strtoul(kt + 1, nullptr, 16);
     }
     P.stream = static_cast<hipStream_t>(o.stream);
     P.n = n;
@@ -160,6 +161,10 @@ void factorize_handle(ifmm_handle h) {
     }
     P.st.t_factor_ms = now_ms() - t0;
     P.factorized = true;
+    if (HostProf::on()) {
+      P.hprof.print("factorize");
+      P.hprof.acc.clear();
+    }
   }
 }
 

@@ -36,7 +36,8 @@ struct FactorStoreBase {
 };
 
 // Kernel-family timing with HIP events on the handle's stream (enabled by
-// IFMM_KTIMING=1): duration, launch count and algorithmic flops / bytes.
+// IFMM_KTIMING=1, or IFMM_KTIMING=m<hex mask> for the families of the mask
+// only): duration, launch count and algorithmic flops / bytes.
 // Families 0-8 group the launches of one phase; families 9-14 hold exactly
 // one kernel each, every launch timed on its own (per-launch averages);
 // family 15 holds the launches of the step-wise pivoted QR.
@@ -46,8 +47,39 @@ enum KFam {
 };
 static_assert(KF_COUNT <= 16, "the query structure holds 16 families");
 
+// Host wall time by section (diagnostics, IFMM_HOSTPROF=1): where the host
+// spends the factorization, waiting on the device included.
+struct HostProf {
+  static bool on() {
+    static const bool v = std::getenv("IFMM_HOSTPROF") != nullptr;
+    return v;
+  }
+  std::vector<std::pair<const char*, double>> acc;
+  void add(const char* name, double ms) {
+    for (auto& x : acc)
+      if (x.first == name) { x.second += ms; return; }
+    acc.push_back({name, ms});
+  }
+  void print(const char* tag) const {
+    for (const auto& x : acc) std::fprintf(stderr, "[ifmm-hostprof] %s %-28s %9.2f ms\n", tag, x.first, x.second);
+  }
+};
+struct HostScope {
+  HostProf* hp;
+  const char* name;
+  double t0;
+  HostScope(HostProf& h, const char* n) : hp(HostProf::on() ? &h : nullptr), name(n), t0(hp ? now_ms() : 0) {}
+  void stop() {
+    if (hp) hp->add(name, now_ms() - t0);
+    hp = nullptr;
+  }
+  ~HostScope() { stop(); }
+};
+
 struct KTimer {
   bool on = false;
+  uint32_t mask = ~0u;        // families that are timed
+  bool last_on = false;       // whether the open range was recorded
   struct Rec { int fam; hipEvent_t a, b; double flops, bytes; int64_t launches; };
   std::vector<Rec> open;
   std::vector<hipEvent_t> pool;   // events of collected records, reused
@@ -64,13 +96,15 @@ struct KTimer {
     return e;
   }
   void begin(hipStream_t s, int fam, double fl, double by, int64_t nl = 1) {
-    if (!on) return;
+    last_on = on && ((mask >> fam) & 1u);
+    if (!last_on) return;
     Rec r{fam, event(), event(), fl, by, nl};
     IFMM_HIP(hipEventRecord(r.a, s));
     open.push_back(r);
   }
   void end(hipStream_t s) {
-    if (!on || open.empty()) return;
+    if (!last_on || open.empty()) return;
+    last_on = false;
     IFMM_HIP(hipEventRecord(open.back().b, s));
   }
   // Fold completed records into the totals (call after a stream sync).
@@ -123,6 +157,7 @@ struct Problem {
   hipStream_t stream = nullptr;
   MemAccount mem;
   Staging stage;
+  HostProf hprof;
   bool factorized = false;
 
   // tree
