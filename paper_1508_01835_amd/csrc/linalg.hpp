@@ -4,6 +4,8 @@
 // workgroup (or a set of tiles) serves one descriptor.
 #pragma once
 
+#include <type_traits>
+
 #include "common.hpp"
 
 namespace ifmm {
@@ -86,12 +88,16 @@ __global__ void __launch_bounds__(WG) k_gemm(const GemmDesc* __restrict__ ds, in
   T* __restrict__ C = static_cast<T*>(d.C);
   __shared__ T As[GK][GT + 1];
   __shared__ T Bs[GK][GT + 1];
-  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;   // 16 x 16 threads, 4x4 each
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;   // 16 x 16 threads, 4x4 each (vector path)
   T acc[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = 0;
+  typedef double v4d __attribute__((ext_vector_type(4)));
+  v4d mfa[4];   // matrix-core accumulators (FP64 path)
+#pragma unroll
+  for (int i = 0; i < 4; ++i) mfa[i] = v4d{0, 0, 0, 0};
   for (int k0 = 0; k0 < d.K; k0 += GK) {
     // load op(A)[m0:m0+64, k0:k0+16] and op(B)[k0:k0+16, n0:n0+64]
     for (int e = threadIdx.x; e < GT * GK; e += WG) {
@@ -112,31 +118,68 @@ __global__ void __launch_bounds__(WG) k_gemm(const GemmDesc* __restrict__ ds, in
       Bs[kk][nn] = w;
     }
     __syncthreads();
+    if constexpr (std::is_same<T, double>::value) {
+      // FP64 matrix cores: wavefront w owns rows 32 (w / 2).., columns 32 (w % 2).. of
+      // the tile as 2 x 2 blocks of 16 x 16. v_mfma_f64_16x16x4f64 takes from lane
+      // l the entry A[l % 16][l / 16] of a 16 x 4 slice and B[l / 16][l % 16] of a
+      // 4 x 16 slice, and lane l's register r holds D[4 r + l / 16][l % 16].
+      const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
+      const int rb0 = 32 * (wv >> 1), cb0 = 32 * (wv & 1);
 #pragma unroll
-    for (int kk = 0; kk < GK; ++kk) {
-      T a[4], b[4];
+      for (int k4 = 0; k4 < GK; k4 += 4) {
+        const int kk = k4 + (lane >> 4);
+        const double a0 = As[kk][rb0 + (lane & 15)], a1 = As[kk][rb0 + 16 + (lane & 15)];
+        const double b0 = Bs[kk][cb0 + (lane & 15)], b1 = Bs[kk][cb0 + 16 + (lane & 15)];
+        mfa[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, mfa[0], 0, 0, 0);
+        mfa[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, mfa[1], 0, 0, 0);
+        mfa[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, mfa[2], 0, 0, 0);
+        mfa[3] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, mfa[3], 0, 0, 0);
+      }
+    } else {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = As[kk][tx + 16 * i];
+      for (int kk = 0; kk < GK; ++kk) {
+        T a[4], b[4];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) b[j] = Bs[kk][ty + 16 * j];
+        for (int i = 0; i < 4; ++i) a[i] = As[kk][tx + 16 * i];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) b[j] = Bs[kk][ty + 16 * j];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * b[j];
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * b[j];
+      }
     }
     __syncthreads();
   }
   const T alpha = (T)d.alpha, beta = (T)d.beta;
+  if constexpr (std::is_same<T, double>::value) {
+    const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
+    const int rb0 = 32 * (wv >> 1), cb0 = 32 * (wv & 1);
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int gn = n0 + ty + 16 * j;
-    if (gn >= d.N) continue;
+    for (int blk = 0; blk < 4; ++blk) {
+      const int gn = n0 + cb0 + 16 * (blk & 1) + (lane & 15);
+      if (gn >= d.N) continue;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int gm = m0 + tx + 16 * i;
-      if (gm >= d.M) continue;
-      T* c = &C[(int64_t)gm + (int64_t)gn * d.ldc];
-      *c = beta == (T)0 ? alpha * acc[i][j] : alpha * acc[i][j] + beta * (*c);
+      for (int r = 0; r < 4; ++r) {
+        const int gm = m0 + rb0 + 16 * (blk >> 1) + 4 * r + (lane >> 4);
+        if (gm >= d.M) continue;
+        T* c = &C[(int64_t)gm + (int64_t)gn * d.ldc];
+        const T v = mfa[blk][r];
+        *c = beta == (T)0 ? alpha * v : alpha * v + beta * (*c);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int gn = n0 + ty + 16 * j;
+      if (gn >= d.N) continue;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int gm = m0 + tx + 16 * i;
+        if (gm >= d.M) continue;
+        T* c = &C[(int64_t)gm + (int64_t)gn * d.ldc];
+        *c = beta == (T)0 ? alpha * acc[i][j] : alpha * acc[i][j] + beta * (*c);
+      }
     }
   }
 }
