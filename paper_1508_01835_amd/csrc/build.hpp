@@ -197,9 +197,24 @@ inline void matvec_tree(Problem& P, const double* x, double* y, int nrhs) {
     IFMM_LAUNCH_CHECK();
   }
   for (int l = 2; l <= L; ++l) {
-    hipLaunchKernelGGL(k_m2l, dim3(T.lev[l].nb), dim3(WG), 0, P.stream, P.ldev[l].in_start.as<int>(),
-                       P.ldev[l].inter.as<int>(), P.ldev[l].coords.as<int>(), T.lev[l].nb, d, q, nrhs,
-                       P.m2l[l].as<double>(), P.mv_w[l].as<double>(), P.mv_g[l].as<double>());
+    const int* ist = P.ldev[l].in_start.as<int>();
+    const int* itr = P.ldev[l].inter.as<int>();
+    const int* crd = P.ldev[l].coords.as<int>();
+    const int nbl = T.lev[l].nb;
+    const double* tb = P.m2l[l].as<double>();
+    // matrix cores for q <= 64 (orders up to 4 in 3D), the vector kernel above that
+    if (q <= 16)
+      hipLaunchKernelGGL(k_m2l_mfma<1>, dim3(nbl), dim3(256), 0, P.stream, ist, itr, crd, nbl, d, q, nrhs, tb,
+                         P.mv_w[l].as<double>(), P.mv_g[l].as<double>());
+    else if (q <= 32)
+      hipLaunchKernelGGL(k_m2l_mfma<2>, dim3(nbl), dim3(256), 0, P.stream, ist, itr, crd, nbl, d, q, nrhs, tb,
+                         P.mv_w[l].as<double>(), P.mv_g[l].as<double>());
+    else if (q <= 64)
+      hipLaunchKernelGGL(k_m2l_mfma<4>, dim3(nbl), dim3(256), 0, P.stream, ist, itr, crd, nbl, d, q, nrhs, tb,
+                         P.mv_w[l].as<double>(), P.mv_g[l].as<double>());
+    else
+      hipLaunchKernelGGL(k_m2l, dim3(nbl), dim3(WG), 0, P.stream, ist, itr, crd, nbl, d, q, nrhs, tb,
+                         P.mv_w[l].as<double>(), P.mv_g[l].as<double>());
     IFMM_LAUNCH_CHECK();
   }
   for (int l = 3; l <= L; ++l) {

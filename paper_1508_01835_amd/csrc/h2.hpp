@@ -167,6 +167,68 @@ __global__ void k_m2l(const int* __restrict__ in_start, const int* __restrict__ 
   }
 }
 
+// M2L on the FP64 matrix cores, for q <= 16 RB: per target box i,
+// g_i (q x nrhs) = sum over I(i) of K_code (q x q) w_j (q x nrhs), i.e. one
+// contraction of depth |I(i)| q. The four wavefronts of the workgroup take
+// every fourth source of the list and accumulate 16 x 16 blocks with
+// v_mfma_f64_16x16x4f64 (lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16]
+// of a 16 x 4 and a 4 x 16 slice; register r of lane l holds D[4 r + l / 16][l % 16]);
+// entries past q or nrhs are supplied as zero. The four partial sums are added
+// through LDS in a fixed order. Columns of the right-hand sides in blocks of 16.
+template <int RB>
+__global__ void __launch_bounds__(256) k_m2l_mfma(const int* __restrict__ in_start, const int* __restrict__ inter,
+                                                  const int* __restrict__ coords, int nb, int d, int q, int nrhs,
+                                                  const double* __restrict__ tab, const double* __restrict__ w,
+                                                  double* __restrict__ g) {
+  typedef double v4d __attribute__((ext_vector_type(4)));
+  __shared__ double red[4][RB * 256];
+  const int i = blockIdx.x;
+  if (i >= nb) return;
+  const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
+  const int t0 = in_start[i], t1 = in_start[i + 1];
+  int ci[3] = {0, 0, 0};
+  for (int k = 0; k < d; ++k) ci[k] = coords[i * d + k];
+  for (int cb = 0; cb < nrhs; cb += 16) {
+    v4d acc[RB];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) acc[rb] = v4d{0, 0, 0, 0};
+    const int rr = cb + (lane & 15);
+    const bool colok = rr < nrhs;
+    for (int t = t0 + wv; t < t1; t += 4) {
+      const int j = inter[t];
+      int code = 0, mul = 1;
+      for (int k = 0; k < d; ++k) {
+        code += (coords[j * d + k] - ci[k] + 3) * mul;
+        mul *= 7;
+      }
+      const double* K = tab + (int64_t)code * q * q;
+      const double* wj = w + (int64_t)j * q * nrhs + (int64_t)rr * q;
+      for (int k4 = 0; k4 < q; k4 += 4) {
+        const int mp = k4 + (lane >> 4);
+        const double b = (mp < q && colok) ? wj[mp] : 0.0;
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+          const int m = rb * 16 + (lane & 15);
+          const double a = (m < q && mp < q) ? K[m + (int64_t)mp * q] : 0.0;
+          acc[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[rb], 0, 0, 0);
+        }
+      }
+    }
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) red[wv][rb * 256 + (4 * r + (lane >> 4)) * 16 + (lane & 15)] = acc[rb][r];
+    __syncthreads();
+    for (int e = threadIdx.x; e < RB * 256; e += 256) {
+      const int rb = e / 256, row = (e % 256) / 16, col = e % 16;
+      const int m = rb * 16 + row, c = cb + col;
+      if (m < q && c < nrhs)
+        g[(int64_t)i * q * nrhs + (int64_t)c * q + m] = ((red[0][e] + red[1][e]) + red[2][e]) + red[3][e];
+    }
+    __syncthreads();
+  }
+}
+
 // Downward pass (L2L): g_c += T_c g_parent.
 __global__ void k_l2l(const int* __restrict__ parent, const int* __restrict__ cbits, int nbc, int q,
                       int nrhs, const double* __restrict__ T, const double* __restrict__ gp,
