@@ -431,53 +431,6 @@ struct QrPanel {
   int M, N, lda, j0, nb, pad;
 };
 
-// Sum of 32 per-lane values over the 64 lanes of a wavefront, reduce-scattered:
-// each exchange halves the values a lane keeps, so the whole reduction takes
-// 32 shuffles instead of 32 x 6. On return lanes 2c and 2c+1 hold the sum of
-// value c.
-template <class T>
-__device__ inline T wave_sum32_scatter(const T (&v)[32], int lane) {
-  T a[16];
-  {
-    const bool hi = lane & 32;
-#pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      const T keep = hi ? v[k + 16] : v[k], send = hi ? v[k] : v[k + 16];
-      a[k] = keep + __shfl_xor(send, 32, WAVE);
-    }
-  }
-  T b[8];
-  {
-    const bool hi = lane & 16;
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const T keep = hi ? a[k + 8] : a[k], send = hi ? a[k] : a[k + 8];
-      b[k] = keep + __shfl_xor(send, 16, WAVE);
-    }
-  }
-  T c[4];
-  {
-    const bool hi = lane & 8;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const T keep = hi ? b[k + 4] : b[k], send = hi ? b[k] : b[k + 4];
-      c[k] = keep + __shfl_xor(send, 8, WAVE);
-    }
-  }
-  T e[2];
-  {
-    const bool hi = lane & 4;
-#pragma unroll
-    for (int k = 0; k < 2; ++k) {
-      const T keep = hi ? c[k + 2] : c[k], send = hi ? c[k] : c[k + 2];
-      e[k] = keep + __shfl_xor(send, 4, WAVE);
-    }
-  }
-  const bool hi = lane & 2;
-  T f = (hi ? e[1] : e[0]) + __shfl_xor(hi ? e[0] : e[1], 2, WAVE);
-  return f + __shfl_xor(f, 1, WAVE);
-}
-
 // One panel of QR_NB columns per workgroup. Each thread owns the panel rows
 // i = tid + k QR_WG and reads a row's panel columns together (independent
 // loads from one per-lane offset), so the panel streams at bandwidth instead of

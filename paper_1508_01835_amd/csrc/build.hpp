@@ -417,6 +417,9 @@ inline void build_r2(Problem& P, double sigma0_override) {
     w.alloc(sizeof(double) * tot, &P.mem);
     // entries of a box beyond its rank are never written by E: keep them zero
     IFMM_HIP(hipMemsetAsync(w.p, 0, sizeof(double) * tot, P.stream));
+    std::vector<int> rmax(L + 1, 0);   // largest rank of each level (kernel choice of the y rows)
+    for (int l = 2; l <= L; ++l)
+      for (int x : R.r[l]) rmax[l] = std::max(rmax[l], x);
     auto applyE = [&](const double* in, double* out) {
       hipLaunchKernelGGL(k_l2p_p2p, dim3(T.lev[L].nb), dim3(WG), 0, P.stream, P.pts.as<double>(),
                          P.leaf_start.as<int64_t>(), P.ldev[L].nb_start.as<int>(), P.ldev[L].nbr.as<int>(),
@@ -433,7 +436,8 @@ inline void build_r2(Problem& P, double sigma0_override) {
                            leaf ? nullptr : in + yo[l + 1], in + yo[l], out + zo[l]);
         IFMM_LAUNCH_CHECK();
         const bool top = l == 2;
-        hipLaunchKernelGGL(k_e_yrows, dim3(nb), dim3(WG), 0, P.stream, nb, q, R.dr[l].as<int>(),
+        hipLaunchKernelGGL(rmax[l] <= 32 ? k_e_yrows32 : k_e_yrows, dim3(nb), dim3(WG), 0, P.stream, nb, q,
+                           R.dr[l].as<int>(),
                            P.ldev[l].in_start.as<int>(), P.ldev[l].inter.as<int>(), R.Kpre[l].as<double>(),
                            R.dkpoff[l].as<int64_t>(), in + zo[l], in + yo[l],
                            top ? nullptr : P.ldev[l].parent.as<int>(), top ? nullptr : R.Pst.as<double>(),

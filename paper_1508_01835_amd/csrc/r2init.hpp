@@ -238,6 +238,60 @@ __global__ void k_e_yrows(int nb, int q, const int* __restrict__ r, const int* _
   }
 }
 
+// The same y rows for levels whose ranks are at most 32: each thread takes
+// whole blocks of the box's interaction list and accumulates every row of the
+// box in registers (all threads busy even when the ranks are small); the
+// workgroup adds the per-thread sums with the wavefront reduce-scatter and one
+// pass over LDS, in a fixed order.
+__global__ void __launch_bounds__(WG) k_e_yrows32(int nb, int q, const int* __restrict__ r,
+                                                  const int* __restrict__ in_start, const int* __restrict__ inter,
+                                                  const double* __restrict__ Kpre, const int64_t* __restrict__ kpoff,
+                                                  const double* __restrict__ zl, const double* __restrict__ yl,
+                                                  const int* __restrict__ parent, const double* __restrict__ Ppre,
+                                                  const int64_t* __restrict__ ppoff, const int* __restrict__ pld,
+                                                  const int* __restrict__ rpar, const double* __restrict__ zpar,
+                                                  double* __restrict__ out) {
+  __shared__ double part[WG / WAVE][32];
+  const int i = blockIdx.x;
+  if (i >= nb) return;
+  const int ri = r[i];
+  double acc[32];
+#pragma unroll
+  for (int m = 0; m < 32; ++m) acc[m] = 0;
+  for (int t = in_start[i] + threadIdx.x; t < in_start[i + 1]; t += WG) {
+    const int j = inter[t];
+    const int rj = r[j];
+    const double* B = Kpre + kpoff[t];
+    const double* yj = yl + (int64_t)j * q;
+    for (int a = 0; a < rj; ++a) {
+      const double y = yj[a];
+#pragma unroll
+      for (int m = 0; m < 32; ++m)
+        if (m < ri) acc[m] += B[m + (int64_t)a * ri] * y;
+    }
+  }
+  if (parent) {
+    const int p = parent[i];
+    const double* Pi = Ppre + ppoff[i];
+    const int ld = pld[i];
+    for (int a = threadIdx.x; a < rpar[p]; a += WG) {
+      const double z = zpar[(int64_t)p * q + a];
+#pragma unroll
+      for (int m = 0; m < 32; ++m)
+        if (m < ri) acc[m] += Pi[m + (int64_t)a * ld] * z;
+    }
+  }
+  const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
+  const double rs = wave_sum32_scatter(acc, lane);
+  if ((lane & 1) == 0) part[wv][lane >> 1] = rs;
+  __syncthreads();
+  if ((int)threadIdx.x < ri) {
+    double s = -zl[(int64_t)i * q + threadIdx.x];
+    for (int w = 0; w < WG / WAVE; ++w) s += part[w][threadIdx.x];
+    out[(int64_t)i * q + threadIdx.x] = s;
+  }
+}
+
 __global__ void k_sumsq_partial(const double* __restrict__ v, int64_t n, double* __restrict__ part) {
   __shared__ double sh[WG / WAVE];
   double s = 0;
