@@ -448,8 +448,23 @@ struct QrPanel {
 // FULL: the panel has exactly QR_NB columns, so no column test is needed and
 // stores cover whole chunks (unchanged columns are rewritten as read).
 // Otherwise columns past the panel are read as aliases and never stored.
+template <class T>
+struct QrShared {
+  T tau[QR_NB];
+  T part[QR_WG / WAVE][QR_NB];
+  T sred[QR_WG / WAVE];
+  T Stot[QR_NB];        // S_c of the column being prepared
+  T stot;               // its squares below the diagonal
+  T rowj[QR_NB];        // its diagonal row, after the updates so far
+  T G[QR_NB * QR_NB];   // G[k + j QR_NB] = V(:,k)^T V(:,j), k < j
+  T Ts[QR_NB * QR_NB];
+};
+
+// Lp: LDS copy of the first QR_WG panel rows (row i < QR_WG at Lp[i + c QR_WG]),
+// loaded once at the start and written back at the end; row i is the first
+// row of thread i, so a panel of at most QR_WG rows touches HBM once each way.
 template <class T, bool FULL>
-__device__ __forceinline__ void qr_panel_run(const QrPanel& d) {
+__device__ __forceinline__ void qr_panel_run(const QrPanel& d, QrShared<T>& shm, T* __restrict__ Lp) {
   constexpr int NW = QR_WG / WAVE;
   constexpr int QC = 4;   // columns per store chunk
   T* __restrict__ A = static_cast<T*>(d.A);
@@ -460,23 +475,30 @@ __device__ __forceinline__ void qr_panel_run(const QrPanel& d) {
   const int nb = FULL ? QR_NB : d.nb;
   const int64_t lda = d.lda;
   const int mv = d.M - j0;
-  __shared__ T tau[QR_NB];
-  __shared__ T part[NW][QR_NB];
-  __shared__ T sred[NW];
-  __shared__ T Stot[QR_NB];        // S_c of the column being prepared
-  __shared__ T stot;               // its squares below the diagonal
-  __shared__ T rowj[QR_NB];        // its diagonal row, after the updates so far
-  __shared__ T G[QR_NB * QR_NB];   // G[k + j QR_NB] = V(:,k)^T V(:,j), k < j
-  __shared__ T Ts[QR_NB * QR_NB];
+  T* tau = shm.tau;
+  auto& part = shm.part;
+  T* sred = shm.sred;
+  T* Stot = shm.Stot;
+  T& stot = shm.stot;
+  T* rowj = shm.rowj;
+  T* G = shm.G;
+  T* Ts = shm.Ts;
   const int tid = threadIdx.x, lane = tid % WAVE, wv = tid / WAVE;
   T* P = A + j0 + (int64_t)j0 * lda;   // panel: P[i + c lda], i < mv, c < nb
   const int ldb = (int)lda * (int)sizeof(T);   // the host checks QR_NB lda sizeof(T) < 2^31
   const __amdgpu_buffer_rsrc_t rs = buf_rsrc(P, (uint32_t)(((int64_t)(nb - 1) * lda + mv) * sizeof(T)));
   // element (i, c); past a partial panel, columns alias its last one (loaded, never stored)
   auto ld = [&](int c, int i) {
-    return buf_ld<T>(rs, i * (int)sizeof(T), (FULL || c < nb ? c : nb - 1) * ldb);
+    const int cc = FULL || c < nb ? c : nb - 1;
+    if (i < QR_WG) return Lp[i + cc * QR_WG];
+    return buf_ld<T>(rs, i * (int)sizeof(T), cc * ldb);
   };
-  auto st = [&](int c, int i, T v) { buf_st(v, rs, i * (int)sizeof(T), c * ldb); };
+  auto st = [&](int c, int i, T v) {
+    if (i < QR_WG) Lp[i + c * QR_WG] = v;
+    else buf_st(v, rs, i * (int)sizeof(T), c * ldb);
+  };
+  if (tid < mv)
+    for (int c = 0; c < nb; ++c) Lp[tid + c * QR_WG] = buf_ld<T>(rs, tid * (int)sizeof(T), c * ldb);
   auto load_row = [&](int i, T (&x)[QR_NB]) {
 #pragma unroll
     for (int c = 0; c < QR_NB; ++c) x[c] = ld(c, i);
@@ -636,15 +658,24 @@ __device__ __forceinline__ void qr_panel_run(const QrPanel& d) {
       Tm[i + j * nb] = val;
     }
   }
+  // the LDS rows back to the matrix (the unscaled R rows included)
+  __syncthreads();
+  if (tid < mv)
+    for (int c = 0; c < nb; ++c) buf_st(Lp[tid + c * QR_WG], rs, tid * (int)sizeof(T), c * ldb);
 }
+
+constexpr size_t QR_LDS = (size_t)QR_WG * QR_NB;   // elements of the LDS panel rows
 
 template <class T>
 __global__ void __launch_bounds__(QR_WG) k_qr_panel(const QrPanel* __restrict__ ds) {
+  extern __shared__ unsigned char qr_dyn[];
+  __shared__ QrShared<T> shm;
   const QrPanel d = ds[blockIdx.x];
+  T* Lp = reinterpret_cast<T*>(qr_dyn);
   if (d.nb == QR_NB)
-    qr_panel_run<T, true>(d);
+    qr_panel_run<T, true>(d, shm, Lp);
   else
-    qr_panel_run<T, false>(d);
+    qr_panel_run<T, false>(d, shm, Lp);
 }
 
 // R (kq x N, leading dimension ldr) from the factorized A and its diagonal.
@@ -684,6 +715,12 @@ struct QrScratch {
 template <class T>
 inline void qr_blocked(Problem& P, const std::vector<QrJob>& jobs, QrScratch& S) {
   if (jobs.empty()) return;
+  static const bool attr = [] {   // once per process (thread-safe initialisation)
+    IFMM_HIP(hipFuncSetAttribute((const void*)k_qr_panel<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)(QR_LDS * sizeof(T))));
+    return true;
+  }();
+  (void)attr;
   // workspace per job: alph (N), V ((M) x QR_NB), T (QR_NB^2), W1, W2 (QR_NB x N)
   std::vector<int64_t> off(jobs.size());
   int64_t tot = 0;
@@ -742,7 +779,7 @@ inline void qr_blocked(Problem& P, const std::vector<QrJob>& jobs, QrScratch& S)
     for (const auto& q : pv) fl += 2.0 * (q.M - q.j0) * (double)q.nb * q.nb - 2.0 / 3.0 * (double)q.nb * q.nb * q.nb;
     panel_total += fl;
     P.kone_begin(KF_QR_PANEL, fl);
-    hipLaunchKernelGGL(k_qr_panel<T>, dim3((unsigned)pv.size()), dim3(QR_WG), 0, P.stream, dp);
+    hipLaunchKernelGGL(k_qr_panel<T>, dim3((unsigned)pv.size()), dim3(QR_WG), QR_LDS * sizeof(T), P.stream, dp);
     IFMM_LAUNCH_CHECK();
     P.kone_end();
     run_gemm<T>(P, g1, S.gd);
