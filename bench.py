@@ -36,7 +36,7 @@ os.environ.setdefault("IFMM_KTIMING", "1")
 # HBM bytes per launch of a roofline kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE counter runs, scaled by
 # what the counters read for a 512 MiB device copy (profiles/k_qr_panel_uniform3d_65536.txt); valid for the
 # kernel version the counters were taken on
-MEASURED_TRAFFIC: dict = {}   # no counter run on the present kernels yet
+MEASURED_TRAFFIC = {"k_qr_panel<double>": 5.341e8}
 
 PEAKS = {  # MI355X published peaks
     "hbm_GBs": 8000.0,
