@@ -485,17 +485,27 @@ __global__ void __launch_bounds__(WG) k_copy(const CopyDesc<Ts, Td>* __restrict_
   const int b = blockIdx.y * gridDim.x + blockIdx.x;
   if (b >= nd) return;
   const CopyDesc<Ts, Td> d = ds[b];
-  const int64_t total = (int64_t)d.rows * d.cols;
-  for (int64_t e = threadIdx.x; e < total; e += WG) {
-    const int i = (int)(e % d.rows), j = (int)(e / d.rows);
+  auto one = [&](int i, int j) {
     Td* o = &d.dst[i + (int64_t)j * d.ldd];
-    if (d.mode == 3) { *o = (Td)0; continue; }
-    if (d.mode == 2) { *o = i == j ? (Td)d.alpha : (Td)0; continue; }
-    if (d.mode == 4) { *o = (Td)(d.alpha * (double)d.src[j + (int64_t)i * d.lds]); continue; }
+    if (d.mode == 3) { *o = (Td)0; return; }
+    if (d.mode == 2) { *o = i == j ? (Td)d.alpha : (Td)0; return; }
+    if (d.mode == 4) { *o = (Td)(d.alpha * (double)d.src[j + (int64_t)i * d.lds]); return; }
     double v = d.alpha * (double)d.src[i + (int64_t)j * d.lds];
     if (d.cs) v *= (double)d.cs[j];
     if (d.mode == 1) *o = (Td)((double)*o + v);
     else *o = (Td)v;
+  };
+  if (d.rows >= WAVE) {   // a wavefront per column, lanes down the rows: no division, coalesced
+    const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
+    for (int j = wv; j < d.cols; j += WG / WAVE)
+      for (int i = lane; i < d.rows; i += WAVE) one(i, j);
+  } else {                // short columns: several per wavefront
+    const int64_t total = (int64_t)d.rows * d.cols;
+    if (total < (int64_t)1 << 31) {
+      for (int e = threadIdx.x; e < (int)total; e += WG) one(e % d.rows, e / d.rows);
+    } else {
+      for (int64_t e = threadIdx.x; e < total; e += WG) one((int)(e % d.rows), (int)(e / d.rows));
+    }
   }
 }
 
