@@ -3,6 +3,8 @@
 #pragma once
 
 #include <atomic>
+#include <mutex>
+#include <map>
 
 #include <hip/hip_runtime.h>
 
@@ -63,6 +65,115 @@ struct AllocClock {
   }
 };
 
+// Stream of the API call running on this thread (set by StreamScope at every
+// entry point that touches a handle); device blocks freed under it are kept for
+// reuse on that stream only.
+inline hipStream_t& tls_stream() {
+  static thread_local hipStream_t s = nullptr;
+  return s;
+}
+struct StreamScope {
+  hipStream_t prev;
+  explicit StreamScope(hipStream_t s) : prev(tls_stream()) { tls_stream() = s; }
+  ~StreamScope() { tls_stream() = prev; }
+};
+
+// Process-wide cache of device blocks. hipMalloc / hipFree cost about 0.1 ms
+// each and serialise host threads, so a build + factorization (hundreds of
+// buffers) and batches of problems would spend much of their time there.
+// Sizes are rounded to 8 classes per power of two. A freed block is reused
+// only by work on the stream that freed it (stream order makes that safe), or
+// by any stream once that stream has been synchronised (idle(), called when a
+// handle is destroyed). Cached bytes beyond CAP go back to HIP; a failed
+// hipMalloc returns every cached block (hipFree waits for the device) and
+// tries again.
+class DevPool {
+ public:
+  static DevPool& inst() {
+    static DevPool* p = new DevPool();   // never destroyed: blocks outlive static destructors
+    return *p;
+  }
+  static size_t cls(size_t b) {
+    if (b <= 4096) return (b + 255) & ~(size_t)255;
+    int e = 63 - __builtin_clzll((unsigned long long)b);
+    const size_t step = (size_t)1 << (e - 3);
+    return (b + step - 1) & ~(step - 1);
+  }
+  void* get(size_t b, hipStream_t s) {
+    const size_t c = cls(b);
+    {
+      std::lock_guard<std::mutex> g(mu_);
+      for (void* tag : {(void*)s, idle_tag()}) {
+        auto it = free_.find({tag, c});
+        if (it != free_.end() && !it->second.empty()) {
+          void* p = it->second.back();
+          it->second.pop_back();
+          cached_ -= c;
+          return p;
+        }
+      }
+    }
+    void* p = nullptr;
+    const int64_t t0 = AllocClock::now_ns();
+    hipError_t e = hipMalloc(&p, c);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      flush();
+      e = hipMalloc(&p, c);
+    }
+    AllocClock::ns_malloc += AllocClock::now_ns() - t0;
+    ++AllocClock::calls;
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      fail(IFMM_ERR_OOM, "hipMalloc(" + std::to_string(c) + ") failed: " + hipGetErrorString(e));
+    }
+    return p;
+  }
+  void put(void* p, size_t b, hipStream_t s) {
+    const size_t c = cls(b);
+    {
+      std::lock_guard<std::mutex> g(mu_);
+      if (cached_ + c <= CAP) {
+        free_[{(void*)s, c}].push_back(p);
+        cached_ += c;
+        return;
+      }
+    }
+    const int64_t t0 = AllocClock::now_ns();
+    (void)hipFree(p);
+    AllocClock::ns_free += AllocClock::now_ns() - t0;
+  }
+  // tag of blocks that any stream may reuse (freed after a synchronisation)
+  static hipStream_t idle_stream() { return reinterpret_cast<hipStream_t>(idle_tag()); }
+  // stream s has been synchronised: its cached blocks may serve any stream
+  void idle(hipStream_t s) {
+    std::lock_guard<std::mutex> g(mu_);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->first.first != (void*)s || it->second.empty()) continue;
+      auto& dst = free_[{idle_tag(), it->first.second}];
+      dst.insert(dst.end(), it->second.begin(), it->second.end());
+      it->second.clear();
+    }
+  }
+  void flush() {
+    std::map<std::pair<void*, size_t>, std::vector<void*>> all;
+    {
+      std::lock_guard<std::mutex> g(mu_);
+      all.swap(free_);
+      cached_ = 0;
+    }
+    for (auto& kv : all)
+      for (void* p : kv.second) (void)hipFree(p);
+  }
+
+ private:
+  static constexpr size_t CAP = (size_t)96 << 30;
+  static void* idle_tag() { return reinterpret_cast<void*>(1); }
+  std::mutex mu_;
+  std::map<std::pair<void*, size_t>, std::vector<void*>> free_;
+  size_t cached_ = 0;
+};
+
 // An owning device buffer. Moves only.
 struct DevBuf {
   void* p = nullptr;
@@ -85,23 +196,19 @@ struct DevBuf {
     release();
     if (b == 0) b = 256;
     if (a) a->add((int64_t)b);
-    const int64_t t0 = AllocClock::now_ns();
-    hipError_t e = hipMalloc(&p, b);
-    AllocClock::ns_malloc += AllocClock::now_ns() - t0;
-    ++AllocClock::calls;
-    if (e != hipSuccess) {
+    try {
+      p = DevPool::inst().get(b, tls_stream());
+    } catch (...) {
       if (a) a->sub((int64_t)b);
       p = nullptr;
-      fail(IFMM_ERR_OOM, "hipMalloc(" + std::to_string(b) + ") failed: " + hipGetErrorString(e));
+      throw;
     }
     bytes = b;
     acct = a;
   }
   void release() {
     if (p) {
-      const int64_t t0 = AllocClock::now_ns();
-      (void)hipFree(p);
-      AllocClock::ns_free += AllocClock::now_ns() - t0;
+      DevPool::inst().put(p, bytes, tls_stream());
       if (acct) acct->sub((int64_t)bytes);
     }
     p = nullptr;

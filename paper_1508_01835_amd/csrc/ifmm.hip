@@ -106,6 +106,7 @@ int ifmm_build(const double* points, int64_t n, int dim, ifmm_kernel k, int dept
       if (kt && kt[0] == 'm') P.kt.mask = (uint32_t)std::strtoul(kt + 1, nullptr, 16);
     }
     P.stream = static_cast<hipStream_t>(o.stream);
+    StreamScope ss(P.stream);
     P.n = n;
     P.d = dim;
     P.order = cheb_order;
@@ -130,7 +131,15 @@ int ifmm_build(const double* points, int64_t n, int dim, ifmm_kernel k, int dept
     P.st.t_build_ms = now_ms() - t0;
     *out = h;
   });
-  if (rc != IFMM_OK) delete h;
+  if (rc != IFMM_OK && h) {   // the build may have left work on the stream
+    const hipStream_t st = h->P.stream;
+    (void)hipStreamSynchronize(st);
+    {
+      StreamScope ss(DevPool::idle_stream());
+      delete h;
+    }
+    DevPool::inst().idle(st);
+  }
   return rc;
 }
 
@@ -142,6 +151,7 @@ void factorize_handle(ifmm_handle h) {
   {
     if (!h) fail(IFMM_ERR_ARG, "null handle");
     Problem& P = h->P;
+    StreamScope ss(P.stream);
     P.arena_reset();
     P.factorized = false;
     P.fac.reset();
@@ -233,6 +243,7 @@ int ifmm_solve(ifmm_handle h, const double* b, double* x, int nrhs, int64_t ld) 
   return guarded([&] {
     if (!h || !b || !x) fail(IFMM_ERR_ARG, "null pointer");
     Problem& P = h->P;
+    StreamScope ss(P.stream);
     if (!P.factorized) fail(IFMM_ERR_STATE, "ifmm_solve needs a factorized handle");
     if (nrhs < 1 || ld < P.n) fail(IFMM_ERR_ARG, "nrhs must be >= 1 and ld >= n");
     const double t0 = now_ms();
@@ -264,6 +275,7 @@ int ifmm_matvec(ifmm_handle h, const double* x, double* y, int nrhs, int64_t ld)
   return guarded([&] {
     if (!h || !x || !y) fail(IFMM_ERR_ARG, "null pointer");
     Problem& P = h->P;
+    StreamScope ss(P.stream);
     if (nrhs < 1 || ld < P.n) fail(IFMM_ERR_ARG, "nrhs must be >= 1 and ld >= n");
     if (x == y) fail(IFMM_ERR_ARG, "x and y must not alias");
     const double t0 = now_ms();
@@ -278,6 +290,7 @@ int ifmm_gmres(ifmm_handle op, ifmm_handle prec, const double* b, double* x, int
   return guarded([&] {
     if (!op || !b || !x) fail(IFMM_ERR_ARG, "null pointer");
     Problem& A = op->P;
+    StreamScope ss(A.stream);
     if (prec) {
       if (A.n != prec->P.n) fail(IFMM_ERR_ARG, "op and prec have different sizes");
       if (!prec->P.factorized) fail(IFMM_ERR_STATE, "the preconditioner handle is not factorized");
@@ -336,8 +349,13 @@ int ifmm_query(ifmm_handle h, ifmm_stats* s) {
 int ifmm_destroy(ifmm_handle h) {
   return guarded([&] {
     if (!h) return;
-    (void)hipStreamSynchronize(h->P.stream);
-    delete h;
+    const hipStream_t st = h->P.stream;
+    (void)hipStreamSynchronize(st);
+    {
+      StreamScope ss(DevPool::idle_stream());   // the stream is idle: the blocks may serve any stream
+      delete h;
+    }
+    DevPool::inst().idle(st);
     if (trace_on())
       std::fprintf(stderr, "[ifmm-trace] hipMalloc %lld calls %.1f ms, hipFree %.1f ms (process totals)\n",
                    (long long)AllocClock::calls.load(), AllocClock::ns_malloc.load() * 1e-6,
