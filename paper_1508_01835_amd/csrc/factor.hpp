@@ -571,13 +571,20 @@ struct Factorizer {
     const int* dpre = P.put(F.d5, pre);
     XfTasks xr{dpre, (int)cs.size(), extra, L.derow_start.template as<int>(), L.derow.template as<int>()};
     XfTasks xc{dpre + cs.size(), (int)cs.size(), 0, L.decol_start.template as<int>(), L.decol.template as<int>()};
-    // small ranks (fine levels): one wavefront per edge, many edges resident per CU
+    // small ranks (fine levels): one wavefront per edge, many edges resident per CU;
+    // every capacity of the level within XF_BOX_R: one workgroup per recompressed box
     int rmax = 0;
     for (const auto& c : cs) rmax = std::max(rmax, L.r[c.box]);
     const bool small = rmax <= XF_SMALL_R;
+    int capmax = 0;
+    for (int x : L.cap) capmax = std::max(capmax, x);
+    const bool perbox = capmax <= XF_BOX_R;
     if (prow.back() > 0) {
       P.kone_begin(KF_ROW_XFORM, frow);
-      if (small)
+      if (perbox)
+        hipLaunchKernelGGL(k_row_xform_box<T>, dim3((unsigned)cs.size()), dim3(256), 0, P.stream, dc, xr, v, L.P(),
+                           (const T*)W);
+      else if (small)
         hipLaunchKernelGGL((k_row_xform<T, 64, 8192>), dim3((unsigned)prow.back()), dim3(64), 0, P.stream, dc, xr, v,
                            L.P(), (const T*)W);
       else
@@ -589,7 +596,10 @@ struct Factorizer {
     chk(L, "row_xform", nullptr, o);
     if (pcol.back() > 0) {
       P.kone_begin(KF_COL_XFORM, fcol);
-      if (small)
+      if (perbox)
+        hipLaunchKernelGGL(k_col_xform_box<T>, dim3((unsigned)cs.size()), dim3(256), 0, P.stream, dc, xc, v, L.P(),
+                           (const T*)W);
+      else if (small)
         hipLaunchKernelGGL((k_col_xform<T, 64, 8192>), dim3((unsigned)pcol.back()), dim3(64), 0, P.stream, dc, xc, v,
                            L.P(), (const T*)W);
       else

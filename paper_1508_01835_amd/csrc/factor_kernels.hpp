@@ -451,6 +451,113 @@ __global__ void __launch_bounds__(BS) k_col_xform(const CompDesc* __restrict__ c
   }
 }
 
+// LDS writes of a wavefront visible to its other lanes (and the slot free for reuse).
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+constexpr int XF_BOX_R = 32;   // per-box basis changes when every capacity of the level is at most this
+
+// Fine levels (every capacity at most XF_BOX_R): one workgroup per recompressed
+// box j for all of its row transforms K(j, q) <- r_j K(j, q) and PU, PV. The
+// transforms (r_j, and t_j for PV) are staged in LDS once; each wavefront takes
+// every fourth edge, stages it in its own LDS slot (the product is written back
+// in place) and writes the k x cols result.
+template <class T>
+__global__ void __launch_bounds__(256) k_row_xform_box(const CompDesc* __restrict__ cs, XfTasks xt, LevelView lv,
+                                                       T* __restrict__ pool, const T* __restrict__ work) {
+  constexpr int R = XF_BOX_R;
+  __shared__ T Xr[R * R], Xt[R * R];
+  __shared__ T slot[4][R * R];
+  const CompDesc c = cs[blockIdx.x];
+  const int j = c.box;
+  const int r = lv.r[j], k = lv.rnew[j], cap = lv.cap[j];
+  const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
+  for (int e = threadIdx.x; e < k * r; e += 256) {
+    const int i = e % k, b = e / k;
+    Xr[i + b * R] = work[c.tr + i + (int64_t)b * cap];
+    Xt[i + b * R] = work[c.tt + i + (int64_t)b * cap];
+  }
+  __syncthreads();
+  const int e0 = xt.estart[j], ne = xt.estart[j + 1] - e0;
+  T* S = slot[wv];
+  for (int t = wv; t < ne + xt.extra; t += 4) {
+    int64_t off;
+    int cols;
+    const T* X = Xr;
+    if (t < ne) {
+      const int code = xt.elist[e0 + t];
+      off = lv.Kt[(int64_t)j * lv.c7 + code];
+      if (off < 0) continue;
+      cols = lv.r[lv.B7[(int64_t)j * lv.c7 + code]];
+    } else {
+      if (!lv.haspar) continue;
+      off = t == ne ? lv.PUo[j] : lv.PVo[j];
+      cols = lv.rpar[j];
+      if (t != ne) X = Xt;
+    }
+    T* E = pool + off;
+    if (r == 0 || cols == 0) {
+      for (int e = lane; e < k * cols; e += WAVE) E[e % k + (int64_t)(e / k) * cap] = (T)0;
+      continue;
+    }
+    for (int e = lane; e < r * cols; e += WAVE) S[e] = E[e % r + (int64_t)(e / r) * cap];
+    wave_lds_sync();
+    for (int e = lane; e < k * cols; e += WAVE) {
+      const int i = e % k, cc = e / k;
+      T acc = 0;
+      for (int b = 0; b < r; ++b) acc += X[i + b * R] * S[b + cc * r];
+      E[i + (int64_t)cc * cap] = acc;
+    }
+    wave_lds_sync();
+  }
+}
+
+// The column transforms K(q, j) <- K(q, j) t_j^T of the same boxes, one
+// workgroup per recompressed box (rows = the new rank of q, at most XF_BOX_R).
+template <class T>
+__global__ void __launch_bounds__(256) k_col_xform_box(const CompDesc* __restrict__ cs, XfTasks xt, LevelView lv,
+                                                       T* __restrict__ pool, const T* __restrict__ work) {
+  constexpr int R = XF_BOX_R;
+  __shared__ T Xt[R * R];
+  __shared__ T slot[4][R * R];
+  const CompDesc c = cs[blockIdx.x];
+  const int j = c.box;
+  const int r = lv.r[j], k = lv.rnew[j], capj = lv.cap[j];
+  const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
+  for (int e = threadIdx.x; e < k * r; e += 256) {
+    const int a = e % k, b = e / k;
+    Xt[a + b * R] = work[c.tt + a + (int64_t)b * capj];
+  }
+  __syncthreads();
+  const int e0 = xt.estart[j], ne = xt.estart[j + 1] - e0;
+  T* S = slot[wv];
+  for (int t = wv; t < ne; t += 4) {
+    const int code = xt.elist[e0 + t];
+    const int qb = lv.B7[(int64_t)j * lv.c7 + code];
+    if (qb < 0) continue;
+    const int64_t off = lv.Kt[(int64_t)qb * lv.c7 + (lv.c7 - 1 - code)];
+    if (off < 0) continue;
+    const int rows = lv.rnew[qb], ldq = lv.cap[qb];
+    T* E = pool + off;
+    if (r == 0 || rows == 0) {
+      for (int e = lane; e < rows * k; e += WAVE) E[e % rows + (int64_t)(e / rows) * ldq] = (T)0;
+      continue;
+    }
+    for (int e = lane; e < rows * r; e += WAVE) S[e] = E[e % rows + (int64_t)(e / rows) * ldq];
+    wave_lds_sync();
+    for (int e = lane; e < rows * k; e += WAVE) {
+      const int ii = e % rows, a = e / rows;
+      T acc = 0;
+      for (int b = 0; b < r; ++b) acc += S[ii + b * rows] * Xt[a + b * R];
+      E[ii + (int64_t)a * ldq] = acc;
+    }
+    wave_lds_sync();
+  }
+}
+
 // Commit the new bases: U_j <- Uhat, V_j <- Vhat, Sigma <- Sigma_hat, r_j <- k.
 template <class T>
 __global__ void __launch_bounds__(WG) k_comp_commit(const CompDesc* __restrict__ cs, LevelView lv, T* __restrict__ pool,
