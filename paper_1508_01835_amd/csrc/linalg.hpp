@@ -476,7 +476,7 @@ struct CopyDesc {
   Td* dst;
   const Ts* cs;
   int rows, cols, lds, ldd;
-  int mode, pad;
+  int mode, j0;   // j0: first column of this piece (large copies are split into pieces of columns)
   double alpha;
 };
 
@@ -485,7 +485,8 @@ __global__ void __launch_bounds__(WG) k_copy(const CopyDesc<Ts, Td>* __restrict_
   const int b = blockIdx.y * gridDim.x + blockIdx.x;
   if (b >= nd) return;
   const CopyDesc<Ts, Td> d = ds[b];
-  auto one = [&](int i, int j) {
+  auto one = [&](int i, int jl) {
+    const int j = jl + d.j0;
     Td* o = &d.dst[i + (int64_t)j * d.ldd];
     if (d.mode == 3) { *o = (Td)0; return; }
     if (d.mode == 2) { *o = i == j ? (Td)d.alpha : (Td)0; return; }
@@ -495,7 +496,7 @@ __global__ void __launch_bounds__(WG) k_copy(const CopyDesc<Ts, Td>* __restrict_
     if (d.mode == 1) *o = (Td)((double)*o + v);
     else *o = (Td)v;
   };
-  if (d.rows >= WAVE) {   // a wavefront per column, lanes down the rows: no division, coalesced
+  if (d.rows >= WAVE) {   // a wavefront per column of the piece, lanes down the rows: coalesced
     const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
     for (int j = wv; j < d.cols; j += WG / WAVE)
       for (int i = lane; i < d.rows; i += WAVE) one(i, j);
@@ -515,10 +516,14 @@ struct CopyBatch {
   void add(const Ts* src, int lds, Td* dst, int ldd, int rows, int cols, int mode = 0,
            double alpha = 1.0, const Ts* cs = nullptr) {
     if (rows <= 0 || cols <= 0) return;
-    CopyDesc<Ts, Td> d;
-    d.src = src; d.dst = dst; d.cs = cs; d.rows = rows; d.cols = cols; d.lds = lds; d.ldd = ldd;
-    d.mode = mode; d.pad = 0; d.alpha = alpha;
-    v.push_back(d);
+    // pieces of at most 32 columns (one workgroup each) for tall copies
+    const int piece = rows >= 64 ? 32 : cols;
+    for (int j0 = 0; j0 < cols; j0 += piece) {
+      CopyDesc<Ts, Td> d;
+      d.src = src; d.dst = dst; d.cs = cs; d.rows = rows; d.cols = std::min(piece, cols - j0); d.lds = lds;
+      d.ldd = ldd; d.mode = mode; d.j0 = j0; d.alpha = alpha;
+      v.push_back(d);
+    }
   }
 };
 
