@@ -396,8 +396,10 @@ struct Factorizer {
     T* W = F.work.template as<T>();
     const CompDesc* dc = P.put(F.d3, cs);
     const LevelView v = L.view(P);
-    hipLaunchKernelGGL(k_comp_gather<T>, dim3((unsigned)cs.size()), dim3(WG), 0, P.stream, dc, d_el, d_F, v,
-                       (const T*)L.P(), W);
+    int mmax = 1;
+    for (const auto& c : cs) mmax = std::max(mmax, L.m[c.box]);
+    hipLaunchKernelGGL(k_comp_gather<T>, dim3((unsigned)cs.size(), (unsigned)ceil_div(mmax, COMP_ROWS)), dim3(WG), 0,
+                       P.stream, dc, d_el, d_F, v, (const T*)L.P(), W);
     IFMM_LAUNCH_CHECK();
     std::vector<QrDesc> qd;
     std::vector<QrcpDesc> pd;

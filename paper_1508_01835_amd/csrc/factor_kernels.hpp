@@ -161,6 +161,8 @@ struct CompDesc {
   int kq, pad;
 };
 
+constexpr int COMP_ROWS = 32;   // rows of a recompression matrix gathered by one workgroup
+
 template <class T>
 __global__ void __launch_bounds__(WG) k_comp_gather(const CompDesc* __restrict__ cs, const ElimDesc* __restrict__ es,
                                                     const FNode* __restrict__ Fs, LevelView lv,
@@ -168,6 +170,10 @@ __global__ void __launch_bounds__(WG) k_comp_gather(const CompDesc* __restrict__
   const CompDesc c = cs[blockIdx.x];
   const int j = c.box;
   const int mj = lv.m[j], rj = lv.r[j];
+  // blockIdx.y: rows (of MU^T, MV^T) r0 .. r0 + COMP_ROWS - 1 of this matrix
+  const int r0 = blockIdx.y * COMP_ROWS;
+  if (r0 >= mj) return;
+  const int nr = min(COMP_ROWS, mj - r0);
   T* MU = work + c.mu;
   T* MV = work + c.mv;
   const int nc = c.ncols;
@@ -175,8 +181,8 @@ __global__ void __launch_bounds__(WG) k_comp_gather(const CompDesc* __restrict__
   const T* V = pool + lv.Vo[j];
   const T* SU = pool + lv.SUo[j];
   const T* SV = pool + lv.SVo[j];
-  for (int t = threadIdx.x; t < rj * mj; t += WG) {
-    const int col = t % rj, row = t / rj;
+  for (int t = threadIdx.x; t < rj * nr; t += WG) {
+    const int col = t % rj, row = r0 + t / rj;
     MU[col + (int64_t)row * nc] = U[row + (int64_t)col * mj] * SU[col];
     MV[col + (int64_t)row * nc] = V[row + (int64_t)col * mj] * SV[col];
   }
@@ -188,8 +194,8 @@ __global__ void __launch_bounds__(WG) k_comp_gather(const CompDesc* __restrict__
   for (int b = 0; b < e.nF; ++b) {
     const FNode B = Fs[e.F0 + b];
     if (code3(lv.coords, lv.d, j, B.box) >= 0) continue;   // near: not compressed
-    for (int t = threadIdx.x; t < B.dim * mj; t += WG) {
-      const int col = t % B.dim, row = t / B.dim;
+    for (int t = threadIdx.x; t < B.dim * nr; t += WG) {
+      const int col = t % B.dim, row = r0 + t / B.dim;
       MU[(o + col) + (int64_t)row * nc] = D[(X.off + row) + (int64_t)(B.off + col) * e.f];
       MV[(o + col) + (int64_t)row * nc] = D[(B.off + col) + (int64_t)(X.off + row) * e.f];
     }
