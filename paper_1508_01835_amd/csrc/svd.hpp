@@ -554,8 +554,9 @@ __device__ inline T wave_sum16_scatter(const T (&v)[16], int lane) {
 // workgroup. Every workgroup of a problem derives the pivot and the reflector
 // from the same data in the same order, so they agree bitwise and none waits
 // for another inside a launch. Columns are not moved: the pivot of step s is
-// recorded in pos[s] and excluded afterwards, and the partial norms are kept
-// twice, read from the copy of step parity s and written to the other one.
+// recorded in pos[s] (for the output order), and the partial norms are kept
+// twice, read from the copy of step parity s and written to the other one,
+// where a pivoted column carries the norm -1 so that later steps skip it.
 // Pivot ties go to the smallest column index; the columns left at the stop
 // follow in increasing index.
 constexpr int QS_CB = 16;    // columns per workgroup
@@ -612,7 +613,6 @@ __global__ void __launch_bounds__(QS_WG) k_qrcp_step(const QrcpStepDesc* __restr
                                                      const QsBlock* __restrict__ blocks, int s, double delta,
                                                      int* nstopped) {
   constexpr int NW = QS_WG / WAVE;
-  __shared__ unsigned char done[SVD_MAXN];
   __shared__ T hv[SVD_MAXN];
   __shared__ T redv[NW], reds[NW];
   __shared__ int redi[NW];
@@ -631,16 +631,13 @@ __global__ void __launch_bounds__(QS_WG) k_qrcp_step(const QrcpStepDesc* __restr
   const T* vn2 = vn1 + n;
   T* wn1 = static_cast<T*>(d.vn) + ((s + 1) & 1) * 2 * n;
   T* wn2 = wn1 + n;
-  for (int c = tid; c < n; c += QS_WG) done[c] = 0;
-  __syncthreads();
-  for (int j = tid; j < s; j += QS_WG) done[d.pos[j]] = 1;
-  __syncthreads();
-  // pivot = the largest remaining partial norm (smallest index on ties); remaining Frobenius norm
+  // pivot = the largest remaining partial norm (smallest index on ties); remaining Frobenius norm.
+  // Columns pivoted at earlier steps carry the partial norm -1.
   T best = (T)-1, ss = 0;
   int bi = n;
   for (int c = tid; c < n; c += QS_WG) {
-    if (done[c]) continue;
     const T x = vn1[c];
+    if (x < (T)0) continue;
     ss += x * x;
     if (x > best) { best = x; bi = c; }
   }
@@ -733,7 +730,7 @@ __global__ void __launch_bounds__(QS_WG) k_qrcp_step(const QrcpStepDesc* __restr
 #pragma unroll
         for (int g = 0; g < QS_CB; ++g) {
           const int j = c0 + g;
-          if (g < nc && !done[j] && j != piv) {
+          if (g < nc && vn1[j] >= (T)0 && j != piv) {
             const T y = x[r][g] - w[g] * hr[r];
             R[i + (int64_t)j * ld] = y;
             if (i == s) rsh[g] = y;
@@ -750,7 +747,10 @@ __global__ void __launch_bounds__(QS_WG) k_qrcp_step(const QrcpStepDesc* __restr
   // downdate (or recompute) the partial norms into the other parity
   if (tid < nc) {
     const int j = c0 + tid;
-    if (!done[j] && j != piv) {
+    if (vn1[j] < (T)0 || j == piv) {   // pivoted: marked for the next steps
+      wn1[j] = (T)-1;
+      wn2[j] = (T)-1;
+    } else {
       const T a1 = vn1[j], a2 = vn2[j];
       T n1 = a1, n2 = a2;
       if (a1 != (T)0) {
