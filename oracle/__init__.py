@@ -18,6 +18,6 @@ Modules:
   h2         the H2 (black-box FMM) representation R1, its matvec, dense form
   extended   extended sparse system E: orthonormal bases, weights, sigma_0
   ifmm       level-by-level elimination with fill compression, merge, solve
-  gmres      right-preconditioned (flexible) GMRES
+  gmres      right-preconditioned (flexible) and left-preconditioned GMRES
   graph      generic block elimination on the graph of a block system
 """

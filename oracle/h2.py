@@ -21,7 +21,7 @@ import numpy as np
 
 from . import chebyshev as cheb
 from . import kernels as kern
-from .tree import Tree
+from .tree import Tree, leaf_boxes
 
 
 class H2:
@@ -129,3 +129,61 @@ class H2:
     def dense(self) -> np.ndarray:
         """A~ as a dense matrix in the caller's order (small N only)."""
         return self.matvec(np.eye(self.tree.n))
+
+
+def h2_rows(points, kind: str, param: float, shift: float, depth: int, n: int, X, rows) -> np.ndarray:
+    """Rows `rows` (caller order) of A~ X, one target at a time, straight from the black-box FMM definition.
+
+    For a target point r_i in leaf box b_L with ancestors b_l:
+      (A~ X)_i = sum_{j in N(b_L)} K(|r_i - r_j|) X_j + s X_i
+               + sum_{l=2..L} sum_{C in I(b_l)} L_{b_l}(r_i) K(xi^{b_l}, xi^C) W^C,
+      W^C = sum_{j in C} L_C(r_j)^T X_j,
+    with L_B the tensor Lagrange basis on the Chebyshev nodes xi^B of box B (Sec. 2.1 lists; Sec. 3
+    opening). Moments and local evaluations are taken directly at every level rather than through the
+    child transfers: interpolating a degree n-1 Lagrange polynomial on a child's n nodes is exact, so the
+    two forms represent the same A~ and differ by rounding only. Cost O(N n^d) per level plus O(n^2d |I|)
+    per target, so it serves at sizes where the full oracle H2 is too slow to build.
+    """
+    P = np.ascontiguousarray(points, dtype=np.float64)
+    X = np.asarray(X, dtype=np.float64)
+    vec = X.ndim == 1
+    X2 = X[:, None] if vec else X
+    N, d = P.shape
+    L = depth
+    origin, side, cL = leaf_boxes(P, L)
+    g = cheb.node_grid(n, d)
+    out = np.zeros((len(rows), X2.shape[1]))
+    # direct moments of every occupied box at every level
+    mom = {}
+    for l in range(2, L + 1):
+        h = side / (1 << l)
+        cl = cL >> (L - l)
+        boxes, inv = np.unique(cl, axis=0, return_inverse=True)
+        inv = inv.reshape(-1)
+        centres = origin + (cl + 0.5) * h
+        Lp = cheb.lagrange_nd(n, (P - centres) * (2.0 / h))            # (N, n^d)
+        W = np.zeros((boxes.shape[0], n ** d, X2.shape[1]))
+        np.add.at(W, inv, Lp[:, :, None] * X2[:, None, :])
+        mom[l] = (boxes, W, h)
+    for t, i in enumerate(rows):
+        i = int(i)
+        bL = cL[i]
+        near = np.max(np.abs(cL - bL), axis=1) <= 1
+        r = np.sqrt(np.sum((P[near] - P[i]) ** 2, axis=1))
+        acc = kern.kernel_of_r(kind, param, r) @ X2[near] + shift * X2[i]
+        for l in range(2, L + 1):
+            boxes, W, h = mom[l]
+            b = bL >> (L - l)
+            far = np.max(np.abs(boxes - b), axis=1) > 1
+            if l > 2:
+                far &= np.max(np.abs((boxes >> 1) - (b >> 1)), axis=1) <= 1
+            if not np.any(far):
+                continue
+            Xi = g * (0.5 * h)
+            Xj = (g[None, :, :] * (0.5 * h) + ((boxes[far] - b) * h)[:, None, :]).reshape(-1, d)
+            K = kern.block(kind, param, Xi, Xj)                          # (n^d, |I| n^d)
+            loc = K @ W[far].reshape(-1, X2.shape[1])
+            ci = origin + (b + 0.5) * h
+            acc = acc + cheb.lagrange_nd(n, ((P[i] - ci) * (2.0 / h))[None, :])[0] @ loc
+        out[t] = acc
+    return out[:, 0] if vec else out

@@ -58,6 +58,23 @@ class Level:
         self.inter: list[list[int]] = []          # I(i), Morton order
 
 
+def leaf_boxes(points: np.ndarray, depth: int):
+    """Root cube (origin, side) and the integer leaf-box coordinates (n, d) of every point."""
+    lo = points.min(axis=0)
+    hi = points.max(axis=0)
+    centre = 0.5 * (lo + hi)
+    side = float(np.max(hi - lo)) * (1.0 + 1e-12)
+    if side == 0.0:
+        side = 1.0
+    origin = centre - 0.5 * side
+    inv = 1.0 / side
+    t = (points - origin) * inv
+    nl = 1 << depth
+    c = np.floor(t * float(nl)).astype(np.int64)
+    c = np.clip(c, 0, nl - 1)
+    return origin, side, c
+
+
 class Tree:
     """Cluster tree of a point cloud (Sec. 2.1, 2.3, 3)."""
 
@@ -67,19 +84,7 @@ class Tree:
         if depth < 2:
             raise ValueError("the method needs a leaf level L >= 2 (no well-separated pairs above)")
         self.n, self.d, self.L = n, d, depth
-        lo = points.min(axis=0)
-        hi = points.max(axis=0)
-        centre = 0.5 * (lo + hi)
-        side = float(np.max(hi - lo)) * (1.0 + 1e-12)
-        if side == 0.0:
-            side = 1.0
-        self.side = side
-        self.origin = centre - 0.5 * side
-        inv = 1.0 / side
-        t = (points - self.origin) * inv
-        nl = 1 << depth
-        c = np.floor(t * float(nl)).astype(np.int64)
-        c = np.clip(c, 0, nl - 1)
+        self.origin, self.side, c = leaf_boxes(points, depth)
         keys = morton_key(c, depth)
         # stable order: leaf key, then original index
         self.perm = np.lexsort((np.arange(n), keys))

@@ -94,3 +94,35 @@ def test_paper_kernel_definition():
     d = 1e-2
     r = np.array([0.0, 0.5e-2, 1e-2, 2e-2])
     assert np.allclose(kernels.kernel_of_r("paper", d, r), [1.0, 0.5, 1.0, 0.5])
+
+
+@pytest.mark.parametrize("dim,depth,order,kind,param,shift", [
+    (3, 3, 3, "imq", 0.005, 1.0),
+    (2, 4, 4, "gauss", 0.3, 0.1),
+    (3, 4, 3, "paper", 1e-2, 0.0),
+])
+def test_row_by_row_product_equals_nested_product(dim, depth, order, kind, param, shift):
+    """Rows of A~ X taken one target at a time with direct moments and direct local evaluation at every
+    level equal the nested product (child transfers up and down): nested Chebyshev interpolation is exact
+    for the degree n-1 Lagrange polynomials, so the two differ by rounding only."""
+    from oracle.h2 import h2_rows
+    n = 1200 if dim == 3 else 900
+    P = W.uniform_cube(n, dim, 31 + depth)
+    X = W.normal_rhs(n, 2, 41 + depth)
+    h = H2(Tree(P, depth), kind, param, shift, order)
+    Y = h.matvec(X)
+    rows = np.arange(0, n, 11)
+    R = h2_rows(P, kind, param, shift, depth, order, X, rows)
+    assert np.max(np.abs(R - Y[rows])) <= 1e-13 * np.max(np.abs(Y))
+
+
+def test_row_by_row_product_reproduces_dense_for_quadratic_kernel():
+    """Independent of the H2 code: with the radial quadratic kernel and order >= 3 every far-field block is
+    interpolated exactly, so the row formula gives rows of the dense A X."""
+    from oracle.h2 import h2_rows
+    P = W.uniform_cube(800, 3, 51)
+    X = W.normal_rhs(800, 3, 52)
+    rows = [0, 1, 399, 798, 799]
+    R = h2_rows(P, "poly2", 0.0, 0.5, 3, 3, X, rows)
+    AX = kernels.dense("poly2", 0.0, 0.5, P) @ X
+    assert np.max(np.abs(R - AX[rows])) <= 1e-12 * np.max(np.abs(AX))
