@@ -171,6 +171,12 @@ PAPER_TABLES = {
     1e-3: {"none": (78, 509.0), 1: (19, 213.0), 2: (6, 119.0), 3: (3, 118.0), 4: (2, 265.0)},
     1e-2: {"none": (500, 4290.0), 1: (305, 2522.0), 2: (61, 521.0), 3: (24, 301.0), 4: (14, 414.0)},
 }
+# App. B, Tables 5-6: left preconditioning by order n -> (iterations, preconditioned relative residual,
+# relative error of x) as printed
+PAPER_LEFT = {
+    1e-3: {1: (19, 3.5e-11, 4.5e-11), 2: (6, 9.1e-12, 9.2e-12), 3: (3, 2.8e-11, 2.8e-11), 4: (2, 2.0e-11, 2.0e-11)},
+    1e-2: {1: (303, 5.4e-11, 5.2e-8), 2: (62, 9.3e-11, 5.2e-9), 3: (27, 3.8e-11, 2.0e-9), 4: (18, 3.8e-11, 1.6e-9)},
+}
 
 
 def run_paper(args):
@@ -178,9 +184,11 @@ def run_paper(args):
     K(0)=1, r/d below d, d/r above, d in {1e-3, 1e-2}; IFMM preconditioner of Chebyshev order n = 1..4 and
     eps 1e-3 (FP64), octree depth 3 (about 195 points per leaf, the depth closest to the paper's 100);
     right-preconditioned non-restarted GMRES to 1e-10, at most 500 iterations, and GMRES without a
-    preconditioner. Products use the Chebyshev H2 of order --paper-op-order (the paper's black-box FMM
-    accuracy is not stated). x has N(0,1) entries and b = A~ x. Time per row = preconditioner build +
-    factorization + GMRES (the operator's own build is reported apart)."""
+    preconditioner; with --paper-left also left preconditioning with the same factorization (App. B,
+    Tables 5-6; its residual is the preconditioned one). Products use the Chebyshev H2 of order
+    --paper-op-order (the paper's black-box FMM accuracy is not stated). x has N(0,1) entries and
+    b = A~ x. Time per row = preconditioner build + factorization + GMRES (the operator's own build is
+    reported apart)."""
     import torch
 
     import workloads as W
@@ -215,6 +223,16 @@ def run_paper(args):
                    "paper_cpu_s": PAPER_TABLES[d][n][1]}
             if pr is not None:
                 row["max_rank"] = pr.stats()["max_rank"]
+                if args.paper_left:
+                    t3 = time.perf_counter()
+                    xl, itl, rpl, rtl = op.gmres_left(b, tol=1e-10, maxit=500, prec=pr)
+                    torch.cuda.synchronize()
+                    errl = float(torch.linalg.norm(xl - xt) / torch.linalg.norm(xt))
+                    row["left"] = {"iters": itl, "relres_prec": rpl, "relres_true": rtl, "relerr": errl,
+                                   "gmres_s": time.perf_counter() - t3, "paper_iters": PAPER_LEFT[d][n][0],
+                                   "paper_relres": PAPER_LEFT[d][n][1], "paper_relerr": PAPER_LEFT[d][n][2]}
+                    log("paper d=%g %s left: %d it, prec relres %.2e, true %.2e, err %.2e (paper %d it, err %.1e)"
+                        % (d, row["precond"], itl, rpl, rtl, errl, PAPER_LEFT[d][n][0], PAPER_LEFT[d][n][2]))
                 pr.close()
             rows.append(row)
             log("paper d=%g %s: %d it, relres %.2e, err %.2e, %.2f s (paper %d it, %.0f s)" %
@@ -249,6 +267,8 @@ def main():
                     help="end with a 512 MiB device-to-device copy, the reference for HBM byte counters")
     ap.add_argument("--workload", choices=["uniform3d", "batch", "serve", "paper"], default="uniform3d")
     ap.add_argument("--paper-n", type=int, default=100000)
+    ap.add_argument("--paper-left", action="store_true",
+                    help="paper workload: also run left-preconditioned GMRES with each factorization")
     ap.add_argument("--paper-op-order", type=int, default=5)
     ap.add_argument("--serve-count", type=int, default=200)
     ap.add_argument("--rate", type=float, default=1.0)

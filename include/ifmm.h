@@ -24,7 +24,7 @@
  *     a longer, thread-local description of the last failure.
  *   - Handle life cycle: BUILT (after ifmm_build) -> FACTORIZED (after
  *     ifmm_factorize). ifmm_matvec is legal in both states; ifmm_solve and
- *     the preconditioner handle of ifmm_gmres need FACTORIZED; factorizing
+ *     the preconditioner handle of ifmm_gmres(_left) need FACTORIZED; factorizing
  *     again is allowed.
  */
 #ifndef IFMM_H
@@ -94,8 +94,8 @@ typedef struct {
   int64_t device_bytes;       /* device memory held by the handle now */
   int64_t device_bytes_peak;  /* peak over the handle's life */
   int error_level, error_box; /* where IFMM_ERR_SINGULAR / NUMERICAL arose, else -1 */
-  int gmres_iters;            /* of the last ifmm_gmres call (max over columns) */
-  double gmres_relres;        /* of the last ifmm_gmres call (max over columns) */
+  int gmres_iters;            /* of the last ifmm_gmres(_left) call (max over columns) */
+  double gmres_relres;        /* monitored residual of that call (max over columns) */
   /* Device time by kernel family, measured with HIP events on the handle's
      stream when the environment variable IFMM_KTIMING=1 is set at build time
      (IFMM_KTIMING=m<hex>: only the families whose bits are set; otherwise
@@ -193,6 +193,23 @@ int ifmm_matvec(ifmm_handle h, const double* x, double* y, int nrhs, int64_t ld)
  */
 int ifmm_gmres(ifmm_handle op, ifmm_handle prec, const double* b, double* x, int nrhs,
                int64_t ld, double tol, int maxit, int* iters_out, double* relres_out);
+
+/*
+ * ifmm_gmres_left - left-preconditioned, non-restarted GMRES (App. B): GMRES
+ * on P^-1 A~ x = P^-1 b, with P^-1 prec's factorization and A~ op's H2
+ * matvec in float64; orthogonalisation is float64, x = V_k y_k. The
+ * monitored residual is the preconditioned one, as the App. B tables report
+ * it for the left variant. Arguments, states and errors as ifmm_gmres;
+ * prec = NULL gives P = I (then the method equals ifmm_gmres without a
+ * preconditioner).
+ *   tol              stop when ||P^-1 (b - A~ x)|| <= tol ||P^-1 b|| (per column)
+ *   relres_out       host, may be NULL: largest preconditioned relative
+ *                    residual at exit (recomputed from x)
+ *   true_relres_out  host, may be NULL: largest ||b - A~ x|| / ||b|| at exit
+ */
+int ifmm_gmres_left(ifmm_handle op, ifmm_handle prec, const double* b, double* x, int nrhs,
+                    int64_t ld, double tol, int maxit, int* iters_out, double* relres_out,
+                    double* true_relres_out);
 
 /* ifmm_query - copy counters and phase times into *s (host). */
 int ifmm_query(ifmm_handle h, ifmm_stats* s);

@@ -1,7 +1,11 @@
-// Right-preconditioned, non-restarted GMRES in float64 (Sec. 3.2): products
-// with the H2 matvec, the IFMM factorization as preconditioner, classical
-// Gram-Schmidt with one re-orthogonalisation, flexible storage of the
-// preconditioned directions Z_k, x0 = 0, true residual recomputed at exit.
+// Non-restarted GMRES in float64 (Sec. 3.2): products with the H2 matvec, the
+// IFMM factorization as preconditioner, classical Gram-Schmidt with one
+// re-orthogonalisation, x0 = 0, residuals recomputed at exit.
+//  - right preconditioning (the paper's default): GMRES on A P^-1 y = b with
+//    flexible storage of the preconditioned directions Z_k = P^-1 v_k, x = Z y;
+//    the monitored residual is the true one, ||b - A x|| / ||b||;
+//  - left preconditioning (App. B): GMRES on P^-1 A x = P^-1 b, x = V y; the
+//    monitored residual is ||P^-1 (b - A x)|| / ||P^-1 b||.
 // Every column of the right-hand side block is an independent GMRES run; all
 // columns share each matvec and each preconditioner solve.
 #pragma once
@@ -89,7 +93,8 @@ __global__ void k_copy_ld(const double* __restrict__ src, int64_t lds, int64_t n
 
 struct GmresResult {
   int iters = 0;
-  double relres = 0;
+  double relres = 0;        // monitored residual at exit (max over columns)
+  double true_relres = 0;   // ||b - A x|| / ||b|| at exit (max over columns)
 };
 
 struct GmresWork {
@@ -97,13 +102,14 @@ struct GmresWork {
 };
 
 // apply_A(x, y): y = A x (both n x nrhs, ld n); apply_M(x, y): y = M^-1 x.
+// left selects left preconditioning (no Z storage).
 inline GmresResult gmres_run(Problem& P, GmresWork& G, const std::function<void(const double*, double*)>& apply_A,
                              const std::function<void(const double*, double*)>& apply_M, const double* b, double* x,
-                             int nrhs, int64_t ld, double tol, int maxit) {
+                             int nrhs, int64_t ld, double tol, int maxit, bool left = false) {
   const int64_t n = P.n;
   const int64_t nv = n * nrhs;
   G.V.reserve(sizeof(double) * nv * (maxit + 1), &P.mem);
-  G.Z.reserve(sizeof(double) * nv * std::max(maxit, 1), &P.mem);
+  if (!left) G.Z.reserve(sizeof(double) * nv * std::max(maxit, 1), &P.mem);
   G.w.reserve(sizeof(double) * nv, &P.mem);
   G.r.reserve(sizeof(double) * nv, &P.mem);
   const int nch = (int)std::max<int64_t>(1, ceil_div(n, DOT_CHUNK));
@@ -128,12 +134,22 @@ inline GmresResult gmres_run(Problem& P, GmresWork& G, const std::function<void(
     IFMM_HIP(hipMemcpyAsync(G.scal.p, h, sizeof(double) * nrhs, hipMemcpyHostToDevice, P.stream));
     P.sync();
   };
-  // v0 = b / ||b||
-  hipLaunchKernelGGL(k_copy_ld, gv, dim3(WG), 0, P.stream, b, ld, n, nrhs, w, n, 1.0);
-  IFMM_LAUNCH_CHECK();
-  std::vector<double> beta;
+  // v0 = r0 / ||r0|| with r0 = b (right) or P^-1 b (left)
+  std::vector<double> beta, bnorm;
+  if (left) {
+    hipLaunchKernelGGL(k_copy_ld, gv, dim3(WG), 0, P.stream, b, ld, n, nrhs, G.r.as<double>(), n, 1.0);
+    IFMM_LAUNCH_CHECK();
+    dots(G.r.as<double>(), nrhs, G.r.as<double>(), bnorm);
+    apply_M(G.r.as<double>(), w);
+  } else {
+    hipLaunchKernelGGL(k_copy_ld, gv, dim3(WG), 0, P.stream, b, ld, n, nrhs, w, n, 1.0);
+    IFMM_LAUNCH_CHECK();
+  }
   dots(w, nrhs, w, beta);
   for (auto& x : beta) x = std::sqrt(x);
+  if (!left) bnorm = beta;
+  else
+    for (auto& x : bnorm) x = std::sqrt(x);
   std::vector<double> inv(nrhs);
   for (int c = 0; c < nrhs; ++c) inv[c] = beta[c] > 0 ? 1.0 / beta[c] : 0.0;
   setscal(inv);
@@ -155,9 +171,14 @@ inline GmresResult gmres_run(Problem& P, GmresWork& G, const std::function<void(
     for (int c = 0; c < nrhs; ++c) any = any || active[c];
     if (!any) break;
     double* vk = V + (int64_t)k * nv;
-    double* zk = Z + (int64_t)k * nv;
-    apply_M(vk, zk);
-    apply_A(zk, w);
+    if (left) {   // w = P^-1 A v_k
+      apply_A(vk, G.r.as<double>());
+      apply_M(G.r.as<double>(), w);
+    } else {      // z_k = P^-1 v_k, w = A z_k
+      double* zk = Z + (int64_t)k * nv;
+      apply_M(vk, zk);
+      apply_A(zk, w);
+    }
     // CGS2
     std::vector<double> h((size_t)(k + 2) * nrhs, 0.0);
     for (int pass = 0; pass < 2; ++pass) {
@@ -219,8 +240,8 @@ inline GmresResult gmres_run(Problem& P, GmresWork& G, const std::function<void(
   }
   P.upload(G.y, Y);
   P.upload(G.kc, kdone);
-  hipLaunchKernelGGL(k_combine, gv, dim3(WG), 0, P.stream, (const double*)Z, G.y.as<double>(), G.kc.as<int>(), maxk,
-                     n, nrhs, x, ld);
+  hipLaunchKernelGGL(k_combine, gv, dim3(WG), 0, P.stream, (const double*)(left ? V : Z), G.y.as<double>(),
+                     G.kc.as<int>(), maxk, n, nrhs, x, ld);
   IFMM_LAUNCH_CHECK();
   // true residual r = b - A x
   hipLaunchKernelGGL(k_copy_ld, gv, dim3(WG), 0, P.stream, x, ld, n, nrhs, G.r.as<double>(), n, 1.0);
@@ -233,7 +254,15 @@ inline GmresResult gmres_run(Problem& P, GmresWork& G, const std::function<void(
   std::vector<double> rn;
   dots(G.r.as<double>(), nrhs, G.r.as<double>(), rn);
   for (int c = 0; c < nrhs; ++c)
-    if (beta[c] > 0) res.relres = std::max(res.relres, std::sqrt(rn[c]) / beta[c]);
+    if (bnorm[c] > 0) res.true_relres = std::max(res.true_relres, std::sqrt(rn[c]) / bnorm[c]);
+  if (left) {   // preconditioned residual P^-1 (b - A x)
+    apply_M(G.r.as<double>(), w);
+    dots(w, nrhs, w, rn);
+    for (int c = 0; c < nrhs; ++c)
+      if (beta[c] > 0) res.relres = std::max(res.relres, std::sqrt(rn[c]) / beta[c]);
+  } else {
+    res.relres = res.true_relres;
+  }
   res.iters = 0;
   for (int c = 0; c < nrhs; ++c) res.iters = std::max(res.iters, kdone[c]);
   return res;

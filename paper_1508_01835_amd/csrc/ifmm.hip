@@ -285,8 +285,8 @@ int ifmm_matvec(ifmm_handle h, const double* x, double* y, int nrhs, int64_t ld)
   });
 }
 
-int ifmm_gmres(ifmm_handle op, ifmm_handle prec, const double* b, double* x, int nrhs, int64_t ld, double tol,
-               int maxit, int* iters_out, double* relres_out) {
+static int gmres_entry(ifmm_handle op, ifmm_handle prec, const double* b, double* x, int nrhs, int64_t ld,
+                       double tol, int maxit, int* iters_out, double* relres_out, double* true_relres_out, bool left) {
   return guarded([&] {
     if (!op || !b || !x) fail(IFMM_ERR_ARG, "null pointer");
     Problem& A = op->P;
@@ -309,13 +309,24 @@ int ifmm_gmres(ifmm_handle op, ifmm_handle prec, const double* b, double* x, int
       solve_any(M, in, out, nrhs, M.n);
       if (M.stream != A.stream) M.sync();
     };
-    const GmresResult r = gmres_run(A, op->G, applyA, applyM, b, x, nrhs, ld, tol, maxit);
+    const GmresResult r = gmres_run(A, op->G, applyA, applyM, b, x, nrhs, ld, tol, maxit, left);
     A.sync();
     A.st.gmres_iters = r.iters;
     A.st.gmres_relres = r.relres;
     if (iters_out) *iters_out = r.iters;
     if (relres_out) *relres_out = r.relres;
+    if (true_relres_out) *true_relres_out = r.true_relres;
   });
+}
+
+int ifmm_gmres(ifmm_handle op, ifmm_handle prec, const double* b, double* x, int nrhs, int64_t ld, double tol,
+               int maxit, int* iters_out, double* relres_out) {
+  return gmres_entry(op, prec, b, x, nrhs, ld, tol, maxit, iters_out, relres_out, nullptr, false);
+}
+
+int ifmm_gmres_left(ifmm_handle op, ifmm_handle prec, const double* b, double* x, int nrhs, int64_t ld, double tol,
+                    int maxit, int* iters_out, double* relres_out, double* true_relres_out) {
+  return gmres_entry(op, prec, b, x, nrhs, ld, tol, maxit, iters_out, relres_out, true_relres_out, true);
 }
 
 int ifmm_query(ifmm_handle h, ifmm_stats* s) {

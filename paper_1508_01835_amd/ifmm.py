@@ -53,7 +53,8 @@ KERNEL_OF_FAMILY = {"svd_round": "k_svd_round", "qr_panel": "k_qr_panel", "qrcp"
 
 
 EXPORTS = ["ifmm_default_options", "ifmm_build", "ifmm_factorize", "ifmm_factorize_batch", "ifmm_solve",
-           "ifmm_matvec", "ifmm_gmres", "ifmm_query", "ifmm_destroy", "ifmm_strerror", "ifmm_last_error"]
+           "ifmm_matvec", "ifmm_gmres", "ifmm_gmres_left", "ifmm_query", "ifmm_destroy", "ifmm_strerror",
+           "ifmm_last_error"]
 
 
 def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
@@ -73,6 +74,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.ifmm_gmres.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                                ctypes.c_int64, ctypes.c_double, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                                ctypes.POINTER(ctypes.c_double)]
+    lib.ifmm_gmres_left.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                    ctypes.c_int, ctypes.c_int64, ctypes.c_double, ctypes.c_int,
+                                    ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double),
+                                    ctypes.POINTER(ctypes.c_double)]
     lib.ifmm_query.argtypes = [ctypes.c_void_p, ctypes.POINTER(Stats)]
     lib.ifmm_destroy.argtypes = [ctypes.c_void_p]
     lib.ifmm_strerror.argtypes = [ctypes.c_int]
@@ -80,7 +85,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.ifmm_last_error.argtypes = []
     lib.ifmm_last_error.restype = ctypes.c_char_p
     for name in ["ifmm_build", "ifmm_factorize", "ifmm_factorize_batch", "ifmm_solve", "ifmm_matvec", "ifmm_gmres",
-                 "ifmm_query", "ifmm_destroy"]:
+                 "ifmm_gmres_left", "ifmm_query", "ifmm_destroy"]:
         getattr(lib, name).restype = ctypes.c_int
     return lib
 
@@ -186,6 +191,23 @@ class IFMM:
                                 B.shape[0], self.n, float(tol), int(maxit), ctypes.byref(it), ctypes.byref(rr)))
         out = X.t()
         return (out[:, 0] if b.dim() == 1 else out), it.value, rr.value
+
+    def gmres_left(self, b, tol: float = 1e-10, maxit: int = 500, prec: "IFMM | None" = None,
+                   precondition: bool = True):
+        """Left-preconditioned GMRES on this handle's H2 operator (preconditioner chosen as in gmres).
+        Returns (x, iterations, preconditioned relative residual, true relative residual)."""
+        B = _colmajor(b, self.n)
+        X = B.new_zeros(B.shape)
+        it = ctypes.c_int()
+        rr = ctypes.c_double()
+        rt = ctypes.c_double()
+        p = None if not precondition else (prec.h if prec is not None else self.h)
+        self._inputs_ready()
+        _check(lib().ifmm_gmres_left(self.h, p, ctypes.c_void_p(B.data_ptr()), ctypes.c_void_p(X.data_ptr()),
+                                     B.shape[0], self.n, float(tol), int(maxit), ctypes.byref(it), ctypes.byref(rr),
+                                     ctypes.byref(rt)))
+        out = X.t()
+        return (out[:, 0] if b.dim() == 1 else out), it.value, rr.value, rt.value
 
     def stats(self) -> dict:
         s = Stats()

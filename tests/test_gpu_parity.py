@@ -218,3 +218,29 @@ def test_paper_kernel_gmres_with_and_without_preconditioner():
     assert abs(itn - ito_n) <= 1 and abs(itp - ito_p) <= 1
     assert itp * 3 <= itn
     assert rel(xn.cpu().numpy(), xo_n) <= 1e-8 and rel(xp.cpu().numpy(), xo_p) <= 1e-8
+
+
+def test_paper_kernel_left_preconditioning_matches_oracle():
+    """App. B: the IFMM as a left preconditioner on the paper's kernel (eps 1e-3). The iteration count,
+    the solution and both residuals follow the oracle's run of the same method; with P = I the left
+    variant is the unpreconditioned method itself."""
+    from oracle.gmres import gmres_left
+    from oracle.ifmm import IFMM as Oracle
+    wl = W.paper_cube(n=2000, d=1e-2, order=3, depth=3, eps=1e-3, seed=6101)
+    b = wl.rhs[:, 0]
+    o = Oracle(wl.points, wl.kernel, wl.kparam, wl.shift, wl.depth, wl.order, wl.eps)
+    o.factorize()
+    g = gpu()(to_dev(wl.points), wl.kernel, wl.kparam, wl.shift, wl.depth, wl.order, wl.eps,
+              sigma0=o.r2.sigma0)
+    xi, iti, rpi, rti = g.gmres_left(to_dev(b), tol=1e-10, maxit=500, precondition=False)
+    xr, itr, rrr = g.gmres(to_dev(b), tol=1e-10, maxit=500, precondition=False)
+    g.factorize()
+    xl, itl, rpl, rtl = g.gmres_left(to_dev(b), tol=1e-10, maxit=500)
+    xo, ito, rpo, rto, _ = gmres_left(o.matvec, o.solve, b, tol=1e-10, maxit=500)
+    g.close()
+    print("left", itl, ito, rpl, rpo, rtl, rto, "identity", iti, itr, flush=True)
+    assert iti == itr and rpi == rti == rrr and torch.equal(xi, xr)
+    assert abs(itl - ito) <= 1
+    assert max(rpl, rpo) <= 1.5e-10           # recomputed; the Arnoldi estimate stopped at 1e-10
+    assert rtl <= 1e-8 and rto <= 1e-8
+    assert rel(xl.cpu().numpy(), xo) <= 1e-8
