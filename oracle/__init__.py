@@ -8,8 +8,8 @@ helper with the HIP library; both sides see the same seeded inputs from
 
 Every function cites the passage of Coulier, Pouransari & Darve,
 "The inverse fast multipole method" (arXiv 1508.01835) that it follows. Where
-the paper is silent or ambiguous the reading taken is the one listed in
-DESIGN.md under "Readings of the paper".
+the paper is silent or ambiguous, each module's header states the reading it
+takes.
 
 Modules:
   tree       cluster tree, neighbour/interaction/children lists, colours

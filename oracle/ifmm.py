@@ -22,7 +22,7 @@ Paper passages followed:
     between them form the parent's near-field blocks.
   * Sec. 2.4, eq. (methods_SVD_rank_spectralnorm): rank rule against tau.
 
-Readings (listed in DESIGN.md):
+Readings (where the paper is silent or ambiguous):
   * Boxes of a level are taken in colour order (independent sets), Morton
     order inside a colour; F of box i lists x~_j of not-yet-eliminated
     neighbours, then y_h of eliminated neighbours (Morton order each), then y_i.

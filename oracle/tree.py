@@ -10,7 +10,7 @@ Paper passages followed:
   * Sec. 2.3: in 3D, |N_i| <= 3^3 and |I_i| <= 6^3 - 3^3.
   * Sec. 3 opening: a uniform tree.
 
-Readings: the root is the tight bounding cube of the points,
+Readings (where the paper is silent): the root is the tight bounding cube of the points,
 slightly enlarged so the largest coordinate falls inside; the leaf level L is
 the requested depth; empty boxes are dropped; points are ordered by the
 Morton key of their leaf box and then by original index; boxes at one level
