@@ -15,7 +15,10 @@
 //  top: y^(2) = T^-1 b(y^(2));
 //  backward, level 2..L, classes in reverse: x~_i = c - W_x x_F.
 // The top and backward products are split over column chunks: partial sums,
-// then a reduction in a fixed order (deterministic), two launches each.
+// then a reduction in a fixed order (deterministic), two launches each. A
+// partial-sum workgroup takes 64 rows (a row per lane) and its four wavefronts
+// split the chunk's columns, so that the few rows of a box at the fine and
+// middle levels still fill the lanes and the columns spread over the chip.
 //
 // Memory bound: every stored factor element is read once per call. The plan
 // (task tables) is uploaded once per factorization; a call only launches.
@@ -25,8 +28,10 @@
 
 namespace ifmm {
 
-constexpr int SV_KCH = 512;   // columns of one partial-sum chunk
+constexpr int SV_KCH = 256;   // columns of one partial-sum chunk
 constexpr int SV_KT = 64;     // columns staged in LDS at a time
+constexpr int SV_RT = WAVE;   // rows of one partial-sum workgroup (a row per lane)
+constexpr int SV_NW = WG / WAVE;   // its wavefronts, which split the columns
 
 struct SvNode {
   int64_t pos;    // V row of the node's first unknown
@@ -64,11 +69,15 @@ __device__ inline int sv_find(const TK* __restrict__ ts, int nt, int b) {
   return lo;
 }
 
-// node of a task owning row (column) k; the nodes of a task are in increasing off
+// node of a task owning row (column) k; the nodes of a task are in increasing
+// off, the first at off 0: binary search for the last node with off <= k
 __device__ inline int64_t sv_pos(const SvNode* __restrict__ nodes, int node0, int nnode, int k) {
-  int a = node0;
-  while (a + 1 < node0 + nnode && nodes[a + 1].off <= k) ++a;
-  return nodes[a].pos + (k - nodes[a].off);
+  int lo = node0, hi = node0 + nnode - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (nodes[mid].off <= k) lo = mid; else hi = mid - 1;
+  }
+  return nodes[lo].pos + (k - nodes[lo].off);
 }
 
 template <class T, int NR>
@@ -106,16 +115,20 @@ __global__ void __launch_bounds__(WG) k_sv_fwd(const FwTask* __restrict__ ts, in
     if (r0 + r < nrhs) V[pos * nrhs + r0 + r] -= acc[r];
 }
 
-// partial sums of rows rc*WG.. over columns kc*SV_KCH..; Part row-major with NR
+// partial sums of rows rc*SV_RT.. over columns kc*SV_KCH..; Part row-major with
+// NR. Wavefront w takes the columns k = w (mod SV_NW) of each staged block; the
+// wavefronts' sums are added in wavefront order.
 template <class T, int NR>
 __global__ void __launch_bounds__(WG) k_sv_part(const BwTask* __restrict__ ts, int nt,
                                                 const SvNode* __restrict__ nodes, const T* __restrict__ V, int nrhs,
                                                 int r0, T* __restrict__ Part) {
   __shared__ T xb[SV_KT * NR];
+  __shared__ T red[(SV_NW - 1) * SV_RT * NR];
   const BwTask t = ts[sv_find(ts, nt, blockIdx.x)];
   const int local = (int)blockIdx.x - t.chunk0;
   const int rc = local % t.nrc, kc = local / t.nrc;
-  const int i = rc * WG + threadIdx.x;
+  const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+  const int i = rc * SV_RT + lane;
   const int kb = kc * SV_KCH, ke = min(t.cols, kb + SV_KCH);
   const T* __restrict__ A = static_cast<const T*>(t.A);
   T acc[NR];
@@ -129,14 +142,22 @@ __global__ void __launch_bounds__(WG) k_sv_part(const BwTask* __restrict__ ts, i
       xb[e] = r0 + r < nrhs ? V[pos * nrhs + r0 + r] : (T)0;
     }
     __syncthreads();
-    if (i < t.rows)
-      for (int k = 0; k < kn; ++k) {
+    if (i < t.rows) {
+#pragma unroll 4
+      for (int k = w; k < kn; k += SV_NW) {
         const T a = A[i + (int64_t)(k0 + k) * t.ld];
         for (int r = 0; r < NR; ++r) acc[r] += a * xb[k * NR + r];
       }
+    }
   }
-  if (i < t.rows)
+  if (w > 0)
+    for (int r = 0; r < NR; ++r) red[((w - 1) * SV_RT + lane) * NR + r] = acc[r];
+  __syncthreads();
+  if (w == 0 && i < t.rows) {
+    for (int v = 0; v < SV_NW - 1; ++v)
+      for (int r = 0; r < NR; ++r) acc[r] += red[(v * SV_RT + lane) * NR + r];
     for (int r = 0; r < NR; ++r) Part[(t.part + (int64_t)kc * t.rows + i) * NR + r] = acc[r];
+  }
 }
 
 // out = c + alpha * (sum of the partial sums in chunk order)
@@ -266,14 +287,14 @@ inline SolvePlan<T>& solve_plan(Problem& P, FactorStore<T>& F, SolvePlan<T>& S) 
         b.out_pos = f.in_pos;
         b.c_pos = cp;
         b.alpha = -1.0;
-        b.nrc = (int)ceil_div((int64_t)e.m, WG);
+        b.nrc = (int)ceil_div((int64_t)e.m, SV_RT);
         b.nkc = std::max(1, (int)ceil_div((int64_t)e.f, SV_KCH));
         b.part = part;
         part += (int64_t)b.nkc * e.m;
         b.chunk0 = wgp;
         wgp += b.nrc * b.nkc;
         b.chunk0b = wgr;
-        wgr += b.nrc;
+        wgr += (int)ceil_div((int64_t)e.m, WG);
         bt.push_back(b);
         cp += e.m;
         S.factor_elems += (double)(e.m + e.f) * e.m + (double)e.m * e.f;
@@ -308,13 +329,13 @@ inline SolvePlan<T>& solve_plan(Problem& P, FactorStore<T>& F, SolvePlan<T>& S) 
     b.out_pos = base[1];
     b.c_pos = -1;
     b.alpha = 1.0;
-    b.nrc = (int)ceil_div((int64_t)F.ntop, WG);
+    b.nrc = (int)ceil_div((int64_t)F.ntop, SV_RT);
     b.nkc = (int)ceil_div((int64_t)F.ntop, SV_KCH);
     b.part = 0;
     b.chunk0 = 0;
     b.chunk0b = 0;
     typename SolvePlan<T>::Launch a;
-    a.kind = 1; a.ntasks = 1; a.nwg = b.nrc * b.nkc; a.nwg2 = b.nrc;
+    a.kind = 1; a.ntasks = 1; a.nwg = b.nrc * b.nkc; a.nwg2 = (int)ceil_div((int64_t)F.ntop, WG);
     std::vector<BwTask> one(1, b);
     P.upload(a.tasks, one);
     S.seq.push_back(std::move(a));
