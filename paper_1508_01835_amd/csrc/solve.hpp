@@ -8,7 +8,7 @@
 // serves all of them.
 //
 //  forward, level L..2, colour classes in order, one launch per class: a
-//    workgroup takes 256 rows of H = [A; G] of one elimination; rows of A
+//    workgroup takes 64 rows of H = [A; G] of one elimination; rows of A
 //    write c, rows of G subtract from the F rows (x~ of later-coloured and y
 //    of earlier-coloured neighbours, disjoint between the eliminations of a
 //    class);
@@ -80,13 +80,18 @@ __device__ inline int64_t sv_pos(const SvNode* __restrict__ nodes, int node0, in
   return nodes[lo].pos + (k - nodes[lo].off);
 }
 
+// A workgroup takes SV_RT rows of H (a row per lane); its wavefronts split
+// the m columns (k = w mod SV_NW of each staged block) and their sums are
+// added in wavefront order before wavefront 0 writes.
 template <class T, int NR>
 __global__ void __launch_bounds__(WG) k_sv_fwd(const FwTask* __restrict__ ts, int nt,
                                                const SvNode* __restrict__ nodes, T* __restrict__ V, int nrhs,
                                                int r0) {
   __shared__ T xb[SV_KT * NR];
+  __shared__ T red[(SV_NW - 1) * SV_RT * NR];
   const FwTask t = ts[sv_find(ts, nt, blockIdx.x)];
-  const int i = ((int)blockIdx.x - t.chunk0) * WG + threadIdx.x;
+  const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+  const int i = ((int)blockIdx.x - t.chunk0) * SV_RT + lane;
   const T* __restrict__ H = static_cast<const T*>(t.H);
   T acc[NR];
   for (int r = 0; r < NR; ++r) acc[r] = 0;
@@ -98,13 +103,20 @@ __global__ void __launch_bounds__(WG) k_sv_fwd(const FwTask* __restrict__ ts, in
       xb[e] = r0 + r < nrhs ? V[(t.in_pos + k0 + k) * nrhs + r0 + r] : (T)0;
     }
     __syncthreads();
-    if (i < t.rows)
-      for (int k = 0; k < kn; ++k) {
+    if (i < t.rows) {
+#pragma unroll 4
+      for (int k = w; k < kn; k += SV_NW) {
         const T h = H[i + (int64_t)(k0 + k) * t.ld];
         for (int r = 0; r < NR; ++r) acc[r] += h * xb[k * NR + r];
       }
+    }
   }
-  if (i >= t.rows) return;
+  if (w > 0)
+    for (int r = 0; r < NR; ++r) red[((w - 1) * SV_RT + lane) * NR + r] = acc[r];
+  __syncthreads();
+  if (w > 0 || i >= t.rows) return;
+  for (int v = 0; v < SV_NW - 1; ++v)
+    for (int r = 0; r < NR; ++r) acc[r] += red[(v * SV_RT + lane) * NR + r];
   if (i < t.m) {
     for (int r = 0; r < NR; ++r)
       if (r0 + r < nrhs) V[(t.c_pos + i) * nrhs + r0 + r] = acc[r];
@@ -275,7 +287,7 @@ inline SolvePlan<T>& solve_plan(Problem& P, FactorStore<T>& F, SolvePlan<T>& S) 
         f.in_pos = base[l] + F.sl[l].xoff[e.box];
         f.c_pos = cp;
         f.chunk0 = wg;
-        wg += (int)ceil_div((int64_t)f.rows, WG);
+        wg += (int)ceil_div((int64_t)f.rows, SV_RT);
         ft.push_back(f);
         BwTask b{};
         b.A = sol + e.wx;
