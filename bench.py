@@ -424,7 +424,10 @@ def main():
         "gmres_relres": relres,
         "time_to_1e-10_s": ttr,
         "solve_latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
-                             "nrhs": 1},
+                             "nrhs": 1, "factor_bytes": int(st0["factor_bytes"]),
+                             # every stored factor element is read once per solve: factor bytes / p50
+                             "hbm_GBs_at_p50": st0["factor_bytes"] / (np.percentile(lat, 50) * 1e-3) / 1e9,
+                             "hbm_peak_GBs": PEAKS["hbm_GBs"]},
         "max_rank": st0["max_rank"],
         "kernel_ms_per_step": breakdown,
         "roofline": roof,
