@@ -28,7 +28,9 @@
 
 namespace ifmm {
 
-constexpr int SV_KCH = 256;   // columns of one partial-sum chunk
+constexpr int SV_KCH = 256;   // widest partial-sum chunk (columns); a launch narrows it to 128 or 64
+constexpr int SV_MIN_WG = 1024;   // while it has fewer workgroups than this. Every right-hand-side
+                                  // count uses the same chunks, so columns are solved bitwise alike
 constexpr int SV_KT = 64;     // columns staged in LDS at a time
 constexpr int SV_RT = WAVE;   // rows of one partial-sum workgroup (a row per lane)
 constexpr int SV_NW = WG / WAVE;   // its wavefronts, which split the columns
@@ -56,6 +58,7 @@ struct BwTask {
   int64_t out_pos, c_pos;  // c_pos < 0: c = 0
   int64_t part;            // first partial-sum row
   int chunk0, nrc, nkc, chunk0b;
+  int kch;                 // columns of one chunk (a multiple of SV_KT)
   double alpha;
 };
 
@@ -127,7 +130,7 @@ __global__ void __launch_bounds__(WG) k_sv_fwd(const FwTask* __restrict__ ts, in
     if (r0 + r < nrhs) V[pos * nrhs + r0 + r] -= acc[r];
 }
 
-// partial sums of rows rc*SV_RT.. over columns kc*SV_KCH..; Part row-major with
+// partial sums of rows rc*SV_RT.. over columns kc*kch..; Part row-major with
 // NR. Wavefront w takes the columns k = w (mod SV_NW) of each staged block; the
 // wavefronts' sums are added in wavefront order.
 template <class T, int NR>
@@ -141,7 +144,7 @@ __global__ void __launch_bounds__(WG) k_sv_part(const BwTask* __restrict__ ts, i
   const int rc = local % t.nrc, kc = local / t.nrc;
   const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
   const int i = rc * SV_RT + lane;
-  const int kb = kc * SV_KCH, ke = min(t.cols, kb + SV_KCH);
+  const int kb = kc * t.kch, ke = min(t.cols, kb + t.kch);
   const T* __restrict__ A = static_cast<const T*>(t.A);
   T acc[NR];
   for (int r = 0; r < NR; ++r) acc[r] = 0;
@@ -272,7 +275,6 @@ inline SolvePlan<T>& solve_plan(Problem& P, FactorStore<T>& F, SolvePlan<T>& S) 
       std::vector<FwTask> ft;
       std::vector<BwTask> bt;
       int wg = 0, wgp = 0, wgr = 0;
-      int64_t part = 0;
       for (const auto& e : cf.el) {
         if (e.m == 0) continue;
         const int n0 = node_list(cf, e, l);
@@ -300,11 +302,6 @@ inline SolvePlan<T>& solve_plan(Problem& P, FactorStore<T>& F, SolvePlan<T>& S) 
         b.c_pos = cp;
         b.alpha = -1.0;
         b.nrc = (int)ceil_div((int64_t)e.m, SV_RT);
-        b.nkc = std::max(1, (int)ceil_div((int64_t)e.f, SV_KCH));
-        b.part = part;
-        part += (int64_t)b.nkc * e.m;
-        b.chunk0 = wgp;
-        wgp += b.nrc * b.nkc;
         b.chunk0b = wgr;
         wgr += (int)ceil_div((int64_t)e.m, WG);
         bt.push_back(b);
@@ -312,6 +309,25 @@ inline SolvePlan<T>& solve_plan(Problem& P, FactorStore<T>& F, SolvePlan<T>& S) 
         S.factor_elems += (double)(e.m + e.f) * e.m + (double)e.m * e.f;
       }
       if (ft.empty()) continue;
+      // chunk layout of the backward tasks for a chunk width kch; returns the workgroup count
+      auto chunking = [&](std::vector<BwTask>& v, int kch) {
+        int64_t pr = 0;
+        int nw = 0;
+        for (auto& b : v) {
+          b.kch = kch;
+          b.nkc = std::max(1, (int)ceil_div((int64_t)b.cols, kch));
+          b.part = pr;
+          pr += (int64_t)b.nkc * b.rows;
+          b.chunk0 = nw;
+          nw += b.nrc * b.nkc;
+        }
+        S.part_rows = std::max(S.part_rows, pr);
+        return nw;
+      };
+      // the widest chunk that still gives SV_MIN_WG workgroups
+      int kch = SV_KCH;
+      wgp = chunking(bt, kch);
+      while (kch > SV_KT && wgp < SV_MIN_WG) wgp = chunking(bt, kch /= 2);
       typename SolvePlan<T>::Launch a;
       a.kind = 0; a.ntasks = (int)ft.size(); a.nwg = wg; a.nwg2 = 0;
       P.upload(a.tasks, ft);
@@ -320,7 +336,6 @@ inline SolvePlan<T>& solve_plan(Problem& P, FactorStore<T>& F, SolvePlan<T>& S) 
       b.kind = 1; b.ntasks = (int)bt.size(); b.nwg = wgp; b.nwg2 = wgr;
       P.upload(b.tasks, bt);
       bw.push_back(std::move(b));
-      S.part_rows = std::max(S.part_rows, part);
     }
   }
   S.seq.clear();
@@ -342,6 +357,7 @@ inline SolvePlan<T>& solve_plan(Problem& P, FactorStore<T>& F, SolvePlan<T>& S) 
     b.c_pos = -1;
     b.alpha = 1.0;
     b.nrc = (int)ceil_div((int64_t)F.ntop, SV_RT);
+    b.kch = SV_KCH;
     b.nkc = (int)ceil_div((int64_t)F.ntop, SV_KCH);
     b.part = 0;
     b.chunk0 = 0;
@@ -371,10 +387,11 @@ inline void solve_pass(Problem& P, SolvePlan<T>& S, T* V, int nrhs, int r0) {
       hipLaunchKernelGGL((k_sv_fwd<T, NR>), dim3((unsigned)a.nwg), dim3(WG), 0, P.stream,
                          a.tasks.template as<FwTask>(), a.ntasks, nodes, V, nrhs, r0);
     } else {
-      hipLaunchKernelGGL((k_sv_part<T, NR>), dim3((unsigned)a.nwg), dim3(WG), 0, P.stream,
-                         a.tasks.template as<BwTask>(), a.ntasks, nodes, (const T*)V, nrhs, r0, Part);
-      hipLaunchKernelGGL((k_sv_reduce<T, NR>), dim3((unsigned)a.nwg2), dim3(WG), 0, P.stream,
-                         a.tasks.template as<BwTask>(), a.ntasks, V, nrhs, r0, (const T*)Part);
+      const BwTask* tk = a.tasks.template as<BwTask>();
+      hipLaunchKernelGGL((k_sv_part<T, NR>), dim3((unsigned)a.nwg), dim3(WG), 0, P.stream, tk, a.ntasks, nodes,
+                         (const T*)V, nrhs, r0, Part);
+      hipLaunchKernelGGL((k_sv_reduce<T, NR>), dim3((unsigned)a.nwg2), dim3(WG), 0, P.stream, tk, a.ntasks, V,
+                         nrhs, r0, (const T*)Part);
     }
     IFMM_LAUNCH_CHECK();
   }
