@@ -186,10 +186,11 @@ __global__ void __launch_bounds__(WG) k_sv_reduce(const BwTask* __restrict__ ts,
     if (ts[mid].chunk0b <= b) lo = mid; else hi = mid - 1;
   }
   const BwTask t = ts[lo];
-  const int i = (b - t.chunk0b) * WG + threadIdx.x;
-  if (i >= t.rows) return;
-  for (int r = 0; r < NR; ++r) {
-    if (r0 + r >= nrhs) break;
+  // the block's WG rows x NR right-hand sides, consecutive threads on consecutive (row, rhs) pairs
+  const int i0 = (b - t.chunk0b) * WG;
+  for (int e = threadIdx.x; e < WG * NR; e += WG) {
+    const int i = i0 + e / NR, r = e % NR;
+    if (i >= t.rows || r0 + r >= nrhs) continue;
     T s = 0;
     for (int kc = 0; kc < t.nkc; ++kc) s += Part[(t.part + (int64_t)kc * t.rows + i) * NR + r];
     const T c = t.c_pos >= 0 ? V[(t.c_pos + i) * nrhs + r0 + r] : (T)0;
