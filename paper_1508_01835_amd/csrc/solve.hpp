@@ -325,7 +325,7 @@ inline SolvePlan<T>& solve_plan(Problem& P, FactorStore<T>& F, SolvePlan<T>& S) 
         S.part_rows = std::max(S.part_rows, pr);
         return nw;
       };
-      // the widest chunk that still gives SV_MIN_WG workgroups
+      // the widest chunk that gives at least SV_MIN_WG workgroups (SV_KT if none does)
       int kch = SV_KCH;
       wgp = chunking(bt, kch);
       while (kch > SV_KT && wgp < SV_MIN_WG) wgp = chunking(bt, kch /= 2);
