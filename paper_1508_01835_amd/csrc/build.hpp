@@ -394,10 +394,19 @@ inline void build_r2(Problem& P, double sigma0_override) {
     R.dkpoff[l] = up(P, ko);
     R.Kpre[l].alloc(sizeof(double) * std::max<int64_t>(kt, 1), &P.mem);
     if (!lv.inter.empty()) {
-      hipLaunchKernelGGL(k_kpre, dim3((unsigned)lv.inter.size()), dim3(WG), 0, P.stream,
-                         P.ldev[l].in_start.as<int>(), P.ldev[l].inter.as<int>(), P.ldev[l].coords.as<int>(), lv.nb,
-                         P.d, q, P.m2l[l].as<double>(), R.R[l].as<double>(), R.droff[l].as<int64_t>(),
-                         R.dr[l].as<int>(), R.Kpre[l].as<double>(), R.dkpoff[l].as<int64_t>());
+      int rmx = 0;
+      for (int i = 0; i < lv.nb; ++i) rmx = std::max(rmx, R.r[l][i]);
+      const int np = (int)lv.inter.size();
+      if ((int64_t)rmx * q <= SWW)   // a wavefront per pair
+        hipLaunchKernelGGL(k_kpre_w, dim3((unsigned)ceil_div(np, WG / WAVE)), dim3(WG), 0, P.stream,
+                           P.ldev[l].in_start.as<int>(), P.ldev[l].inter.as<int>(), P.ldev[l].coords.as<int>(),
+                           lv.nb, P.d, q, P.m2l[l].as<double>(), R.R[l].as<double>(), R.droff[l].as<int64_t>(),
+                           R.dr[l].as<int>(), R.Kpre[l].as<double>(), R.dkpoff[l].as<int64_t>(), np);
+      else
+        hipLaunchKernelGGL(k_kpre, dim3((unsigned)np), dim3(WG), 0, P.stream, P.ldev[l].in_start.as<int>(),
+                           P.ldev[l].inter.as<int>(), P.ldev[l].coords.as<int>(), lv.nb, P.d, q,
+                           P.m2l[l].as<double>(), R.R[l].as<double>(), R.droff[l].as<int64_t>(), R.dr[l].as<int>(),
+                           R.Kpre[l].as<double>(), R.dkpoff[l].as<int64_t>());
       IFMM_LAUNCH_CHECK();
     }
   }
@@ -605,10 +614,22 @@ inline void build_r2(Problem& P, double sigma0_override) {
     z.K.alloc(sizeof(double) * std::max<int64_t>(kt, 1), &P.mem);
     DevBuf dko = up(P, z.k_off);
     if (!lv.inter.empty()) {
-      hipLaunchKernelGGL(k_krot, dim3((unsigned)lv.inter.size()), dim3(WG), 0, P.stream,
-                         P.ldev[l].in_start.as<int>(), P.ldev[l].inter.as<int>(), lv.nb, R.Kpre[l].as<double>(),
-                         R.dkpoff[l].as<int64_t>(), R.dr[l].as<int>(), WU[l].as<double>(), WV[l].as<double>(),
-                         dwoff[l].as<int64_t>(), dk[l].as<int>(), z.K.as<double>(), dko.as<int64_t>());
+      int kmx = 0, rmx = 0;
+      for (int i = 0; i < lv.nb; ++i) {
+        kmx = std::max(kmx, k[i]);
+        rmx = std::max(rmx, R.r[l][i]);
+      }
+      const int np = (int)lv.inter.size();
+      if ((int64_t)kmx * rmx <= SWW)   // a wavefront per pair
+        hipLaunchKernelGGL(k_krot_w, dim3((unsigned)ceil_div(np, WG / WAVE)), dim3(WG), 0, P.stream,
+                           P.ldev[l].in_start.as<int>(), P.ldev[l].inter.as<int>(), lv.nb, R.Kpre[l].as<double>(),
+                           R.dkpoff[l].as<int64_t>(), R.dr[l].as<int>(), WU[l].as<double>(), WV[l].as<double>(),
+                           dwoff[l].as<int64_t>(), dk[l].as<int>(), z.K.as<double>(), dko.as<int64_t>(), np);
+      else
+        hipLaunchKernelGGL(k_krot, dim3((unsigned)np), dim3(WG), 0, P.stream, P.ldev[l].in_start.as<int>(),
+                           P.ldev[l].inter.as<int>(), lv.nb, R.Kpre[l].as<double>(), R.dkpoff[l].as<int64_t>(),
+                           R.dr[l].as<int>(), WU[l].as<double>(), WV[l].as<double>(), dwoff[l].as<int64_t>(),
+                           dk[l].as<int>(), z.K.as<double>(), dko.as<int64_t>());
       IFMM_LAUNCH_CHECK();
     }
     z.s_off.resize(lv.nb);

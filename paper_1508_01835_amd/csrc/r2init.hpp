@@ -78,6 +78,53 @@ __global__ void __launch_bounds__(WG) k_kpre(const int* __restrict__ in_start, c
            [&](int x, int y, double v) { out[x + (int64_t)y * ri] = v; }, sh);
 }
 
+// The same triple product by one wavefront, for a * c <= SWW: the a x c
+// intermediate sits in the wavefront's LDS slice, and both sums run in the same
+// order as in sandwich(), so the results are the same bit for bit. A pair of
+// small boxes then costs a wavefront instead of a workgroup and its barriers.
+constexpr int SWW = 1024;   // LDS doubles per wavefront
+template <class FX, class FY, class FZ, class FO>
+__device__ inline void wave_sandwich(int a, int b, int c, int e, FX X, FY Y, FZ Z, FO O, double* sh, int lane) {
+  for (int t = lane; t < a * c; t += WAVE) {
+    const int ii = t % a, kc = t / a;
+    double s = 0;
+    for (int kb = 0; kb < b; ++kb) s += X(ii, kb) * Y(kb, kc);
+    sh[ii + kc * a] = s;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  for (int t = lane; t < a * e; t += WAVE) {
+    const int ii = t % a, jj = t / a;
+    double s = 0;
+    for (int kc = 0; kc < c; ++kc) s += sh[ii + kc * a] * Z(kc, jj);
+    O(ii, jj, s);
+  }
+}
+
+// k_kpre with a wavefront per pair (every r_i q <= SWW).
+__global__ void __launch_bounds__(WG) k_kpre_w(const int* __restrict__ in_start, const int* __restrict__ inter,
+                                               const int* __restrict__ coords, int nb, int d, int q,
+                                               const double* __restrict__ tab, const double* __restrict__ R,
+                                               const int64_t* __restrict__ roff, const int* __restrict__ r,
+                                               double* __restrict__ K, const int64_t* __restrict__ koff, int npairs) {
+  __shared__ double sh[(WG / WAVE) * SWW];
+  const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
+  const int t = blockIdx.x * (WG / WAVE) + wv;
+  if (t >= npairs) return;
+  const int i = find_row(in_start, nb, t);
+  const int j = inter[t];
+  const int ri = r[i], rj = r[j];
+  const double* Ri = R + roff[i];
+  const double* Rj = R + roff[j];
+  const double* Kb = tab + (int64_t)offset_code(coords, d, i, j) * q * q;
+  double* out = K + koff[t];
+  wave_sandwich(ri, q, q, rj, [&](int x, int y) { return Ri[x + (int64_t)y * ri]; },
+                [&](int x, int y) { return Kb[x + (int64_t)y * q]; },
+                [&](int x, int y) { return Rj[y + (int64_t)x * rj]; },
+                [&](int x, int y, double v) { out[x + (int64_t)y * ri] = v; }, sh + wv * SWW, lane);
+}
+
 // K(i, j) = WU_i[:, :k_i]^T K_pre(i, j) WV_j[:, :k_j].
 __global__ void __launch_bounds__(WG) k_krot(const int* __restrict__ in_start, const int* __restrict__ inter, int nb,
                                              const double* __restrict__ Kpre, const int64_t* __restrict__ kpoff,
@@ -98,6 +145,30 @@ __global__ void __launch_bounds__(WG) k_krot(const int* __restrict__ in_start, c
            [&](int x, int y) { return B[x + (int64_t)y * ri]; },
            [&](int x, int y) { return C[x + (int64_t)y * rj]; },
            [&](int x, int y, double v) { out[x + (int64_t)y * ki] = v; }, sh);
+}
+
+// k_krot with a wavefront per pair (every k_i r_j <= SWW).
+__global__ void __launch_bounds__(WG) k_krot_w(const int* __restrict__ in_start, const int* __restrict__ inter, int nb,
+                                               const double* __restrict__ Kpre, const int64_t* __restrict__ kpoff,
+                                               const int* __restrict__ r, const double* __restrict__ WU,
+                                               const double* __restrict__ WV, const int64_t* __restrict__ woff,
+                                               const int* __restrict__ k, double* __restrict__ K,
+                                               const int64_t* __restrict__ koff, int npairs) {
+  __shared__ double sh[(WG / WAVE) * SWW];
+  const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
+  const int t = blockIdx.x * (WG / WAVE) + wv;
+  if (t >= npairs) return;
+  const int i = find_row(in_start, nb, t);
+  const int j = inter[t];
+  const int ri = r[i], rj = r[j], ki = k[i], kj = k[j];
+  const double* A = WU + woff[i];
+  const double* B = Kpre + kpoff[t];
+  const double* C = WV + woff[j];
+  double* out = K + koff[t];
+  wave_sandwich(ki, ri, rj, kj, [&](int x, int y) { return A[y + (int64_t)x * ri]; },
+                [&](int x, int y) { return B[x + (int64_t)y * ri]; },
+                [&](int x, int y) { return C[x + (int64_t)y * rj]; },
+                [&](int x, int y, double v) { out[x + (int64_t)y * ki] = v; }, sh + wv * SWW, lane);
 }
 
 // P(i) = W_i[:, :k_i]^T Ppre(i) W_parent[:, :k_parent]; Ppre(i) is r_i x r_p with leading dim pld[i].
