@@ -136,3 +136,22 @@ def test_preconditioned_gmres_iterations_grow_with_eps():
         its.append(it)
     assert its[0] == 1
     assert its[0] <= its[1] <= its[2] and its[2] > its[0]
+
+
+def test_left_preconditioned_gmres_iterations_grow_with_eps():
+    """App. B with the oracle's own factorization: at eps = 0 the factorization is the exact inverse of the
+    H2 operator, so left-preconditioned GMRES takes one step; coarser eps needs more, and the reported
+    (preconditioned) residual and the true residual both end small."""
+    from oracle.gmres import gmres_left
+    wl = W.small_uniform(600, 2, 93, 4, 3, 1e-8)
+    its = []
+    s0 = None
+    for eps in (0.0, 1e-6, 1e-2):
+        f = IFMM(wl.points, wl.kernel, wl.kparam, wl.shift, 4, 3, eps, sigma0=s0)
+        s0 = f.r2.sigma0
+        f.factorize()
+        x, it, rp, rt, _ = gmres_left(f.matvec, f.solve, wl.rhs[:, 0], tol=1e-10, maxit=100)
+        assert rp <= 2e-10 and rt <= 1e-8
+        its.append(it)
+    assert its[0] == 1
+    assert its[0] <= its[1] <= its[2] and its[2] > its[0]
