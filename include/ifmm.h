@@ -145,6 +145,9 @@ int ifmm_build(const double* points, int64_t n, int dim, ifmm_kernel k, int dept
  * compress and redirect well-separated fill-in, merge each level into its
  * parent and factorize the dense top system (Alg. 1 and 2; Alg. 3; eqs.
  * P2P_kj to K_merge). Stores the factors for any number of later solves.
+ * Errors: IFMM_ERR_SINGULAR (a zero pivot; stats error_level / error_box),
+ * IFMM_ERR_NUMERICAL (a NaN or infinity in the stored factors; stats
+ * error_level = the finest level holding one, 1 = top system).
  */
 int ifmm_factorize(ifmm_handle h);
 
@@ -167,8 +170,21 @@ int ifmm_factorize_batch(ifmm_handle* hs, int count, int nthreads, int* status);
  * ifmm_solve - x = IFMM^-1 b for nrhs right-hand sides (Alg. 1, substitution).
  *   b, x   device, n x nrhs column-major float64, leading dimension ld;
  *          x may alias b
+ * Returns when x is complete. IFMM_ERR_NUMERICAL if b holds a NaN or an
+ * infinity, or if the result does (x is then not meaningful).
  */
 int ifmm_solve(ifmm_handle h, const double* b, double* x, int nrhs, int64_t ld);
+
+/*
+ * ifmm_query_ranks - final rank of every box of one level, i.e. the size of
+ * y_i when box i is eliminated (Alg. 2), after the recompressions of Sec. 2.2.
+ *   level  in [2, depth]
+ *   out    host array of count ints, boxes in the level's order (occupied
+ *          boxes sorted by Morton code)
+ *   count  must equal the occupied boxes of the level (ifmm_stats.boxes)
+ * Needs a factorized handle (IFMM_ERR_STATE otherwise).
+ */
+int ifmm_query_ranks(ifmm_handle h, int level, int* out, int count);
 
 /*
  * ifmm_matvec - y = A~ x with the H2 operators of the build (eq. A_decomp_l3
@@ -182,14 +198,17 @@ int ifmm_matvec(ifmm_handle h, const double* x, double* y, int nrhs, int64_t ld)
  * products use op's H2 matvec in float64, the preconditioner is prec's
  * factorization (float32 or float64); orthogonalisation is float64.
  * op and prec must describe the same points (same n); they may be the same
- * handle. prec = NULL runs GMRES without a preconditioner (the comparison
+ * handle, or live on different streams (the calls order the two streams with
+ * events). prec = NULL runs GMRES without a preconditioner (the comparison
  * runs of Sec. 3.2); op then need not be factorized. Each column is an
  * independent GMRES run.
- *   b, x        device, n x nrhs, leading dimension ld; x is overwritten
+ *   b, x        device, n x nrhs, leading dimension ld; x is overwritten;
+ *               x and b must not overlap (IFMM_ERR_ARG)
  *   tol         stop when ||b - A~ x|| <= tol ||b|| (per column)
  *   maxit       iteration limit (<= 1000)
  *   iters_out   host, may be NULL: largest iteration count over the columns
  *   relres_out  host, may be NULL: largest true relative residual at exit
+ * IFMM_ERR_NUMERICAL if b holds a NaN or an infinity.
  */
 int ifmm_gmres(ifmm_handle op, ifmm_handle prec, const double* b, double* x, int nrhs,
                int64_t ld, double tol, int maxit, int* iters_out, double* relres_out);

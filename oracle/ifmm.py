@@ -34,6 +34,11 @@ Readings (where the paper is silent or ambiguous):
     SVD of each fill, then recompression with U' Sigma') up to the order in
     which pairs are folded in. r_j = Uhat_j^T U_j and t_j = Vhat_j^T V_j, which
     equal Sigma_hat phi_j Sigma_U^-1 and Sigma_hat psi_j Sigma_V^-1 exactly.
+  * mode="literal" follows the paper's pairwise route instead: unordered
+    well-separated pairs of F one at a time (F order), a truncated SVD of
+    each directed fill block, recompression of the bases with the compressed
+    fill, the edge rewrite of Alg. 3 and the redirect, before the next pair.
+    Both modes are exact as eps -> 0 and agree with each other to O(eps).
   * After each merge the parent bases [U_p Sigma_U] and [V_p Sigma_V] are
     recompressed at tau, so every pivot block starts with orthonormal bases
     and at most as many basis columns as x~ rows.
@@ -107,7 +112,10 @@ class IFMM:
     """FP64 IFMM on a point cloud: build, factorize, solve, matvec (oracle)."""
 
     def __init__(self, points, kind, param, shift, depth, order, eps, sigma0=None,
-                 rank_max=0, unit_roundoff=2.0 ** -53, class_shuffle_seed=None):
+                 rank_max=0, unit_roundoff=2.0 ** -53, class_shuffle_seed=None, mode="aggregated"):
+        if mode not in ("aggregated", "literal"):
+            raise ValueError("mode must be 'aggregated' or 'literal'")
+        self.mode = mode
         self.tree = Tree(points, depth)
         self.h2 = H2(self.tree, kind, param, shift, order)
         self.r2 = R2(self.h2, eps, unit_roundoff=unit_roundoff, sigma0=sigma0, rank_max=rank_max)
@@ -257,6 +265,9 @@ class IFMM:
                 else:
                     ws_pairs.append((a, c))
 
+        if self.mode == "literal":
+            self._compress_pairwise(st, F, ws_pairs, blk)
+            return rec
         # aggregated recompression of every not-yet-eliminated neighbour with ws fill
         new_basis = {}
         for a, (ta, j) in enumerate(F):
@@ -281,6 +292,76 @@ class IFMM:
                 B = B @ new_basis[bc][2]
             self._redirect_add(st, ba, bc, B)
         return rec
+
+    def _compress_pairwise(self, st: LevelState, F, ws_pairs, blk) -> None:
+        """The paper's own route for the well-separated fill of one elimination (Alg. 2 and 3).
+
+        Unordered pairs {a, c} of F (a before c in F's order) are taken one at a time. Each of the two
+        directed fill blocks D(a, c), D(c, a) is approximated by its truncated SVD U' S' V'^T at tau (eqs.
+        P2P_kj and P2P_jk; only the x~ side of an x~-y fill is compressed). Then the bases of the x~ boxes
+        involved are recompressed from [U_j Sigma_U | U' S'] and [V_j Sigma_V | V' S'] (eqs. U_j_recomp
+        and V_j_recomp), every edge of y_j is rewritten in the new bases (Alg. 3), and the compressed fill
+        is added to K (eq. K_kj_update) in those new bases. The next pair sees the updated bases.
+        """
+        wset = set(ws_pairs)
+        done = set()
+        for (a, c) in ws_pairs:
+            key = (min(a, c), max(a, c))
+            if key in done:
+                continue
+            done.add(key)
+            lo, hi = key
+            addU, addV, pending = {}, {}, []
+            for (p, q) in ((lo, hi), (hi, lo)):
+                if (p, q) not in wset:
+                    continue
+                tp, bp = F[p]
+                tq, bq = F[q]
+                Uq, sq, Vq = self._truncated_svd(blk(p, q))
+                if sq.shape[0] == 0:
+                    continue
+                if tp == "x":
+                    addU.setdefault(bp, []).append(Uq * sq[None, :])
+                if tq == "x":
+                    addV.setdefault(bq, []).append(Vq * sq[None, :])
+                pending.append((tp, bp, tq, bq, Uq, sq, Vq))
+            if not pending:
+                continue
+            new_basis = {}
+            for j in sorted(set(addU) | set(addV)):
+                MU = np.hstack([st.U[j] * st.SU[j][None, :]] + addU.get(j, []))
+                MV = np.hstack([st.V[j] * st.SV[j][None, :]] + addV.get(j, []))
+                new_basis[j] = self._recompress_full(MU, MV, st.m[j])
+            self._apply_basis_change(st, new_basis)
+            for (tp, bp, tq, bq, Uq, sq, Vq) in pending:
+                left = st.U[bp].T @ Uq if tp == "x" else Uq
+                right = Vq.T @ st.V[bq] if tq == "x" else Vq.T
+                self._redirect_add(st, bp, bq, (left * sq[None, :]) @ right)
+
+    def _truncated_svd(self, B: np.ndarray):
+        """U', S', V' of B keeping the singular values strictly above tau (eq. methods_SVD_rank_spectralnorm)."""
+        if B.size == 0:
+            return np.zeros((B.shape[0], 0)), np.zeros(0), np.zeros((B.shape[1], 0))
+        U, s, Vt = np.linalg.svd(B, full_matrices=False)
+        k = int(np.sum(s > self.tau))
+        return U[:, :k], s[:k], Vt[:k].T
+
+    def _recompress_full(self, MU, MV, m_j):
+        """As _recompress, with complete left singular bases so that a side that resolves fewer directions
+        than the common rank is completed by orthonormal vectors of weight zero."""
+        def full(M):
+            if M.shape[0] == 0:
+                return np.zeros((0, 0)), np.zeros(0)
+            W, s, _ = np.linalg.svd(M, full_matrices=True)
+            sp = np.zeros(M.shape[0])
+            sp[:s.shape[0]] = s[:M.shape[0]]
+            return W, sp
+        Uh, sU = full(MU)
+        Vh, sV = full(MV)
+        k = min(max(int(np.sum(sU > self.tau)), int(np.sum(sV > self.tau))), m_j)
+        if self.rank_max > 0:
+            k = min(k, self.rank_max)
+        return Uh[:, :k], sU[:k].copy(), Vh[:, :k], sV[:k].copy()
 
     def _redirect_add(self, st: LevelState, a: int, c: int, B: np.ndarray) -> None:
         """K(a, c) += compressed fill, eqs. (K_kj_update) and Alg. 3."""

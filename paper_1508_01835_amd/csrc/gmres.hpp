@@ -99,7 +99,20 @@ struct GmresResult {
 
 struct GmresWork {
   DevBuf V, Z, w, part, dots, hbuf, scal, y, kc, r;
+  void release() {
+    for (DevBuf* b : {&V, &Z, &w, &part, &dots, &hbuf, &scal, &y, &kc, &r}) b->release();
+  }
 };
+
+// Grow b to hold at least `need` bytes, keeping its first `used` bytes
+// (stream-ordered copy); capacity doubles, up to `cap` bytes.
+inline void grow_keep(Problem& P, DevBuf& b, size_t need, size_t used, size_t cap) {
+  if (need <= b.bytes) return;
+  DevBuf nb;
+  nb.alloc(std::min(cap, std::max(need, 2 * b.bytes)), &P.mem);
+  if (used > 0) IFMM_HIP(hipMemcpyAsync(nb.p, b.p, used, hipMemcpyDeviceToDevice, P.stream));
+  b = std::move(nb);
+}
 
 // apply_A(x, y): y = A x (both n x nrhs, ld n); apply_M(x, y): y = M^-1 x.
 // left selects left preconditioning (no Z storage).
@@ -108,8 +121,11 @@ inline GmresResult gmres_run(Problem& P, GmresWork& G, const std::function<void(
                              int nrhs, int64_t ld, double tol, int maxit, bool left = false) {
   const int64_t n = P.n;
   const int64_t nv = n * nrhs;
-  G.V.reserve(sizeof(double) * nv * (maxit + 1), &P.mem);
-  if (!left) G.Z.reserve(sizeof(double) * nv * std::max(maxit, 1), &P.mem);
+  // Krylov storage grows with the iterations (a few vectors first), so a call
+  // that converges early never holds maxit + 1 vectors
+  const size_t vb = sizeof(double) * (size_t)nv;
+  grow_keep(P, G.V, vb * (size_t)std::min(maxit + 1, 8), 0, vb * (size_t)(maxit + 1));
+  if (!left) grow_keep(P, G.Z, vb * (size_t)std::min(maxit, 8), 0, vb * (size_t)maxit);
   G.w.reserve(sizeof(double) * nv, &P.mem);
   G.r.reserve(sizeof(double) * nv, &P.mem);
   const int nch = (int)std::max<int64_t>(1, ceil_div(n, DOT_CHUNK));
@@ -170,6 +186,12 @@ inline GmresResult gmres_run(Problem& P, GmresWork& G, const std::function<void(
     bool any = false;
     for (int c = 0; c < nrhs; ++c) any = any || active[c];
     if (!any) break;
+    grow_keep(P, G.V, vb * (size_t)(k + 2), vb * (size_t)(k + 1), vb * (size_t)(maxit + 1));
+    V = G.V.as<double>();
+    if (!left) {
+      grow_keep(P, G.Z, vb * (size_t)(k + 1), vb * (size_t)k, vb * (size_t)maxit);
+      Z = G.Z.as<double>();
+    }
     double* vk = V + (int64_t)k * nv;
     if (left) {   // w = P^-1 A v_k
       apply_A(vk, G.r.as<double>());

@@ -2,6 +2,8 @@
 // failures into status codes; nothing throws across the boundary.
 #include <algorithm>
 #include <atomic>
+#include <map>
+#include <mutex>
 #include <thread>
 
 #include "gmres.hpp"
@@ -39,11 +41,107 @@ int guarded(F&& fn) {
   }
 }
 
-void check_finite_vec(Problem& P, const double* v, int64_t n, int nrhs, int64_t ld, const char* what) {
-  (void)P; (void)v; (void)n; (void)nrhs; (void)ld; (void)what;
+// Non-finite detection (IFMM_ERR_NUMERICAL). Word 2 of the handle's device
+// info block is set by the vector checks, word 3 by the factor scan; -1 means
+// clean. A thread that meets a NaN or an infinity stores its tag: every such
+// store writes the same kind of value, so the race between them is harmless.
+constexpr int INFO_VEC = 2, INFO_FAC = 3;
+
+__global__ void k_nonfinite_vec(const double* __restrict__ v, int64_t n, int nrhs, int64_t ld, int tag,
+                                int* __restrict__ info) {
+  const int64_t total = n * nrhs;
+  bool bad = false;
+  for (int64_t e = (int64_t)blockIdx.x * WG + threadIdx.x; e < total; e += (int64_t)gridDim.x * WG) {
+    const int64_t t = e % n, c = e / n;
+    bad = bad || !isfinite(v[t + c * ld]);
+  }
+  if (bad) info[INFO_VEC] = tag;
+}
+
+struct FiniteSpan {
+  const void* p;
+  int64_t count;
+  int tag;
+  int pad;
+};
+
+// One workgroup per span (a stored factor block).
+template <class T>
+__global__ void k_nonfinite_spans(const FiniteSpan* __restrict__ sp, int* __restrict__ info) {
+  const FiniteSpan s = sp[blockIdx.x];
+  const T* v = static_cast<const T*>(s.p);
+  bool bad = false;
+  for (int64_t e = threadIdx.x; e < s.count; e += WG) bad = bad || !isfinite((double)v[e]);
+  if (bad) atomicMax(info + INFO_FAC, s.tag);   // the finest level holding one (-1: none)
+}
+
+// Launch the check of an n x nrhs block (leading dimension ld); the host reads
+// the verdict with finite_verdict after its next synchronisation.
+void check_finite_vec(Problem& P, const double* v, int64_t n, int nrhs, int64_t ld, int tag) {
+  const int64_t total = n * nrhs;
+  const unsigned g = (unsigned)std::min<int64_t>(1024, std::max<int64_t>(1, ceil_div(total, WG)));
+  hipLaunchKernelGGL(k_nonfinite_vec, dim3(g), dim3(WG), 0, P.stream, v, n, nrhs, ld, tag, P.d_info);
+  IFMM_LAUNCH_CHECK();
+}
+
+void reset_finite(Problem& P) {
+  IFMM_HIP(hipMemsetAsync(P.d_info + INFO_VEC, 0xff, sizeof(int) * 2, P.stream));
+}
+
+// Reads both words (synchronises); returns the vector tag (-1: clean).
+int finite_verdict(Problem& P) {
+  std::vector<int> info;
+  P.download(info, P.d_info, 4);
+  return info[INFO_VEC];
+}
+
+// Scan the stored factors for non-finite values; fails with IFMM_ERR_NUMERICAL
+// naming the finest level where one sits (where it arose: the elimination
+// carries fill upwards only).
+template <class T>
+void scan_factors(Problem& P, FactorStore<T>& F) {
+  // the blocks H = [A; G] and W_x of every elimination (padding between them is never written)
+  std::vector<FiniteSpan> sp;
+  for (int l = (int)F.cls.size() - 1; l >= 2; --l)
+    for (const auto& cf : F.cls[l]) {
+      const T* sol = cf.sol.template as<T>();
+      for (const auto& e : cf.el) {
+        if (e.m == 0) continue;
+        sp.push_back({sol + e.h, (int64_t)(e.m + e.f) * e.m, l, 0});
+        if (e.f > 0) sp.push_back({sol + e.wx, (int64_t)e.m * e.f, l, 0});
+      }
+    }
+  if (F.ntop > 0) sp.push_back({F.topinv.p, (int64_t)F.ntop * F.ntop, 1, 0});
+  if (sp.empty()) return;
+  DevBuf d;
+  P.upload(d, sp);
+  hipLaunchKernelGGL(k_nonfinite_spans<T>, dim3((unsigned)sp.size()), dim3(WG), 0, P.stream,
+                     d.as<FiniteSpan>(), P.d_info);
+  IFMM_LAUNCH_CHECK();
+  std::vector<int> info;
+  P.download(info, P.d_info, 4);
+  if (info[INFO_FAC] != -1) {
+    P.st.error_level = info[INFO_FAC];
+    P.st.error_box = -1;
+    fail(IFMM_ERR_NUMERICAL, "non-finite value in the factors (level " + std::to_string(info[INFO_FAC]) +
+                                 "; 1 = top system)");
+  }
 }
 
 }  // namespace
+
+// Two events without timing, destroyed with the scope.
+struct EventPair {
+  hipEvent_t a = nullptr, b = nullptr;
+  void create() {
+    IFMM_HIP(hipEventCreateWithFlags(&a, hipEventDisableTiming));
+    IFMM_HIP(hipEventCreateWithFlags(&b, hipEventDisableTiming));
+  }
+  ~EventPair() {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+  }
+};
 
 struct ifmm_problem {
   Problem P;
@@ -107,6 +205,7 @@ int ifmm_build(const double* points, int64_t n, int dim, ifmm_kernel k, int dept
     }
     P.stream = static_cast<hipStream_t>(o.stream);
     StreamScope ss(P.stream);
+    IFMM_HIP(hipGetDevice(&P.device));
     P.n = n;
     P.d = dim;
     P.order = cheb_order;
@@ -158,15 +257,20 @@ void factorize_handle(ifmm_handle h) {
     IFMM_HIP(hipMemsetAsync(P.d_info, 0xff, sizeof(int) * 4, P.stream));
     P.st.error_level = P.st.error_box = -1;
     const double t0 = now_ms();
+    reset_finite(P);
     if (P.precision == 64) {
       auto f = std::make_unique<Factors<double>>();
       Factorizer<double> z(P, f->F);
       z.run();
+      scan_factors(P, f->F);
+      solve_plan(P, f->F, f->S);   // built now, so that a solve only launches
       P.fac = std::move(f);
     } else {
       auto f = std::make_unique<Factors<float>>();
       Factorizer<float> z(P, f->F);
       z.run();
+      scan_factors(P, f->F);
+      solve_plan(P, f->F, f->S);
       P.fac = std::move(f);
     }
     P.st.t_factor_ms = now_ms() - t0;
@@ -247,9 +351,28 @@ int ifmm_solve(ifmm_handle h, const double* b, double* x, int nrhs, int64_t ld) 
     if (!P.factorized) fail(IFMM_ERR_STATE, "ifmm_solve needs a factorized handle");
     if (nrhs < 1 || ld < P.n) fail(IFMM_ERR_ARG, "nrhs must be >= 1 and ld >= n");
     const double t0 = now_ms();
+    reset_finite(P);
+    check_finite_vec(P, b, P.n, nrhs, ld, 1);
     solve_any(P, b, x, nrhs, ld);
-    P.sync();
+    check_finite_vec(P, x, P.n, nrhs, ld, 2);
+    const int bad = finite_verdict(P);   // synchronises
     P.st.t_last_solve_ms = now_ms() - t0;
+    if (bad == 1) fail(IFMM_ERR_NUMERICAL, "b holds a non-finite value");
+    if (bad != -1) fail(IFMM_ERR_NUMERICAL, "the solve produced a non-finite value");
+  });
+}
+
+int ifmm_query_ranks(ifmm_handle h, int level, int* out, int count) {
+  return guarded([&] {
+    if (!h || !out) fail(IFMM_ERR_ARG, "null pointer");
+    Problem& P = h->P;
+    if (!P.factorized) fail(IFMM_ERR_STATE, "ifmm_query_ranks needs a factorized handle");
+    if (level < 2 || level > P.L) fail(IFMM_ERR_ARG, "level must be in [2, depth]");
+    if (count != P.T.lev[level].nb) fail(IFMM_ERR_ARG, "count must equal the occupied boxes of the level");
+    const std::vector<int64_t>& y = P.precision == 64
+                                        ? static_cast<Factors<double>*>(P.fac.get())->F.sl[level].yoff
+                                        : static_cast<Factors<float>*>(P.fac.get())->F.sl[level].yoff;
+    for (int i = 0; i < count; ++i) out[i] = (int)(y[i + 1] - y[i]);
   });
 }
 
@@ -298,6 +421,20 @@ static int gmres_entry(ifmm_handle op, ifmm_handle prec, const double* b, double
     if (nrhs < 1 || ld < A.n) fail(IFMM_ERR_ARG, "nrhs must be >= 1 and ld >= n");
     if (maxit < 1 || maxit > 1000) fail(IFMM_ERR_ARG, "maxit must be in [1, 1000]");
     if (!(tol > 0)) fail(IFMM_ERR_ARG, "tol must be > 0");
+    {   // x is written before b is read for the last time (exit residual): the two must not overlap
+      const char* b0 = reinterpret_cast<const char*>(b);
+      const char* x0 = reinterpret_cast<const char*>(x);
+      const size_t span = sizeof(double) * (size_t)(ld * (nrhs - 1) + A.n);
+      if (b0 < x0 + span && x0 < b0 + span) fail(IFMM_ERR_ARG, "x and b must not overlap");
+    }
+    reset_finite(A);
+    check_finite_vec(A, b, A.n, nrhs, ld, 1);
+    if (finite_verdict(A) != -1) fail(IFMM_ERR_NUMERICAL, "b holds a non-finite value");
+    // op and prec may live on different streams: every preconditioner solve
+    // waits for the work of op's stream that wrote its input, and op's stream
+    // waits for the solve before reading its output (device-side, by events)
+    EventPair ev;
+    if (prec && prec->P.stream != A.stream) ev.create();
     if (prec && prec->P.stream != A.stream) prec->P.sync();
     auto applyA = [&](const double* in, double* out) { matvec_any(A, in, out, nrhs, A.n); };
     auto applyM = [&](const double* in, double* out) {
@@ -306,11 +443,28 @@ static int gmres_entry(ifmm_handle op, ifmm_handle prec, const double* b, double
         return;
       }
       Problem& M = prec->P;
+      if (M.stream != A.stream) {
+        IFMM_HIP(hipEventRecord(ev.a, A.stream));
+        IFMM_HIP(hipStreamWaitEvent(M.stream, ev.a, 0));
+      }
       solve_any(M, in, out, nrhs, M.n);
-      if (M.stream != A.stream) M.sync();
+      if (M.stream != A.stream) {
+        IFMM_HIP(hipEventRecord(ev.b, M.stream));
+        IFMM_HIP(hipStreamWaitEvent(A.stream, ev.b, 0));
+      }
     };
-    const GmresResult r = gmres_run(A, op->G, applyA, applyM, b, x, nrhs, ld, tol, maxit, left);
+    GmresResult r;
+    try {
+      r = gmres_run(A, op->G, applyA, applyM, b, x, nrhs, ld, tol, maxit, left);
+    } catch (...) {
+      (void)hipStreamSynchronize(A.stream);
+      if (prec) (void)hipStreamSynchronize(prec->P.stream);
+      op->G.release();
+      throw;
+    }
     A.sync();
+    if (prec && prec->P.stream != A.stream) prec->P.sync();
+    op->G.release();   // the Krylov storage is not kept between calls
     A.st.gmres_iters = r.iters;
     A.st.gmres_relres = r.relres;
     if (iters_out) *iters_out = r.iters;

@@ -155,6 +155,7 @@ struct Problem {
   KernelFn kf{};
   ChebConst cc{};
   hipStream_t stream = nullptr;
+  int device = 0;                  // HIP device current at the build
   MemAccount mem;
   Staging stage;
   HostProf hprof;

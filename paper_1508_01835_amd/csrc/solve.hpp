@@ -380,8 +380,7 @@ inline SolvePlan<T>& solve_plan(Problem& P, FactorStore<T>& F, SolvePlan<T>& S) 
 }
 
 template <class T, int NR>
-inline void solve_pass(Problem& P, SolvePlan<T>& S, T* V, int nrhs, int r0) {
-  T* Part = S.Part.template as<T>();
+inline void solve_pass(Problem& P, SolvePlan<T>& S, T* V, T* Part, int nrhs, int r0) {
   const SvNode* nodes = S.nodes.template as<SvNode>();
   for (auto& a : S.seq) {
     if (a.kind == 0) {
@@ -398,18 +397,21 @@ inline void solve_pass(Problem& P, SolvePlan<T>& S, T* V, int nrhs, int r0) {
   }
 }
 
-// x = IFMM^-1 b, b and x in caller order (float64, column-major, ld), nrhs columns.
+// Elements of the per-call storage of one call: V (S.rows x nrhs) and the
+// partial sums (part_rows x the pass width), with the pass width used.
 template <class T>
-inline void solve_impl(Problem& P, FactorStore<T>& F, SolvePlan<T>& S, const double* b, double* x, int nrhs,
-                       int64_t ld) {
-  solve_plan(P, F, S);
-  const int NRmax = 16;
+inline int solve_pass_width(int nrhs) {
+  constexpr int NRmax = 16;
   const int nr = nrhs >= NRmax ? NRmax : nrhs;
-  S.V.reserve(sizeof(T) * (size_t)std::max<int64_t>(S.rows * nrhs, 1), &P.mem);
-  S.Part.reserve(sizeof(T) * (size_t)std::max<int64_t>(S.part_rows * NRmax, 1), &P.mem);
-  T* V = S.V.template as<T>();
-  P.kset(KF_SOLVE, 2.0 * S.factor_elems * nrhs, S.factor_elems * sizeof(T));
-  P.kbegin();
+  return nr == 1 ? 1 : nr == 2 ? 2 : nr <= 4 ? 4 : nr <= 8 ? 8 : 16;
+}
+
+// The substitution proper, with caller-provided storage V (S.rows * nrhs
+// elements) and Part (S.part_rows * solve_pass_width(nrhs) elements). Launches
+// only: no allocation, no synchronisation.
+template <class T>
+inline void solve_core(Problem& P, SolvePlan<T>& S, const double* b, double* x, int nrhs, int64_t ld, T* V, T* Part) {
+  const int nw = solve_pass_width<T>(nrhs);
   const int64_t ne = P.n * nrhs;
   hipLaunchKernelGGL((k_sv_perm<double, T>), dim3((unsigned)std::max<int64_t>(1, ceil_div(ne, WG))), dim3(WG), 0,
                      P.stream, b, ld, P.perm.template as<int>(), P.n, nrhs, V, (int64_t)0, 1);
@@ -417,16 +419,29 @@ inline void solve_impl(Problem& P, FactorStore<T>& F, SolvePlan<T>& S, const dou
   if (nz > 0)
     hipLaunchKernelGGL(k_sv_zero<T>, dim3((unsigned)ceil_div(nz, WG)), dim3(WG), 0, P.stream, V + S.nL * nrhs, nz);
   IFMM_LAUNCH_CHECK();
-  for (int r0 = 0; r0 < nrhs; r0 += nr) {
-    if (nr == 1) solve_pass<T, 1>(P, S, V, nrhs, r0);
-    else if (nr == 2) solve_pass<T, 2>(P, S, V, nrhs, r0);
-    else if (nr <= 4) solve_pass<T, 4>(P, S, V, nrhs, r0);
-    else if (nr <= 8) solve_pass<T, 8>(P, S, V, nrhs, r0);
-    else solve_pass<T, 16>(P, S, V, nrhs, r0);
+  for (int r0 = 0; r0 < nrhs; r0 += nw) {
+    if (nw == 1) solve_pass<T, 1>(P, S, V, Part, nrhs, r0);
+    else if (nw == 2) solve_pass<T, 2>(P, S, V, Part, nrhs, r0);
+    else if (nw == 4) solve_pass<T, 4>(P, S, V, Part, nrhs, r0);
+    else if (nw == 8) solve_pass<T, 8>(P, S, V, Part, nrhs, r0);
+    else solve_pass<T, 16>(P, S, V, Part, nrhs, r0);
   }
   hipLaunchKernelGGL((k_sv_perm<T, double>), dim3((unsigned)std::max<int64_t>(1, ceil_div(ne, WG))), dim3(WG), 0,
                      P.stream, (const T*)V, (int64_t)0, P.perm.template as<int>(), P.n, nrhs, x, ld, 0);
   IFMM_LAUNCH_CHECK();
+}
+
+// x = IFMM^-1 b, b and x in caller order (float64, column-major, ld), nrhs
+// columns; per-call storage held by the plan (grown on demand).
+template <class T>
+inline void solve_impl(Problem& P, FactorStore<T>& F, SolvePlan<T>& S, const double* b, double* x, int nrhs,
+                       int64_t ld) {
+  solve_plan(P, F, S);
+  S.V.reserve(sizeof(T) * (size_t)std::max<int64_t>(S.rows * nrhs, 1), &P.mem);
+  S.Part.reserve(sizeof(T) * (size_t)std::max<int64_t>(S.part_rows * solve_pass_width<T>(nrhs), 1), &P.mem);
+  P.kset(KF_SOLVE, 2.0 * S.factor_elems * nrhs, S.factor_elems * sizeof(T));
+  P.kbegin();
+  solve_core(P, S, b, x, nrhs, ld, S.V.template as<T>(), S.Part.template as<T>());
   P.kend();
   P.kset(-1);
 }

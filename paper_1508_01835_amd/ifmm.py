@@ -53,8 +53,8 @@ KERNEL_OF_FAMILY = {"svd_round": "k_svd_round", "qr_panel": "k_qr_panel", "qrcp"
 
 
 EXPORTS = ["ifmm_default_options", "ifmm_build", "ifmm_factorize", "ifmm_factorize_batch", "ifmm_solve",
-           "ifmm_matvec", "ifmm_gmres", "ifmm_gmres_left", "ifmm_query", "ifmm_destroy", "ifmm_strerror",
-           "ifmm_last_error"]
+           "ifmm_matvec", "ifmm_gmres", "ifmm_gmres_left", "ifmm_query", "ifmm_query_ranks",
+           "ifmm_destroy", "ifmm_strerror", "ifmm_last_error"]
 
 
 def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
@@ -70,6 +70,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.ifmm_factorize_batch.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.c_int,
                                          ctypes.POINTER(ctypes.c_int)]
     lib.ifmm_solve.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int64]
+    lib.ifmm_query_ranks.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.c_int]
     lib.ifmm_matvec.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int64]
     lib.ifmm_gmres.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                                ctypes.c_int64, ctypes.c_double, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
@@ -84,8 +85,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.ifmm_strerror.restype = ctypes.c_char_p
     lib.ifmm_last_error.argtypes = []
     lib.ifmm_last_error.restype = ctypes.c_char_p
-    for name in ["ifmm_build", "ifmm_factorize", "ifmm_factorize_batch", "ifmm_solve", "ifmm_matvec", "ifmm_gmres",
-                 "ifmm_gmres_left", "ifmm_query", "ifmm_destroy"]:
+    for name in ["ifmm_build", "ifmm_factorize", "ifmm_factorize_batch", "ifmm_solve",
+                 "ifmm_matvec", "ifmm_gmres", "ifmm_gmres_left", "ifmm_query", "ifmm_query_ranks", "ifmm_destroy"]:
         getattr(lib, name).restype = ctypes.c_int
     return lib
 
@@ -167,6 +168,13 @@ class IFMM:
                                 B.shape[0], self.n))
         out = X.t()
         return out[:, 0] if b.dim() == 1 else out
+
+    def ranks(self, level: int) -> list:
+        """Final rank of every box of a level (ifmm_query_ranks), boxes in Morton order."""
+        nb = self.stats()["boxes"][level]
+        out = (ctypes.c_int * max(nb, 1))()
+        _check(lib().ifmm_query_ranks(self.h, int(level), out, int(nb)))
+        return [out[i] for i in range(nb)]
 
     def matvec(self, x):
         Xc = _colmajor(x, self.n)

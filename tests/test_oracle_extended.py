@@ -82,3 +82,47 @@ def test_truncation_rank_rule_strict():
     for l in a.k_init:
         assert all(x <= y for x, y in zip(a.k_init[l], b.k_init[l]))
     assert sum(map(sum, a.k_init.values())) < sum(map(sum, b.k_init.values()))
+
+
+def _box_points(tr, l, i):
+    """Tree-order indices of the points in box i of level l (leaf coordinates shifted to level l)."""
+    levL = tr.levels[tr.L]
+    shift = tr.L - l
+    box = tr.levels[l].coords[i]
+    idx = []
+    for j in range(levL.nb):
+        if np.all((levL.coords[j] >> shift) == box):
+            s = tr.leaf_points(j)
+            idx.extend(range(s.start, s.stop))
+    return np.array(idx, dtype=np.int64)
+
+
+@pytest.mark.parametrize("dim,n,depth,order,kernel,kp", [(2, 700, 4, 3, "imq", 0.02), (3, 900, 3, 3, "gauss", 0.3)])
+def test_weights_are_far_field_singular_values(dim, n, depth, order, kernel, kp):
+    """Sec. 2.2 footnote on initial weights: the weights of a box are the singular values of the block row
+    of U K V^T over its far field. Pinned against the dense A~ itself: for every box i of every level, the
+    kept weights Sigma_U equal the leading singular values of A~(points of i, points outside N(i)), and
+    Sigma_V those of A~(points outside N(i), points of i)^T. The far field outside N(i) holds the interaction
+    list and every ancestor's far field, so weights built from the level's interaction list alone fail."""
+    pts = W.uniform_cube(n, dim, 51)
+    tr = Tree(pts, depth)
+    h = H2(tr, kernel, kp, 1.0, order)
+    r2 = R2(h, 1e-9)
+    Ad = h.dense()
+    A = Ad[np.ix_(tr.perm, tr.perm)]             # tree order
+    for l in range(2, depth + 1):
+        lev = tr.levels[l]
+        for i in range(lev.nb):
+            rows = _box_points(tr, l, i)
+            near = np.concatenate([_box_points(tr, l, j) for j in lev.nbrs[i]])
+            far = np.setdiff1d(np.arange(tr.n), near)
+            k = r2.k_init[l][i]
+            for side, M in (("U", A[np.ix_(rows, far)]), ("V", A[np.ix_(far, rows)].T)):
+                s = np.linalg.svd(M, compute_uv=False) if M.size else np.zeros(0)
+                want = np.zeros(k)
+                want[:min(k, s.shape[0])] = s[:k]
+                got = (r2.SU if side == "U" else r2.SV)[l][i]
+                assert np.allclose(got, want, rtol=0, atol=1e-12 * r2.sigma0), (l, i, side)
+                # every dropped direction is at or below tau
+                if s.shape[0] > k:
+                    assert s[k] <= r2.tau * (1 + 1e-10), (l, i, side)

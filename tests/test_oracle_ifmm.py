@@ -155,3 +155,38 @@ def test_left_preconditioned_gmres_iterations_grow_with_eps():
         its.append(it)
     assert its[0] == 1
     assert its[0] <= its[1] <= its[2] and its[2] > its[0]
+
+
+@pytest.mark.parametrize("n,dim,depth,order", [(400, 2, 3, 3), (500, 3, 2, 2)])
+def test_literal_mode_exact_limit(n, dim, depth, order):
+    """The paper's own pairwise route (Alg. 2 and 3: truncated SVD of each well-separated fill, then
+    recompression of [U Sigma | U' S'] and the redirect) is exact at eps -> 0, like the aggregated one."""
+    wl = W.small_uniform(n, dim, 100 + n, depth, order, 0.0)
+    f = IFMM(wl.points, wl.kernel, wl.kparam, wl.shift, depth, order, 0.0, mode="literal")
+    f.factorize()
+    Ad = f.h2.dense()
+    b = wl.rhs[:, 0]
+    assert rel(f.solve(b), np.linalg.solve(Ad, b)) <= 1e-13 * np.linalg.cond(Ad)
+
+
+def test_literal_and_aggregated_modes_agree_to_order_eps():
+    """Aggregated recompression (one recompression per affected box and elimination) against the paper's
+    pairwise route on the same sigma_0: both solutions are within a small multiple of eps of the dense
+    solve of A~ and of each other, and their difference shrinks with eps."""
+    wl = W.small_uniform(600, 2, 301, 4, 3, 1e-6)
+    b = wl.rhs[:, 0]
+    base = IFMM(wl.points, wl.kernel, wl.kparam, wl.shift, 4, 3, 1e-6)
+    xd = np.linalg.solve(base.h2.dense(), b)
+    diffs = []
+    for eps in (1e-4, 1e-6, 1e-8):
+        xs = {}
+        for mode in ("aggregated", "literal"):
+            f = IFMM(wl.points, wl.kernel, wl.kparam, wl.shift, 4, 3, eps, sigma0=base.r2.sigma0, mode=mode)
+            f.factorize()
+            xs[mode] = f.solve(b)
+        ea, el = rel(xs["aggregated"], xd), rel(xs["literal"], xd)
+        d = rel(xs["literal"], xs["aggregated"])
+        assert ea <= 10 * eps and el <= 10 * eps, (eps, ea, el)
+        assert d <= 10 * eps, (eps, d)
+        diffs.append(d)
+    assert diffs[0] > diffs[1] > diffs[2]
