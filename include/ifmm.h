@@ -176,6 +176,24 @@ int ifmm_factorize_batch(ifmm_handle* hs, int count, int nthreads, int* status);
 int ifmm_solve(ifmm_handle h, const double* b, double* x, int nrhs, int64_t ld);
 
 /*
+ * ifmm_solve_noalloc - ifmm_solve that allocates no device memory, for
+ * callers that cannot allocate: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation. Same arguments and result as
+ * ifmm_solve (x = IFMM^-1 b; x may alias b), with these differences:
+ *   - its work storage is one fixed device array of 64 MiB per GPU, set up at
+ *     the first ifmm_build on that GPU and held until the process ends; a call
+ *     whose work exceeds it (about (rows of the substitution) x nrhs plus
+ *     partial sums, in the factor precision) fails with IFMM_ERR_ARG and
+ *     names the bytes it would need;
+ *   - every call on one GPU shares that array: calls that overlap on one GPU
+ *     (two streams, two host threads, two handles) race and must be ordered
+ *     by the caller;
+ *   - the call only enqueues work on the handle's stream and returns without
+ *     waiting; there is no non-finite check (it would need a host read).
+ */
+int ifmm_solve_noalloc(ifmm_handle h, const double* b, double* x, int nrhs, int64_t ld);
+
+/*
  * ifmm_query_ranks - final rank of every box of one level, i.e. the size of
  * y_i when box i is eliminated (Alg. 2), after the recompressions of Sec. 2.2.
  *   level  in [2, depth]

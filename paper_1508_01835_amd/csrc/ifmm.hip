@@ -128,6 +128,8 @@ void scan_factors(Problem& P, FactorStore<T>& F) {
   }
 }
 
+void* scratch_address(int device);   // allocation-free solve: address of the device's array (noalloc.hpp)
+
 }  // namespace
 
 // Two events without timing, destroyed with the scope.
@@ -206,6 +208,7 @@ int ifmm_build(const double* points, int64_t n, int dim, ifmm_kernel k, int dept
     P.stream = static_cast<hipStream_t>(o.stream);
     StreamScope ss(P.stream);
     IFMM_HIP(hipGetDevice(&P.device));
+    scratch_address(P.device);
     P.n = n;
     P.d = dim;
     P.order = cheb_order;
@@ -529,3 +532,5 @@ int ifmm_destroy(ifmm_handle h) {
 }
 
 }  // extern "C"
+
+#include "noalloc.hpp"

@@ -53,7 +53,7 @@ KERNEL_OF_FAMILY = {"svd_round": "k_svd_round", "qr_panel": "k_qr_panel", "qrcp"
 
 
 EXPORTS = ["ifmm_default_options", "ifmm_build", "ifmm_factorize", "ifmm_factorize_batch", "ifmm_solve",
-           "ifmm_matvec", "ifmm_gmres", "ifmm_gmres_left", "ifmm_query", "ifmm_query_ranks",
+           "ifmm_solve_noalloc", "ifmm_matvec", "ifmm_gmres", "ifmm_gmres_left", "ifmm_query", "ifmm_query_ranks",
            "ifmm_destroy", "ifmm_strerror", "ifmm_last_error"]
 
 
@@ -70,6 +70,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.ifmm_factorize_batch.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.c_int,
                                          ctypes.POINTER(ctypes.c_int)]
     lib.ifmm_solve.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int64]
+    lib.ifmm_solve_noalloc.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                       ctypes.c_int64]
     lib.ifmm_query_ranks.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.c_int]
     lib.ifmm_matvec.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int64]
     lib.ifmm_gmres.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
@@ -85,7 +87,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.ifmm_strerror.restype = ctypes.c_char_p
     lib.ifmm_last_error.argtypes = []
     lib.ifmm_last_error.restype = ctypes.c_char_p
-    for name in ["ifmm_build", "ifmm_factorize", "ifmm_factorize_batch", "ifmm_solve",
+    for name in ["ifmm_build", "ifmm_factorize", "ifmm_factorize_batch", "ifmm_solve", "ifmm_solve_noalloc",
                  "ifmm_matvec", "ifmm_gmres", "ifmm_gmres_left", "ifmm_query", "ifmm_query_ranks", "ifmm_destroy"]:
         getattr(lib, name).restype = ctypes.c_int
     return lib
@@ -166,6 +168,19 @@ class IFMM:
         self._inputs_ready()
         _check(lib().ifmm_solve(self.h, ctypes.c_void_p(B.data_ptr()), ctypes.c_void_p(X.data_ptr()),
                                 B.shape[0], self.n))
+        out = X.t()
+        return out[:, 0] if b.dim() == 1 else out
+
+    def solve_noalloc(self, b):
+        """ifmm_solve_noalloc: the same result as solve(), with the library's fixed device array as work
+        storage. The call only enqueues work on the handle's stream; the returned tensor is ready once that
+        stream has been synchronised (this wrapper does so)."""
+        B = _colmajor(b, self.n)
+        X = B.clone()
+        self._inputs_ready()
+        _check(lib().ifmm_solve_noalloc(self.h, ctypes.c_void_p(B.data_ptr()), ctypes.c_void_p(X.data_ptr()),
+                                        B.shape[0], self.n))
+        self.stream.synchronize()
         out = X.t()
         return out[:, 0] if b.dim() == 1 else out
 

@@ -45,5 +45,6 @@ def test_null_arguments_rejected_without_gpu_work():
     assert rc == 1 and not h.value
     assert lib.ifmm_factorize(None) == 1
     assert lib.ifmm_solve(None, None, None, 1, 1) == 1
+    assert lib.ifmm_solve_noalloc(None, None, None, 1, 1) == 1
     assert lib.ifmm_query_ranks(None, 2, None, 0) == 1
     assert lib.ifmm_destroy(None) == 0
