@@ -16,9 +16,11 @@ Paper passages followed:
     of its parent reached through the transfer, so a direction that only an
     ancestor's far field uses does not get a zero weight.
   * Sec. 2.4, eq. (methods_SVD_rank_spectralnorm): ranks are decided against
-    eps * sigma_0(E), sigma_0 the largest singular value of E. Reading: a
-    deterministic power iteration on E^T E (start vector all ones), stopped
-    when sigma changes by <= 1e-10 relatively, at most 200 iterations; the
+    eps * sigma_0(E), sigma_0 the largest singular value of E. Reading: E is
+    symmetric for the radial kernels, so sigma_0 is the largest eigenvalue
+    magnitude of E, taken from a deterministic Lanczos process on E (start
+    vector all ones; three-term recurrence; stopped when the largest Ritz
+    value magnitude changes by <= 1e-12 relatively, at most 300 steps); the
     kept directions are those with sigma strictly above
     tau = max(eps, 64 u) sigma_0 (u the unit roundoff of the factor
     precision); where U and V of a box keep different counts, both keep the
@@ -106,7 +108,7 @@ class R2:
         # --- sigma_0 and tau ----------------------------------------------------
         self.sigma0_estimated = None
         if sigma0 is None:
-            sigma0 = self.power_sigma0()
+            sigma0 = self.lanczos_sigma0()
             self.sigma0_estimated = sigma0
         self.sigma0 = float(sigma0)
         self.tau = max(eps, 64.0 * unit_roundoff) * self.sigma0
@@ -221,6 +223,35 @@ class R2:
         n = self.size()
         I = np.eye(n)
         return np.column_stack([self.apply_E(I[:, k]) for k in range(n)])
+
+    def lanczos_sigma0(self, maxit: int = 300, rtol: float = 1e-12) -> float:
+        """Largest |eigenvalue| of the symmetric E by the Lanczos process (Ritz values of the tridiagonal)."""
+        n = self.size()
+        q = np.ones(n) / np.sqrt(n)
+        q_prev = np.zeros(n)
+        alphas, betas = [], []
+        beta = 0.0
+        theta_old = None
+        theta = 0.0
+        self.sigma0_steps = 0
+        for k in range(maxit):
+            w = self.apply_E(q) - beta * q_prev
+            alpha = float(q @ w)
+            w = w - alpha * q
+            alphas.append(alpha)
+            T = np.diag(alphas) + np.diag(betas, 1) + np.diag(betas, -1)
+            ev = np.linalg.eigvalsh(T)
+            theta = float(max(abs(ev[0]), abs(ev[-1])))
+            self.sigma0_steps = k + 1
+            if theta_old is not None and abs(theta - theta_old) <= rtol * theta:
+                break
+            theta_old = theta
+            beta = float(np.linalg.norm(w))
+            if beta == 0.0:
+                break
+            betas.append(beta)
+            q_prev, q = q, w / beta
+        return theta
 
     def power_sigma0(self, maxit: int = 200, rtol: float = 1e-10) -> float:
         n = self.size()

@@ -333,7 +333,7 @@ inline void lu_blocked(Problem& P, const std::vector<LuJob>& jobs, LuScratch& S)
     int rows = 0;
     for (const auto& q : pd) rows = std::max(rows, q.n - q.k0);
     const size_t lds = (size_t)rows * LU_NB * sizeof(T);
-    const bool inlds = lds <= LU_LDS_MAX;
+    const bool inlds = lds <= LU_LDS_MAX && !force_streamed();
     P.kbegin();
     hipLaunchKernelGGL(k_lu_panel<T>, dim3((unsigned)pd.size()), dim3(WG), inlds ? lds : 0, P.stream, dp, P.d_info,
                        inlds ? rows : 0);

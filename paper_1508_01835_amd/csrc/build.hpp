@@ -172,6 +172,22 @@ inline void build_r1(Problem& P) {
   }
 }
 
+// Leaf output (L2P + P2P): a wavefront per box when the leaves are small (at
+// most 64 points on average), a workgroup per box otherwise.
+inline void launch_l2p_p2p(Problem& P, int nrhs, const double* ubar, const double* g, const double* x, int64_t ldx,
+                           double* y, int64_t ldy, int with_far) {
+  const HTree& T = P.T;
+  const int L = P.L, nb = T.lev[L].nb;
+  if (P.n <= (int64_t)WAVE * nb)
+    hipLaunchKernelGGL(k_l2p_p2p_w, dim3((unsigned)ceil_div(nb, WG / WAVE)), dim3(WG), 0, P.stream,
+                       P.pts.as<double>(), P.leaf_start.as<int64_t>(), P.ldev[L].nb_start.as<int>(),
+                       P.ldev[L].nbr.as<int>(), nb, P.d, P.q, nrhs, P.kf, ubar, g, x, ldx, y, ldy, with_far);
+  else
+    hipLaunchKernelGGL(k_l2p_p2p, dim3(nb), dim3(WG), 0, P.stream, P.pts.as<double>(), P.leaf_start.as<int64_t>(),
+                       P.ldev[L].nb_start.as<int>(), P.ldev[L].nbr.as<int>(), nb, P.d, P.q, nrhs, P.kf, ubar, g, x,
+                       ldx, y, ldy, with_far);
+}
+
 // y = A~ x (tree order in and out), nrhs columns; x, y device, leading dim n.
 inline void matvec_tree(Problem& P, const double* x, double* y, int nrhs) {
   const int q = P.q, L = P.L, d = P.d;
@@ -223,10 +239,7 @@ inline void matvec_tree(Problem& P, const double* x, double* y, int nrhs) {
                        P.mv_g[l - 1].as<double>(), P.mv_g[l].as<double>());
     IFMM_LAUNCH_CHECK();
   }
-  hipLaunchKernelGGL(k_l2p_p2p, dim3(T.lev[L].nb), dim3(WG), 0, P.stream, P.pts.as<double>(),
-                     P.leaf_start.as<int64_t>(), P.ldev[L].nb_start.as<int>(), P.ldev[L].nbr.as<int>(),
-                     T.lev[L].nb, d, q, nrhs, P.kf, P.ubar.as<double>(), P.mv_g[L].as<double>(), x, P.n, y,
-                     P.n, 1);
+  launch_l2p_p2p(P, nrhs, P.ubar.as<double>(), P.mv_g[L].as<double>(), x, P.n, y, P.n, 1);
   IFMM_LAUNCH_CHECK();
 }
 
@@ -258,6 +271,55 @@ inline double norm2(Problem& P, const double* v, int64_t n, DevBuf& part) {
   double s = 0;
   for (double x : h) s += x;
   return std::sqrt(s);
+}
+
+constexpr int64_t WEIGHT_CHUNK = (int64_t)1 << 29;   // doubles of far-field block rows formed at a time (4 GiB)
+
+inline double dot(Problem& P, const double* a, const double* b, int64_t n, DevBuf& part) {
+  const int nb = (int)std::min<int64_t>(512, std::max<int64_t>(1, ceil_div(n, WG)));
+  part.reserve(sizeof(double) * nb, &P.mem);
+  hipLaunchKernelGGL(k_dot_partial, dim3(nb), dim3(WG), 0, P.stream, a, b, n, part.as<double>());
+  IFMM_LAUNCH_CHECK();
+  std::vector<double> h;
+  P.download(h, part.p, (size_t)nb);
+  double s = 0;
+  for (double x : h) s += x;
+  return s;
+}
+
+// Number of eigenvalues below x of the symmetric tridiagonal (diagonal a,
+// off-diagonal b) by the Sturm sequence of its LDL^T pivots.
+inline int sturm_count(const std::vector<double>& a, const std::vector<double>& b, double x) {
+  int c = 0;
+  double d = 1.0;
+  for (size_t i = 0; i < a.size(); ++i) {
+    const double off = i > 0 ? b[i - 1] * b[i - 1] : 0.0;
+    d = (a[i] - x) - (i > 0 ? off / d : 0.0);
+    if (d == 0.0) d = -1e-300;
+    if (d < 0) ++c;
+  }
+  return c;
+}
+
+// max |eigenvalue| of the symmetric tridiagonal: its smallest and largest
+// eigenvalues by bisection inside the Gershgorin interval.
+inline double tridiag_extreme_abs(const std::vector<double>& a, const std::vector<double>& b) {
+  const size_t n = a.size();
+  double lo = 0, hi = 0;
+  for (size_t i = 0; i < n; ++i) {
+    const double r = (i > 0 ? std::fabs(b[i - 1]) : 0.0) + (i + 1 < n ? std::fabs(b[i]) : 0.0);
+    lo = i == 0 ? a[i] - r : std::min(lo, a[i] - r);
+    hi = i == 0 ? a[i] + r : std::max(hi, a[i] + r);
+  }
+  auto kth = [&](int k) {   // the k-th smallest eigenvalue (0-based)
+    double l = lo, h = hi;
+    for (int t = 0; t < 200 && h - l > 1e-15 * std::max(std::fabs(l), std::fabs(h)); ++t) {
+      const double m = 0.5 * (l + h);
+      if (sturm_count(a, b, m) > k) h = m; else l = m;
+    }
+    return 0.5 * (l + h);
+  };
+  return std::max(std::fabs(kth(0)), std::fabs(kth((int)n - 1)));
 }
 
 inline void build_r2(Problem& P, double sigma0_override) {
@@ -410,7 +472,7 @@ inline void build_r2(Problem& P, double sigma0_override) {
       IFMM_LAUNCH_CHECK();
     }
   }
-  // ---- sigma_0 by power iteration on E (symmetric: E^T E = E E)
+  // ---- sigma_0: the largest eigenvalue magnitude of the symmetric E (Lanczos)
   const double t_s0 = now_ms();
   {
     std::vector<int64_t> zo(L + 1), yo(L + 1);
@@ -430,9 +492,7 @@ inline void build_r2(Problem& P, double sigma0_override) {
     for (int l = 2; l <= L; ++l)
       for (int x : R.r[l]) rmax[l] = std::max(rmax[l], x);
     auto applyE = [&](const double* in, double* out) {
-      hipLaunchKernelGGL(k_l2p_p2p, dim3(T.lev[L].nb), dim3(WG), 0, P.stream, P.pts.as<double>(),
-                         P.leaf_start.as<int64_t>(), P.ldev[L].nb_start.as<int>(), P.ldev[L].nbr.as<int>(),
-                         T.lev[L].nb, P.d, q, 1, P.kf, R.Q.as<double>(), in + zo[L], in, P.n, out, P.n, 1);
+      launch_l2p_p2p(P, 1, R.Q.as<double>(), in + zo[L], in, P.n, out, P.n, 1);
       IFMM_LAUNCH_CHECK();
       for (int l = L; l >= 2; --l) {
         const int nb = T.lev[l].nb;
@@ -459,7 +519,14 @@ inline void build_r2(Problem& P, double sigma0_override) {
     if (sigma0_override > 0) {
       P.sigma0 = sigma0_override;
     } else {
+      // Lanczos on the symmetric E from the all-ones vector (over the unknowns
+      // that exist): q_{k+1} beta_k = E q_k - alpha_k q_k - beta_{k-1} q_{k-1};
+      // sigma_0 = the largest Ritz value magnitude of the tridiagonal, stopped
+      // when it changes by <= 1e-12 relatively (at most 300 steps)
+      DevBuf u;
+      u.alloc(sizeof(double) * tot, &P.mem);
       IFMM_HIP(hipMemsetAsync(v.p, 0, sizeof(double) * tot, P.stream));
+      IFMM_HIP(hipMemsetAsync(u.p, 0, sizeof(double) * tot, P.stream));
       dim3 g;
       grid1(P.n, g);
       hipLaunchKernelGGL(k_fill, g, dim3(WG), 0, P.stream, v.as<double>(), P.n, 1.0);
@@ -474,21 +541,34 @@ inline void build_r2(Problem& P, double sigma0_override) {
       dim3 gt;
       grid1(tot, gt);
       hipLaunchKernelGGL(k_scale, gt, dim3(WG), 0, P.stream, v.as<double>(), tot, 1.0 / std::sqrt((double)cnt));
-      double s_old = -1, s = 0;
+      double* qk = v.as<double>();    // q_k
+      double* qp = u.as<double>();    // q_{k-1}, then the next q
+      double* wv = w.as<double>();
+      std::vector<double> al, be;
+      double beta = 0, theta = 0, theta_old = -1;
       int it = 0;
-      for (it = 0; it < 200; ++it) {
-        applyE(v.as<double>(), w.as<double>());
-        s = norm2(P, w.as<double>(), tot, part);
-        if (it > 0 && std::fabs(s - s_old) <= 1e-10 * s) break;
-        s_old = s;
-        applyE(w.as<double>(), v.as<double>());
-        const double nu = norm2(P, v.as<double>(), tot, part);
-        if (nu == 0.0) break;
-        hipLaunchKernelGGL(k_scale, gt, dim3(WG), 0, P.stream, v.as<double>(), tot, 1.0 / nu);
+      for (it = 0; it < 300; ++it) {
+        applyE(qk, wv);
+        // w -= beta q_{k-1}; alpha = q_k . w; w -= alpha q_k
+        hipLaunchKernelGGL(k_axpy, gt, dim3(WG), 0, P.stream, wv, (const double*)qp, tot, -beta);
+        const double alpha = dot(P, qk, wv, tot, part);
+        hipLaunchKernelGGL(k_axpy, gt, dim3(WG), 0, P.stream, wv, (const double*)qk, tot, -alpha);
+        IFMM_LAUNCH_CHECK();
+        al.push_back(alpha);
+        theta = tridiag_extreme_abs(al, be);
+        if (it > 0 && std::fabs(theta - theta_old) <= 1e-12 * theta) break;
+        theta_old = theta;
+        beta = norm2(P, wv, tot, part);
+        if (beta == 0.0) break;
+        be.push_back(beta);
+        // q_{k-1} <- q_k, q_k <- w / beta
+        hipLaunchKernelGGL(k_copy_scaled, gt, dim3(WG), 0, P.stream, qp, (const double*)wv, tot, 1.0 / beta);
+        IFMM_LAUNCH_CHECK();
+        std::swap(qk, qp);
       }
-      P.sigma0 = s;
-      P.sigma0_estimated = s;
-      P.sigma0_iters = it;
+      P.sigma0 = theta;
+      P.sigma0_estimated = theta;
+      P.sigma0_iters = std::min(it + 1, 300);
     }
   }
   P.st.t_sigma0_ms = now_ms() - t_s0;
@@ -529,15 +609,29 @@ inline void build_r2(Problem& P, double sigma0_override) {
     dwoff[l] = up(P, woff[l]);
     dgcols[l] = up(P, gcols[l]);
     DevBuf dm = up(P, moff), dmr = up(P, mrows);
+    // the far-field block rows are formed and factorized in chunks of boxes of
+    // at most WEIGHT_CHUNK doubles (their total reaches a hundred GB at 2^20 points)
+    std::vector<int> cut(1, 0);
+    for (int i = 0; i < lv.nb; ++i) {
+      const int64_t sz = (int64_t)mrows[i] * r[i];
+      if (i > cut.back() && moff[i] + sz - moff[cut.back()] > WEIGHT_CHUNK) cut.push_back(i);
+    }
+    cut.push_back(lv.nb);
+    int64_t mchunk = 1;
+    for (size_t c = 0; c + 1 < cut.size(); ++c)
+      mchunk = std::max<int64_t>(mchunk, (cut[c + 1] < lv.nb ? moff[cut[c + 1]] : mt) - moff[cut[c]]);
     DevBuf Mw, Rw, Bw;
-    Mw.alloc(sizeof(double) * std::max<int64_t>(mt, 1), &P.mem);
+    Mw.alloc(sizeof(double) * mchunk, &P.mem);
     Rw.alloc(sizeof(double) * std::max<int64_t>(wt, 1), &P.mem);
     Bw.alloc(sizeof(double) * std::max<int64_t>(wt, 1), &P.mem);
-    for (int side = 0; side < 2; ++side) {
+    for (int side = 0; side < 2; ++side)
+     for (size_t ch = 0; ch + 1 < cut.size(); ++ch) {
+      const int i0 = cut[ch], i1 = cut[ch + 1];
+      double* Mbase = Mw.as<double>() - moff[i0];   // Mbase + moff[i] lies in the chunk buffer for i in [i0, i1)
       DevBuf& G = side ? GV[l] : GU[l];
       DevBuf& W = side ? WV[l] : WU[l];
       DevBuf& S = side ? SV[l] : SU[l];
-      hipLaunchKernelGGL(k_weight_rows, dim3(lv.nb), dim3(WG), 0, P.stream, P.ldev[l].in_start.as<int>(),
+      hipLaunchKernelGGL(k_weight_rows, dim3((unsigned)(i1 - i0)), dim3(WG), 0, P.stream, P.ldev[l].in_start.as<int>(),
                          P.ldev[l].inter.as<int>(), nullptr, lv.nb, side, P.ldev[l].in_rev.as<int>(),
                          R.Kpre[l].as<double>(), R.dkpoff[l].as<int64_t>(), R.dr[l].as<int>(),
                          l > 2 ? P.ldev[l].parent.as<int>() : nullptr, R.Pst.as<double>(),
@@ -545,17 +639,17 @@ inline void build_r2(Problem& P, double sigma0_override) {
                          l > 2 ? R.dr[l - 1].as<int>() : nullptr,
                          l > 2 ? (side ? GV[l - 1].as<double>() : GU[l - 1].as<double>()) : nullptr,
                          l > 2 ? dwoff[l - 1].as<int64_t>() : nullptr, l > 2 ? dgcols[l - 1].as<int>() : nullptr,
-                         Mw.as<double>(), dm.as<int64_t>(), dmr.as<int>());
+                         Mbase, dm.as<int64_t>(), dmr.as<int>(), i0);
       IFMM_LAUNCH_CHECK();
       std::vector<QrDesc> qd;
       CopyBatch<double, double> tb;
       std::vector<SvdDesc> sd;
       CopyBatch<double, double> gbat;
-      for (int i = 0; i < lv.nb; ++i) {
+      for (int i = i0; i < i1; ++i) {
         const int kq = gcols[l][i];
         if (kq == 0) continue;
         QrDesc dd;
-        dd.A = Mw.as<double>() + moff[i];
+        dd.A = Mbase + moff[i];
         dd.R = Rw.as<double>() + woff[l][i];
         dd.Q = nullptr;
         dd.M = mrows[i]; dd.N = r[i]; dd.lda = mrows[i]; dd.ldr = kq; dd.ldq = 1; dd.pad = 0;
@@ -575,6 +669,7 @@ inline void build_r2(Problem& P, double sigma0_override) {
       run_copy(P, tb, dscr);
       run_svd<double>(P, sd, dscr);
       run_copy(P, gbat, dscr);
+      P.sync();   // the chunk buffer is refilled by the next chunk
     }
     P.download(hsu[l], SU[l].p, (size_t)std::max<int64_t>(stt, 1));
     P.download(hsv[l], SV[l].p, (size_t)std::max<int64_t>(stt, 1));

@@ -17,7 +17,14 @@
 
 namespace ifmm {
 
-constexpr int MAXDIM = 1024;    // largest x~ size and rank capacity of a box
+constexpr double RT_GEMM_WORK = 64.0 * 64 * 64;   // r_j / t_j by batched GEMMs above this kq r m_j
+constexpr double CLASS_BYTES = 6.0e9;   // transient bytes of one batch of a colour class (the class is split above)
+constexpr int CAP_MAX = 4096;   // largest rank capacity of a box (the basis-change kernels stage r rows in LDS)
+
+// Capacity of y_i (rows of its K edges, columns of U_i / V_i) for a rank k,
+// at most the box's x~ size: room for some growth, so that a recompression
+// that adds a few directions does not re-lay out the box's edges.
+inline int cap_for_rank(int k, int m) { return std::min(m, k + std::max(4, k / 4)); }
 
 template <class T>
 struct LevelPool {
@@ -29,7 +36,8 @@ struct LevelPool {
   // (column), CSR; built on first use, the edge tables of a level are fixed
   std::vector<int> erow_start, erow, ecol_start, ecol;
   DevBuf derow_start, derow, decol_start, decol;
-  int64_t size = 0;
+  int64_t size = 0;       // elements of the pool in use (slots are appended; a grown box leaves its old slots)
+  int64_t capacity = 0;   // elements allocated
   DevBuf pool;
   DevBuf dm, dcap, dr, drnew, dKt, dB7, dSt, dXYt, dYXt, dUo, dVo, dSUo, dSVo, dPUo, dPVo, drpar, dparent;
   T* P() const { return pool.template as<T>(); }
@@ -205,6 +213,12 @@ __global__ void k_top_gather(int nb, const int* __restrict__ coords, int d, int 
   }
 }
 
+// table[upd[2t]] = upd[2t + 1] for every pair t (offset-table updates of grown boxes).
+__global__ void k_scatter_offsets(const int64_t* __restrict__ upd, int64_t n, int64_t* __restrict__ table) {
+  const int64_t t = (int64_t)blockIdx.x * WG + threadIdx.x;
+  if (t < n) table[upd[2 * t]] = upd[2 * t + 1];
+}
+
 // ---------------------------------------------------------------- host logic
 template <class T>
 struct Factorizer {
@@ -227,13 +241,13 @@ struct Factorizer {
     L.r = r0;
     L.cap.resize(lv.nb);
     for (int i = 0; i < lv.nb; ++i) {
-      if (m[i] > MAXDIM)
-        fail(IFMM_ERR_ARG, "a box at level " + std::to_string(l) + " has " + std::to_string(m[i]) +
-                               " unknowns (limit " + std::to_string(MAXDIM) + "): use a deeper tree or a looser eps");
-      int c = m[i];
+      // sized for the present rank (grown by grow_boxes when a recompression needs more)
+      int c = cap_for_rank(r0[i], m[i]);
       if (P.rank_max > 0) c = std::min(c, P.rank_max);
       L.cap[i] = std::max(c, r0[i]);
-      if (L.cap[i] > MAXDIM) fail(IFMM_ERR_ARG, "rank capacity above the limit");
+      if (L.cap[i] > CAP_MAX)
+        fail(IFMM_ERR_ARG, "a basis at level " + std::to_string(l) + " needs " + std::to_string(L.cap[i]) +
+                               " columns (limit " + std::to_string(CAP_MAX) + ")");
     }
     L.rpar.assign(lv.nb, 0);
     if (l > 2)
@@ -273,12 +287,112 @@ struct Factorizer {
       for (int t = lv.in_start[i]; t < lv.in_start[i + 1]; ++t) addK(lv.inter[t]);
     }
     L.size = o;
-    L.pool.alloc(sizeof(T) * std::max<int64_t>(o, 2), &P.mem);
-    IFMM_HIP(hipMemsetAsync(L.pool.p, 0, sizeof(T) * std::max<int64_t>(o, 2), P.stream));
+    L.capacity = std::max<int64_t>(o + o / 8, 2);   // some room for boxes that grow
+    L.pool.alloc(sizeof(T) * L.capacity, &P.mem);
+    IFMM_HIP(hipMemsetAsync(L.pool.p, 0, sizeof(T) * L.capacity, P.stream));
     P.upload(L.dm, L.m); P.upload(L.dcap, L.cap); P.upload(L.dr, L.r); P.upload(L.drnew, L.r);
     P.upload(L.dKt, L.Kt); P.upload(L.dB7, L.B7); P.upload(L.dSt, L.St); P.upload(L.dXYt, L.XYt);
     P.upload(L.dYXt, L.YXt); P.upload(L.dUo, L.Uo); P.upload(L.dVo, L.Vo); P.upload(L.dSUo, L.SUo);
     P.upload(L.dSVo, L.SVo); P.upload(L.dPUo, L.PUo); P.upload(L.dPVo, L.PVo); P.upload(L.drpar, L.rpar);
+  }
+
+  // Give the boxes of `want` (box, new capacity) larger y capacities: new
+  // slots for U, V, the weights, the parent transfers and every K edge in
+  // which they take part (copied, leading dimensions adjusted), and for the
+  // x~-y fill blocks XY / YX of their y (zero: a box that grows is not yet
+  // eliminated). Old slots stay unused until the level is released. The pool
+  // is reallocated (and copied) when the new slots do not fit.
+  void grow_boxes(LevelPool<T>& L, const std::vector<std::pair<int, int>>& want) {
+    if (want.empty()) return;
+    const HLevel& lv = P.T.lev[L.l];
+    std::vector<int> nc = L.cap;
+    std::vector<char> g(L.nb, 0);
+    for (const auto& w : want) {
+      if (w.second > CAP_MAX)
+        fail(IFMM_ERR_ARG, "a basis at level " + std::to_string(L.l) + " needs " + std::to_string(w.second) +
+                               " columns (limit " + std::to_string(CAP_MAX) + ")");
+      if (w.second > nc[w.first]) { nc[w.first] = w.second; g[w.first] = 1; }
+    }
+    int64_t o = L.size;
+    auto take = [&](int64_t n) { const int64_t a = o; o += (n + 1) & ~int64_t(1); return a; };
+    struct Mv { int64_t src, dst; int lds, ldd, rows, cols; };
+    std::vector<Mv> mv;
+    std::vector<std::pair<int64_t, int64_t>> upd7, updxy, updyx;   // (table index, new offset)
+    std::vector<int64_t> edges;                                    // row box * c7 + code of every K edge to move
+    for (int j = 0; j < L.nb; ++j) {
+      if (!g[j]) continue;
+      const int co = L.cap[j], cn = nc[j], mj = L.m[j];
+      int64_t a = take((int64_t)mj * cn);
+      mv.push_back({L.Uo[j], a, mj, mj, mj, co}); L.Uo[j] = a;
+      a = take((int64_t)mj * cn);
+      mv.push_back({L.Vo[j], a, mj, mj, mj, co}); L.Vo[j] = a;
+      a = take(cn); mv.push_back({L.SUo[j], a, co, cn, co, 1}); L.SUo[j] = a;
+      a = take(cn); mv.push_back({L.SVo[j], a, co, cn, co, 1}); L.SVo[j] = a;
+      if (L.l > 2 && L.rpar[j] > 0) {
+        a = take((int64_t)cn * L.rpar[j]); mv.push_back({L.PUo[j], a, co, cn, co, L.rpar[j]}); L.PUo[j] = a;
+        a = take((int64_t)cn * L.rpar[j]); mv.push_back({L.PVo[j], a, co, cn, co, L.rpar[j]}); L.PVo[j] = a;
+      }
+      for (int code = 0; code < L.c7; ++code) {
+        const int q = L.B7[(size_t)j * L.c7 + code];
+        if (q < 0) continue;
+        if (L.Kt[(size_t)j * L.c7 + code] >= 0) edges.push_back((int64_t)j * L.c7 + code);
+        const int back = L.c7 - 1 - code;
+        if (L.Kt[(size_t)q * L.c7 + back] >= 0) edges.push_back((int64_t)q * L.c7 + back);
+      }
+      for (int t = lv.nb_start[j]; t < lv.nb_start[j + 1]; ++t) {
+        const int q = lv.nbr[t];
+        if (q == j) continue;
+        const size_t ixy = (size_t)q * L.c3 + offset3(lv, q, j), iyx = (size_t)j * L.c3 + offset3(lv, j, q);
+        if (L.XYt[ixy] >= 0) { a = take((int64_t)L.m[q] * cn); mv.push_back({-1, a, 0, L.m[q], L.m[q], cn}); L.XYt[ixy] = a; updxy.push_back({(int64_t)ixy, a}); }
+        if (L.YXt[iyx] >= 0) { a = take((int64_t)cn * L.m[q]); mv.push_back({-1, a, 0, cn, cn, L.m[q]}); L.YXt[iyx] = a; updyx.push_back({(int64_t)iyx, a}); }
+      }
+    }
+    std::sort(edges.begin(), edges.end());
+    edges.erase(std::unique(edges.begin(), edges.end()), edges.end());
+    for (int64_t e : edges) {
+      const int a = (int)(e / L.c7), code = (int)(e % L.c7);
+      const int b = L.B7[(size_t)e];
+      const int64_t d = take((int64_t)nc[a] * nc[b]);
+      mv.push_back({L.Kt[(size_t)e], d, L.cap[a], nc[a], L.cap[a], L.cap[b]});
+      L.Kt[(size_t)e] = d;
+      upd7.push_back({e, d});
+      (void)code;
+    }
+    // room for the new slots (the pool is copied when it moves), then zero them
+    const int64_t used = L.size;
+    if (o > L.capacity) {
+      DevBuf np;
+      const int64_t ncap = o + o / 4;
+      np.alloc(sizeof(T) * ncap, &P.mem);
+      IFMM_HIP(hipMemcpyAsync(np.p, L.pool.p, sizeof(T) * used, hipMemcpyDeviceToDevice, P.stream));
+      L.pool = std::move(np);
+      L.capacity = ncap;
+    }
+    IFMM_HIP(hipMemsetAsync(L.P() + used, 0, sizeof(T) * (o - used), P.stream));
+    L.size = o;
+    CopyBatch<T, T> cb;
+    for (const auto& x : mv)
+      if (x.src >= 0) cb.add(L.P() + x.src, x.lds, L.P() + x.dst, x.ldd, x.rows, x.cols);
+    run_copy(P, cb, F.d4);
+    L.cap = nc;
+    // device tables: per-box arrays whole, the offset tables by scatter
+    P.upload(L.dcap, L.cap); P.upload(L.dUo, L.Uo); P.upload(L.dVo, L.Vo); P.upload(L.dSUo, L.SUo);
+    P.upload(L.dSVo, L.SVo); P.upload(L.dPUo, L.PUo); P.upload(L.dPVo, L.PVo);
+    scatter_offsets(L.dKt, upd7);
+    scatter_offsets(L.dXYt, updxy);
+    scatter_offsets(L.dYXt, updyx);
+    ++grow_events;
+  }
+  int64_t grow_events = 0;
+
+  void scatter_offsets(DevBuf& table, const std::vector<std::pair<int64_t, int64_t>>& upd) {
+    if (upd.empty()) return;
+    DevBuf d;
+    P.upload(d, upd);
+    hipLaunchKernelGGL(k_scatter_offsets, dim3((unsigned)ceil_div((int64_t)upd.size(), WG)), dim3(WG), 0, P.stream,
+                       d.template as<const int64_t>(), (int64_t)upd.size(), table.template as<int64_t>());
+    IFMM_LAUNCH_CHECK();
+    P.sync();   // d is released on return
   }
 
   // adjacency of two offsets in {-1, 0, 1}^d (codes as offset3): |o_a - o_b| <= 1 per axis
@@ -378,8 +492,9 @@ struct Factorizer {
       c.vv = take((int64_t)mj * c.kq);
       c.su = take(c.kq);
       c.sv = take(c.kq);
-      c.tr = take((int64_t)L.cap[c.box] * L.cap[c.box]);
-      c.tt = take((int64_t)L.cap[c.box] * L.cap[c.box]);
+      c.ldt = std::max(c.kq, 1);   // r_j, t_j: (new rank <= kq) x (old rank), leading dimension kq
+      c.tr = take((int64_t)c.ldt * std::max(L.r[c.box], 1));
+      c.tt = take((int64_t)c.ldt * std::max(L.r[c.box], 1));
       c.pu = take(mj + 2);
       c.pv = take(mj + 2);
       flops_comp += 2.0 * 2.0 * c.ncols * mj * mj + 2.0 * 12.0 * (double)mj * c.kq * c.kq;
@@ -421,6 +536,7 @@ struct Factorizer {
         r.perm = perm;
         r.kout = perm + mj;
         r.m = c.kq; r.n = mj; r.ldr = c.kq; r.ldy = mj;
+        r.over = P.d_info + 1;
         pd.push_back(r);
         SvdDesc s{};
         s.B = W + (side ? c.mv : c.mu);
@@ -478,6 +594,23 @@ struct Factorizer {
     hipLaunchKernelGGL(k_comp_rank<T>, dim3((unsigned)ceil_div((int64_t)cs.size(), WG)), dim3(WG), 0, P.stream, dc,
                        (int)cs.size(), v, (const T*)W, P.tau, P.rank_max);
     IFMM_LAUNCH_CHECK();
+    // large boxes: r_j and t_j as batched products on the matrix cores, which
+    // needs the new ranks on the host
+    double rt_work = 0;
+    for (const auto& c : cs) rt_work = std::max(rt_work, (double)c.kq * L.r[c.box] * L.m[c.box]);
+    const bool rt_gemm = rt_work > RT_GEMM_WORK;
+    std::vector<int> rn;
+    {   // boxes whose new rank exceeds their capacity get larger slots first
+      bool may = false;
+      for (const auto& c : cs) may = may || c.kq > L.cap[c.box];
+      if (may || rt_gemm) P.download(rn, L.drnew.p, (size_t)L.nb);
+      if (may) {
+        std::vector<std::pair<int, int>> want;
+        for (const auto& c : cs)
+          if (rn[c.box] > L.cap[c.box]) want.push_back({c.box, cap_for_rank(rn[c.box], L.m[c.box])});
+        grow_boxes(L, want);
+      }
+    }
     if (trace_on()) {   // boxes whose common rank exceeds the resolved directions of one side
       std::vector<int> rn;
       P.download(rn, L.drnew.p, (size_t)L.nb);
@@ -502,11 +635,36 @@ struct Factorizer {
                        k > 0 ? (double)su[k - 1] / P.tau : 0.0, k > 0 ? (double)sv[k - 1] / P.tau : 0.0);
       }
     }
-    hipLaunchKernelGGL(k_comp_complete<T>, dim3((unsigned)cs.size(), 2), dim3(WG), 0, P.stream, dc, v, W,
-                       2e-6 * P.tau);
-    IFMM_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_comp_rt<T>, dim3((unsigned)cs.size()), dim3(WG), 0, P.stream, dc, v, (const T*)L.P(), W);
-    IFMM_LAUNCH_CHECK();
+    {   // work vectors of the orthonormal completion in LDS: m_j + k values
+      int64_t need = 1;
+      for (const auto& c : cs) need = std::max<int64_t>(need, (int64_t)L.m[c.box] + c.kq);
+      const size_t lds = sizeof(T) * (size_t)need;
+      if (lds > COMPLETE_LDS_MAX) fail(IFMM_ERR_ARG, "a recompressed box is too large for the completion kernel");
+      static const bool attr = [] {
+        IFMM_HIP(hipFuncSetAttribute((const void*)k_comp_complete<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)COMPLETE_LDS_MAX));
+        return true;
+      }();
+      (void)attr;
+      hipLaunchKernelGGL(k_comp_complete<T>, dim3((unsigned)cs.size(), 2), dim3(WG), lds, P.stream, dc, v, W,
+                         2e-6 * P.tau);
+      IFMM_LAUNCH_CHECK();
+    }
+    if (rt_gemm) {   // r_j = Uhat^T U_j, t_j = Vhat^T V_j: (k x m_j)(m_j x r), leading dimension ldt
+      GemmBatch g;
+      for (const auto& c : cs) {
+        const int j = c.box, k = rn[j], r = L.r[j], mj = L.m[j];
+        if (k == 0 || r == 0 || mj == 0) continue;
+        g.add(W + c.uu, mj, 1, L.P() + L.Uo[j], mj, 0, W + c.tr, c.ldt, k, r, mj, 1.0, 0.0);
+        g.add(W + c.vv, mj, 1, L.P() + L.Vo[j], mj, 0, W + c.tt, c.ldt, k, r, mj, 1.0, 0.0);
+      }
+      P.kend();   // run_gemm times its launch as a range of its own (same family)
+      run_gemm<T>(P, g, F.d5);
+      P.kbegin();
+    } else {
+      hipLaunchKernelGGL(k_comp_rt<T>, dim3((unsigned)cs.size()), dim3(WG), 0, P.stream, dc, v, (const T*)L.P(), W);
+      IFMM_LAUNCH_CHECK();
+    }
     chk(L, "comp_rt", nullptr, o);
     P.kend();
     // one task per existing edge (the host holds the edge tables); flops of the
@@ -579,8 +737,10 @@ struct Factorizer {
     for (const auto& c : cs) rmax = std::max(rmax, L.r[c.box]);
     const bool small = rmax <= XF_SMALL_R;
     int capmax = 0;
+    int64_t staged = 0;   // largest rank x parent-rank block a per-box workgroup stages
     for (int x : L.cap) capmax = std::max(capmax, x);
-    const bool perbox = capmax <= XF_BOX_R;
+    for (const auto& c : cs) staged = std::max<int64_t>(staged, (int64_t)L.cap[c.box] * L.rpar[c.box]);
+    const bool perbox = capmax <= XF_BOX_R && staged <= (int64_t)XF_BOX_R * XF_BOX_R;
     if (prow.back() > 0) {
       P.kone_begin(KF_ROW_XFORM, frow);
       if (perbox)
@@ -756,19 +916,83 @@ struct Factorizer {
     const HLevel& lv = P.T.lev[l];
     const int d = P.d;
     F.cls[l].clear();
-    F.cls[l].resize(lv.ncolour);
     for (int c = 0; c < lv.ncolour; ++c) {
-      const auto& boxes = lv.classes[c];
-      if (boxes.empty()) continue;
-      // ranks are exact on the host at the start of every class; the stream is
-      // idle, so the descriptors of the previous class can be recycled
+      if (lv.classes[c].empty()) continue;
       {
         HostScope hs(P.hprof, "class: wait + read ranks");
         P.download(L.r, L.dr.p, (size_t)lv.nb);
       }
+      // A class whose transient blocks (pivot blocks, couplings, Schur fill
+      // f x f, recompression matrices) would exceed CLASS_BYTES is taken in
+      // several batches, one after the other. The boxes of a class are an
+      // independent set, so the split leaves every elimination's F unchanged.
+      std::vector<std::vector<int>> batches(1);
+      {
+        double acc = 0;
+        for (int i : lv.classes[c]) {
+          const double est = elim_bytes(L, lv, i);
+          if (acc > 0 && acc + est > (double)CLASS_BYTES) { batches.emplace_back(); acc = 0; }
+          batches.back().push_back(i);
+          acc += est;
+        }
+      }
+      for (size_t bt = 0; bt < batches.size(); ++bt) {
+        eliminate_batch(L, batches[bt], c, bt > 0);
+        if (progress_level() >= 2) {
+          double est = 0;
+          for (int i : batches[bt]) est += elim_bytes(L, lv, i);
+          P.sync();
+          std::fprintf(stderr, "[ifmm]     level %d class %d batch %zu: %zu boxes, estimate %.2f GB, device %.2f GB "
+                       "(peak %.2f GB)\n", l, c, bt, batches[bt].size(), est * 1e-9, P.mem.cur * 1e-9,
+                       P.mem.peak * 1e-9);
+          std::fflush(stderr);
+        }
+      }
+      if (progress_on() && l <= 4) {
+        P.sync();
+        std::fprintf(stderr, "[ifmm]   level %d class %d: %zu boxes done, device %.1f GB\n", l, c,
+                     lv.classes[c].size(), P.mem.cur * 1e-9);
+        std::fflush(stderr);
+      }
+    }
+    P.download(L.r, L.dr.p, (size_t)lv.nb);
+  }
+
+  // Host estimate of the transient bytes of eliminating box i now: the class
+  // arena (2 p^2 + 3 p f), the Schur fill (f^2), the solve blocks ((m + f) m +
+  // m f) and the recompression matrices of its neighbours (about 6 (r_j + f) m_j).
+  double elim_bytes(const LevelPool<T>& L, const HLevel& lv, int i) const {
+    const double m = L.m[i], p = m + L.r[i];
+    double f = L.r[i], rec = 0;
+    for (int t = lv.nb_start[i]; t < lv.nb_start[i + 1]; ++t) {
+      const int j = lv.nbr[t];
+      if (j != i) f += std::max(L.m[j], L.cap[j]);
+    }
+    for (int t = lv.nb_start[i]; t < lv.nb_start[i + 1]; ++t) {
+      const int j = lv.nbr[t];
+      if (j != i) rec += 6.0 * (L.r[j] + f) * L.m[j];
+    }
+    return sizeof(T) * (2 * p * p + 3 * p * f + f * f + (m + f) * m + m * f + rec);
+  }
+
+  // Eliminate the boxes of one batch of colour class c (all of it, or a part
+  // when the class is split); `again`: a later batch of the same class, whose
+  // ranks must be read back first.
+  void eliminate_batch(LevelPool<T>& L, const std::vector<int>& boxes, int c, bool again) {
+    const int l = L.l;
+    const HLevel& lv = P.T.lev[l];
+    const int d = P.d;
+    {
+      if (again) {
+        HostScope hs(P.hprof, "class: wait + read ranks");
+        P.download(L.r, L.dr.p, (size_t)lv.nb);
+      }
+      // ranks are exact on the host at the start of every batch; the stream is
+      // idle, so the descriptors of the previous batch can be recycled
       P.arena_reset();
       HostScope hs_plan(P.hprof, "class: plan");
-      ClassFactors<T>& cf = F.cls[l][c];
+      F.cls[l].emplace_back();
+      ClassFactors<T>& cf = F.cls[l].back();
       std::vector<ElimDesc>& el = cf.el;
       std::vector<FNode>& Fs = cf.F;
       el.clear();
@@ -953,9 +1177,10 @@ struct Factorizer {
       HostScope hs_red(P.hprof, "class: redirect");
       chk(L, "recompress", nullptr, 0);
       {   // coarse levels (large ranks): batched products; fine levels: one workgroup per pair on the device
-        int rmax = 0;
+        int rmax = 0, mmax = 0;
         for (int x : L.cap) rmax = std::max(rmax, x);
-        if (rmax > XF_SMALL_R) {
+        for (int x : L.m) mmax = std::max(mmax, x);
+        if (rmax > XF_SMALL_R || mmax > REDIRECT_MAXM || force_streamed()) {
           redirect(L, el, Fs, lv);
         } else {
           P.kset(KF_XFORM);
@@ -969,7 +1194,6 @@ struct Factorizer {
       }
       if (debug_on()) debug_class(L, cf, c);
     }
-    P.download(L.r, L.dr.p, (size_t)lv.nb);
   }
 
   // ---------------------------------------------------- merge into l - 1
@@ -1072,9 +1296,16 @@ struct Factorizer {
     F.cls.resize(Lv + 1);
     F.sl.assign(Lv + 1, SolveLevel<T>());
     auto cur = std::make_unique<LevelPool<T>>();
+    const double t0 = now_ms();
     {
       HostScope hs(P.hprof, "setup leaf level");
       setup_leaf(*cur);
+    }
+    if (progress_on()) {
+      P.sync();
+      std::fprintf(stderr, "[ifmm] leaf level set up: pool %.2f GB, device %.2f GB (peak %.2f GB)\n",
+                   cur->capacity * sizeof(T) * 1e-9, P.mem.cur * 1e-9, P.mem.peak * 1e-9);
+      std::fflush(stderr);
     }
     for (int l = Lv; l >= 2; --l) {
       P.trace_level = l;
@@ -1086,6 +1317,16 @@ struct Factorizer {
       double sum = 0;
       for (int x : cur->r) { P.st.max_rank[l] = std::max(P.st.max_rank[l], x); sum += x; }
       P.st.mean_rank[l] = cur->nb ? sum / cur->nb : 0.0;
+      if (progress_on()) {
+        int mmax = 0;
+        for (int x : cur->m) mmax = std::max(mmax, x);
+        std::fprintf(stderr,
+                     "[ifmm] level %d eliminated: %d boxes in %zu batches, largest x~ %d, max rank %d, mean %.1f, "
+                     "grown boxes %lld, %.1f s, device %.1f GB (peak %.1f GB)\n",
+                     l, cur->nb, F.cls[l].size(), mmax, P.st.max_rank[l], P.st.mean_rank[l], (long long)grow_events,
+                     (now_ms() - t0) * 1e-3, P.mem.cur * 1e-9, P.mem.peak * 1e-9);
+        std::fflush(stderr);
+      }
       if (l > 2) {
         HostScope hs(P.hprof, "merge");
         auto nxt = std::make_unique<LevelPool<T>>();
@@ -1102,7 +1343,10 @@ struct Factorizer {
       P.sync();
     }
     std::vector<int> info;
-    P.download(info, P.d_info, 1);
+    P.download(info, P.d_info, 2);
+    if (info[1] != -1)
+      fail(IFMM_ERR_ARG, "a recompression kept more than " + std::to_string(SVD_MAXK) +
+                             " directions (the largest rank the SVD kernels take)");
     if (info[0] != -1) {
       P.st.error_level = info[0] == 999999999 ? 1 : info[0] / 1000000;
       P.st.error_box = info[0] == 999999999 ? -1 : info[0] % 1000000;

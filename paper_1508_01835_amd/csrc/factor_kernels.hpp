@@ -156,9 +156,9 @@ struct CompDesc {
   int64_t ru, rv;              // workspace offsets of R factors / B = R^T (m_j x kq)
   int64_t uu, vv;              // workspace offsets of the left singular vectors (m_j x kq, ld m_j)
   int64_t su, sv;              // workspace offsets of the singular values (kq)
-  int64_t tr, tt;              // workspace offsets of r_j (k x r, ld cap) and t_j
+  int64_t tr, tt;              // workspace offsets of r_j (k x r, ld ldt) and t_j
   int64_t pu, pv;              // workspace offsets of the pivoted-QR row permutations (m_j ints + count)
-  int kq, pad;
+  int kq, ldt;                 // kq = min(ncols, m_j) bounds the new rank; ldt = max(kq, 1)
 };
 
 constexpr int COMP_ROWS = 32;   // rows of a recompression matrix gathered by one workgroup
@@ -217,8 +217,7 @@ __global__ void k_comp_rank(const CompDesc* __restrict__ cs, int nc, LevelView l
   }
   int k = ku > kv ? ku : kv;
   if (rank_max > 0 && k > rank_max) k = rank_max;
-  if (k > lv.cap[c.box]) k = lv.cap[c.box];
-  lv.rnew[c.box] = k;
+  lv.rnew[c.box] = k;   // the host grows the box's capacity to k before the basis changes
 }
 
 // The common rank k may exceed the number of resolved singular directions of
@@ -228,11 +227,15 @@ __global__ void k_comp_rank(const CompDesc* __restrict__ cs, int nc, LevelView l
 // largest component outside the columns kept so far (1 - sum_a U[i, a]^2 is
 // largest), orthogonalised twice against them and normalised; its singular
 // value is 0. blockIdx.y = side (0: U, 1: V).
+constexpr size_t COMPLETE_LDS_MAX = 144 * 1024;   // dynamic LDS of k_comp_complete: m_j + k values
+
 template <class T>
 __global__ void __launch_bounds__(WG) k_comp_complete(const CompDesc* __restrict__ cs, LevelView lv,
                                                       T* __restrict__ work, double good_level) {
-  __shared__ T v[1024];
-  __shared__ T coef[1024];
+  extern __shared__ unsigned char cc_dyn[];
+  const CompDesc c0 = cs[blockIdx.x];
+  T* v = reinterpret_cast<T*>(cc_dyn);      // m_j values
+  T* coef = v + lv.m[c0.box];               // k values
   __shared__ T red[WG / WAVE];
   __shared__ T bv[WG / WAVE];
   __shared__ int bi[WG / WAVE];
@@ -313,8 +316,8 @@ __global__ void __launch_bounds__(WG) k_comp_rt(const CompDesc* __restrict__ cs,
       su += Uh[i + (int64_t)a * mj] * U[i + (int64_t)b * mj];
       sv += Vh[i + (int64_t)a * mj] * V[i + (int64_t)b * mj];
     }
-    work[c.tr + a + (int64_t)b * cap] = su;
-    work[c.tt + a + (int64_t)b * cap] = sv;
+    work[c.tr + a + (int64_t)b * c.ldt] = su;
+    work[c.tt + a + (int64_t)b * c.ldt] = sv;
   }
 }
 
@@ -393,7 +396,7 @@ __global__ void __launch_bounds__(BS) k_row_xform(const CompDesc* __restrict__ c
 #pragma unroll
       for (int cc = 0; cc < XF_CHUNK; ++cc) acc[cc] = 0;
       for (int b = 0; b < r; ++b) {
-        const T x = X[i + (int64_t)b * cap];
+        const T x = X[i + (int64_t)b * c.ldt];
 #pragma unroll
         for (int cc = 0; cc < XF_CHUNK; ++cc)
           if (cc < nc) acc[cc] += x * sh[b + cc * r];
@@ -444,7 +447,7 @@ __global__ void __launch_bounds__(BS) k_col_xform(const CompDesc* __restrict__ c
 #pragma unroll
       for (int ii = 0; ii < XF_CHUNK; ++ii) acc[ii] = 0;
       for (int b = 0; b < r; ++b) {
-        const T x = X[a + (int64_t)b * capj];
+        const T x = X[a + (int64_t)b * c.ldt];
 #pragma unroll
         for (int ii = 0; ii < XF_CHUNK; ++ii)
           if (ii < nr) acc[ii] += sh[ii + b * hmax] * x;
@@ -483,8 +486,8 @@ __global__ void __launch_bounds__(256) k_row_xform_box(const CompDesc* __restric
   const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
   for (int e = threadIdx.x; e < k * r; e += 256) {
     const int i = e % k, b = e / k;
-    Xr[i + b * R] = work[c.tr + i + (int64_t)b * cap];
-    Xt[i + b * R] = work[c.tt + i + (int64_t)b * cap];
+    Xr[i + b * R] = work[c.tr + i + (int64_t)b * c.ldt];
+    Xt[i + b * R] = work[c.tt + i + (int64_t)b * c.ldt];
   }
   __syncthreads();
   const int e0 = xt.estart[j], ne = xt.estart[j + 1] - e0;
@@ -535,7 +538,7 @@ __global__ void __launch_bounds__(256) k_col_xform_box(const CompDesc* __restric
   const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
   for (int e = threadIdx.x; e < k * r; e += 256) {
     const int a = e % k, b = e / k;
-    Xt[a + b * R] = work[c.tt + a + (int64_t)b * capj];
+    Xt[a + b * R] = work[c.tt + a + (int64_t)b * c.ldt];
   }
   __syncthreads();
   const int e0 = xt.estart[j], ne = xt.estart[j + 1] - e0;
@@ -588,6 +591,8 @@ __global__ void k_commit_ranks(const CompDesc* __restrict__ cs, int nc, LevelVie
   if (t < nc) lv.r[cs[t].box] = lv.rnew[cs[t].box];
 }
 
+constexpr int REDIRECT_MAXM = 1024;   // largest x~ size of a box for k_redirect (LDS rows of D Vb)
+
 // Redirect the compressed well-separated fill through K (eq. K_kj_update and
 // Alg. 3): K(a, b) += op_a(D(a, b)) op_b with op = Uhat^T on an x~ row side
 // and Vhat on an x~ column side. blockIdx.x: elimination; blockIdx.y: pair.
@@ -611,7 +616,7 @@ __global__ void __launch_bounds__(WG) k_redirect(const ElimDesc* __restrict__ es
   const T* Ua = A.type == 0 ? pool + lv.Uo[A.box] : nullptr;
   const T* Vb = B.type == 0 ? pool + lv.Vo[B.box] : nullptr;
   const int ma = A.dim, mb = B.dim;
-  __shared__ T sh[8 * 1024];
+  __shared__ T sh[8 * REDIRECT_MAXM];
   T* out = pool + dst;
   // rows of (D Vb) in chunks of 8, then Ua^T times them
   for (int a0 = 0; a0 < ka; a0 += 8) {

@@ -300,6 +300,69 @@ __global__ void __launch_bounds__(WG) k_l2p_p2p(const double* __restrict__ pts, 
   }
 }
 
+// The same product with one wavefront per leaf box (four boxes per
+// workgroup), for leaves of a few points: lanes split over (target, source
+// subset). A target gets G = 64 / min(64, pow2ceil(m)) lanes, lane sub of a
+// target takes the sources sub, sub + G, ... of every neighbour in turn, and
+// the G partial sums are added by a butterfly inside the lane group. The
+// order of every sum depends on the box sizes only, so each right-hand side
+// gets the same result whatever the number of right-hand sides.
+__global__ void __launch_bounds__(WG) k_l2p_p2p_w(const double* __restrict__ pts, const int64_t* __restrict__ leaf_start,
+                                                  const int* __restrict__ nb_start, const int* __restrict__ nbr,
+                                                  int nb, int d, int q, int nrhs, KernelFn kf,
+                                                  const double* __restrict__ ubar, const double* __restrict__ g,
+                                                  const double* __restrict__ x, int64_t ldx, double* __restrict__ y,
+                                                  int64_t ldy, int with_far) {
+  const int lane = threadIdx.x % WAVE;
+  const int i = (int)blockIdx.x * (WG / WAVE) + (int)(threadIdx.x / WAVE);
+  if (i >= nb) return;   // whole wavefronts leave together; no barrier below
+  const int64_t s = leaf_start[i];
+  const int m = (int)(leaf_start[i + 1] - s);
+  int mt = 1;
+  while (mt < m && mt < WAVE) mt <<= 1;
+  const int G = WAVE / mt;          // lanes per target
+  const int tp = WAVE / G;          // targets per pass
+  const int sub = lane % G;
+  const int t0 = nb_start[i], t1 = nb_start[i + 1];
+  for (int rr = 0; rr < nrhs; ++rr) {
+    for (int a0 = 0; a0 < m; a0 += tp) {
+      const int a = a0 + lane / G;
+      const bool act = a < m;
+      double acc = 0;
+      if (act) {
+        double xa[3] = {0, 0, 0};
+        for (int k = 0; k < d; ++k) xa[k] = pts[(s + a) * d + k];
+        for (int t = t0; t < t1; ++t) {
+          const int j = nbr[t];
+          const int64_t sj = leaf_start[j];
+          const int mj = (int)(leaf_start[j + 1] - sj);
+          for (int u = sub; u < mj; u += G) {
+            double r2 = 0;
+            for (int k = 0; k < d; ++k) {
+              const double df = xa[k] - pts[(sj + u) * d + k];
+              r2 += df * df;
+            }
+            double kv = kappa(kf, sqrt(r2));
+            if (sj + u == s + a) kv += kf.shift;
+            acc += kv * x[(sj + u) + (int64_t)rr * ldx];
+          }
+        }
+      }
+      for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, WAVE);
+      if (act && sub == 0) {
+        if (with_far) {
+          const double* U = ubar + s * q;
+          const double* gi = g + (int64_t)i * q * nrhs + (int64_t)rr * q;
+          double far = 0;
+          for (int mm = 0; mm < q; ++mm) far += U[a + (int64_t)mm * m] * gi[mm];
+          acc += far;
+        }
+        y[(s + a) + (int64_t)rr * ldy] = acc;
+      }
+    }
+  }
+}
+
 // caller order <-> tree order
 __global__ void k_perm_gather(const double* __restrict__ src, int64_t lds, const int* __restrict__ perm,
                               int64_t n, int nrhs, double* __restrict__ dst, int64_t ldd) {

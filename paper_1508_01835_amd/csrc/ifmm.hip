@@ -227,9 +227,22 @@ int ifmm_build(const double* points, int64_t n, int dim, ifmm_kernel k, int dept
     P.d_info = P.info_buf.as<int>();
     IFMM_HIP(hipMemsetAsync(P.d_info, 0xff, sizeof(int) * 4, P.stream));
     const double t0 = now_ms();
+    auto phase = [&](const char* what) {
+      if (!progress_on()) return;
+      P.sync();
+      std::fprintf(stderr, "[ifmm] build: %s done, %.1f s, device %.1f GB\n", what, (now_ms() - t0) * 1e-3,
+                   P.mem.cur * 1e-9);
+      std::fflush(stderr);
+    };
     build_tree(P, points, depth, o.leaf_max);
+    phase("tree");
     build_r1(P);
+    phase("H2 operators");
     build_r2(P, o.sigma0_override);
+    if (progress_on())
+      std::fprintf(stderr, "[ifmm] build: sigma_0 %.6e in %d Lanczos steps, %.1f s\n", P.sigma0, P.sigma0_iters,
+                   P.st.t_sigma0_ms * 1e-3);
+    phase("weighted system");
     P.st.t_build_ms = now_ms() - t0;
     *out = h;
   });

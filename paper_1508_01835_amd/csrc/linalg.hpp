@@ -116,6 +116,25 @@ struct GemmDesc {
 constexpr int GT = 64;   // output tile edge
 constexpr int GK = 16;   // K chunk
 
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// One 16 x 16 x 4 matrix-core step in the precision of T (FP32 accumulates in
+// FP32, FP64 in FP64). Both take from lane l the entry A[l % 16][l / 16] of a
+// 16 x 4 slice and B[l / 16][l % 16] of a 4 x 16 slice. Their outputs are laid
+// out differently: lane l's register r holds D[4 r + l / 16][l % 16] for
+// v_mfma_f64_16x16x4f64 and D[4 (l / 16) + r][l % 16] for
+// v_mfma_f32_16x16x4f32 (both checked on the device).
+__device__ inline v4d mfma16(double a, double b, v4d c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+__device__ inline v4f mfma16(float a, float b, v4f c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+template <class T>
+__device__ inline int mfma16_row(int lane, int r) {
+  return std::is_same<T, double>::value ? 4 * r + (lane >> 4) : 4 * (lane >> 4) + r;
+}
+
+// Batched GEMM on the matrix cores: a 64 x 64 output tile per workgroup, each
+// wavefront a 32 x 32 quarter (rows 32 (w / 2).., columns 32 (w % 2)..) as
+// 2 x 2 blocks of 16 x 16; op(A) and op(B) staged through LDS in K chunks of 16.
 template <class T>
 __global__ void __launch_bounds__(WG) k_gemm(const GemmDesc* __restrict__ ds, int nd) {
   // find the problem owning this tile (descriptors sorted by tile0)
@@ -135,16 +154,12 @@ __global__ void __launch_bounds__(WG) k_gemm(const GemmDesc* __restrict__ ds, in
   T* __restrict__ C = static_cast<T*>(d.C);
   __shared__ T As[GK][GT + 1];
   __shared__ T Bs[GK][GT + 1];
-  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;   // 16 x 16 threads, 4x4 each (vector path)
-  T acc[4][4];
+  using acc_t = typename std::conditional<std::is_same<T, double>::value, v4d, v4f>::type;
+  acc_t mfa[4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = 0;
-  typedef double v4d __attribute__((ext_vector_type(4)));
-  v4d mfa[4];   // matrix-core accumulators (FP64 path)
-#pragma unroll
-  for (int i = 0; i < 4; ++i) mfa[i] = v4d{0, 0, 0, 0};
+  for (int i = 0; i < 4; ++i) mfa[i] = acc_t{0, 0, 0, 0};
+  const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
+  const int rb0 = 32 * (wv >> 1), cb0 = 32 * (wv & 1);
   for (int k0 = 0; k0 < d.K; k0 += GK) {
     // load op(A)[m0:m0+64, k0:k0+16] and op(B)[k0:k0+16, n0:n0+64]
     for (int e = threadIdx.x; e < GT * GK; e += WG) {
@@ -165,68 +180,30 @@ __global__ void __launch_bounds__(WG) k_gemm(const GemmDesc* __restrict__ ds, in
       Bs[kk][nn] = w;
     }
     __syncthreads();
-    if constexpr (std::is_same<T, double>::value) {
-      // FP64 matrix cores: wavefront w owns rows 32 (w / 2).., columns 32 (w % 2).. of
-      // the tile as 2 x 2 blocks of 16 x 16. v_mfma_f64_16x16x4f64 takes from lane
-      // l the entry A[l % 16][l / 16] of a 16 x 4 slice and B[l / 16][l % 16] of a
-      // 4 x 16 slice, and lane l's register r holds D[4 r + l / 16][l % 16].
-      const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
-      const int rb0 = 32 * (wv >> 1), cb0 = 32 * (wv & 1);
 #pragma unroll
-      for (int k4 = 0; k4 < GK; k4 += 4) {
-        const int kk = k4 + (lane >> 4);
-        const double a0 = As[kk][rb0 + (lane & 15)], a1 = As[kk][rb0 + 16 + (lane & 15)];
-        const double b0 = Bs[kk][cb0 + (lane & 15)], b1 = Bs[kk][cb0 + 16 + (lane & 15)];
-        mfa[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, mfa[0], 0, 0, 0);
-        mfa[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, mfa[1], 0, 0, 0);
-        mfa[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, mfa[2], 0, 0, 0);
-        mfa[3] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, mfa[3], 0, 0, 0);
-      }
-    } else {
-#pragma unroll
-      for (int kk = 0; kk < GK; ++kk) {
-        T a[4], b[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) a[i] = As[kk][tx + 16 * i];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) b[j] = Bs[kk][ty + 16 * j];
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * b[j];
-      }
+    for (int k4 = 0; k4 < GK; k4 += 4) {
+      const int kk = k4 + (lane >> 4);
+      const T a0 = As[kk][rb0 + (lane & 15)], a1 = As[kk][rb0 + 16 + (lane & 15)];
+      const T b0 = Bs[kk][cb0 + (lane & 15)], b1 = Bs[kk][cb0 + 16 + (lane & 15)];
+      mfa[0] = mfma16(a0, b0, mfa[0]);
+      mfa[1] = mfma16(a0, b1, mfa[1]);
+      mfa[2] = mfma16(a1, b0, mfa[2]);
+      mfa[3] = mfma16(a1, b1, mfa[3]);
     }
     __syncthreads();
   }
   const T alpha = (T)d.alpha, beta = (T)d.beta;
-  if constexpr (std::is_same<T, double>::value) {
-    const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
-    const int rb0 = 32 * (wv >> 1), cb0 = 32 * (wv & 1);
 #pragma unroll
-    for (int blk = 0; blk < 4; ++blk) {
-      const int gn = n0 + cb0 + 16 * (blk & 1) + (lane & 15);
-      if (gn >= d.N) continue;
+  for (int blk = 0; blk < 4; ++blk) {
+    const int gn = n0 + cb0 + 16 * (blk & 1) + (lane & 15);
+    if (gn >= d.N) continue;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int gm = m0 + rb0 + 16 * (blk >> 1) + 4 * r + (lane >> 4);
-        if (gm >= d.M) continue;
-        T* c = &C[(int64_t)gm + (int64_t)gn * d.ldc];
-        const T v = mfa[blk][r];
-        *c = beta == (T)0 ? alpha * v : alpha * v + beta * (*c);
-      }
-    }
-  } else {
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int gn = n0 + ty + 16 * j;
-      if (gn >= d.N) continue;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int gm = m0 + tx + 16 * i;
-        if (gm >= d.M) continue;
-        T* c = &C[(int64_t)gm + (int64_t)gn * d.ldc];
-        *c = beta == (T)0 ? alpha * acc[i][j] : alpha * acc[i][j] + beta * (*c);
-      }
+    for (int r = 0; r < 4; ++r) {
+      const int gm = m0 + rb0 + 16 * (blk >> 1) + mfma16_row<T>(lane, r);
+      if (gm >= d.M) continue;
+      T* c = &C[(int64_t)gm + (int64_t)gn * d.ldc];
+      const T v = mfa[blk][r];
+      *c = beta == (T)0 ? alpha * v : alpha * v + beta * (*c);
     }
   }
 }

@@ -80,7 +80,7 @@ struct KTimer {
   bool on = false;
   uint32_t mask = ~0u;        // families that are timed
   bool last_on = false;       // whether the open range was recorded
-  struct Rec { int fam; hipEvent_t a, b; double flops, bytes; int64_t launches; };
+  struct Rec { int fam; hipEvent_t a, b; double flops, bytes; int64_t launches; bool closed; };
   std::vector<Rec> open;
   std::vector<hipEvent_t> pool;   // events of collected records, reused
   double ms[KF_COUNT] = {}, flops[KF_COUNT] = {}, bytes[KF_COUNT] = {};
@@ -98,7 +98,7 @@ struct KTimer {
   void begin(hipStream_t s, int fam, double fl, double by, int64_t nl = 1) {
     last_on = on && ((mask >> fam) & 1u);
     if (!last_on) return;
-    Rec r{fam, event(), event(), fl, by, nl};
+    Rec r{fam, event(), event(), fl, by, nl, false};
     IFMM_HIP(hipEventRecord(r.a, s));
     open.push_back(r);
   }
@@ -106,16 +106,24 @@ struct KTimer {
     if (!last_on || open.empty()) return;
     last_on = false;
     IFMM_HIP(hipEventRecord(open.back().b, s));
+    open.back().closed = true;
   }
   // Fold completed records into the totals (call after a stream sync).
   void collect() {
     for (auto& r : open) {
       float t = 0;
+      if (!r.closed) {   // a range left open is dropped (never queried: that would raise a HIP error)
+        pool.push_back(r.a);
+        pool.push_back(r.b);
+        continue;
+      }
       if (hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) {
         ms[r.fam] += t;
         flops[r.fam] += r.flops;
         bytes[r.fam] += r.bytes;
         launches[r.fam] += r.launches;
+      } else {
+        (void)hipGetLastError();   // not left for the caller's next HIP call to report
       }
       pool.push_back(r.a);
       pool.push_back(r.b);
@@ -269,6 +277,23 @@ inline bool debug_on() {
   static const bool on = std::getenv("IFMM_DEBUG") != nullptr;
   return on;
 }
+
+// Progress lines on stderr (IFMM_PROGRESS set in the environment): one per
+// phase of the build and per eliminated level, with the time since the call
+// began and the handle's device memory.
+inline int progress_level() {
+  const char* e = std::getenv("IFMM_PROGRESS");
+  return e ? std::max(1, std::atoi(e)) : 0;
+}
+inline bool progress_on() { return progress_level() > 0; }
+
+// Test switch (IFMM_FORCE_STREAMED set in the environment): the dense kernels
+// take the variants meant for large blocks on every size: LU panels streamed
+// from memory instead of LDS, the block-Jacobi SVD, the one-workgroup pivoted
+// QR and the redirect by batched products. Results agree with the default
+// variants to rounding; tests use it to compare those variants with the
+// oracle at sizes the oracle runs.
+inline bool force_streamed() { return std::getenv("IFMM_FORCE_STREAMED") != nullptr; }
 
 // Per-launch trace of the dense batched kernels (IFMM_TRACE=1): synchronises
 // after each launch and prints sizes and duration to stderr.

@@ -2,7 +2,8 @@
 //  * orthonormal bases by an exact QR of the Chebyshev bases, bottom-up, the
 //    R factors folded into K and the transfers (Sec. 3 opening: an SVD after
 //    interpolation reduces the rank; here the rank is min(rows, n^d));
-//  * sigma_0(E) by a deterministic power iteration (Sec. 2.4);
+//  * sigma_0(E), the largest eigenvalue magnitude of the symmetric E, by a
+//    deterministic Lanczos process (Sec. 2.4);
 //  * weights Sigma_U, Sigma_V from an SVD of each box's far-field block row /
 //    column (Sec. 2.2, footnote on initial weights), top-down so that the
 //    parent's far field is included;
@@ -207,8 +208,8 @@ __global__ void __launch_bounds__(WG) k_weight_rows(const int* __restrict__ in_s
                                                     const int* __restrict__ rpar, const double* __restrict__ Gp,
                                                     const int64_t* __restrict__ gpoff, const int* __restrict__ gpcols,
                                                     double* __restrict__ M, const int64_t* __restrict__ moff,
-                                                    const int* __restrict__ mrows) {
-  const int i = blockIdx.x;
+                                                    const int* __restrict__ mrows, int i0) {
+  const int i = i0 + (int)blockIdx.x;   // boxes i0 .. nb - 1
   if (i >= nb) return;
   const int ri = r[i];
   const int rows = mrows[i];
@@ -367,6 +368,25 @@ __global__ void k_sumsq_partial(const double* __restrict__ v, int64_t n, double*
   __shared__ double sh[WG / WAVE];
   double s = 0;
   for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < n; i += (int64_t)gridDim.x * WG) s += v[i] * v[i];
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ void k_axpy(double* __restrict__ y, const double* __restrict__ x, int64_t n, double a) {
+  const int64_t e = (int64_t)blockIdx.x * WG + threadIdx.x;
+  if (e < n) y[e] += a * x[e];
+}
+
+__global__ void k_copy_scaled(double* __restrict__ y, const double* __restrict__ x, int64_t n, double a) {
+  const int64_t e = (int64_t)blockIdx.x * WG + threadIdx.x;
+  if (e < n) y[e] = a * x[e];
+}
+
+__global__ void k_dot_partial(const double* __restrict__ a, const double* __restrict__ b, int64_t n,
+                              double* __restrict__ part) {
+  __shared__ double sh[WG / WAVE];
+  double s = 0;
+  for (int64_t e = (int64_t)blockIdx.x * WG + threadIdx.x; e < n; e += (int64_t)gridDim.x * WG) s += a[e] * b[e];
   s = block_sum(s, sh);
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }

@@ -24,6 +24,8 @@
 // (task tables) is uploaded once per factorization; a call only launches.
 #pragma once
 
+#include <map>
+
 #include "factor.hpp"
 
 namespace ifmm {
@@ -236,6 +238,21 @@ struct SolvePlan {
   int64_t launches = 0;
   bool built = false;
   DevBuf V, Part;             // per-call storage (grown on demand)
+  // The passes of a solve as replayable HIP graphs, one per right-hand-side
+  // count, captured on a stream of their own for the storage (V, Part) they
+  // were recorded with; dropped when that storage moves.
+  std::map<int, hipGraphExec_t> graphs;
+  const void* gV = nullptr;
+  const void* gPart = nullptr;
+  hipStream_t cap = nullptr;
+  void drop_graphs() {
+    for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
+    graphs.clear();
+  }
+  ~SolvePlan() {
+    drop_graphs();
+    if (cap) (void)hipStreamDestroy(cap);
+  }
 };
 
 template <class T>
@@ -409,16 +426,12 @@ inline int solve_pass_width(int nrhs) {
 // The substitution proper, with caller-provided storage V (S.rows * nrhs
 // elements) and Part (S.part_rows * solve_pass_width(nrhs) elements). Launches
 // only: no allocation, no synchronisation.
+// Every pass over the factors (forward, top, backward) for all right-hand sides, on stream st.
 template <class T>
-inline void solve_core(Problem& P, SolvePlan<T>& S, const double* b, double* x, int nrhs, int64_t ld, T* V, T* Part) {
+inline void solve_passes(Problem& P, SolvePlan<T>& S, T* V, T* Part, int nrhs, hipStream_t st) {
+  const hipStream_t keep = P.stream;
+  P.stream = st;
   const int nw = solve_pass_width<T>(nrhs);
-  const int64_t ne = P.n * nrhs;
-  hipLaunchKernelGGL((k_sv_perm<double, T>), dim3((unsigned)std::max<int64_t>(1, ceil_div(ne, WG))), dim3(WG), 0,
-                     P.stream, b, ld, P.perm.template as<int>(), P.n, nrhs, V, (int64_t)0, 1);
-  const int64_t nz = (S.rows - S.nL) * nrhs;
-  if (nz > 0)
-    hipLaunchKernelGGL(k_sv_zero<T>, dim3((unsigned)ceil_div(nz, WG)), dim3(WG), 0, P.stream, V + S.nL * nrhs, nz);
-  IFMM_LAUNCH_CHECK();
   for (int r0 = 0; r0 < nrhs; r0 += nw) {
     if (nw == 1) solve_pass<T, 1>(P, S, V, Part, nrhs, r0);
     else if (nw == 2) solve_pass<T, 2>(P, S, V, Part, nrhs, r0);
@@ -426,6 +439,59 @@ inline void solve_core(Problem& P, SolvePlan<T>& S, const double* b, double* x, 
     else if (nw == 8) solve_pass<T, 8>(P, S, V, Part, nrhs, r0);
     else solve_pass<T, 16>(P, S, V, Part, nrhs, r0);
   }
+  P.stream = keep;
+}
+
+// The same as one graph launch on the handle's stream: the hundreds of
+// dependent launches of the fine levels are recorded once per right-hand-side
+// count and replayed, so the host no longer issues them one by one. The graph
+// holds kernel nodes only. IFMM_SOLVE_GRAPH=0 turns replay off.
+inline bool solve_graph_on() {
+  const char* e = std::getenv("IFMM_SOLVE_GRAPH");
+  return !(e && e[0] == '0');
+}
+
+template <class T>
+inline void solve_passes_graph(Problem& P, SolvePlan<T>& S, T* V, T* Part, int nrhs) {
+  if (S.gV != (const void*)V || S.gPart != (const void*)Part) {
+    S.drop_graphs();
+    S.gV = V;
+    S.gPart = Part;
+  }
+  auto it = S.graphs.find(nrhs);
+  if (it == S.graphs.end()) {
+    if (!S.cap) IFMM_HIP(hipStreamCreateWithFlags(&S.cap, hipStreamNonBlocking));
+    hipGraph_t g = nullptr;
+    IFMM_HIP(hipStreamBeginCapture(S.cap, hipStreamCaptureModeThreadLocal));
+    try {
+      solve_passes(P, S, V, Part, nrhs, S.cap);
+    } catch (...) {
+      (void)hipStreamEndCapture(S.cap, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    IFMM_HIP(hipStreamEndCapture(S.cap, &g));
+    hipGraphExec_t ex = nullptr;
+    const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    IFMM_HIP(e);
+    it = S.graphs.emplace(nrhs, ex).first;
+  }
+  IFMM_HIP(hipGraphLaunch(it->second, P.stream));
+}
+
+template <class T>
+inline void solve_core(Problem& P, SolvePlan<T>& S, const double* b, double* x, int nrhs, int64_t ld, T* V, T* Part,
+                       bool graph = false) {
+  const int64_t ne = P.n * nrhs;
+  hipLaunchKernelGGL((k_sv_perm<double, T>), dim3((unsigned)std::max<int64_t>(1, ceil_div(ne, WG))), dim3(WG), 0,
+                     P.stream, b, ld, P.perm.template as<int>(), P.n, nrhs, V, (int64_t)0, 1);
+  const int64_t nz = (S.rows - S.nL) * nrhs;
+  if (nz > 0)
+    hipLaunchKernelGGL(k_sv_zero<T>, dim3((unsigned)ceil_div(nz, WG)), dim3(WG), 0, P.stream, V + S.nL * nrhs, nz);
+  IFMM_LAUNCH_CHECK();
+  if (graph) solve_passes_graph(P, S, V, Part, nrhs);
+  else solve_passes(P, S, V, Part, nrhs, P.stream);
   hipLaunchKernelGGL((k_sv_perm<T, double>), dim3((unsigned)std::max<int64_t>(1, ceil_div(ne, WG))), dim3(WG), 0,
                      P.stream, (const T*)V, (int64_t)0, P.perm.template as<int>(), P.n, nrhs, x, ld, 0);
   IFMM_LAUNCH_CHECK();
@@ -441,7 +507,7 @@ inline void solve_impl(Problem& P, FactorStore<T>& F, SolvePlan<T>& S, const dou
   S.Part.reserve(sizeof(T) * (size_t)std::max<int64_t>(S.part_rows * solve_pass_width<T>(nrhs), 1), &P.mem);
   P.kset(KF_SOLVE, 2.0 * S.factor_elems * nrhs, S.factor_elems * sizeof(T));
   P.kbegin();
-  solve_core(P, S, b, x, nrhs, ld, S.V.template as<T>(), S.Part.template as<T>());
+  solve_core(P, S, b, x, nrhs, ld, S.V.template as<T>(), S.Part.template as<T>(), solve_graph_on());
   P.kend();
   P.kset(-1);
 }

@@ -36,11 +36,15 @@ struct SvdDesc {
   int M, N, ldb, ldu;
 };
 
-__device__ inline int svd_cols(const SvdDesc& d) { return d.nlive ? max(0, min(d.N, *d.nlive)) : d.N; }
+constexpr int SVD_MAXN = 1024;   // widest problem of the step-wise pivoted QR (LDS arrays and rows per thread)
+constexpr int SVD_MAXK = 2048;   // most live columns of one Jacobi SVD (the pivoted QR keeps at most that many)
 
-constexpr int SVD_MAXN = 1024;
+// live columns: at most SVD_MAXK
+__device__ inline int svd_cols(const SvdDesc& d) {
+  return d.nlive ? max(0, min(min(d.N, SVD_MAXK), *d.nlive)) : d.N;
+}
 constexpr int SVD_WG = 1024;                // 16 wavefronts: 16 column pairs at once
-constexpr size_t SVD_LDS_MAX = 144 * 1024;  // dynamic LDS per workgroup (gfx950: 160 KB)
+constexpr size_t SVD_LDS_MAX = 128 * 1024;  // dynamic LDS per workgroup (gfx950: 160 KB, 24 KB static for the norms)
 
 // Rotates columns p and q of B (ld) when the rule above asks for it; one
 // wavefront. nrm2 holds the squared column norms: only the inner product is
@@ -131,7 +135,7 @@ __device__ inline int jacobi_sweeps(T* __restrict__ B, int64_t ld, int M, int nc
 
 // Column norms, order by decreasing norm (ties by index), U = B / norm,
 // S = norm * 2^-sh over the N live columns (rows placed through perm when
-// given); columns N..Nout-1 of U and S are zero. Whole workgroup; N <= SVD_MAXN.
+// given); columns N..Nout-1 of U and S are zero. Whole workgroup; N <= SVD_MAXK.
 template <class T>
 __device__ inline void svd_finish(const T* __restrict__ B, int64_t ldb, int M, int N, int Nout, T* __restrict__ U,
                                   int64_t ldu, T* __restrict__ S, int sh, const int* __restrict__ perm, T* nrm,
@@ -189,8 +193,8 @@ __global__ void __launch_bounds__(SVD_WG) k_svd_small(const SvdDesc* __restrict_
                                                    int* __restrict__ sweeps_out) {
   extern __shared__ unsigned char svd_dyn[];
   __shared__ T red[SVD_WG / WAVE];
-  __shared__ T nrm[SVD_MAXN];
-  __shared__ int order[SVD_MAXN];
+  __shared__ T nrm[SVD_MAXK];
+  __shared__ int order[SVD_MAXK];
   __shared__ int flag;
   const SvdDesc d = ds[blockIdx.x];
   T* Bg = static_cast<T*>(d.B);
@@ -324,8 +328,8 @@ __global__ void k_svd_sweep_end(int* __restrict__ flags, int n, int sweep, int* 
 template <class T>
 __global__ void __launch_bounds__(SVD_WG) k_svd_block_finish(const SvdDesc* __restrict__ ds,
                                                           const int* __restrict__ shs) {
-  __shared__ T nrm[SVD_MAXN];
-  __shared__ int order[SVD_MAXN];
+  __shared__ T nrm[SVD_MAXK];
+  __shared__ int order[SVD_MAXK];
   const SvdDesc d = ds[blockIdx.x];
   svd_finish(static_cast<const T*>(d.B), d.ldb, d.M, svd_cols(d), d.N, static_cast<T*>(d.U), d.ldu,
              static_cast<T*>(d.S), shs[blockIdx.x], d.perm, nrm, order);
@@ -350,13 +354,25 @@ struct QrcpDesc {
   int* perm;
   int* kout;
   int m, n, ldr, ldy;
+  int* over;   // set to 1 when more than SVD_MAXK directions stay above the stop level (the SVD takes at most that)
 };
+
+// Dynamic LDS of k_qrcp for an m x n problem: partial norms (two copies) and
+// pivots of the n columns, the Householder vector of m rows.
+template <class T>
+inline size_t qrcp_lds(int m, int n) {
+  return ((sizeof(T) * 2 + sizeof(int)) * (size_t)n + 15) / 16 * 16 + sizeof(T) * (size_t)m;
+}
+constexpr size_t QRCP_LDS_MAX = 144 * 1024;
 
 template <class T>
 __global__ void __launch_bounds__(SVD_WG) k_qrcp(const QrcpDesc* __restrict__ ds, double delta) {
-  __shared__ T vn1[SVD_MAXN], vn2[SVD_MAXN];
-  __shared__ int pv[SVD_MAXN];
-  __shared__ T hv[SVD_MAXN];
+  extern __shared__ unsigned char qrcp_dyn[];
+  const QrcpDesc d0 = ds[blockIdx.x];
+  T* vn1 = reinterpret_cast<T*>(qrcp_dyn);
+  T* vn2 = vn1 + d0.n;
+  int* pv = reinterpret_cast<int*>(vn2 + d0.n);
+  T* hv = reinterpret_cast<T*>(qrcp_dyn + ((sizeof(T) * 2 + sizeof(int)) * (size_t)d0.n + 15) / 16 * 16);
   __shared__ T redv[SVD_WG / WAVE], reds[SVD_WG / WAVE];
   __shared__ int redi[SVD_WG / WAVE];
   __shared__ T sh_tau, sh_stop;
@@ -384,8 +400,9 @@ __global__ void __launch_bounds__(SVD_WG) k_qrcp(const QrcpDesc* __restrict__ ds
   __syncthreads();
   delta = ldexp(delta, sh);
   const T tol3z = sqrt((T)Prec<T>::u);
-  const int kmax = min(m, n);
+  const int kfull = min(m, n), kmax = min(kfull, SVD_MAXK);
   int k = 0;
+  bool stopped = false;
   for (int s = 0; s < kmax; ++s) {
     // pivot = the largest remaining partial norm (first on ties); remaining Frobenius norm
     T best = (T)-1, ss = 0;
@@ -415,7 +432,7 @@ __global__ void __launch_bounds__(SVD_WG) k_qrcp(const QrcpDesc* __restrict__ ds
     }
     __syncthreads();
     const int piv = sh_piv;
-    if (piv < 0) break;
+    if (piv < 0) { stopped = true; break; }
     if (piv != s) {
       for (int i = threadIdx.x; i < m; i += SVD_WG) {
         const T a = R[i + (int64_t)s * ld];
@@ -507,6 +524,7 @@ __global__ void __launch_bounds__(SVD_WG) k_qrcp(const QrcpDesc* __restrict__ ds
   }
   for (int i = threadIdx.x; i < n; i += SVD_WG) d.perm[i] = pv[i];
   if (threadIdx.x == 0) *d.kout = k;
+  if (threadIdx.x == 0 && !stopped && k == SVD_MAXK && kmax < kfull && d.over) *d.over = 1;
 }
 
 // Sum of 16 per-lane values over the 64 lanes of a wavefront, reduce-scattered
@@ -874,29 +892,66 @@ template <class T>
 inline void run_qrcp(Problem& P, const std::vector<QrcpDesc>& v, DevBuf& scratch, DevBuf& work, double delta) {
   if (v.empty()) return;
   int64_t nblk = 0;
+  bool large = false;   // a problem beyond the step-wise kernel's LDS arrays: one workgroup per problem
+  size_t lds = 0;
   for (const auto& q : v) {
-    if (q.n > SVD_MAXN || q.m > SVD_MAXN || q.m > q.n) fail(IFMM_ERR_INTERNAL, "QRCP shape out of range");
+    if (q.m > q.n) fail(IFMM_ERR_INTERNAL, "QRCP shape out of range");
     nblk += ceil_div(q.n, QS_CB);
+    large = large || q.n > SVD_MAXN || q.m > SVD_MAXN;
+    lds = std::max(lds, qrcp_lds<T>(q.m, q.n));
   }
-  if (v.size() < 128 && nblk <= 2048) {
+  if (lds > QRCP_LDS_MAX) fail(IFMM_ERR_ARG, "a recompressed box is too large for the pivoted QR (x~ size)");
+  if (!large && !force_streamed() && v.size() < 128 && nblk <= 2048) {
     run_qrcp_steps<T>(P, v, scratch, work, delta);
     return;
   }
+  static const bool attr = [] {
+    IFMM_HIP(hipFuncSetAttribute((const void*)k_qrcp<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)QRCP_LDS_MAX));
+    return true;
+  }();
+  (void)attr;
   const QrcpDesc* d = P.put(scratch, v);
   // Householder QR flops of the untruncated factorization (m <= n): 2 n m^2 - 2/3 m^3
   double fl = 0;
   for (const auto& q : v) fl += 2.0 * q.n * (double)q.m * q.m - 2.0 / 3.0 * (double)q.m * q.m * q.m;
   P.kone_begin(KF_QRCP, fl);
-  hipLaunchKernelGGL(k_qrcp<T>, dim3((unsigned)v.size()), dim3(SVD_WG), 0, P.stream, d, delta);
+  hipLaunchKernelGGL(k_qrcp<T>, dim3((unsigned)v.size()), dim3(SVD_WG), lds, P.stream, d, delta);
   IFMM_LAUNCH_CHECK();
   P.kone_end();
+}
+
+// live[t] = the live column count of problem t (what the pivoted QR kept).
+__global__ void k_svd_live(const SvdDesc* __restrict__ ds, int n, int* __restrict__ live) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) live[t] = svd_cols(ds[t]);
 }
 
 // ------------------------------------------------------------------ launcher
 // defl: singular directions below this absolute level are not resolved (they
 // fall far under the truncation threshold and are discarded).
 template <class T>
-inline void run_svd(Problem& P, const std::vector<SvdDesc>& v, DevBuf& scratch, double defl = 0.0) {
+inline void run_svd(Problem& P, const std::vector<SvdDesc>& v_in, DevBuf& scratch, double defl = 0.0) {
+  if (v_in.empty()) return;
+  // Problems whose allocated width would send them to the block scheme: read
+  // the live column counts first (one synchronisation), so that a problem
+  // whose pivoted QR kept few columns takes the LDS scheme and the block
+  // scheme plans its rounds for the live columns only.
+  std::vector<SvdDesc> v = v_in;
+  std::vector<int> livecount(v.size(), -1);
+  {
+    bool any = false;
+    for (const auto& s : v) any = any || (s.nlive && (size_t)s.M * s.N * sizeof(T) > SVD_LDS_MAX);
+    if (any) {
+      const SvdDesc* d0 = P.put(scratch, v);
+      DevBuf lv;
+      lv.alloc(sizeof(int) * v.size(), &P.mem);
+      hipLaunchKernelGGL(k_svd_live, dim3((unsigned)ceil_div((int64_t)v.size(), 256)), dim3(256), 0, P.stream, d0,
+                         (int)v.size(), lv.as<int>());
+      IFMM_LAUNCH_CHECK();
+      P.download(livecount, lv.p, v.size());
+    }
+  }
   if (v.empty()) return;
   static const bool attr = [] {   // once per process (thread-safe initialisation)
     IFMM_HIP(hipFuncSetAttribute((const void*)k_svd_small<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -907,18 +962,21 @@ inline void run_svd(Problem& P, const std::vector<SvdDesc>& v, DevBuf& scratch, 
   }();
   (void)attr;
   std::vector<SvdDesc> small, big;
+  std::vector<int> bigN;   // columns the block scheme plans for (live when known)
   size_t lds = 0;
   int bigM = 0, bigBlocks = 0;
-  for (const auto& s : v) {
-    if (s.N > SVD_MAXN) fail(IFMM_ERR_INTERNAL, "SVD wider than SVD_MAXN");
-    const size_t b = (size_t)s.M * s.N * sizeof(T);
-    if (b <= SVD_LDS_MAX) { small.push_back(s); lds = std::max(lds, b); }
-    else { big.push_back(s); bigM = std::max(bigM, s.M); }
+  for (size_t t = 0; t < v.size(); ++t) {
+    const auto& s = v[t];
+    if (s.N > SVD_MAXN && !s.nlive) fail(IFMM_ERR_INTERNAL, "SVD wider than SVD_MAXN");
+    const int ncols = livecount[t] >= 0 ? livecount[t] : s.N;
+    const size_t b = (size_t)s.M * ncols * sizeof(T);
+    if (b <= SVD_LDS_MAX && !force_streamed()) { small.push_back(s); lds = std::max(lds, b); }
+    else { big.push_back(s); bigN.push_back(ncols); bigM = std::max(bigM, s.M); }
   }
   // column block width of the block scheme: two blocks of M_max rows in LDS
   int nb = 16;
   while (nb > 2 && (size_t)bigM * 2 * nb * sizeof(T) > SVD_LDS_MAX) nb /= 2;
-  for (const auto& s : big) bigBlocks = std::max(bigBlocks, (s.N + nb - 1) / nb);
+  for (int nc : bigN) bigBlocks = std::max(bigBlocks, (nc + nb - 1) / nb);
   const double u = Prec<T>::u;
   const int max_sweeps = 60;
   // algorithmic flops of an SVD with left vectors (LAWN 41 style): 4 M N^2 + 8 N^3

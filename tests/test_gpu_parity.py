@@ -295,3 +295,23 @@ def test_gmres_op_and_prec_on_different_streams():
     assert torch.equal(x1, x2)
     for h in (op, pr, op2, pr2):
         h.close()
+
+
+def test_solve_graph_replays_equal_eager_launches(monkeypatch):
+    """The substitution replayed as a HIP graph gives bitwise the result of launching its kernels one by one,
+    on every replay, with other device work and synchronisations between the replays, for several
+    right-hand-side counts (one graph each)."""
+    wl = W.small_uniform(1500, 3, 227, 3, 3, 1e-6, kparam=0.005, nrhs=4)
+    g = gpu()(to_dev(wl.points), wl.kernel, wl.kparam, wl.shift, 3, 3, 1e-6)
+    g.factorize()
+    monkeypatch.setenv("IFMM_SOLVE_GRAPH", "0")
+    ref = {k: g.solve(to_dev(wl.rhs[:, :k])).cpu() for k in (1, 2, 4)}
+    monkeypatch.delenv("IFMM_SOLVE_GRAPH")
+    for rep in range(4):
+        for k in (1, 2, 4):
+            x = g.solve(to_dev(wl.rhs[:, :k])).cpu()
+            assert torch.equal(x, ref[k]), (rep, k)
+            y = g.matvec(to_dev(wl.rhs[:, :k]))      # other work between replays
+            torch.cuda.synchronize()
+            assert torch.isfinite(y).all()
+    g.close()
