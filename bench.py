@@ -1,25 +1,33 @@
 """Benchmark of the IFMM hot path on one MI355X.
 
-Workload (the 3D preconditioner configuration): N = 65536 points uniform in
-[0,1]^3, inverse multiquadric kernel c = 0.005 with 1.0 on the diagonal,
-octree depth 5, Chebyshev order 3 (27 nodes per box), eps = 1e-6, FP64
-factors, used as the preconditioner of FP64 GMRES for 16 N(0,1) right-hand
-sides to relative residual 1e-10. Inputs are seeded synthetic arrays
-(workloads.py) already resident in HBM when the timed region starts.
+Default workload (the precision configuration, the largest single-GPU one):
+N = 2^20 points in 3D as 8 Gaussian clusters (sigma 0.05, seeded centres in
+[0,1]^3), Gaussian kernel exp(-r^2/0.1^2) with 0.1 on the diagonal, octree
+depth 7, Chebyshev order 4 (64 nodes per box), one N(0,1) right-hand side.
+Two paths on the same GPU:
+  * FP32 factors at eps = 1e-5 preconditioning FP64 GMRES (the timed step);
+  * the plain FP64 IFMM at eps = 1e-10 preconditioning FP64 GMRES.
+Inputs are seeded synthetic arrays (workloads.py) already resident in HBM
+when the timed region starts.
 
-One step = the whole path: tree + H2 operators + sigma_0 + weights (build),
-level-by-level factorization, and preconditioned GMRES (factor solves and H2
-matvecs) for the 16 right-hand sides.
+One timed step = the whole path of the FP32 configuration: tree + H2
+operators + sigma_0 + weights (build), level-by-level factorization in FP32,
+and FP64 GMRES (H2 matvecs, FP32 factor solves) toward relative residual
+1e-10 within --maxit iterations. value = the factorization rate N / t_factor
+(Mpts/s), the metric's "IFMM factor Mpts/s".
 
-Printed on one JSON line: value = points processed per second by the whole
-step (Mpts/s); the factorization-only rate, GMRES time-to-1e-10 with FP32 and
-with FP64 factors, p50/p99 single-RHS solve latency, the roofline of the
-dominant kernel family and the CPU oracle timed on a bounded sample of the
-same workload. Kernel timing uses HIP events inside the library: the warm-up
-steps time every family (the per-family breakdown and the choice of the
-dominant single-kernel family come from the last one); the timed steps time
-only that family, every launch on its own, so that the events of the other
-families do not slow the timed region.
+Printed on one JSON line besides: GMRES time-to-1e-10 of both paths (build +
+factorization + GMRES, with iterations, residual reached and whether 1e-10
+was reached), p50/p99 single-RHS solve latency, the factorization's
+utilisation of the matrix-core peak (algorithmic flops / time / peak), the
+roofline of the dominant single-kernel family and the CPU oracle timed on a
+bounded sample of the same workload. Kernel timing uses HIP events inside
+the library: the warm-up step times every family; the timed steps time only
+the dominant single-kernel family, every launch on its own.
+
+The timed work is kept to about --time-budget seconds: when K steps of the
+warm-up's duration would not fit, fewer are timed and "steps" says how many
+("steps_requested" the number asked for).
 """
 from __future__ import annotations
 
@@ -75,6 +83,259 @@ def cpu_baseline():
     return {"value": n / t / 1e6, "unit": "Mpts/s", "cores": int(cores), "kind": "oracle",
             "sample": "N=1024 uniform in [0,1]^3, depth 3 (2 points per leaf as in the full workload), "
                       "order 3, eps 1e-6, build + factorize + GMRES to 1e-10 for 16 RHS; %.1f s" % t}
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline_cluster():
+    """The oracle, as it stands, on a bounded sample of the clustered workload: the same generator, kernel,
+    Chebyshev order and FP32-path tolerance at 2048 points (8 clusters of 256, depth 4), timed with every
+    host thread the BLAS has and with one thread. value = the oracle's factorization rate (Mpts/s)."""
+    import workloads as W
+    from oracle.gmres import gmres_right
+    from oracle.ifmm import IFMM as Oracle
+    try:
+        from threadpoolctl import threadpool_info, threadpool_limits
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        threadpool_limits, cores = None, 1
+    wl = W.cluster3d(256, 4, 1e-5)
+
+    def one():
+        t0 = time.perf_counter()
+        o = Oracle(wl.points, wl.kernel, wl.kparam, wl.shift, wl.depth, wl.order, wl.eps)
+        t1 = time.perf_counter()
+        o.factorize()
+        t2 = time.perf_counter()
+        _, it, rr, _ = gmres_right(o.matvec, o.solve, wl.rhs[:, 0], tol=1e-10, maxit=200)
+        t3 = time.perf_counter()
+        return t1 - t0, t2 - t1, t3 - t2, it
+
+    b_all, f_all, g_all, it = one()
+    out = {"value": wl.n / f_all / 1e6, "unit": "Mpts/s", "cores": int(cores), "kind": "oracle",
+           "cpu_model": cpu_model(),
+           "sample": "clustered 3D, N=%d (8 clusters of 256, sigma 0.05), Gaussian h=0.1 + 0.1 I, depth 4, order 4, "
+                     "eps 1e-5, FP64 oracle: build %.1f s, factorize %.1f s, GMRES to 1e-10 %.1f s (%d it); "
+                     "value = N / factorize" % (wl.n, b_all, f_all, g_all, it)}
+    if threadpool_limits is not None:
+        with threadpool_limits(limits=1):
+            b1, f1, g1, _ = one()
+        out["one_thread"] = {"value": wl.n / f1 / 1e6, "build_s": b1, "factorize_s": f1, "gmres_s": g1}
+    return out
+
+
+def run_cluster3d(args):
+    """The clustered 2^20-point workload: FP32 factors (eps 1e-5) preconditioning FP64 GMRES as the timed
+    step, the FP64 IFMM (eps 1e-10) path beside it, solve latency, utilisation and the CPU oracle."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_1508_01835_amd import IFMM
+
+    wl = W.cluster3d(args.n_per_cluster, args.depth_cluster)
+    dev = torch.device("cuda:0")
+    pts = torch.tensor(wl.points, device=dev)
+    b = torch.tensor(np.ascontiguousarray(wl.rhs[:, 0]), device=dev)
+    n = wl.n
+    eps32, eps64 = 1e-5, 1e-10
+
+    def step(precision, eps, maxit):
+        t0 = time.perf_counter()
+        g = IFMM(pts, wl.kernel, wl.kparam, wl.shift, wl.depth, wl.order, eps, precision=precision)
+        g.factorize()
+        x, it, rr = g.gmres(b, tol=1e-10, maxit=maxit)
+        torch.cuda.synchronize()
+        return g, x, it, rr, time.perf_counter() - t0
+
+    single = [f for f in range(len(FAMILIES)) if FAMILIES[f] in KERNEL_OF_FAMILY]
+    os.environ["IFMM_KTIMING"] = "1"
+    warm_stats, t_warm = None, None
+    for _ in range(max(1, min(args.warmup, 1))):
+        g, x, it, rr, t_warm = step(32, eps32, args.maxit)
+        warm_stats = g.stats()
+        g.close()
+        log("warm-up step: %.1f s (factorize %.1f s), GMRES %d it, relres %.2e"
+            % (t_warm, warm_stats["t_factor_ms"] * 1e-3, it, rr))
+    torch.cuda.synchronize()
+    K = max(1, min(args.steps, int(args.time_budget // max(t_warm, 1e-3))))
+    dom_w = max(single, key=lambda f: warm_stats["kfam_ms"][f])
+    os.environ["IFMM_KTIMING"] = "m%x" % (1 << dom_w)
+    runs = []
+    keep = None
+    t0 = time.perf_counter()
+    for k in range(K):
+        g, x, it, rr, sec = step(32, eps32, args.maxit)
+        runs.append((g.stats(), it, rr))
+        log("timed step %d/%d: %.1f s" % (k + 1, K, sec))
+        if k == K - 1:
+            keep = (g, x, it, rr, sec)   # serves the latency and the FP32 leg below (outside the timed region)
+        else:
+            g.close()
+    torch.cuda.synchronize()
+    T = time.perf_counter() - t0
+    os.environ["IFMM_KTIMING"] = "1"
+    stats = [r[0] for r in runs]
+    factor_ms = float(np.mean([s_["t_factor_ms"] for s_ in stats]))
+    build_ms = float(np.mean([s_["t_build_ms"] for s_ in stats]))
+    fam_ms = [sum(s_["kfam_ms"][f] for s_ in stats) for f in range(len(FAMILIES))]
+    fam_fl = [sum(s_["kfam_flops"][f] for s_ in stats) for f in range(len(FAMILIES))]
+    fam_nl = [sum(s_["kfam_launches"][f] for s_ in stats) for f in range(len(FAMILIES))]
+    name = FAMILIES[dom_w]
+    kname = KERNEL_OF_FAMILY[name] + "<float>"
+    # this family's kernels run on the vector ALUs in FP32 (157.3 TFLOP/s: 256 CUs x 2.4 GHz x 256 flop/clk)
+    achieved = fam_fl[dom_w] / (fam_ms[dom_w] * 1e-3) / 1e12 if fam_ms[dom_w] > 0 else 0.0
+    roof = {"bound": "alu", "achieved": achieved, "peak": PEAKS["fp32_vec_TFs"], "unit": "TFLOP/s",
+            "frac": achieved / PEAKS["fp32_vec_TFs"], "traffic": MEASURED_TRAFFIC.get(kname), "kernel": kname,
+            "launches_per_step": fam_nl[dom_w] / K, "avg_launch_ms": fam_ms[dom_w] / max(fam_nl[dom_w], 1),
+            "flops_per_launch": fam_fl[dom_w] / max(fam_nl[dom_w], 1)}
+    breakdown = {FAMILIES[f]: round(warm_stats["kfam_ms"][f], 1) for f in range(len(FAMILIES))
+                 if warm_stats["kfam_ms"][f] > 0}
+    flops32 = float(np.mean([s_["factor_flops"] for s_ in stats]))
+    util32 = flops32 / (factor_ms * 1e-3) / 1e12
+    if args.quick:   # counter and trace runs: the timed steps only
+        keep[0].close()
+        out = {"metric": "IFMM factor Mpts/s (quick run)", "value": n / (factor_ms * 1e-3) / 1e6, "unit": "Mpts/s",
+               "steps": K, "ms_per_step": T / K * 1e3, "kernel_ms_warmup_step": breakdown, "roofline": roof}
+        if args.calib_copy:
+            src = torch.ones(64 << 20, dtype=torch.float64, device=dev)   # 512 MiB
+            dst = torch.empty_like(src)
+            torch.cuda.synchronize()
+            dst.copy_(src)
+            torch.cuda.synchronize()
+            out["calib_copy_bytes"] = src.numel() * 8
+        print(json.dumps(out))
+        return
+
+    # solve latency of the FP32 factors of the last timed step, one right-hand side
+    g = keep[0]
+    lat = []
+    for _ in range(args.latency_reps + 3):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        g.solve(b)
+        torch.cuda.synchronize()
+        lat.append((time.perf_counter() - t) * 1e3)
+    lat = np.array(lat[3:])
+    st_lat = g.stats()
+
+    # time to 1e-10 of both paths (build + factorization + GMRES). The FP32 path continues from the last timed
+    # step's handle: its build and factorization times plus a GMRES run of up to --maxit-ttr iterations.
+    ttr = {}
+    legs = [("fp32", 32, eps32)] + ([] if args.skip_fp64 else [("fp64", 64, eps64)])
+    for tag, prec, eps in legs:
+        # the FP64 factorization takes minutes at 2^20: the library prints a line per eliminated level
+        if prec == 64:
+            os.environ["IFMM_PROGRESS"] = "1"
+        if tag == "fp32":
+            g = keep[0]
+            t_g = time.perf_counter()
+            x, it, rr = g.gmres(b, tol=1e-10, maxit=args.maxit_ttr)
+            torch.cuda.synchronize()
+            sg = g.stats()
+            sec = sg["t_build_ms"] * 1e-3 + sg["t_factor_ms"] * 1e-3 + (time.perf_counter() - t_g)
+        else:
+            g, x, it, rr, sec = step(prec, eps, args.maxit_ttr)
+            sg = g.stats()
+        ttr[tag] = {"seconds": sec, "reached_1e-10": bool(rr <= 1e-10), "iters": it, "relres": rr, "eps": eps,
+                    "build_s": sg["t_build_ms"] * 1e-3, "factor_s": sg["t_factor_ms"] * 1e-3,
+                    "factor_mpts_s": n / sg["t_factor_ms"] / 1e3, "factor_flops": sg["factor_flops"],
+                    "device_bytes_peak": sg["device_bytes_peak"], "factor_bytes": sg["factor_bytes"],
+                    "max_rank": sg["max_rank"],
+                    "kernel_ms": {FAMILIES[f]: round(sg["kfam_ms"][f], 1) for f in range(len(FAMILIES))
+                                  if sg["kfam_ms"][f] > 0}}
+        ttr[tag]["matrix_core_utilisation"] = {
+            "achieved_TFs": sg["factor_flops"] / (sg["t_factor_ms"] * 1e-3) / 1e12,
+            "peak_TFs": PEAKS["fp64_TFs"] if prec == 64 else PEAKS["fp32_mfma_TFs"]}
+        ttr[tag]["matrix_core_utilisation"]["frac"] = (ttr[tag]["matrix_core_utilisation"]["achieved_TFs"] /
+                                                      ttr[tag]["matrix_core_utilisation"]["peak_TFs"])
+        log("%s leg: %.1f s (build %.1f, factorize %.1f), GMRES %d it, relres %.2e"
+            % (tag, sec, sg["t_build_ms"] * 1e-3, sg["t_factor_ms"] * 1e-3, it, rr))
+        if tag == "fp64":
+            x64 = x
+        else:
+            x32 = x
+        g.close()
+        os.environ.pop("IFMM_PROGRESS", None)
+    if "fp64" in ttr and ttr["fp64"]["reached_1e-10"]:
+        # error of the FP32-preconditioned result against the FP64 path's converged solution
+        ttr["fp32"]["relerr_vs_fp64_path"] = float(torch.linalg.norm(x32 - x64) / torch.linalg.norm(x64))
+    keep[0].close()
+    del pts, b
+    torch.cuda.empty_cache()
+
+    # the same two paths on the uniform 3D configuration (65536 points, IMQ c = 0.005 + 1.0 I, depth 5,
+    # order 3, 16 right-hand sides), where FP32 factors are accurate enough to precondition
+    ttr_u = {}
+    if not args.skip_uniform:
+        wu = W.uniform3d_65536()
+        pu = torch.tensor(wu.points, device=dev)
+        Bu = torch.tensor(np.ascontiguousarray(wu.rhs), device=dev)
+        xs = {}
+        for tag, prec, eps in (("fp32", 32, 1e-5), ("fp64", 64, 1e-10)):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            g = IFMM(pu, wu.kernel, wu.kparam, wu.shift, wu.depth, wu.order, eps, precision=prec)
+            g.factorize()
+            X, it, rr = g.gmres(Bu, tol=1e-10, maxit=200)
+            torch.cuda.synchronize()
+            sec = time.perf_counter() - t
+            sg = g.stats()
+            xs[tag] = X
+            ttr_u[tag] = {"seconds": sec, "reached_1e-10": bool(rr <= 1e-10), "iters": it, "relres": rr, "eps": eps,
+                          "build_s": sg["t_build_ms"] * 1e-3, "factor_s": sg["t_factor_ms"] * 1e-3}
+            g.close()
+            log("uniform3d %s: %.2f s, GMRES %d it, relres %.2e" % (tag, sec, it, rr))
+        ttr_u["fp32"]["relerr_vs_fp64_path"] = float(torch.linalg.norm(xs["fp32"] - xs["fp64"]) /
+                                                     torch.linalg.norm(xs["fp64"]))
+
+    out = {
+        "metric": "IFMM factor Mpts/s, GMRES time-to-1e-10 FP32 vs FP64; p50/p99 solve latency",
+        "value": n / (factor_ms * 1e-3) / 1e6,
+        "unit": "Mpts/s",
+        "n_gpus": 1,
+        "steps": K,
+        "steps_requested": args.steps,
+        "warmup": 1,
+        "ms_per_step": T / K * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "cluster3d_%d: 8 Gaussian clusters (sigma 0.05) in 3D, Gaussian kernel h=0.1 + 0.1 I, "
+                               "depth %d, Chebyshev order 4; step = build + FP32 factorization (eps 1e-5) + FP64 GMRES "
+                               "(1 RHS, tol 1e-10, <= %d it)" % (n, wl.depth, args.maxit),
+                   "n": n, "depth": wl.depth, "cheb_order": wl.order, "eps": eps32, "nrhs": 1},
+        "factor_ms": factor_ms,
+        "build_ms": build_ms,
+        "step_gmres": {"iters": max(r[1] for r in runs), "relres": max(r[2] for r in runs)},
+        "factor_matrix_core_utilisation": {"achieved_TFs": util32, "peak_TFs": PEAKS["fp32_mfma_TFs"],
+                                           "frac": util32 / PEAKS["fp32_mfma_TFs"],
+                                           "flops": "LAWN-41 counts of LU, triangular solves, Schur products, "
+                                                    "recompressions, edge updates, merge and top (ifmm_stats)"},
+        "time_to_1e-10_s": ttr,
+        "time_to_1e-10_s_uniform3d_65536": ttr_u,
+        "solve_latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                             "nrhs": 1, "factors": "fp32", "factor_bytes": int(st_lat["factor_bytes"]),
+                             "hbm_GBs_at_p50": st_lat["factor_bytes"] / (np.percentile(lat, 50) * 1e-3) / 1e9,
+                             "hbm_peak_GBs": PEAKS["hbm_GBs"]},
+        "max_rank": stats[0]["max_rank"],
+        "device_bytes_peak": stats[0]["device_bytes_peak"],
+        "kernel_ms_warmup_step": breakdown,
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_cluster()
+    print(json.dumps(out))
 
 
 def run_batch(args):
@@ -139,7 +400,7 @@ def run_batch(args):
 
 
 def run_serve(args):
-    """Serving loop: Poisson arrivals, 25% factorize (+ one solve) with N log-uniform in [4096, 32768]
+    """Serving loop: Poisson arrivals, 25% factorize (+ one solve) with N log-uniform in [8192, 524288]
     (uniform cube or 8 Gaussian clusters, half each), 75% solves of 1..64 right-hand sides on a resident
     factor; IMQ c = 0.01 + 1.0 I, Chebyshev order 3, eps 1e-5, FP32 factors, FP64 GMRES to 1e-10."""
     import torch
@@ -149,17 +410,17 @@ def run_serve(args):
     warm = synthetic_requests(3, rate=100.0, n_lo=2048, n_hi=2048, seed=5000)
     Server(hbm_budget_bytes=args.serve_budget).run(warm)
     torch.cuda.synchronize()
-    reqs = synthetic_requests(args.serve_count, rate=args.rate, n_lo=4096, n_hi=32768, seed=5001)
-    res = Server(hbm_budget_bytes=args.serve_budget).run(reqs)
+    reqs = synthetic_requests(args.serve_count, rate=args.rate, n_lo=8192, n_hi=524288, seed=5001)
+    res = Server(hbm_budget_bytes=args.serve_budget, factor_workers=args.factor_workers).run(reqs)
     out = {
         "metric": "IFMM serving p99 request latency (continuous batching, FP32 factors + FP64 GMRES 1e-10)",
         "value": res["p99_ms"], "unit": "ms", "n_gpus": 1, "steps": 1, "warmup": 1,
         "ms_per_step": res["wall_s"] * 1e3, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32+f64", "data": "synthetic",
-        "config": {"workload": "serve%d: Poisson %.1f req/s, 25%% factorize N log-uniform [4096, 32768] "
+        "config": {"workload": "serve%d: Poisson %.2f req/s, 25%% factorize N log-uniform [8192, 524288] "
                                "(cube / 8 clusters), 75%% solve nrhs 1..64, IMQ c=0.01 + 1.0 I, order 3, "
                                "eps 1e-5" % (args.serve_count, args.rate),
-                   "hbm_budget_bytes": args.serve_budget},
+                   "hbm_budget_bytes": args.serve_budget, "factor_workers": args.factor_workers},
         "serve": res,
     }
     print(json.dumps(out))
@@ -265,13 +526,23 @@ def main():
                     help="timed steps only: no latency, time-to-tolerance or CPU runs (for counter runs)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="end with a 512 MiB device-to-device copy, the reference for HBM byte counters")
-    ap.add_argument("--workload", choices=["uniform3d", "batch", "serve", "paper"], default="uniform3d")
+    ap.add_argument("--workload", choices=["cluster3d", "uniform3d", "batch", "serve", "paper"], default="cluster3d")
+    ap.add_argument("--n-per-cluster", type=int, default=131072)
+    ap.add_argument("--depth-cluster", type=int, default=7)
+    ap.add_argument("--maxit", type=int, default=30, help="GMRES iterations of a timed step at most")
+    ap.add_argument("--maxit-ttr", type=int, default=100, help="GMRES iterations of the time-to-1e-10 legs")
+    ap.add_argument("--latency-reps", type=int, default=30)
+    ap.add_argument("--skip-fp64", action="store_true", help="no FP64 eps 1e-10 leg (it takes minutes at 2^20)")
+    ap.add_argument("--skip-uniform", action="store_true", help="no FP32 / FP64 comparison on the uniform workload")
+    ap.add_argument("--time-budget", type=float, default=100.0,
+                    help="seconds of timed steps at most; fewer than --steps are timed when they would not fit")
     ap.add_argument("--paper-n", type=int, default=100000)
     ap.add_argument("--paper-left", action="store_true",
                     help="paper workload: also run left-preconditioned GMRES with each factorization")
     ap.add_argument("--paper-op-order", type=int, default=5)
-    ap.add_argument("--serve-count", type=int, default=200)
+    ap.add_argument("--serve-count", type=int, default=120)
     ap.add_argument("--rate", type=float, default=1.0)
+    ap.add_argument("--factor-workers", type=int, default=2)
     ap.add_argument("--serve-budget", type=int, default=64 << 30)
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--threads", type=int, default=8)
@@ -287,6 +558,9 @@ def main():
         return
     if args.workload == "serve":
         run_serve(args)
+        return
+    if args.workload == "cluster3d":
+        run_cluster3d(args)
         return
 
     import numpy as np
@@ -423,6 +697,7 @@ def main():
         "gmres_iters": iters,
         "gmres_relres": relres,
         "time_to_1e-10_s": ttr,
+        "time_to_1e-10_s_uniform3d_65536": ttr_u,
         "solve_latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                              "nrhs": 1, "factor_bytes": int(st0["factor_bytes"]),
                              # every stored factor element is read once per solve: factor bytes / p50

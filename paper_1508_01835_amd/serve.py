@@ -9,10 +9,12 @@ Two request kinds:
 
 Scheduling (host side; every step of a request runs in the HIP library):
   * admission: a factorization starts only when the device bytes of the
-    resident factors plus its estimate fit the budget; least-recently-used
-    factors with no pending work are evicted to make room;
-  * factorizations run one at a time on a worker thread, each on its own
-    stream, overlapping the solves;
+    resident factors, of the factorizations in flight and of the solve
+    lane's GMRES workspace, plus its own estimate, fit the budget;
+    least-recently-used factors with no pending work are evicted to make
+    room. A factor's bytes are re-read after every call on it;
+  * up to `factor_workers` factorizations run at once, each on a worker
+    thread and a stream of its own, overlapping each other and the solves;
   * continuous batching: when the solve lane is free it takes the factor of
     the oldest pending solve and runs all pending solves of that factor as one
     multi-column GMRES call. Columns are independent GMRES runs, so a request
@@ -60,12 +62,15 @@ class _Factor:
 
 class Server:
     def __init__(self, hbm_budget_bytes: int, kernel=("imq", 0.01, 1.0), order: int = 3, eps: float = 1e-5,
-                 leaf_max: int = 64, tol: float = 1e-10, maxit: int = 200, keep_results: bool = False):
+                 leaf_max: int = 64, tol: float = 1e-10, maxit: int = 200, keep_results: bool = False,
+                 factor_workers: int = 2, gmres_iters_estimate: int = 40):
         import torch
         self.torch = torch
         self.budget = int(hbm_budget_bytes)
         self.kernel, self.order, self.eps, self.leaf_max = kernel, order, eps, leaf_max
         self.tol, self.maxit, self.keep = tol, maxit, keep_results
+        self.factor_workers = max(1, int(factor_workers))
+        self.gmres_iters_estimate = gmres_iters_estimate
         self.factors: "OrderedDict[int, _Factor]" = OrderedDict()
         self.bytes_per_point = 4.0e4      # first estimate; replaced by what factorizations use
         self.solve_stream = torch.cuda.Stream()
@@ -76,8 +81,12 @@ class Server:
     def _resident_bytes(self) -> int:
         return sum(f.bytes for f in self.factors.values())
 
+    def _gmres_bytes(self, n: int, nrhs: int) -> int:
+        """Device bytes of one GMRES call: Krylov and preconditioned bases (2 x iterations) plus work vectors."""
+        return 8 * n * nrhs * (2 * self.gmres_iters_estimate + 6)
+
     def _make_room(self, need: int, busy: set) -> bool:
-        while self._resident_bytes() + need > self.budget:
+        while self._resident_bytes() + self.inflight + need > self.budget:
             victims = [f for f in self.factors.values() if not f.pending and f.fid not in busy]
             if not victims:
                 return False
@@ -111,6 +120,7 @@ class Server:
         with torch.cuda.stream(f.handle.stream):
             X, it, rr = f.handle.gmres(B, tol=self.tol, maxit=self.maxit)
         self.stats["solve_busy_s"] += time.perf_counter() - t0
+        f.bytes = int(f.handle.stats()["device_bytes"])   # what the handle holds now (the Krylov storage is freed)
         self.stats["gmres_calls"] += 1
         self.stats["rhs"] += B.shape[1]
         t_done = now()
@@ -135,9 +145,11 @@ class Server:
         arrived = 0
         fq: list = []                 # factorize requests waiting for admission
         orphans: list = []            # solve requests that arrived with no resident factor
-        worker = None                 # (thread, request, out, stream)
+        workers: list = []            # (thread, request, out, stream, reserved bytes)
+        self.inflight = 0             # bytes reserved by the factorizations in flight
         done = 0
         total = len(requests)
+        peak_inflight = 0
         while done < total:
             t = now()
             while arrived < total and requests[arrived].arrival <= t:
@@ -154,34 +166,39 @@ class Server:
                     r.factor = ids[int(rng.integers(len(ids)))]
                     self.factors[r.factor].pending.append(r)
                 orphans = []
-            # finished factorization: make it resident, queue its own solve
-            if worker is not None and not worker[0].is_alive():
-                th, r, out, stream = worker
-                worker = None
+            # finished factorizations: make them resident, queue their own solves
+            for w in [w for w in workers if not w[0].is_alive()]:
+                workers.remove(w)
+                th, r, out, stream, reserved = w
+                self.inflight -= reserved
                 self.stats["factor_busy_s"] += out["seconds"]
                 if "error" in out:
                     r.t_done, r.relres = now(), float("nan")
                     done += 1
-                else:
-                    h = out["handle"]
-                    st = h.stats()
-                    f = _Factor(r.rid, h, h.n, int(st["device_bytes"]), now())
-                    self.bytes_per_point = max(self.bytes_per_point * 0.5, 1.2 * f.bytes / f.n)
-                    self.factors[r.rid] = f
-                    self.stats["factorized_points"] += f.n
-                    r.factor = r.rid
-                    f.pending.append(r)
-            # start the next admitted factorization
-            if worker is None and fq:
+                    continue
+                h = out["handle"]
+                st = h.stats()
+                f = _Factor(r.rid, h, h.n, int(st["device_bytes"]), now())
+                self.bytes_per_point = max(self.bytes_per_point * 0.5, 1.2 * f.bytes / f.n)
+                self.factors[r.rid] = f
+                self.stats["factorized_points"] += f.n
+                r.factor = r.rid
+                f.pending.append(r)
+            # start admitted factorizations while workers are free
+            while len(workers) < self.factor_workers and fq:
                 r = fq[0]
-                need = int(self.bytes_per_point * r.points.shape[0])
-                if self._make_room(need, set()) or not self.factors:
-                    fq.pop(0)
-                    out: dict = {}
-                    stream = self.torch.cuda.Stream()
-                    th = threading.Thread(target=self._factorize, args=(r, stream, out))
-                    th.start()
-                    worker = (th, r, out, stream)
+                n = r.points.shape[0]
+                need = int(self.bytes_per_point * n) + self._gmres_bytes(n, 1)
+                if not (self._make_room(need, set()) or (not self.factors and not workers)):
+                    break
+                fq.pop(0)
+                out: dict = {}
+                stream = self.torch.cuda.Stream()
+                th = threading.Thread(target=self._factorize, args=(r, stream, out))
+                th.start()
+                workers.append((th, r, out, stream, need))
+                self.inflight += need
+                peak_inflight = max(peak_inflight, len(workers))
             # solve lane: the factor of the oldest pending solve, all its pending solves at once
             pend = [f for f in self.factors.values() if f.pending]
             if pend:
@@ -190,10 +207,10 @@ class Server:
                 self._solve_batch(f, reqs, now)
                 done += len(reqs)
                 continue
-            if worker is None and not fq and arrived < total:
+            if not workers and not fq and arrived < total:
                 time.sleep(max(0.0, min(0.002, requests[arrived].arrival - now())))
-            elif worker is not None:
-                worker[0].join(timeout=0.002)
+            elif workers:
+                workers[0][0].join(timeout=0.002)
         wall = now()
         for f in self.factors.values():
             f.handle.close()
@@ -211,6 +228,8 @@ class Server:
             "solve_p99_ms": float(np.percentile(sl, 99) * 1e3) if sl.size else None,
             "max_relres": float(max(r.relres for r in requests)),
             "max_iters": int(max(r.iters for r in requests)),
+            "solve_requests": int(sum(r.kind == "solve" for r in requests)),
+            "factorizations_in_flight_max": peak_inflight,
         }
         res.update(self.stats)
         return res

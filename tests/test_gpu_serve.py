@@ -16,12 +16,14 @@ torch = pytest.importorskip("torch")
 def test_mixed_requests_equal_alone():
     from paper_1508_01835_amd import IFMM
     from paper_1508_01835_amd.serve import Server, synthetic_requests
-    reqs = synthetic_requests(14, rate=400.0, n_lo=1200, n_hi=3000, seed=5101, factorize_frac=0.3, nrhs_max=4)
-    srv = Server(hbm_budget_bytes=1 << 36, keep_results=True)
+    # a burst of mixed sizes (1000 to 12000 points): factorizations overlap each other and the solves
+    reqs = synthetic_requests(16, rate=400.0, n_lo=1000, n_hi=12000, seed=5101, factorize_frac=0.3, nrhs_max=6)
+    srv = Server(hbm_budget_bytes=1 << 36, keep_results=True, factor_workers=2)
     res = srv.run(reqs)
     print("serve", res, flush=True)
     assert res["requests"] == len(reqs)
     assert res["gmres_calls"] < len(reqs)           # some solves were coalesced
+    assert res["factorizations_in_flight_max"] == 2
     assert res["max_relres"] <= 1e-10
     assert all(r.t_done >= r.arrival for r in reqs)
     pts = {r.rid: r.points for r in reqs if r.kind == "factorize"}
