@@ -109,11 +109,13 @@ typedef struct {
      10 Householder QR panel, 11 truncated pivoted QR, 12 one-workgroup
      Jacobi SVD, 13 row basis change, 14 column basis change. Family 15
      holds the launches of the step-wise truncated pivoted QR (batches of
-     few problems: one launch per Householder step). */
-  double kfam_ms[16];
-  double kfam_flops[16];      /* algorithmic flops attributed to the family */
-  double kfam_bytes[16];      /* algorithmic bytes attributed to the family */
-  int64_t kfam_launches[16];
+     few problems: one launch per Householder step). Family 16 holds one
+     kernel, the one-wavefront QR of matrices at most 32 columns wide.
+     Entries 17-23 are zero. */
+  double kfam_ms[24];
+  double kfam_flops[24];      /* algorithmic flops attributed to the family */
+  double kfam_bytes[24];      /* algorithmic bytes attributed to the family */
+  int64_t kfam_launches[24];
 } ifmm_stats;
 
 typedef struct ifmm_problem* ifmm_handle;

@@ -708,12 +708,155 @@ struct QrJob {
   int M, N, lda, ldr;
 };
 
+// R-only Householder QR of a narrow M x N matrix (N <= QR_NB) by one
+// wavefront, four matrices per workgroup, reading A once: the rows stream
+// through in chunks of 64 (lane l holds row i0 + l of the chunk in registers)
+// and each chunk is folded into the running triangle R (lane j holds row j)
+// by N reflectors, the j-th acting on row j of R and column j of the chunk.
+// The reflector convention is the panel kernel's (alpha = -sign(x0) ||x||,
+// tau = (alpha - x0) / alpha, tau = 0 for a zero column) and the matrix is
+// scaled once by an exact power of two. A is left as it was; R
+// (min(M, N) x N, ldr, zero below the diagonal) is written at the end.
+template <class T>
+__global__ void __launch_bounds__(WG) k_qr_narrow(const QrJob* __restrict__ js, int nj) {
+  const int lane = threadIdx.x % WAVE;
+  const int t = (int)blockIdx.x * (WG / WAVE) + (int)(threadIdx.x / WAVE);
+  if (t >= nj) return;   // whole wavefronts leave together; no barrier below
+  const QrJob d = js[t];
+  const T* __restrict__ A = static_cast<const T*>(d.A);
+  T* __restrict__ R = static_cast<T*>(d.R);
+  const int M = d.M, N = d.N;
+  const int64_t lda = d.lda, ldr = d.ldr;
+  const int kq = M < N ? M : N;
+  T am = 0;
+  for (int c = 0; c < N; ++c)
+    for (int i = lane; i < M; i += WAVE) am = fmax(am, fabs(A[i + c * lda]));
+  am = wave_max(am);
+  const int sh = am > (T)0 ? -ilogb((double)am) : 0;
+  T r[QR_NB], x[QR_NB];
+#pragma unroll
+  for (int c = 0; c < QR_NB; ++c) r[c] = 0;
+  for (int i0 = 0; i0 < M; i0 += WAVE) {
+    const int i = i0 + lane;
+#pragma unroll
+    for (int c = 0; c < QR_NB; ++c) x[c] = (c < N && i < M) ? ldexp(A[i + c * lda], sh) : (T)0;
+    for (int j = 0; j < N; ++j) {
+      T xj = 0, rj = 0;
+#pragma unroll
+      for (int c = 0; c < QR_NB; ++c)
+        if (c == j) { xj = x[c]; rj = r[c]; }
+      const T s = wave_sum(xj * xj);   // identical in every lane: a butterfly adds the same pairs
+      if (!(s > (T)0)) continue;
+      const T x0 = __shfl(rj, j, WAVE);
+      const T al = x0 >= (T)0 ? -sqrt(x0 * x0 + s) : sqrt(x0 * x0 + s);
+      const T tj = (al - x0) / al;
+      const T v = xj * ((T)1 / (x0 - al));
+      // w_c = R[j, c] + v^T chunk[:, c], reduce-scattered to lanes 2c, 2c + 1
+      T pc[QR_NB];
+#pragma unroll
+      for (int c = 0; c < QR_NB; ++c) pc[c] = v * x[c] + (lane == j ? r[c] : (T)0);
+      const T ws = wave_sum32_scatter(pc, lane);
+#pragma unroll
+      for (int c = 0; c < QR_NB; ++c) {
+        const T w = __shfl(ws, 2 * c, WAVE) * tj;
+        if (c > j) {
+          x[c] -= w * v;
+          if (lane == j) r[c] -= w;
+        } else if (c == j) {
+          x[c] = 0;
+          if (lane == j) r[c] = al;
+        }
+      }
+    }
+  }
+  if (lane < kq)
+#pragma unroll
+    for (int c = 0; c < QR_NB; ++c)
+      if (c < N) R[lane + c * ldr] = c >= lane ? ldexp(r[c], -sh) : (T)0;
+}
+
 struct QrScratch {
-  DevBuf w, pd, gd, od;
+  DevBuf w, pd, gd, od, nw, od2;
 };
 
+// Narrow jobs on the one-wavefront kernel. A wavefront streams its rows one
+// after the other, so a tall matrix (M > QR_SEG_MIN) is cut into S row
+// segments of about sqrt(M N) rows (at least 32 >= N, so each segment's
+// triangle is a full N x N); their triangles, stacked into an S N x N matrix,
+// are reduced by a second launch to the job's R. Both stages then stream
+// about sqrt(M N) / 64 chunks per wavefront.
+constexpr int QR_SEG_MIN = 1024;
+
 template <class T>
-inline void qr_blocked(Problem& P, const std::vector<QrJob>& jobs, QrScratch& S) {
+inline void qr_narrow_run(Problem& P, const std::vector<QrJob>& narrow, QrScratch& S) {
+  double fl = 0;   // Householder R of an M x N matrix: 2 a b^2 - 2/3 b^3, a = max(M, N), b = min(M, N)
+  for (const auto& j : narrow) {
+    const double a = std::max(j.M, j.N), b = std::min(j.M, j.N);
+    fl += 2.0 * a * b * b - 2.0 / 3.0 * b * b * b;
+  }
+  std::vector<QrJob> s1, s2;
+  s1.reserve(narrow.size());
+  std::vector<int> nseg(narrow.size(), 1);
+  int64_t stack = 0;
+  for (size_t t = 0; t < narrow.size(); ++t) {
+    const auto& j = narrow[t];
+    if (j.M > QR_SEG_MIN && j.M > j.N) {
+      const int64_t seg = std::max<int64_t>(64, (int64_t)std::ceil(std::sqrt((double)j.M * std::max(j.N, 1))));
+      nseg[t] = (int)ceil_div(j.M, seg);
+      stack += (int64_t)nseg[t] * j.N * j.N;
+    }
+  }
+  if (stack > 0 && (size_t)stack * sizeof(T) > S.nw.bytes) {
+    P.sync();
+    S.nw.alloc((size_t)stack * sizeof(T) * 5 / 4 + 64, &P.mem);
+  }
+  T* W = stack > 0 ? S.nw.template as<T>() : nullptr;
+  int64_t off = 0;
+  for (size_t t = 0; t < narrow.size(); ++t) {
+    const auto& j = narrow[t];
+    if (nseg[t] == 1) {
+      s1.push_back(j);
+      continue;
+    }
+    const int ns = nseg[t], ld = ns * j.N;
+    const int per = j.M / ns;   // > seg (ns - 1) / ns >= 32 >= N; the last segment takes the rest
+    for (int k = 0; k < ns; ++k) {
+      const int r0 = k * per, mk = k + 1 < ns ? per : j.M - r0;
+      s1.push_back({static_cast<T*>(j.A) + r0, W + off + (int64_t)k * j.N, mk, j.N, j.lda, ld});
+    }
+    s2.push_back({W + off, j.R, ld, j.N, ld, j.ldr});
+    off += (int64_t)ns * j.N * j.N;
+  }
+  if (qr_stats_on()) {
+    int64_t sm = 0, sm2 = 0;
+    int mx = 0, nx = 0, mx2 = 0;
+    for (const auto& j : narrow) { sm += j.M; mx = std::max(mx, j.M); nx = std::max(nx, j.N); }
+    for (const auto& j : s2) { sm2 += j.M; mx2 = std::max(mx2, j.M); }
+    std::fprintf(stderr, "[ifmm-qr] narrow jobs=%zu sumM=%lld maxM=%d maxN=%d stage1=%zu stage2=%zu sumM2=%lld maxM2=%d\n",
+                 narrow.size(), (long long)sm, mx, nx, s1.size(), s2.size(), (long long)sm2, mx2);
+  }
+  P.kone_begin(KF_QR_NARROW, fl);
+  const QrJob* d1 = P.put(S.od, s1);
+  hipLaunchKernelGGL(k_qr_narrow<T>, dim3((unsigned)ceil_div((int64_t)s1.size(), WG / WAVE)), dim3(WG), 0, P.stream,
+                     d1, (int)s1.size());
+  IFMM_LAUNCH_CHECK();
+  if (!s2.empty()) {
+    const QrJob* d2 = P.put(S.od2, s2);
+    hipLaunchKernelGGL(k_qr_narrow<T>, dim3((unsigned)ceil_div((int64_t)s2.size(), WG / WAVE)), dim3(WG), 0,
+                       P.stream, d2, (int)s2.size());
+    IFMM_LAUNCH_CHECK();
+  }
+  P.kone_end();
+  if (P.kt.on && P.kcur >= 0) P.kt.flops[P.kcur] -= fl;
+}
+
+template <class T>
+inline void qr_blocked(Problem& P, const std::vector<QrJob>& jobs_in, QrScratch& S) {
+  if (jobs_in.empty()) return;
+  // matrices of at most one panel's width: one wavefront each
+  std::vector<QrJob> narrow, jobs;
+  for (const auto& j : jobs_in) (j.N <= QR_NB && j.R && !force_streamed() ? narrow : jobs).push_back(j);
+  if (!narrow.empty()) qr_narrow_run<T>(P, narrow, S);
   if (jobs.empty()) return;
   static const bool attr = [] {   // once per process (thread-safe initialisation)
     IFMM_HIP(hipFuncSetAttribute((const void*)k_qr_panel<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -767,7 +910,7 @@ inline void qr_blocked(Problem& P, const std::vector<QrJob>& jobs, QrScratch& S)
       }
     }
     if (pv.empty()) break;
-    if (trace_on() && j0 == 0) {
+    if ((trace_on() || qr_stats_on()) && j0 == 0) {
       int64_t sm = 0;
       int mx = 0, nx = 0;
       for (const auto& q : pv) { sm += q.M; mx = std::max(mx, q.M); nx = std::max(nx, q.N); }

@@ -142,6 +142,8 @@ inline void build_tree(Problem& P, const double* d_points, int depth, int leaf_m
 }
 
 // ------------------------------------------------------------------- R1
+inline void build_m2l_tiles(Problem& P);
+
 inline void build_r1(Problem& P) {
   const int d = P.d, q = P.q, L = P.L;
   const HTree& T = P.T;
@@ -169,6 +171,70 @@ inline void build_r1(Problem& P) {
     hipLaunchKernelGGL(k_m2l_table, dim3(c7), dim3(WG), 0, P.stream, P.cc, P.kf, T.box_size(l),
                        P.m2l[l].as<double>());
     IFMM_LAUNCH_CHECK();
+  }
+  if (q > 32 && q <= M2L_QP) build_m2l_tiles(P);
+}
+
+// Tables of the offset-tiled M2L: for a box with child position b (bit k =
+// coordinate k mod 2), the children of its parent's neighbours lie at offsets
+// in [-2 - b_k, 3 - b_k] per axis; those outside [-1, 1]^d form its
+// interaction offsets, listed in increasing 7^d code.
+inline void build_m2l_tiles(Problem& P) {
+  const int d = P.d, L = P.L;
+  const int nb2 = 1 << d;
+  int c7 = 1, p6 = 1, p3 = 1;
+  for (int k = 0; k < d; ++k) { c7 *= 7; p6 *= 6; p3 *= 3; }
+  const int nofs = p6 - p3;
+  P.m2l_nofs = nofs;
+  std::vector<int> ocode, kof((size_t)nb2 * c7, -1);
+  for (int b = 0; b < nb2; ++b) {
+    int k = 0;
+    for (int code = 0; code < c7; ++code) {
+      bool in = true, near = true;
+      for (int a = 0, x = code; a < d; ++a, x /= 7) {
+        const int o = x % 7 - 3, bb = (b >> a) & 1;
+        if (o < -2 - bb || o > 3 - bb) in = false;
+        if (o < -1 || o > 1) near = false;
+      }
+      if (!in || near) continue;
+      ocode.push_back(code);
+      kof[(size_t)b * c7 + code] = k++;
+    }
+    if (k != nofs) fail(IFMM_ERR_INTERNAL, "interaction offsets of a child position");
+  }
+  P.upload(P.m2l_ocode, ocode);
+  const HTree& T = P.T;
+  for (int l = 2; l <= L; ++l) {
+    const HLevel& lv = T.lev[l];
+    LevelDev& ld = P.ldev[l];
+    std::vector<int> cb(lv.nb), tord;
+    for (int i = 0; i < lv.nb; ++i) {
+      int b = 0;
+      for (int a = 0; a < d; ++a) b |= (lv.coords[(size_t)i * d + a] & 1) << a;
+      cb[i] = b;
+    }
+    ld.m2l_gstart.assign(nb2 + 1, 0);
+    for (int b = 0; b < nb2; ++b) {
+      ld.m2l_gstart[b] = (int)tord.size();
+      for (int i = 0; i < lv.nb; ++i)
+        if (cb[i] == b) tord.push_back(i);
+    }
+    ld.m2l_gstart[nb2] = (int)tord.size();
+    std::vector<int> bo((size_t)lv.nb * nofs, -1);
+    for (int i = 0; i < lv.nb; ++i)
+      for (int t = lv.in_start[i]; t < lv.in_start[i + 1]; ++t) {
+        const int j = lv.inter[t];
+        int code = 0, mul = 1;
+        for (int a = 0; a < d; ++a) {
+          code += (lv.coords[(size_t)j * d + a] - lv.coords[(size_t)i * d + a] + 3) * mul;
+          mul *= 7;
+        }
+        const int k = kof[(size_t)cb[i] * c7 + code];
+        if (k < 0) fail(IFMM_ERR_INTERNAL, "an interaction pair outside its child position's offsets");
+        bo[(size_t)i * nofs + k] = j;
+      }
+    P.upload(ld.m2l_tord, tord);
+    P.upload(ld.m2l_bo, bo);
   }
 }
 
@@ -218,14 +284,27 @@ inline void matvec_tree(Problem& P, const double* x, double* y, int nrhs) {
     const int* crd = P.ldev[l].coords.as<int>();
     const int nbl = T.lev[l].nb;
     const double* tb = P.m2l[l].as<double>();
-    // matrix cores for q <= 64 (orders up to 4 in 3D), the vector kernel above that
+    // matrix cores for q <= 64 (orders up to 4 in 3D; offset tiles above q = 32), the vector kernel above that
     if (q <= 16)
       hipLaunchKernelGGL(k_m2l_mfma<1>, dim3(nbl), dim3(256), 0, P.stream, ist, itr, crd, nbl, d, q, nrhs, tb,
                          P.mv_w[l].as<double>(), P.mv_g[l].as<double>());
     else if (q <= 32)
       hipLaunchKernelGGL(k_m2l_mfma<2>, dim3(nbl), dim3(256), 0, P.stream, ist, itr, crd, nbl, d, q, nrhs, tb,
                          P.mv_w[l].as<double>(), P.mv_g[l].as<double>());
-    else if (q <= 64)
+    else if (q <= M2L_QP && nrhs <= M2L_QP && !P.ldev[l].m2l_gstart.empty()) {
+      const int tpw = M2L_QP / nrhs, ng = 1 << d;   // targets per workgroup
+      M2LGroups gr{};
+      int nwg = 0;
+      for (int b = 0; b <= ng; ++b) {
+        gr.start[b] = P.ldev[l].m2l_gstart[b];
+        gr.wg0[b] = nwg;
+        if (b < ng) nwg += (int)ceil_div(P.ldev[l].m2l_gstart[b + 1] - P.ldev[l].m2l_gstart[b], tpw);
+      }
+      if (nwg > 0)
+        hipLaunchKernelGGL(k_m2l_tile, dim3((unsigned)nwg), dim3(256), 0, P.stream, P.ldev[l].m2l_tord.as<int>(),
+                           P.ldev[l].m2l_bo.as<int>(), P.m2l_nofs, P.m2l_ocode.as<int>(), gr, ng, tpw, q, nrhs, tb,
+                           P.mv_w[l].as<double>(), P.mv_g[l].as<double>());
+    } else if (q <= 64)
       hipLaunchKernelGGL(k_m2l_mfma<4>, dim3(nbl), dim3(256), 0, P.stream, ist, itr, crd, nbl, d, q, nrhs, tb,
                          P.mv_w[l].as<double>(), P.mv_g[l].as<double>());
     else
@@ -339,6 +418,7 @@ inline void build_r2(Problem& P, double sigma0_override) {
   R.dpld.resize(L + 1);
   R.dkpoff.resize(L + 1);
   DevBuf dscr, work;
+  QrScratch qrs;
   // ---- leaf QR
   {
     const HLevel& lv = T.lev[L];
@@ -641,19 +721,14 @@ inline void build_r2(Problem& P, double sigma0_override) {
                          l > 2 ? dwoff[l - 1].as<int64_t>() : nullptr, l > 2 ? dgcols[l - 1].as<int>() : nullptr,
                          Mbase, dm.as<int64_t>(), dmr.as<int>(), i0);
       IFMM_LAUNCH_CHECK();
-      std::vector<QrDesc> qd;
+      std::vector<QrJob> qd;   // R only: the blocked Householder QR (panels, matrix-core updates)
       CopyBatch<double, double> tb;
       std::vector<SvdDesc> sd;
       CopyBatch<double, double> gbat;
       for (int i = i0; i < i1; ++i) {
         const int kq = gcols[l][i];
         if (kq == 0) continue;
-        QrDesc dd;
-        dd.A = Mbase + moff[i];
-        dd.R = Rw.as<double>() + woff[l][i];
-        dd.Q = nullptr;
-        dd.M = mrows[i]; dd.N = r[i]; dd.lda = mrows[i]; dd.ldr = kq; dd.ldq = 1; dd.pad = 0;
-        qd.push_back(dd);
+        qd.push_back({Mbase + moff[i], Rw.as<double>() + woff[l][i], mrows[i], r[i], mrows[i], kq});
         // B = R^T (r_i x kq)
         tb.add(Rw.as<double>() + woff[l][i], kq, Bw.as<double>() + woff[l][i], r[i], r[i], kq, 4);
         SvdDesc s{};
@@ -665,7 +740,7 @@ inline void build_r2(Problem& P, double sigma0_override) {
         gbat.add(W.as<double>() + woff[l][i], r[i], G.as<double>() + woff[l][i], r[i], r[i], kq, 0, 1.0,
                  S.as<double>() + soff[l][i]);
       }
-      run_qr<double>(P, qd, dscr);
+      qr_blocked<double>(P, qd, qrs);
       run_copy(P, tb, dscr);
       run_svd<double>(P, sd, dscr);
       run_copy(P, gbat, dscr);

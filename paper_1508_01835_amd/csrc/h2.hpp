@@ -229,6 +229,82 @@ __global__ void __launch_bounds__(256) k_m2l_mfma(const int* __restrict__ in_sta
   }
 }
 
+// M2L by offset tiles (orders with 32 < q <= 64): the targets of one child
+// position share the same list of interaction offsets, so a workgroup takes
+// up to T of them (T x nrhs <= 64 output columns) and walks that list once:
+// per offset it stages the translation table K~_o (q x q) and the T source
+// vectors in LDS and adds their product on the FP64 matrix cores. A table is
+// then read once per workgroup instead of once per (target, source) pair.
+// Every output column sums its offsets in list order, whatever T and nrhs.
+struct M2LGroups {
+  int start[9];   // group b = targets of child position b at tord[start[b] .. start[b + 1])
+  int wg0[9];     // first workgroup of group b
+};
+
+constexpr int M2L_QP = 64;   // padded table order of k_m2l_tile
+
+__global__ void __launch_bounds__(256) k_m2l_tile(const int* __restrict__ tord, const int* __restrict__ bo, int nofs,
+                                                  const int* __restrict__ ocode, M2LGroups gr, int ngroups, int T,
+                                                  int q, int nrhs, const double* __restrict__ tab,
+                                                  const double* __restrict__ w, double* __restrict__ g) {
+  typedef double v4d __attribute__((ext_vector_type(4)));
+  __shared__ double As[M2L_QP][M2L_QP + 1];   // As[k][m] = K~_o[m, k]
+  __shared__ double Bs[M2L_QP][M2L_QP + 1];   // Bs[k][col] = w_src(col)[k]
+  __shared__ int src[M2L_QP];                 // source box of each output column for this offset
+  int b = 0;
+  while (b + 1 < ngroups && gr.wg0[b + 1] <= (int)blockIdx.x) ++b;
+  const int t0 = gr.start[b] + ((int)blockIdx.x - gr.wg0[b]) * T;
+  const int cnt = min(T, gr.start[b + 1] - t0);
+  const int ncol = cnt * nrhs;
+  const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
+  const int rb0 = 32 * (wv >> 1), cb0 = 32 * (wv & 1);
+  v4d acc[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) acc[i] = v4d{0, 0, 0, 0};
+  const int* codes = ocode + b * nofs;
+  for (int k = 0; k < nofs; ++k) {
+    __syncthreads();
+    if (threadIdx.x < M2L_QP) {
+      const int col = threadIdx.x;
+      src[col] = col < ncol ? bo[(int64_t)tord[t0 + col / nrhs] * nofs + k] : -1;
+    }
+    const double* K = tab + (int64_t)codes[k] * q * q;
+    for (int e = threadIdx.x; e < M2L_QP * M2L_QP; e += 256) {
+      const int m = e % M2L_QP, kk = e / M2L_QP;
+      As[kk][m] = (m < q && kk < q) ? K[m + (int64_t)kk * q] : 0.0;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < M2L_QP * M2L_QP; e += 256) {
+      const int kk = e % M2L_QP, col = e / M2L_QP;
+      const int j = src[col];
+      Bs[kk][col] = (j >= 0 && kk < q) ? w[((int64_t)j * nrhs + col % nrhs) * q + kk] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int k4 = 0; k4 < M2L_QP; k4 += 4) {
+      const int kk = k4 + (lane >> 4);
+      const double a0 = As[kk][rb0 + (lane & 15)], a1 = As[kk][rb0 + 16 + (lane & 15)];
+      const double b0 = Bs[kk][cb0 + (lane & 15)], b1 = Bs[kk][cb0 + 16 + (lane & 15)];
+      acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0], 0, 0, 0);
+      acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[1], 0, 0, 0);
+      acc[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[2], 0, 0, 0);
+      acc[3] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[3], 0, 0, 0);
+    }
+  }
+  // lane l's register r of a 16 x 16 block holds row 4 r + l / 16, column l % 16
+#pragma unroll
+  for (int blk = 0; blk < 4; ++blk) {
+    const int col = cb0 + 16 * (blk & 1) + (lane & 15);
+    if (col >= ncol) continue;
+    const int tg = tord[t0 + col / nrhs], rr = col % nrhs;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int m = rb0 + 16 * (blk >> 1) + 4 * r + (lane >> 4);
+      if (m < q) g[((int64_t)tg * nrhs + rr) * q + m] = acc[blk][r];
+    }
+  }
+}
+
 // Downward pass (L2L): g_c += T_c g_parent.
 __global__ void k_l2l(const int* __restrict__ parent, const int* __restrict__ cbits, int nbc, int q,
                       int nrhs, const double* __restrict__ T, const double* __restrict__ gp,

@@ -517,7 +517,7 @@ int ifmm_query(ifmm_handle h, ifmm_stats* s) {
     P.st.device_bytes_peak = P.mem.peak;
     P.sync();
     P.kt.collect();
-    for (int f = 0; f < KF_COUNT && f < 16; ++f) {
+    for (int f = 0; f < KF_COUNT && f < 24; ++f) {
       P.st.kfam_ms[f] = P.kt.ms[f];
       P.st.kfam_flops[f] = P.kt.flops[f];
       P.st.kfam_bytes[f] = P.kt.bytes[f];

@@ -14,6 +14,10 @@ struct LevelDev {
   int nb = 0;
   DevBuf coords, nb_start, nbr, in_start, inter, parent, ch_start, cbits, in_rev;
   int64_t npairs = 0;   // size of the interaction-list CSR
+  // M2L by offset tiles: boxes ordered by child position (tord), the source
+  // box at every interaction offset of each box (bo, -1: none), group starts
+  DevBuf m2l_tord, m2l_bo;
+  std::vector<int> m2l_gstart;
 };
 
 // Initial operators of one level after QR, weighting and truncation (float64).
@@ -43,9 +47,10 @@ struct FactorStoreBase {
 // family 15 holds the launches of the step-wise pivoted QR.
 enum KFam {
   KF_SCHUR = 0, KF_LU, KF_TRSM, KF_QR, KF_SVD, KF_XFORM, KF_SOLVE, KF_MATVEC, KF_OTHER,
-  KF_SVD_ROUND, KF_QR_PANEL, KF_QRCP, KF_SVD_SMALL, KF_ROW_XFORM, KF_COL_XFORM, KF_QRCP_STEP, KF_COUNT
+  KF_SVD_ROUND, KF_QR_PANEL, KF_QRCP, KF_SVD_SMALL, KF_ROW_XFORM, KF_COL_XFORM, KF_QRCP_STEP, KF_QR_NARROW,
+  KF_COUNT
 };
-static_assert(KF_COUNT <= 16, "the query structure holds 16 families");
+static_assert(KF_COUNT <= 24, "the query structure holds 24 families");
 
 // Host wall time by section (diagnostics, IFMM_HOSTPROF=1): where the host
 // spends the factorization, waiting on the device included.
@@ -180,6 +185,8 @@ struct Problem {
   DevBuf ubar;                     // leaf interpolation, per leaf at leaf_start * q
   DevBuf Ttab;                     // 2^d transfers (q x q)
   std::vector<DevBuf> m2l;         // by level: 7^d tables of q x q
+  DevBuf m2l_ocode;                // per child position: the codes of its interaction offsets
+  int m2l_nofs = 0;                // interaction offsets of a child position: 6^d - 3^d
   std::vector<DevBuf> mv_w, mv_g;  // matvec scratch by level
   int mv_nrhs = 0;
   DevBuf mv_x, mv_y;
@@ -299,6 +306,12 @@ inline bool force_streamed() { return std::getenv("IFMM_FORCE_STREAMED") != null
 // after each launch and prints sizes and duration to stderr.
 inline bool trace_on() {
   static const bool on = std::getenv("IFMM_TRACE") != nullptr;
+  return on;
+}
+
+// IFMM_QR_STATS=1: one line per batched QR launch with the job shapes
+inline bool qr_stats_on() {
+  static const bool on = std::getenv("IFMM_QR_STATS") != nullptr;
   return on;
 }
 

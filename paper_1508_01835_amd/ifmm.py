@@ -42,14 +42,16 @@ class Stats(ctypes.Structure):
                 ("device_bytes", ctypes.c_int64), ("device_bytes_peak", ctypes.c_int64),
                 ("error_level", ctypes.c_int), ("error_box", ctypes.c_int),
                 ("gmres_iters", ctypes.c_int), ("gmres_relres", ctypes.c_double),
-                ("kfam_ms", ctypes.c_double * 16), ("kfam_flops", ctypes.c_double * 16),
-                ("kfam_bytes", ctypes.c_double * 16), ("kfam_launches", ctypes.c_int64 * 16)]
+                ("kfam_ms", ctypes.c_double * 24), ("kfam_flops", ctypes.c_double * 24),
+                ("kfam_bytes", ctypes.c_double * 24), ("kfam_launches", ctypes.c_int64 * 24)]
 
 KFAMILIES = ["schur_gemm", "pivot_lu", "trsm_w", "qr", "jacobi_svd", "edge_update", "solve", "matvec", "other",
-             "svd_round", "qr_panel", "qrcp", "svd_small", "row_xform", "col_xform", "qrcp_step"]
+             "svd_round", "qr_panel", "qrcp", "svd_small", "row_xform", "col_xform", "qrcp_step", "qr_narrow",
+             "unused17", "unused18", "unused19", "unused20", "unused21", "unused22", "unused23"]
 # families holding exactly one kernel (per-launch timing), with its name
 KERNEL_OF_FAMILY = {"svd_round": "k_svd_round", "qr_panel": "k_qr_panel", "qrcp": "k_qrcp",
-                    "svd_small": "k_svd_small", "row_xform": "k_row_xform", "col_xform": "k_col_xform"}
+                    "svd_small": "k_svd_small", "row_xform": "k_row_xform", "col_xform": "k_col_xform",
+                    "qr_narrow": "k_qr_narrow"}
 
 
 EXPORTS = ["ifmm_default_options", "ifmm_build", "ifmm_factorize", "ifmm_factorize_batch", "ifmm_solve",
