@@ -175,10 +175,11 @@ inline void build_r1(Problem& P) {
   if (q > 32 && q <= M2L_QP) build_m2l_tiles(P);
 }
 
-// Tables of the offset-tiled M2L: for a box with child position b (bit k =
-// coordinate k mod 2), the children of its parent's neighbours lie at offsets
-// in [-2 - b_k, 3 - b_k] per axis; those outside [-1, 1]^d form its
-// interaction offsets, listed in increasing 7^d code.
+// Tables of the offset-tiled M2L and K_pre: for a box with child position b
+// (bit k = coordinate k mod 2), the children of its parent's neighbours lie at
+// offsets in [-2 - b_k, 3 - b_k] per axis; those outside [-1, 1]^d form its
+// interaction offsets, listed in increasing 7^d code. bo holds, per box and
+// offset, the position of that pair in the interaction-list CSR (-1: none).
 inline void build_m2l_tiles(Problem& P) {
   const int d = P.d, L = P.L;
   const int nb2 = 1 << d;
@@ -231,9 +232,10 @@ inline void build_m2l_tiles(Problem& P) {
         }
         const int k = kof[(size_t)cb[i] * c7 + code];
         if (k < 0) fail(IFMM_ERR_INTERNAL, "an interaction pair outside its child position's offsets");
-        bo[(size_t)i * nofs + k] = j;
+        bo[(size_t)i * nofs + k] = t;
       }
     P.upload(ld.m2l_tord, tord);
+    ld.m2l_tord_h = tord;
     P.upload(ld.m2l_bo, bo);
   }
 }
@@ -302,7 +304,7 @@ inline void matvec_tree(Problem& P, const double* x, double* y, int nrhs) {
       }
       if (nwg > 0)
         hipLaunchKernelGGL(k_m2l_tile, dim3((unsigned)nwg), dim3(256), 0, P.stream, P.ldev[l].m2l_tord.as<int>(),
-                           P.ldev[l].m2l_bo.as<int>(), P.m2l_nofs, P.m2l_ocode.as<int>(), gr, ng, tpw, q, nrhs, tb,
+                           P.ldev[l].m2l_bo.as<int>(), itr, P.m2l_nofs, P.m2l_ocode.as<int>(), gr, ng, tpw, q, nrhs, tb,
                            P.mv_w[l].as<double>(), P.mv_g[l].as<double>());
     } else if (q <= 64)
       hipLaunchKernelGGL(k_m2l_mfma<4>, dim3(nbl), dim3(256), 0, P.stream, ist, itr, crd, nbl, d, q, nrhs, tb,
@@ -539,7 +541,31 @@ inline void build_r2(Problem& P, double sigma0_override) {
       int rmx = 0;
       for (int i = 0; i < lv.nb; ++i) rmx = std::max(rmx, R.r[l][i]);
       const int np = (int)lv.inter.size();
-      if ((int64_t)rmx * q <= SWW)   // a wavefront per pair
+      if (!P.ldev[l].m2l_gstart.empty() && !force_streamed()) {   // offset tiles on the matrix cores
+        const int nb2 = 1 << P.d;
+        std::vector<int> tl;
+        std::vector<KpreWg> wg;
+        const auto& gs = P.ldev[l].m2l_gstart;
+        const auto& tord = P.ldev[l].m2l_tord_h;
+        for (int b = 0; b < nb2; ++b)
+          for (int rb = 1; rb <= 4; ++rb) {
+            const int per = rb == 1 ? 4 : rb == 2 ? 2 : 1;
+            const int s0 = (int)tl.size();
+            for (int x = gs[b]; x < gs[b + 1]; ++x)
+              if ((R.r[l][tord[x]] + 15) / 16 == rb) tl.push_back(tord[x]);
+            for (int x = s0; x < (int)tl.size(); x += per)
+              wg.push_back({x, std::min(per, (int)tl.size() - x), rb, b});
+          }
+        DevBuf dtl = up(P, tl), dwg;
+        P.upload(dwg, wg);
+        hipLaunchKernelGGL(k_kpre_tile, dim3((unsigned)wg.size()), dim3(256), 0, P.stream, dwg.as<KpreWg>(),
+                           dtl.as<int>(), P.ldev[l].m2l_bo.as<int>(), P.ldev[l].inter.as<int>(), P.m2l_nofs,
+                           P.m2l_ocode.as<int>(), q, P.m2l[l].as<double>(), R.R[l].as<double>(),
+                           R.droff[l].as<int64_t>(), R.dr[l].as<int>(), R.Kpre[l].as<double>(),
+                           R.dkpoff[l].as<int64_t>());
+        IFMM_LAUNCH_CHECK();
+        P.sync();   // the launch tables are freed at the end of this scope
+      } else if ((int64_t)rmx * q <= SWW)   // a wavefront per pair
         hipLaunchKernelGGL(k_kpre_w, dim3((unsigned)ceil_div(np, WG / WAVE)), dim3(WG), 0, P.stream,
                            P.ldev[l].in_start.as<int>(), P.ldev[l].inter.as<int>(), P.ldev[l].coords.as<int>(),
                            lv.nb, P.d, q, P.m2l[l].as<double>(), R.R[l].as<double>(), R.droff[l].as<int64_t>(),

@@ -243,7 +243,8 @@ struct M2LGroups {
 
 constexpr int M2L_QP = 64;   // padded table order of k_m2l_tile
 
-__global__ void __launch_bounds__(256) k_m2l_tile(const int* __restrict__ tord, const int* __restrict__ bo, int nofs,
+__global__ void __launch_bounds__(256) k_m2l_tile(const int* __restrict__ tord, const int* __restrict__ bo,
+                                                  const int* __restrict__ inter, int nofs,
                                                   const int* __restrict__ ocode, M2LGroups gr, int ngroups, int T,
                                                   int q, int nrhs, const double* __restrict__ tab,
                                                   const double* __restrict__ w, double* __restrict__ g) {
@@ -266,7 +267,8 @@ __global__ void __launch_bounds__(256) k_m2l_tile(const int* __restrict__ tord, 
     __syncthreads();
     if (threadIdx.x < M2L_QP) {
       const int col = threadIdx.x;
-      src[col] = col < ncol ? bo[(int64_t)tord[t0 + col / nrhs] * nofs + k] : -1;
+      const int pr = col < ncol ? bo[(int64_t)tord[t0 + col / nrhs] * nofs + k] : -1;
+      src[col] = pr >= 0 ? inter[pr] : -1;
     }
     const double* K = tab + (int64_t)codes[k] * q * q;
     for (int e = threadIdx.x; e < M2L_QP * M2L_QP; e += 256) {

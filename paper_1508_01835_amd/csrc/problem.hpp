@@ -14,9 +14,10 @@ struct LevelDev {
   int nb = 0;
   DevBuf coords, nb_start, nbr, in_start, inter, parent, ch_start, cbits, in_rev;
   int64_t npairs = 0;   // size of the interaction-list CSR
-  // M2L by offset tiles: boxes ordered by child position (tord), the source
-  // box at every interaction offset of each box (bo, -1: none), group starts
+  // M2L by offset tiles: boxes ordered by child position (tord), the
+  // interaction pair at every offset of each box (bo, -1: none), group starts
   DevBuf m2l_tord, m2l_bo;
+  std::vector<int> m2l_tord_h;
   std::vector<int> m2l_gstart;
 };
 

@@ -126,6 +126,109 @@ __global__ void __launch_bounds__(WG) k_kpre_w(const int* __restrict__ in_start,
                 [&](int x, int y, double v) { out[x + (int64_t)y * ri] = v; }, sh + wv * SWW, lane);
 }
 
+// K_pre by offset tiles on the FP64 matrix cores (q <= 64). A workgroup holds
+// targets of one child position, stacked in 16-row blocks of their R_i (one
+// wavefront per block: four targets of rank <= 16, two of rank <= 32 or one
+// larger), and walks the position's interaction offsets o. Per offset the
+// table K~_o is staged in LDS once for all its targets; each wavefront forms
+// X = R_i[16 rows] K~_o, passes it through its own LDS slice into the operand
+// layout, and multiplies by R_j^T, R_j read straight from memory, j the
+// source at offset o. Every entry is summed in a fixed order (over the table
+// index in steps of 4, then over the source node), whatever the grouping.
+struct KpreWg {
+  int start, cnt, rb, pos;   // targets tlist[start .. start + cnt), 16-row blocks per target, child position
+};
+
+__global__ void __launch_bounds__(256, 2) k_kpre_tile(const KpreWg* __restrict__ wgs, const int* __restrict__ tlist,
+                                                   const int* __restrict__ bo, const int* __restrict__ inter,
+                                                   int nofs, const int* __restrict__ ocode, int q,
+                                                   const double* __restrict__ tab, const double* __restrict__ R,
+                                                   const int64_t* __restrict__ roff, const int* __restrict__ r,
+                                                   double* __restrict__ K, const int64_t* __restrict__ koff) {
+  typedef double v4d __attribute__((ext_vector_type(4)));
+  __shared__ double Ks[64][65];       // Ks[k][n] = K~_o[k, n]
+  __shared__ double Xs[4][16][65];    // per wavefront: its 16 x q block of X
+  const KpreWg g = wgs[blockIdx.x];
+  const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+  const bool act = w < g.cnt * g.rb;
+  const int ti = act ? tlist[g.start + w / g.rb] : 0;
+  const int rb = act ? w % g.rb : 0;
+  const int ri = act ? r[ti] : 0;
+  const int nks = (q + 3) / 4, ncb = (q + 15) / 16;
+  // A operand of R_i rows 16 rb .. 16 rb + 15: lane l holds row l % 16, column 4 ks + l / 16
+  double af[16];
+  {
+    const double* Ri = R + roff[ti];
+    const int a = 16 * rb + (lane & 15);
+#pragma unroll
+    for (int ks = 0; ks < 16; ++ks) {
+      const int k = 4 * ks + (lane >> 4);
+      af[ks] = (act && a < ri && k < q) ? Ri[a + (int64_t)k * ri] : 0.0;
+    }
+  }
+  const int* codes = ocode + g.pos * nofs;
+  for (int o = 0; o < nofs; ++o) {
+    const int t = act ? bo[(int64_t)ti * nofs + o] : -1;
+    if (!__syncthreads_or(t >= 0)) continue;   // also: the previous offset's reads of Ks are done
+    const double* Kt = tab + (int64_t)codes[o] * q * q;
+    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+      const int k = e & 63, n = e >> 6;
+      Ks[k][n] = (k < q && n < q) ? Kt[k + (int64_t)n * q] : 0.0;
+    }
+    __syncthreads();
+    if (t < 0) continue;
+    v4d x[4];
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) x[cb] = v4d{0, 0, 0, 0};
+#pragma unroll
+    for (int ks = 0; ks < 16; ++ks) {
+      const int k = 4 * ks + (lane >> 4);
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb)
+        if (ks < nks && cb < ncb)
+          x[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[ks], Ks[k][16 * cb + (lane & 15)], x[cb], 0, 0, 0);
+    }
+    // result lane layout: register e of block cb holds row 4 e + l / 16, column 16 cb + l % 16
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) Xs[w][4 * e + (lane >> 4)][16 * cb + (lane & 15)] = x[cb][e];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int j = inter[t], rj = r[j];
+    const double* Rj = R + roff[j];
+    const int nyb = (rj + 15) / 16;
+    v4d y[4];
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) y[cb] = v4d{0, 0, 0, 0};
+#pragma unroll
+    for (int ks = 0; ks < 16; ++ks) {
+      const int n = 4 * ks + (lane >> 4);
+      const double a = Xs[w][lane & 15][n];
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb) {
+        if (ks < nks && cb < nyb) {
+          const int b = 16 * cb + (lane & 15);
+          const double bv = (b < rj && n < q) ? Rj[b + (int64_t)n * rj] : 0.0;
+          y[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, y[cb], 0, 0, 0);
+        }
+      }
+    }
+    double* out = K + koff[t];
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) {
+      const int b = 16 * cb + (lane & 15);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int a = 16 * rb + 4 * e + (lane >> 4);
+        if (cb < nyb && a < ri && b < rj) out[a + (int64_t)b * ri] = y[cb][e];
+      }
+    }
+    // Xs is rewritten only after the next offset's barrier
+  }
+}
+
 // K(i, j) = WU_i[:, :k_i]^T K_pre(i, j) WV_j[:, :k_j].
 __global__ void __launch_bounds__(WG) k_krot(const int* __restrict__ in_start, const int* __restrict__ inter, int nb,
                                              const double* __restrict__ Kpre, const int64_t* __restrict__ kpoff,
