@@ -708,71 +708,110 @@ struct QrJob {
   int M, N, lda, ldr;
 };
 
-// R-only Householder QR of a narrow M x N matrix (N <= QR_NB) by one
-// wavefront, four matrices per workgroup, reading A once: the rows stream
-// through in chunks of 64 (lane l holds row i0 + l of the chunk in registers)
-// and each chunk is folded into the running triangle R (lane j holds row j)
-// by N reflectors, the j-th acting on row j of R and column j of the chunk.
-// The reflector convention is the panel kernel's (alpha = -sign(x0) ||x||,
-// tau = (alpha - x0) / alpha, tau = 0 for a zero column) and the matrix is
-// scaled once by an exact power of two. A is left as it was; R
-// (min(M, N) x N, ldr, zero below the diagonal) is written at the end.
-template <class T>
-__global__ void __launch_bounds__(WG) k_qr_narrow(const QrJob* __restrict__ js, int nj) {
-  const int lane = threadIdx.x % WAVE;
-  const int t = (int)blockIdx.x * (WG / WAVE) + (int)(threadIdx.x / WAVE);
-  if (t >= nj) return;   // whole wavefronts leave together; no barrier below
-  const QrJob d = js[t];
+// R-only Householder QR of a narrow M x N matrix (N <= 64), a column per lane:
+// lanes g NP .. g NP + NP - 1 of a wavefront own the columns of job g (NP =
+// 16, 32 or 64, so 4, 2 or 1 jobs per wavefront), and the rows stream through
+// in chunks of QC_CH (each lane holds its column of the chunk in registers)
+// while the running triangle R sits in LDS, column c with lane c. The chunk
+// is folded into R by one reflector per column j, acting on row j of R and
+// column j of the chunk: column j is broadcast to the job's lanes, and every
+// trailing column takes its dot product with it in its own lane, so no
+// reduction crosses lanes. The reflector convention is the panel kernel's
+// (alpha = -sign(x0) ||x||, tau = (alpha - x0) / alpha, tau = 0 for a zero
+// column) and each job is scaled once by an exact power of two. A is left as
+// it was; R (min(M, N) x N, ldr, zero below the diagonal) is written at the end.
+constexpr int QC_CH = 32;
+constexpr int QC_NMAX = 64;
+
+template <class T, int NP>
+struct QrCols {
+  static constexpr int G = WAVE / NP;   // jobs per wavefront
+  static constexpr int WAVES = sizeof(T) * G * NP * (NP + 1) > 20000 ? 2 : 4;
+};
+
+template <int G, class T>
+__device__ inline T qc_bcast(T x, int src) {
+  if constexpr (G == 1) {   // one job per wavefront: the source lane is uniform
+    if constexpr (sizeof(T) == 8) {
+      const int64_t b = __double_as_longlong((double)x);
+      const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), src);
+      const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+      return (T)__longlong_as_double(((int64_t)hi << 32) | (uint32_t)lo);
+    } else {
+      return __int_as_float(__builtin_amdgcn_readlane(__float_as_int((float)x), src));
+    }
+  } else {
+    return __shfl(x, src, WAVE);
+  }
+}
+
+template <class T, int NP, int NT = QrCols<T, NP>::WAVES * WAVE>
+__global__ void __launch_bounds__(NT) k_qr_cols(const QrJob* __restrict__ js, int nj) {
+  constexpr int G = QrCols<T, NP>::G, WAVES = QrCols<T, NP>::WAVES;
+  __shared__ T Rs[WAVES][G][NP][NP + 1];   // Rs[.][.][i][c] = R[i, c]
+  const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+  const int g = lane / NP, c = lane % NP;
+  const int t = ((int)blockIdx.x * WAVES + w) * G + g;
+  QrJob d{};
+  if (t < nj) d = js[t];
   const T* __restrict__ A = static_cast<const T*>(d.A);
-  T* __restrict__ R = static_cast<T*>(d.R);
-  const int M = d.M, N = d.N;
-  const int64_t lda = d.lda, ldr = d.ldr;
-  const int kq = M < N ? M : N;
+  const int M = t < nj ? d.M : 0, N = t < nj ? d.N : 0;
+  const int64_t lda = d.lda;
+  const bool col = c < N;
+  T (*R)[NP + 1] = Rs[w][g];
+#pragma unroll 4
+  for (int i = 0; i < NP; ++i) R[i][c] = 0;
+  // exact power-of-two scaling by the job's largest magnitude
   T am = 0;
-  for (int c = 0; c < N; ++c)
-    for (int i = lane; i < M; i += WAVE) am = fmax(am, fabs(A[i + c * lda]));
-  am = wave_max(am);
+  if (col)
+    for (int i = 0; i < M; ++i) am = fmax(am, fabs(A[i + c * lda]));
+#pragma unroll
+  for (int o = NP / 2; o > 0; o >>= 1) am = fmax(am, __shfl_xor(am, o, WAVE));
   const int sh = am > (T)0 ? -ilogb((double)am) : 0;
-  T r[QR_NB], x[QR_NB];
+  // the wavefront walks the largest of its jobs' row and column counts
+  int Mw = M, Nw = N;
 #pragma unroll
-  for (int c = 0; c < QR_NB; ++c) r[c] = 0;
-  for (int i0 = 0; i0 < M; i0 += WAVE) {
-    const int i = i0 + lane;
+  for (int o = NP; o < WAVE; o <<= 1) {
+    Mw = max(Mw, __shfl_xor(Mw, o, WAVE));
+    Nw = max(Nw, __shfl_xor(Nw, o, WAVE));
+  }
+  T x[QC_CH], v[QC_CH];
+  for (int i0 = 0; i0 < Mw; i0 += QC_CH) {
 #pragma unroll
-    for (int c = 0; c < QR_NB; ++c) x[c] = (c < N && i < M) ? ldexp(A[i + c * lda], sh) : (T)0;
-    for (int j = 0; j < N; ++j) {
-      T xj = 0, rj = 0;
+    for (int i = 0; i < QC_CH; ++i) x[i] = (col && i0 + i < M) ? ldexp(A[i0 + i + c * lda], sh) : (T)0;
+    for (int j = 0; j < Nw; ++j) {
+      const int src = g * NP + j;   // lane of column j of this job (a zero column when j >= N)
+      T s = 0, dot = 0;
 #pragma unroll
-      for (int c = 0; c < QR_NB; ++c)
-        if (c == j) { xj = x[c]; rj = r[c]; }
-      const T s = wave_sum(xj * xj);   // identical in every lane: a butterfly adds the same pairs
-      if (!(s > (T)0)) continue;
-      const T x0 = __shfl(rj, j, WAVE);
-      const T al = x0 >= (T)0 ? -sqrt(x0 * x0 + s) : sqrt(x0 * x0 + s);
-      const T tj = (al - x0) / al;
-      const T v = xj * ((T)1 / (x0 - al));
-      // w_c = R[j, c] + v^T chunk[:, c], reduce-scattered to lanes 2c, 2c + 1
-      T pc[QR_NB];
+      for (int i = 0; i < QC_CH; ++i) {
+        v[i] = qc_bcast<G>(x[i], src);
+        s += v[i] * v[i];
+        dot += v[i] * x[i];
+      }
+      const T x0 = R[j < NP ? j : 0][j < NP ? j : 0];
+      if (j < N && s > (T)0) {
+        const T al = x0 >= (T)0 ? -sqrt(x0 * x0 + s) : sqrt(x0 * x0 + s);
+        const T tj = (al - x0) / al;
+        const T scal = (T)1 / (x0 - al);
+        if (c > j && col) {
+          const T wc = tj * (R[j][c] + scal * dot);
+          R[j][c] -= wc;
+          const T f = wc * scal;
 #pragma unroll
-      for (int c = 0; c < QR_NB; ++c) pc[c] = v * x[c] + (lane == j ? r[c] : (T)0);
-      const T ws = wave_sum32_scatter(pc, lane);
-#pragma unroll
-      for (int c = 0; c < QR_NB; ++c) {
-        const T w = __shfl(ws, 2 * c, WAVE) * tj;
-        if (c > j) {
-          x[c] -= w * v;
-          if (lane == j) r[c] -= w;
+          for (int i = 0; i < QC_CH; ++i) x[i] -= f * v[i];
         } else if (c == j) {
-          x[c] = 0;
-          if (lane == j) r[c] = al;
+#pragma unroll
+          for (int i = 0; i < QC_CH; ++i) x[i] = 0;
+          R[j][j] = al;
         }
       }
     }
   }
-  if (lane < kq)
-#pragma unroll
-    for (int c = 0; c < QR_NB; ++c)
-      if (c < N) R[lane + c * ldr] = c >= lane ? ldexp(r[c], -sh) : (T)0;
+  const int kq = M < N ? M : N;
+  if (col) {
+    T* __restrict__ Ro = static_cast<T*>(d.R);
+    for (int i = 0; i < kq; ++i) Ro[i + c * d.ldr] = i <= c ? ldexp(R[i][c], -sh) : (T)0;
+  }
 }
 
 struct QrScratch {
@@ -796,12 +835,13 @@ inline void qr_narrow_run(Problem& P, const std::vector<QrJob>& narrow, QrScratc
   }
   std::vector<QrJob> s1, s2;
   s1.reserve(narrow.size());
+  // segments of at least 64 rows: every segment's triangle is a full N x N
   std::vector<int> nseg(narrow.size(), 1);
   int64_t stack = 0;
   for (size_t t = 0; t < narrow.size(); ++t) {
     const auto& j = narrow[t];
     if (j.M > QR_SEG_MIN && j.M > j.N) {
-      const int64_t seg = std::max<int64_t>(64, (int64_t)std::ceil(std::sqrt((double)j.M * std::max(j.N, 1))));
+      const int64_t seg = std::max<int64_t>(128, (int64_t)std::ceil(std::sqrt((double)j.M * std::max(j.N, 1))));
       nseg[t] = (int)ceil_div(j.M, seg);
       stack += (int64_t)nseg[t] * j.N * j.N;
     }
@@ -819,7 +859,7 @@ inline void qr_narrow_run(Problem& P, const std::vector<QrJob>& narrow, QrScratc
       continue;
     }
     const int ns = nseg[t], ld = ns * j.N;
-    const int per = j.M / ns;   // > seg (ns - 1) / ns >= 32 >= N; the last segment takes the rest
+    const int per = j.M / ns;   // > seg (ns - 1) / ns >= 64 >= N; the last segment takes the rest
     for (int k = 0; k < ns; ++k) {
       const int r0 = k * per, mk = k + 1 < ns ? per : j.M - r0;
       s1.push_back({static_cast<T*>(j.A) + r0, W + off + (int64_t)k * j.N, mk, j.N, j.lda, ld});
@@ -836,16 +876,37 @@ inline void qr_narrow_run(Problem& P, const std::vector<QrJob>& narrow, QrScratc
                  narrow.size(), (long long)sm, mx, nx, s1.size(), s2.size(), (long long)sm2, mx2);
   }
   P.kone_begin(KF_QR_NARROW, fl);
-  const QrJob* d1 = P.put(S.od, s1);
-  hipLaunchKernelGGL(k_qr_narrow<T>, dim3((unsigned)ceil_div((int64_t)s1.size(), WG / WAVE)), dim3(WG), 0, P.stream,
-                     d1, (int)s1.size());
-  IFMM_LAUNCH_CHECK();
-  if (!s2.empty()) {
-    const QrJob* d2 = P.put(S.od2, s2);
-    hipLaunchKernelGGL(k_qr_narrow<T>, dim3((unsigned)ceil_div((int64_t)s2.size(), WG / WAVE)), dim3(WG), 0,
-                       P.stream, d2, (int)s2.size());
-    IFMM_LAUNCH_CHECK();
-  }
+  // one launch per column class (16, 32, 64), jobs of a class contiguous
+  auto launch = [&](std::vector<QrJob>& v, DevBuf& buf) {
+    std::stable_sort(v.begin(), v.end(), [](const QrJob& a, const QrJob& b) {
+      return (a.N > 16) + (a.N > 32) < (b.N > 16) + (b.N > 32);
+    });
+    const QrJob* dv = P.put(buf, v);
+    size_t b0 = 0;
+    while (b0 < v.size()) {
+      const int cls = (v[b0].N > 16) + (v[b0].N > 32);
+      size_t b1 = b0;
+      while (b1 < v.size() && (v[b1].N > 16) + (v[b1].N > 32) == cls) ++b1;
+      const int n = (int)(b1 - b0);
+      if (cls == 0) {
+        constexpr int per = QrCols<T, 16>::G * QrCols<T, 16>::WAVES;
+        hipLaunchKernelGGL((k_qr_cols<T, 16>), dim3((unsigned)ceil_div(n, per)), dim3(QrCols<T, 16>::WAVES * WAVE),
+                           0, P.stream, dv + b0, n);
+      } else if (cls == 1) {
+        constexpr int per = QrCols<T, 32>::G * QrCols<T, 32>::WAVES;
+        hipLaunchKernelGGL((k_qr_cols<T, 32>), dim3((unsigned)ceil_div(n, per)), dim3(QrCols<T, 32>::WAVES * WAVE),
+                           0, P.stream, dv + b0, n);
+      } else {
+        constexpr int per = QrCols<T, 64>::G * QrCols<T, 64>::WAVES;
+        hipLaunchKernelGGL((k_qr_cols<T, 64>), dim3((unsigned)ceil_div(n, per)), dim3(QrCols<T, 64>::WAVES * WAVE),
+                           0, P.stream, dv + b0, n);
+      }
+      IFMM_LAUNCH_CHECK();
+      b0 = b1;
+    }
+  };
+  launch(s1, S.od);
+  if (!s2.empty()) launch(s2, S.od2);
   P.kone_end();
   if (P.kt.on && P.kcur >= 0) P.kt.flops[P.kcur] -= fl;
 }
@@ -853,9 +914,9 @@ inline void qr_narrow_run(Problem& P, const std::vector<QrJob>& narrow, QrScratc
 template <class T>
 inline void qr_blocked(Problem& P, const std::vector<QrJob>& jobs_in, QrScratch& S) {
   if (jobs_in.empty()) return;
-  // matrices of at most one panel's width: one wavefront each
+  // matrices of at most 64 columns: the column-per-lane streaming kernel
   std::vector<QrJob> narrow, jobs;
-  for (const auto& j : jobs_in) (j.N <= QR_NB && j.R && !force_streamed() ? narrow : jobs).push_back(j);
+  for (const auto& j : jobs_in) (j.N <= QC_NMAX && j.R && !force_streamed() ? narrow : jobs).push_back(j);
   if (!narrow.empty()) qr_narrow_run<T>(P, narrow, S);
   if (jobs.empty()) return;
   static const bool attr = [] {   // once per process (thread-safe initialisation)
