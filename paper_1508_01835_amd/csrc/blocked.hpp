@@ -781,13 +781,15 @@ __global__ void __launch_bounds__(NT) k_qr_cols(const QrJob* __restrict__ js, in
     for (int i = 0; i < QC_CH; ++i) x[i] = (col && i0 + i < M) ? ldexp(A[i0 + i + c * lda], sh) : (T)0;
     for (int j = 0; j < Nw; ++j) {
       const int src = g * NP + j;   // lane of column j of this job (a zero column when j >= N)
-      T s = 0, dot = 0;
+      // four partial sums each: independent chains instead of one 32-long
+      T s4[4] = {0, 0, 0, 0}, d4[4] = {0, 0, 0, 0};
 #pragma unroll
       for (int i = 0; i < QC_CH; ++i) {
         v[i] = qc_bcast<G>(x[i], src);
-        s += v[i] * v[i];
-        dot += v[i] * x[i];
+        s4[i & 3] += v[i] * v[i];
+        d4[i & 3] += v[i] * x[i];
       }
+      const T s = (s4[0] + s4[1]) + (s4[2] + s4[3]), dot = (d4[0] + d4[1]) + (d4[2] + d4[3]);
       const T x0 = R[j < NP ? j : 0][j < NP ? j : 0];
       if (j < N && s > (T)0) {
         const T al = x0 >= (T)0 ? -sqrt(x0 * x0 + s) : sqrt(x0 * x0 + s);

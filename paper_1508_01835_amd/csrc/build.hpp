@@ -143,6 +143,7 @@ inline void build_tree(Problem& P, const double* d_points, int depth, int leaf_m
 
 // ------------------------------------------------------------------- R1
 inline void build_m2l_tiles(Problem& P);
+inline void build_near_cache(Problem& P);
 
 inline void build_r1(Problem& P) {
   const int d = P.d, q = P.q, L = P.L;
@@ -173,6 +174,43 @@ inline void build_r1(Problem& P) {
     IFMM_LAUNCH_CHECK();
   }
   if (q > 32 && q <= M2L_QP) build_m2l_tiles(P);
+  build_near_cache(P);
+}
+
+// Leaf near-field blocks, stored once when they fit NEAR_CACHE_MAX bytes and
+// the leaves are small enough for the wavefront product (IFMM_NEAR_CACHE=0:
+// never): every product with A~ or E then reads them instead of evaluating
+// the kernel again.
+constexpr int64_t NEAR_CACHE_MAX = (int64_t)16 << 30;
+
+inline void build_near_cache(Problem& P) {
+  const HTree& T = P.T;
+  const int L = P.L, nb = T.lev[L].nb;
+  const char* env = std::getenv("IFMM_NEAR_CACHE");
+  if ((env && env[0] == '0') || P.n > (int64_t)WAVE * nb) return;
+  const HLevel& lv = T.lev[L];
+  std::vector<int64_t> off(nb);
+  std::vector<int> col(lv.nbr.size());
+  int64_t tot = 0;
+  for (int i = 0; i < nb; ++i) {
+    const int64_t m = T.leaf_start[i + 1] - T.leaf_start[i];
+    int c = 0;
+    for (int t = lv.nb_start[i]; t < lv.nb_start[i + 1]; ++t) {
+      col[t] = c;
+      const int j = lv.nbr[t];
+      c += (int)(T.leaf_start[j + 1] - T.leaf_start[j]);
+    }
+    off[i] = tot;
+    tot += m * c;
+  }
+  if (tot * (int64_t)sizeof(double) > NEAR_CACHE_MAX) return;
+  P.upload(P.nfoff, off);
+  P.upload(P.nfcol, col);
+  P.nf.alloc(sizeof(double) * std::max<int64_t>(tot, 1), &P.mem);
+  hipLaunchKernelGGL(k_near_fill, dim3((unsigned)ceil_div(nb, WG / WAVE)), dim3(WG), 0, P.stream, P.pts.as<double>(),
+                     P.leaf_start.as<int64_t>(), P.ldev[L].nb_start.as<int>(), P.ldev[L].nbr.as<int>(), nb, P.d,
+                     P.kf, P.nfoff.as<int64_t>(), P.nfcol.as<int>(), P.nf.as<double>());
+  IFMM_LAUNCH_CHECK();
 }
 
 // Tables of the offset-tiled M2L and K_pre: for a box with child position b
@@ -249,11 +287,31 @@ inline void launch_l2p_p2p(Problem& P, int nrhs, const double* ubar, const doubl
   if (P.n <= (int64_t)WAVE * nb)
     hipLaunchKernelGGL(k_l2p_p2p_w, dim3((unsigned)ceil_div(nb, WG / WAVE)), dim3(WG), 0, P.stream,
                        P.pts.as<double>(), P.leaf_start.as<int64_t>(), P.ldev[L].nb_start.as<int>(),
-                       P.ldev[L].nbr.as<int>(), nb, P.d, P.q, nrhs, P.kf, ubar, g, x, ldx, y, ldy, with_far);
+                       P.ldev[L].nbr.as<int>(), nb, P.d, P.q, nrhs, P.kf, ubar, g, x, ldx, y, ldy, with_far,
+                       P.nf.p ? P.nf.as<double>() : nullptr, P.nfoff.as<int64_t>(), P.nfcol.as<int>());
   else
     hipLaunchKernelGGL(k_l2p_p2p, dim3(nb), dim3(WG), 0, P.stream, P.pts.as<double>(), P.leaf_start.as<int64_t>(),
                        P.ldev[L].nb_start.as<int>(), P.ldev[L].nbr.as<int>(), nb, P.d, P.q, nrhs, P.kf, ubar, g, x,
                        ldx, y, ldy, with_far);
+}
+
+// g = M2L(w) at level l by offset tiles (the level has them, q and nrhs <= 64).
+inline void launch_m2l_tile(Problem& P, int l, int nrhs, const double* w, double* g) {
+  const int q = P.q, ng = 1 << P.d;
+  const int tpw = M2L_QP / nrhs;   // targets per workgroup
+  const auto& gs = P.ldev[l].m2l_gstart;
+  M2LGroups gr{};
+  int nwg = 0;
+  for (int b = 0; b <= ng; ++b) {
+    gr.start[b] = gs[b];
+    gr.wg0[b] = nwg;
+    if (b < ng) nwg += (int)ceil_div(gs[b + 1] - gs[b], tpw);
+  }
+  if (nwg > 0)
+    hipLaunchKernelGGL(k_m2l_tile, dim3((unsigned)nwg), dim3(256), 0, P.stream, P.ldev[l].m2l_tord.as<int>(),
+                       P.ldev[l].m2l_bo.as<int>(), P.ldev[l].inter.as<int>(), P.m2l_nofs, P.m2l_ocode.as<int>(), gr,
+                       ng, tpw, q, nrhs, P.m2l[l].as<double>(), w, g);
+  IFMM_LAUNCH_CHECK();
 }
 
 // y = A~ x (tree order in and out), nrhs columns; x, y device, leading dim n.
@@ -293,20 +351,9 @@ inline void matvec_tree(Problem& P, const double* x, double* y, int nrhs) {
     else if (q <= 32)
       hipLaunchKernelGGL(k_m2l_mfma<2>, dim3(nbl), dim3(256), 0, P.stream, ist, itr, crd, nbl, d, q, nrhs, tb,
                          P.mv_w[l].as<double>(), P.mv_g[l].as<double>());
-    else if (q <= M2L_QP && nrhs <= M2L_QP && !P.ldev[l].m2l_gstart.empty()) {
-      const int tpw = M2L_QP / nrhs, ng = 1 << d;   // targets per workgroup
-      M2LGroups gr{};
-      int nwg = 0;
-      for (int b = 0; b <= ng; ++b) {
-        gr.start[b] = P.ldev[l].m2l_gstart[b];
-        gr.wg0[b] = nwg;
-        if (b < ng) nwg += (int)ceil_div(P.ldev[l].m2l_gstart[b + 1] - P.ldev[l].m2l_gstart[b], tpw);
-      }
-      if (nwg > 0)
-        hipLaunchKernelGGL(k_m2l_tile, dim3((unsigned)nwg), dim3(256), 0, P.stream, P.ldev[l].m2l_tord.as<int>(),
-                           P.ldev[l].m2l_bo.as<int>(), itr, P.m2l_nofs, P.m2l_ocode.as<int>(), gr, ng, tpw, q, nrhs, tb,
-                           P.mv_w[l].as<double>(), P.mv_g[l].as<double>());
-    } else if (q <= 64)
+    else if (q <= M2L_QP && nrhs <= M2L_QP && !P.ldev[l].m2l_gstart.empty())
+      launch_m2l_tile(P, l, nrhs, P.mv_w[l].as<double>(), P.mv_g[l].as<double>());
+    else if (q <= 64)
       hipLaunchKernelGGL(k_m2l_mfma<4>, dim3(nbl), dim3(256), 0, P.stream, ist, itr, crd, nbl, d, q, nrhs, tb,
                          P.mv_w[l].as<double>(), P.mv_g[l].as<double>());
     else
@@ -594,6 +641,13 @@ inline void build_r2(Problem& P, double sigma0_override) {
     w.alloc(sizeof(double) * tot, &P.mem);
     // entries of a box beyond its rank are never written by E: keep them zero
     IFMM_HIP(hipMemsetAsync(w.p, 0, sizeof(double) * tot, P.stream));
+    DevBuf ew, eg;   // w = R^T y and g = M2L(w) of one level
+    {
+      int nbmax = 0;
+      for (int l = 2; l <= L; ++l) nbmax = std::max(nbmax, T.lev[l].nb);
+      ew.alloc(sizeof(double) * (size_t)nbmax * q, &P.mem);
+      eg.alloc(sizeof(double) * (size_t)nbmax * q, &P.mem);
+    }
     std::vector<int> rmax(L + 1, 0);   // largest rank of each level (kernel choice of the y rows)
     for (int l = 2; l <= L; ++l)
       for (int x : R.r[l]) rmax[l] = std::max(rmax[l], x);
@@ -611,6 +665,21 @@ inline void build_r2(Problem& P, double sigma0_override) {
                            leaf ? nullptr : in + yo[l + 1], in + yo[l], out + zo[l]);
         IFMM_LAUNCH_CHECK();
         const bool top = l == 2;
+        if (!P.ldev[l].m2l_gstart.empty() && !T.lev[l].inter.empty()) {   // far field through the M2L tables
+          hipLaunchKernelGGL(k_e_rty, dim3((unsigned)ceil_div(nb, WG / WAVE)), dim3(WG), 0, P.stream, nb, q,
+                             R.dr[l].as<int>(), R.R[l].as<double>(), R.droff[l].as<int64_t>(), in + yo[l],
+                             ew.as<double>());
+          IFMM_LAUNCH_CHECK();
+          launch_m2l_tile(P, l, 1, ew.as<double>(), eg.as<double>());
+          hipLaunchKernelGGL(k_e_yrows_g, dim3((unsigned)ceil_div(nb, WG / WAVE)), dim3(WG), 0, P.stream, nb, q,
+                             R.dr[l].as<int>(), R.R[l].as<double>(), R.droff[l].as<int64_t>(), eg.as<double>(),
+                             in + zo[l], top ? nullptr : P.ldev[l].parent.as<int>(),
+                             top ? nullptr : R.Pst.as<double>(), top ? nullptr : R.dppoff[l].as<int64_t>(),
+                             top ? nullptr : R.dpld[l].as<int>(), top ? nullptr : R.dr[l - 1].as<int>(),
+                             top ? nullptr : in + zo[l - 1], out + yo[l]);
+          IFMM_LAUNCH_CHECK();
+          continue;
+        }
         hipLaunchKernelGGL(rmax[l] <= 32 ? k_e_yrows32 : k_e_yrows, dim3(nb), dim3(WG), 0, P.stream, nb, q,
                            R.dr[l].as<int>(),
                            P.ldev[l].in_start.as<int>(), P.ldev[l].inter.as<int>(), R.Kpre[l].as<double>(),

@@ -385,12 +385,46 @@ __global__ void __launch_bounds__(WG) k_l2p_p2p(const double* __restrict__ pts, 
 // the G partial sums are added by a butterfly inside the lane group. The
 // order of every sum depends on the box sizes only, so each right-hand side
 // gets the same result whatever the number of right-hand sides.
+// Near-field blocks of the leaves, evaluated once: box i's block is m_i x S_i
+// (S_i the points of its neighbour list, in list order), column-major at
+// nfoff[i]; nfcol[t] is the first column of neighbour pair t. The entries are
+// the ones k_l2p_p2p_w evaluates (kernel plus the shift on the diagonal).
+__global__ void __launch_bounds__(WG) k_near_fill(const double* __restrict__ pts, const int64_t* __restrict__ leaf_start,
+                                                  const int* __restrict__ nb_start, const int* __restrict__ nbr, int nb,
+                                                  int d, KernelFn kf, const int64_t* __restrict__ nfoff,
+                                                  const int* __restrict__ nfcol, double* __restrict__ nf) {
+  const int lane = threadIdx.x % WAVE;
+  const int i = (int)blockIdx.x * (WG / WAVE) + (int)(threadIdx.x / WAVE);
+  if (i >= nb) return;
+  const int64_t s = leaf_start[i];
+  const int m = (int)(leaf_start[i + 1] - s);
+  double* B = nf + nfoff[i];
+  for (int t = nb_start[i]; t < nb_start[i + 1]; ++t) {
+    const int j = nbr[t];
+    const int64_t sj = leaf_start[j];
+    const int mj = (int)(leaf_start[j + 1] - sj);
+    double* Bt = B + (int64_t)nfcol[t] * m;
+    for (int e = lane; e < m * mj; e += WAVE) {
+      const int a = e % m, u = e / m;
+      double r2 = 0;
+      for (int k = 0; k < d; ++k) {
+        const double df = pts[(s + a) * d + k] - pts[(sj + u) * d + k];
+        r2 += df * df;
+      }
+      double kv = kappa(kf, sqrt(r2));
+      if (sj + u == s + a) kv += kf.shift;
+      Bt[e] = kv;
+    }
+  }
+}
+
 __global__ void __launch_bounds__(WG) k_l2p_p2p_w(const double* __restrict__ pts, const int64_t* __restrict__ leaf_start,
                                                   const int* __restrict__ nb_start, const int* __restrict__ nbr,
                                                   int nb, int d, int q, int nrhs, KernelFn kf,
                                                   const double* __restrict__ ubar, const double* __restrict__ g,
                                                   const double* __restrict__ x, int64_t ldx, double* __restrict__ y,
-                                                  int64_t ldy, int with_far) {
+                                                  int64_t ldy, int with_far, const double* __restrict__ nf,
+                                                  const int64_t* __restrict__ nfoff, const int* __restrict__ nfcol) {
   const int lane = threadIdx.x % WAVE;
   const int i = (int)blockIdx.x * (WG / WAVE) + (int)(threadIdx.x / WAVE);
   if (i >= nb) return;   // whole wavefronts leave together; no barrier below
@@ -408,21 +442,32 @@ __global__ void __launch_bounds__(WG) k_l2p_p2p_w(const double* __restrict__ pts
       const bool act = a < m;
       double acc = 0;
       if (act) {
-        double xa[3] = {0, 0, 0};
-        for (int k = 0; k < d; ++k) xa[k] = pts[(s + a) * d + k];
-        for (int t = t0; t < t1; ++t) {
-          const int j = nbr[t];
-          const int64_t sj = leaf_start[j];
-          const int mj = (int)(leaf_start[j + 1] - sj);
-          for (int u = sub; u < mj; u += G) {
-            double r2 = 0;
-            for (int k = 0; k < d; ++k) {
-              const double df = xa[k] - pts[(sj + u) * d + k];
-              r2 += df * df;
+        if (nf) {   // the stored near-field block; same entries, same order
+          const double* B = nf + nfoff[i] + a;
+          for (int t = t0; t < t1; ++t) {
+            const int j = nbr[t];
+            const int64_t sj = leaf_start[j];
+            const int mj = (int)(leaf_start[j + 1] - sj);
+            const double* Bt = B + (int64_t)nfcol[t] * m;
+            for (int u = sub; u < mj; u += G) acc += Bt[(int64_t)u * m] * x[(sj + u) + (int64_t)rr * ldx];
+          }
+        } else {
+          double xa[3] = {0, 0, 0};
+          for (int k = 0; k < d; ++k) xa[k] = pts[(s + a) * d + k];
+          for (int t = t0; t < t1; ++t) {
+            const int j = nbr[t];
+            const int64_t sj = leaf_start[j];
+            const int mj = (int)(leaf_start[j + 1] - sj);
+            for (int u = sub; u < mj; u += G) {
+              double r2 = 0;
+              for (int k = 0; k < d; ++k) {
+                const double df = xa[k] - pts[(sj + u) * d + k];
+                r2 += df * df;
+              }
+              double kv = kappa(kf, sqrt(r2));
+              if (sj + u == s + a) kv += kf.shift;
+              acc += kv * x[(sj + u) + (int64_t)rr * ldx];
             }
-            double kv = kappa(kf, sqrt(r2));
-            if (sj + u == s + a) kv += kf.shift;
-            acc += kv * x[(sj + u) + (int64_t)rr * ldx];
           }
         }
       }

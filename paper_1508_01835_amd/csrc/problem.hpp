@@ -187,6 +187,7 @@ struct Problem {
   DevBuf Ttab;                     // 2^d transfers (q x q)
   std::vector<DevBuf> m2l;         // by level: 7^d tables of q x q
   DevBuf m2l_ocode;                // per child position: the codes of its interaction offsets
+  DevBuf nf, nfoff, nfcol;         // stored leaf near-field blocks (empty: evaluated in every product)
   int m2l_nofs = 0;                // interaction offsets of a child position: 6^d - 3^d
   std::vector<DevBuf> mv_w, mv_g;  // matvec scratch by level
   int mv_nrhs = 0;

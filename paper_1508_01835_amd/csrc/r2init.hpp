@@ -384,6 +384,50 @@ __global__ void k_e_zrows(int nb, int q, const int* __restrict__ r, int leaf,
   }
 }
 
+// The far-field sum of the y rows without the K_pre blocks: since
+// K_pre(i,j) = R_i K~_o R_j^T, sum_j K_pre(i,j) y_j = R_i g_i with
+// g = M2L(w), w_j = R_j^T y_j. Both transforms take a wavefront per box,
+// a lane per entry (q <= 64).
+__global__ void __launch_bounds__(WG) k_e_rty(int nb, int q, const int* __restrict__ r, const double* __restrict__ R,
+                                              const int64_t* __restrict__ roff, const double* __restrict__ yl,
+                                              double* __restrict__ w) {
+  const int lane = threadIdx.x % WAVE;
+  const int j = (int)blockIdx.x * (WG / WAVE) + (int)(threadIdx.x / WAVE);
+  if (j >= nb || lane >= q) return;
+  const int rj = r[j];
+  const double* Rj = R + roff[j];
+  const double* y = yl + (int64_t)j * q;
+  double s = 0;
+  for (int a = 0; a < rj; ++a) s += Rj[a + (int64_t)lane * rj] * y[a];
+  w[(int64_t)j * q + lane] = s;
+}
+
+// y-type rows from the M2L result g: -z_i + R_i g_i + PU(i) z_parent.
+__global__ void __launch_bounds__(WG) k_e_yrows_g(int nb, int q, const int* __restrict__ r,
+                                                  const double* __restrict__ R, const int64_t* __restrict__ roff,
+                                                  const double* __restrict__ g, const double* __restrict__ zl,
+                                                  const int* __restrict__ parent, const double* __restrict__ Ppre,
+                                                  const int64_t* __restrict__ ppoff, const int* __restrict__ pld,
+                                                  const int* __restrict__ rpar, const double* __restrict__ zpar,
+                                                  double* __restrict__ out) {
+  const int lane = threadIdx.x % WAVE;
+  const int i = (int)blockIdx.x * (WG / WAVE) + (int)(threadIdx.x / WAVE);
+  if (i >= nb) return;
+  const int ri = r[i];
+  if (lane >= ri) return;
+  const double* Ri = R + roff[i];
+  const double* gi = g + (int64_t)i * q;
+  double s = -zl[(int64_t)i * q + lane];
+  for (int k = 0; k < q; ++k) s += Ri[lane + (int64_t)k * ri] * gi[k];
+  if (parent) {
+    const int p = parent[i];
+    const double* Pi = Ppre + ppoff[i];
+    const int ld = pld[i];
+    for (int a = 0; a < rpar[p]; ++a) s += Pi[lane + (int64_t)a * ld] * zpar[(int64_t)p * q + a];
+  }
+  out[(int64_t)i * q + lane] = s;
+}
+
 // y-type rows at level l: -z_i + sum_{j in I(i)} K_pre(i,j) y_j + PU(i) z_parent.
 __global__ void k_e_yrows(int nb, int q, const int* __restrict__ r, const int* __restrict__ in_start,
                           const int* __restrict__ inter, const double* __restrict__ Kpre,
