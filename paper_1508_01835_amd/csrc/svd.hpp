@@ -212,6 +212,150 @@ __global__ void __launch_bounds__(SVD_WG) k_svd_small(const SvdDesc* __restrict_
   svd_finish(B, ldb, M, N, d.N, static_cast<T*>(d.U), d.ldu, static_cast<T*>(d.S), sh, d.perm, nrm, order);
 }
 
+// ------------------------------------------------------------- lane scheme
+// Matrices of at most NP rows and NP live columns (NP = 16, 32 or 64): a lane
+// per column pair. The NP / 2 lanes of a matrix each take one pair of the
+// round of the same tournament as the small scheme, form its inner product
+// over the rows and rotate it, so a round costs one pass over the rows and no
+// cross-lane reduction; 128 / NP matrices share a wavefront and each keeps
+// its own sweep count. Same rotation rule, sweeps and outputs as k_svd_small.
+template <class T, int NP>
+struct SvdLanes {
+  static constexpr int PPW = 2 * WAVE / NP;    // matrices per wavefront
+  static constexpr int WAVES = 4 * 16 / NP;    // wavefronts per workgroup
+};
+
+template <class T, int NP, int NT = SvdLanes<T, NP>::WAVES * WAVE>
+__global__ void __launch_bounds__(NT) k_svd_lanes(const SvdDesc* __restrict__ ds, int nd, double u, int max_sweeps,
+                                                  double defl) {
+  constexpr int PPW = SvdLanes<T, NP>::PPW, WAVES = SvdLanes<T, NP>::WAVES, H = NP / 2;
+  __shared__ T Bs[WAVES][PPW][NP][NP + 1];   // Bs[.][.][c][i] = B[i, c]
+  __shared__ T nrs[WAVES][PPW][NP];
+  __shared__ int ords[WAVES][PPW][NP];
+  const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+  const int grp = lane / H, k = lane % H;
+  const int prob = ((int)blockIdx.x * WAVES + w) * PPW + grp;
+  const bool valid = prob < nd;
+  SvdDesc d{};
+  if (valid) d = ds[prob];
+  const T* Bg = static_cast<const T*>(d.B);
+  const int M = valid ? d.M : 0, N = valid ? svd_cols(d) : 0;
+  T (*B)[NP + 1] = Bs[w][grp];
+  T* nr = nrs[w][grp];
+  int* ord = ords[w][grp];
+  auto wsync = [] {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  };
+  // exact power-of-two scaling of each matrix: its largest entry into [1, 2)
+  T am = 0;
+  for (int c = k; c < N; c += H)
+    for (int i = 0; i < M; ++i) am = fmax(am, fabs(Bg[i + (int64_t)c * d.ldb]));
+#pragma unroll
+  for (int o = H / 2; o > 0; o >>= 1) am = fmax(am, __shfl_xor(am, o, WAVE));
+  const int sh = am > (T)0 ? -ilogb((double)am) : 0;
+  for (int c = k; c < NP; c += H)
+    for (int i = 0; i < NP; ++i) B[c][i] = (c < N && i < M) ? ldexp(Bg[i + (int64_t)c * d.ldb], sh) : (T)0;
+  const T defl_s = (T)ldexp(defl, sh);
+  const T defl2 = defl_s * defl_s;
+  const T tol = (T)(u * fmax(4.0, sqrt((double)max(M, 1))));
+  auto norms2 = [&] {   // squared norms of the lane's two columns
+    for (int c = k; c < N; c += H) {
+      T s0 = 0, s1 = 0;
+      for (int i = 0; i < M; i += 2) {
+        s0 += B[c][i] * B[c][i];
+        s1 += B[c][i + 1] * B[c][i + 1];   // row M (when M is odd) is zero padding
+      }
+      nr[c] = s0 + s1;
+    }
+  };
+  const int np = N + (N & 1);
+  bool live = N >= 2;   // this matrix still sweeps
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    if (!__builtin_amdgcn_ballot_w64(live)) break;
+    if (live) norms2();
+    wsync();
+    bool rot = false;
+    const int rmax = np - 1;
+    int rw = live ? rmax : 0;   // rounds of the wavefront: the largest of its live matrices
+#pragma unroll
+    for (int o = H; o < WAVE; o <<= 1) rw = max(rw, __shfl_xor(rw, o, WAVE));
+    for (int r = 0; r < rw; ++r) {
+      if (live && r < rmax && k < np / 2) {
+        int x, y;
+        rr_pair(np, r, k, x, y);
+        if (x < N && y < N) {
+          const int p = min(x, y), q = max(x, y);
+          const T a = nr[p], b = nr[q];
+          if (a >= defl2 && b >= defl2) {
+            T g0 = 0, g1 = 0;
+            for (int i = 0; i < M; i += 2) {
+              g0 += B[p][i] * B[q][i];
+              g1 += B[p][i + 1] * B[q][i + 1];
+            }
+            const T g = g0 + g1;
+            if (fabs(g) > tol * sqrt(a * b)) {
+              const T zeta = (b - a) / ((T)2 * g);
+              const T t = (zeta >= (T)0 ? (T)1 : (T)-1) / (fabs(zeta) + sqrt((T)1 + zeta * zeta));
+              const T c = (T)1 / sqrt((T)1 + t * t);
+              const T sn = c * t;
+              for (int i = 0; i < M; ++i) {
+                const T xp = B[p][i], yq = B[q][i];
+                B[p][i] = c * xp - sn * yq;
+                B[q][i] = sn * xp + c * yq;
+              }
+              nr[p] = fmax((T)0, a - t * g);
+              nr[q] = b + t * g;
+              rot = true;
+            }
+          }
+        }
+      }
+      wsync();
+    }
+    // a matrix whose sweep rotated nothing is done
+    bool any = rot;
+#pragma unroll
+    for (int o = H / 2; o > 0; o >>= 1) any = any || __shfl_xor((int)any, o, WAVE);
+    live = live && any;
+  }
+  // finish: norms, decreasing order (ties by index, NaN last), U = B / norm, S
+  for (int c = k; c < N; c += H) {
+    T s0 = 0, s1 = 0;
+    for (int i = 0; i < M; i += 2) {
+      s0 += B[c][i] * B[c][i];
+      s1 += B[c][i + 1] * B[c][i + 1];
+    }
+    nr[c] = sqrt(s0 + s1);
+  }
+  wsync();
+  for (int c = k; c < N; c += H) {
+    const T v = nr[c] == nr[c] ? nr[c] : (T)-1;
+    int rk = 0;
+    for (int j = 0; j < N; ++j) {
+      const T x = nr[j] == nr[j] ? nr[j] : (T)-1;
+      rk += (x > v) || (x == v && j < c);
+    }
+    ord[rk] = c;
+  }
+  wsync();
+  if (!valid) return;
+  T* U = static_cast<T*>(d.U);
+  T* S = static_cast<T*>(d.S);
+  for (int c = k; c < d.N; c += H) {
+    if (c < N) {
+      const int src = ord[c];
+      const T sv = nr[src];
+      for (int i = 0; i < M; ++i) U[(d.perm ? d.perm[i] : i) + (int64_t)c * d.ldu] = sv > (T)0 ? B[src][i] / sv : (T)0;
+      S[c] = ldexp(sv, -sh);
+    } else {
+      for (int i = 0; i < M; ++i) U[i + (int64_t)c * d.ldu] = (T)0;
+      S[c] = (T)0;
+    }
+  }
+}
+
 // ------------------------------------------------------------- block scheme
 // Per matrix: shs[s] = the scaling exponent sh; flags[2s] = rotations in the
 // current sweep, flags[2s + 1] = converged.
@@ -901,6 +1045,16 @@ inline void run_qrcp(Problem& P, const std::vector<QrcpDesc>& v, DevBuf& scratch
     lds = std::max(lds, qrcp_lds<T>(q.m, q.n));
   }
   if (lds > QRCP_LDS_MAX) fail(IFMM_ERR_ARG, "a recompressed box is too large for the pivoted QR (x~ size)");
+  if (qr_stats_on()) {
+    int64_t sm = 0, sn = 0;
+    int mm = 0, mn = 0, h[5] = {0, 0, 0, 0, 0};
+    for (const auto& q : v) {
+      sm += q.m; sn += q.n; mm = std::max(mm, q.m); mn = std::max(mn, q.n);
+      ++h[q.n <= 16 ? 0 : q.n <= 32 ? 1 : q.n <= 64 ? 2 : q.n <= 128 ? 3 : 4];
+    }
+    std::fprintf(stderr, "[ifmm-qr] qrcp n=%zu sumM=%lld sumN=%lld maxM=%d maxN=%d le16=%d le32=%d le64=%d le128=%d gt=%d\n",
+                 v.size(), (long long)sm, (long long)sn, mm, mn, h[0], h[1], h[2], h[3], h[4]);
+  }
   if (!large && !force_streamed() && v.size() < 128 && nblk <= 2048) {
     run_qrcp_steps<T>(P, v, scratch, work, delta);
     return;
@@ -953,6 +1107,18 @@ inline void run_svd(Problem& P, const std::vector<SvdDesc>& v_in, DevBuf& scratc
     }
   }
   if (v.empty()) return;
+  if (qr_stats_on()) {   // shapes of the batch: count, sum and max of M and N, histogram of max(M, N)
+    int64_t sm = 0, sn = 0;
+    int mm = 0, mn = 0, h[5] = {0, 0, 0, 0, 0};
+    for (size_t t = 0; t < v.size(); ++t) {
+      const int nc = livecount[t] >= 0 ? livecount[t] : v[t].N;
+      sm += v[t].M; sn += nc; mm = std::max(mm, v[t].M); mn = std::max(mn, nc);
+      const int x = std::max(v[t].M, nc);
+      ++h[x <= 16 ? 0 : x <= 32 ? 1 : x <= 64 ? 2 : x <= 128 ? 3 : 4];
+    }
+    std::fprintf(stderr, "[ifmm-qr] svd n=%zu sumM=%lld sumN=%lld maxM=%d maxN=%d le16=%d le32=%d le64=%d le128=%d gt=%d\n",
+                 v.size(), (long long)sm, (long long)sn, mm, mn, h[0], h[1], h[2], h[3], h[4]);
+  }
   static const bool attr = [] {   // once per process (thread-safe initialisation)
     IFMM_HIP(hipFuncSetAttribute((const void*)k_svd_small<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                  (int)SVD_LDS_MAX));
@@ -961,7 +1127,7 @@ inline void run_svd(Problem& P, const std::vector<SvdDesc>& v_in, DevBuf& scratc
     return true;
   }();
   (void)attr;
-  std::vector<SvdDesc> small, big;
+  std::vector<SvdDesc> small, big, lanes[3];   // lane scheme: NP = 16, 32, 64
   std::vector<int> bigN;   // columns the block scheme plans for (live when known)
   size_t lds = 0;
   int bigM = 0, bigBlocks = 0;
@@ -970,7 +1136,9 @@ inline void run_svd(Problem& P, const std::vector<SvdDesc>& v_in, DevBuf& scratc
     if (s.N > SVD_MAXN && !s.nlive) fail(IFMM_ERR_INTERNAL, "SVD wider than SVD_MAXN");
     const int ncols = livecount[t] >= 0 ? livecount[t] : s.N;
     const size_t b = (size_t)s.M * ncols * sizeof(T);
-    if (b <= SVD_LDS_MAX && !force_streamed()) { small.push_back(s); lds = std::max(lds, b); }
+    const int mx = std::max(s.M, s.N);
+    if (mx <= 64 && !force_streamed()) lanes[mx <= 16 ? 0 : mx <= 32 ? 1 : 2].push_back(s);
+    else if (b <= SVD_LDS_MAX && !force_streamed()) { small.push_back(s); lds = std::max(lds, b); }
     else { big.push_back(s); bigN.push_back(ncols); bigM = std::max(bigM, s.M); }
   }
   // column block width of the block scheme: two blocks of M_max rows in LDS
@@ -980,7 +1148,27 @@ inline void run_svd(Problem& P, const std::vector<SvdDesc>& v_in, DevBuf& scratc
   const double u = Prec<T>::u;
   const int max_sweeps = 60;
   // algorithmic flops of an SVD with left vectors (LAWN 41 style): 4 M N^2 + 8 N^3
-  double fl_small = 0, fl_big = 0;
+  double fl_small = 0, fl_big = 0, fl_lanes = 0;
+  for (const auto& lv : lanes)
+    for (const auto& s : lv) fl_lanes += 4.0 * s.M * (double)s.N * s.N + 8.0 * (double)s.N * s.N * s.N;
+  if (fl_lanes > 0) {
+    P.kone_begin(KF_SVD_SMALL, fl_lanes);
+    auto go = [&](auto np_tag, const std::vector<SvdDesc>& lv) {
+      constexpr int NP = decltype(np_tag)::value;
+      if (lv.empty()) return;
+      const SvdDesc* dl = P.put(scratch, lv);
+      constexpr int per = SvdLanes<T, NP>::PPW * SvdLanes<T, NP>::WAVES;
+      hipLaunchKernelGGL((k_svd_lanes<T, NP>), dim3((unsigned)ceil_div((int64_t)lv.size(), per)),
+                         dim3(SvdLanes<T, NP>::WAVES * WAVE), 0, P.stream, dl, (int)lv.size(), Prec<T>::u, max_sweeps,
+                         defl);
+      IFMM_LAUNCH_CHECK();
+    };
+    go(std::integral_constant<int, 16>(), lanes[0]);
+    go(std::integral_constant<int, 32>(), lanes[1]);
+    go(std::integral_constant<int, 64>(), lanes[2]);
+    P.kone_end();
+  }
+  if (small.empty() && big.empty()) return;
   for (const auto& s : small) fl_small += 4.0 * s.M * (double)s.N * s.N + 8.0 * (double)s.N * s.N * s.N;
   for (const auto& s : big) fl_big += 4.0 * s.M * (double)s.N * s.N + 8.0 * (double)s.N * s.N * s.N;
   const size_t ns = small.size();
