@@ -712,11 +712,11 @@ struct QrJob {
 // lanes g NP .. g NP + NP - 1 of a wavefront own the columns of job g (NP =
 // 16, 32 or 64, so 4, 2 or 1 jobs per wavefront), and the rows stream through
 // in chunks of QC_CH (each lane holds its column of the chunk in registers)
-// while the running triangle R sits in LDS, column c with lane c. The chunk
-// is folded into R by one reflector per column j, acting on row j of R and
-// column j of the chunk: column j is broadcast to the job's lanes, and every
-// trailing column takes its dot product with it in its own lane, so no
-// reduction crosses lanes. The reflector convention is the panel kernel's
+// while the running triangle R sits in LDS, packed by columns, column c with
+// lane c. The chunk is folded into R by one reflector per column j, acting on
+// row j of R and column j of the chunk: column j is broadcast to the job's
+// lanes, and every trailing column takes its dot product with it in its own
+// lane, so no reduction crosses lanes. The reflector convention is the panel kernel's
 // (alpha = -sign(x0) ||x||, tau = (alpha - x0) / alpha, tau = 0 for a zero
 // column) and each job is scaled once by an exact power of two. A is left as
 // it was; R (min(M, N) x N, ldr, zero below the diagonal) is written at the end.
@@ -725,9 +725,12 @@ constexpr int QC_NMAX = 64;
 
 template <class T, int NP>
 struct QrCols {
-  static constexpr int G = WAVE / NP;   // jobs per wavefront
-  static constexpr int WAVES = sizeof(T) * G * NP * (NP + 1) > 20000 ? 2 : 4;
+  static constexpr int G = WAVE / NP;                 // jobs per wavefront
+  static constexpr int TRI = NP * (NP + 1) / 2;       // packed upper triangle of R
+  static constexpr int WAVES = 4;                     // at most 66.5 KB of LDS (FP64, NP = 64)
 };
+// R[i, c] (i <= c) of the packed column-major upper triangle
+__device__ inline int qc_tri(int i, int c) { return c * (c + 1) / 2 + i; }
 
 template <int G, class T>
 __device__ inline T qc_bcast(T x, int src) {
@@ -747,8 +750,8 @@ __device__ inline T qc_bcast(T x, int src) {
 
 template <class T, int NP, int NT = QrCols<T, NP>::WAVES * WAVE>
 __global__ void __launch_bounds__(NT) k_qr_cols(const QrJob* __restrict__ js, int nj) {
-  constexpr int G = QrCols<T, NP>::G, WAVES = QrCols<T, NP>::WAVES;
-  __shared__ T Rs[WAVES][G][NP][NP + 1];   // Rs[.][.][i][c] = R[i, c]
+  constexpr int G = QrCols<T, NP>::G, WAVES = QrCols<T, NP>::WAVES, TRI = QrCols<T, NP>::TRI;
+  __shared__ T Rs[WAVES][G][TRI];   // the running triangle, packed by columns
   const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
   const int g = lane / NP, c = lane % NP;
   const int t = ((int)blockIdx.x * WAVES + w) * G + g;
@@ -758,9 +761,8 @@ __global__ void __launch_bounds__(NT) k_qr_cols(const QrJob* __restrict__ js, in
   const int M = t < nj ? d.M : 0, N = t < nj ? d.N : 0;
   const int64_t lda = d.lda;
   const bool col = c < N;
-  T (*R)[NP + 1] = Rs[w][g];
-#pragma unroll 4
-  for (int i = 0; i < NP; ++i) R[i][c] = 0;
+  T* R = Rs[w][g];
+  for (int i = 0; i <= c; ++i) R[qc_tri(i, c)] = 0;
   // exact power-of-two scaling by the job's largest magnitude
   T am = 0;
   if (col)
@@ -790,21 +792,21 @@ __global__ void __launch_bounds__(NT) k_qr_cols(const QrJob* __restrict__ js, in
         d4[i & 3] += v[i] * x[i];
       }
       const T s = (s4[0] + s4[1]) + (s4[2] + s4[3]), dot = (d4[0] + d4[1]) + (d4[2] + d4[3]);
-      const T x0 = R[j < NP ? j : 0][j < NP ? j : 0];
+      const T x0 = R[qc_tri(j, j)];
       if (j < N && s > (T)0) {
         const T al = x0 >= (T)0 ? -sqrt(x0 * x0 + s) : sqrt(x0 * x0 + s);
         const T tj = (al - x0) / al;
         const T scal = (T)1 / (x0 - al);
         if (c > j && col) {
-          const T wc = tj * (R[j][c] + scal * dot);
-          R[j][c] -= wc;
+          const T wc = tj * (R[qc_tri(j, c)] + scal * dot);
+          R[qc_tri(j, c)] -= wc;
           const T f = wc * scal;
 #pragma unroll
           for (int i = 0; i < QC_CH; ++i) x[i] -= f * v[i];
         } else if (c == j) {
 #pragma unroll
           for (int i = 0; i < QC_CH; ++i) x[i] = 0;
-          R[j][j] = al;
+          R[qc_tri(j, j)] = al;
         }
       }
     }
@@ -812,7 +814,7 @@ __global__ void __launch_bounds__(NT) k_qr_cols(const QrJob* __restrict__ js, in
   const int kq = M < N ? M : N;
   if (col) {
     T* __restrict__ Ro = static_cast<T*>(d.R);
-    for (int i = 0; i < kq; ++i) Ro[i + c * d.ldr] = i <= c ? ldexp(R[i][c], -sh) : (T)0;
+    for (int i = 0; i < kq; ++i) Ro[i + c * d.ldr] = i <= c ? ldexp(R[qc_tri(i, c)], -sh) : (T)0;
   }
 }
 

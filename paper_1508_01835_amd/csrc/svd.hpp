@@ -509,6 +509,148 @@ inline size_t qrcp_lds(int m, int n) {
 }
 constexpr size_t QRCP_LDS_MAX = 144 * 1024;
 
+// The same truncated pivoted QR for n <= NP (NP = 16, 32 or 64), a lane per
+// column: 64 / NP problems share a wavefront, lane c of a problem owns
+// column c (its partial norms and its place in the pivoted order), and the
+// problem's R sits in LDS. The pivot is a reduction over the problem's lanes
+// (largest partial norm, first place on ties); columns are not moved, their
+// places are; the reflector's norm is a reduction with lane i reading row i
+// (m <= n <= NP); each trailing column applies it, downdates or recomputes
+// its partial norm in its own lane. Same stop rule and outputs as k_qrcp.
+template <class T, int NP>
+struct QrcpLanes {
+  static constexpr int G = WAVE / NP;
+  static constexpr int PER_WAVE = (int)sizeof(T) * G * NP * (NP + 1);
+  static constexpr int WAVES = PER_WAVE * 8 <= 69632 ? 8 : PER_WAVE * 4 <= 69632 ? 4 : 2;
+};
+
+template <class T, int NP, int NT = QrcpLanes<T, NP>::WAVES * WAVE>
+__global__ void __launch_bounds__(NT) k_qrcp_lanes(const QrcpDesc* __restrict__ ds, int nd, double delta) {
+  constexpr int G = QrcpLanes<T, NP>::G, WAVES = QrcpLanes<T, NP>::WAVES;
+  __shared__ T Rs[WAVES][G][NP][NP + 1];   // Rs[.][.][c][i] = R[i, c]
+  const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+  const int g = lane / NP, c = lane % NP;
+  const int prob = ((int)blockIdx.x * WAVES + w) * G + g;
+  const bool valid = prob < nd;
+  QrcpDesc d{};
+  if (valid) d = ds[prob];
+  const int m = valid ? d.m : 0, n = valid ? d.n : 0;
+  const bool col = c < n;
+  T (*R)[NP + 1] = Rs[w][g];
+  const T* Rg = static_cast<const T*>(d.R);
+  auto gmax = [](T v) {
+#pragma unroll
+    for (int o = NP / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, WAVE));
+    return v;
+  };
+  auto gsum = [](T v) {
+#pragma unroll
+    for (int o = NP / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+    return v;
+  };
+  T am = 0;
+  if (col)
+    for (int i = 0; i < m; ++i) am = fmax(am, fabs(Rg[i + (int64_t)c * d.ldr]));
+  am = gmax(am);
+  const int sh = am > (T)0 ? -ilogb((double)am) : 0;
+  T s2 = 0;
+  for (int i = 0; i < NP; ++i) {
+    const T x = (col && i < m) ? ldexp(Rg[i + (int64_t)c * d.ldr], sh) : (T)0;
+    R[c][i] = x;
+    s2 += x * x;
+  }
+  T vn1 = col ? sqrt(s2) : (T)0, vn2 = vn1;
+  int pos = c;                  // place of this column in the pivoted order
+  bool done = !col;             // chosen as a pivot (or no column)
+  const T dl = (T)ldexp(delta, sh);
+  const T tol3z = sqrt((T)Prec<T>::u);
+  const int kfull = min(m, n);
+  int k = 0;
+  bool stopped = false;
+  T stop = 0;
+  int kw = kfull;   // steps of the wavefront: the largest of its problems
+#pragma unroll
+  for (int o = NP; o < WAVE; o <<= 1) kw = max(kw, __shfl_xor(kw, o, WAVE));
+  bool act = valid;   // this problem still factors
+  for (int s = 0; s < kw; ++s) {
+    act = act && s < kfull && !stopped;
+    // pivot: the largest remaining partial norm, first place on ties; remaining Frobenius norm
+    T best = (!done && act) ? vn1 : (T)-1;
+    int bp = (!done && act) ? pos : NP;
+    T ss = (!done && act) ? vn1 * vn1 : (T)0;
+#pragma unroll
+    for (int o = NP / 2; o > 0; o >>= 1) {
+      const T ob = __shfl_xor(best, o, WAVE);
+      const int op = __shfl_xor(bp, o, WAVE);
+      if (ob > best || (ob == best && op < bp)) { best = ob; bp = op; }
+      ss += __shfl_xor(ss, o, WAVE);
+    }
+    if (s == 0) stop = fmax(dl, (T)4 * (T)Prec<T>::u * sqrt(ss));
+    if (act && sqrt(ss) <= stop) { stopped = true; act = false; }
+    // the pivot column: the lane whose place is bp; it moves to place s, the column at place s to bp
+    const bool piv = act && !done && pos == bp;
+    int pl = piv ? c : -1;
+#pragma unroll
+    for (int o = NP / 2; o > 0; o >>= 1) pl = max(pl, __shfl_xor(pl, o, WAVE));
+    if (act && !done && pos == s) pos = bp;
+    if (piv) { pos = s; done = true; }
+    // reflector of column pl, rows s..m-1; lane i reads row i
+    T x0 = 0, x2 = 0;
+    if (act) {
+      x0 = R[pl][s];
+      const T xi = (c > s && c < m) ? R[pl][c] : (T)0;
+      x2 = xi * xi;
+    }
+    x2 = gsum(x2);
+    T tau = 0, beta = x0, scale = 0;
+    if (x2 > (T)0) {
+      beta = x0 >= (T)0 ? -sqrt(x0 * x0 + x2) : sqrt(x0 * x0 + x2);
+      tau = (beta - x0) / beta;
+      scale = (T)1 / (x0 - beta);
+    }
+    if (act && !done) {   // a trailing column: apply, then downdate or recompute the partial norm
+      T wv = R[c][s];
+      for (int i = s + 1; i < m; ++i) wv += R[pl][i] * scale * R[c][i];
+      wv *= tau;
+      T rest = 0;
+      const T rs = R[c][s] - wv;
+      R[c][s] = rs;
+      for (int i = s + 1; i < m; ++i) {
+        const T x = R[c][i] - wv * (R[pl][i] * scale);
+        R[c][i] = x;
+        rest += x * x;
+      }
+      if (vn1 != (T)0) {
+        const T r = fabs(rs) / vn1;
+        const T t = fmax((T)0, ((T)1 + r) * ((T)1 - r));
+        const T q = vn1 / vn2;
+        if (t * q * q <= tol3z) { vn1 = sqrt(rest); vn2 = vn1; }
+        else vn1 *= sqrt(t);
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (act && c == pl) {   // the pivot column itself: beta on the diagonal, zeros below
+      R[c][s] = beta;
+      for (int i = s + 1; i < m; ++i) R[c][i] = (T)0;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (act) k = s + 1;
+  }
+  if (!valid || !col) return;
+  // Y = R'[0:k, :]^T: the column at place p gives row p of Y
+  T* __restrict__ Y = static_cast<T*>(d.Y);
+  for (int r = 0; r < k; ++r) Y[pos + (int64_t)r * d.ldy] = pos >= r ? ldexp(R[c][r], -sh) : (T)0;
+  d.perm[pos] = c;
+  if (c == 0) {
+    *d.kout = k;
+    if (!stopped && k == SVD_MAXK && kfull > SVD_MAXK && d.over) *d.over = 1;
+  }
+}
+
 template <class T>
 __global__ void __launch_bounds__(SVD_WG) k_qrcp(const QrcpDesc* __restrict__ ds, double delta) {
   extern __shared__ unsigned char qrcp_dyn[];
@@ -1054,6 +1196,34 @@ inline void run_qrcp(Problem& P, const std::vector<QrcpDesc>& v, DevBuf& scratch
     }
     std::fprintf(stderr, "[ifmm-qr] qrcp n=%zu sumM=%lld sumN=%lld maxM=%d maxN=%d le16=%d le32=%d le64=%d le128=%d gt=%d\n",
                  v.size(), (long long)sm, (long long)sn, mm, mn, h[0], h[1], h[2], h[3], h[4]);
+  }
+  // problems of at most 64 columns: a lane per column
+  std::vector<QrcpDesc> lanes[3], rest;
+  for (const auto& q : v) {
+    if (q.n <= 64 && !force_streamed()) lanes[q.n <= 16 ? 0 : q.n <= 32 ? 1 : 2].push_back(q);
+    else rest.push_back(q);
+  }
+  if (rest.size() < v.size()) {
+    double fl = 0;
+    for (const auto& lv : lanes)
+      for (const auto& q : lv) fl += 2.0 * q.n * (double)q.m * q.m - 2.0 / 3.0 * (double)q.m * q.m * q.m;
+    P.kone_begin(KF_QRCP, fl);
+    auto go = [&](auto np_tag, const std::vector<QrcpDesc>& lv) {
+      constexpr int NP = decltype(np_tag)::value;
+      if (lv.empty()) return;
+      const QrcpDesc* dl = P.put(scratch, lv);
+      constexpr int per = QrcpLanes<T, NP>::G * QrcpLanes<T, NP>::WAVES;
+      hipLaunchKernelGGL((k_qrcp_lanes<T, NP>), dim3((unsigned)ceil_div((int64_t)lv.size(), per)),
+                         dim3(QrcpLanes<T, NP>::WAVES * WAVE), 0, P.stream, dl, (int)lv.size(), delta);
+      IFMM_LAUNCH_CHECK();
+    };
+    go(std::integral_constant<int, 16>(), lanes[0]);
+    go(std::integral_constant<int, 32>(), lanes[1]);
+    go(std::integral_constant<int, 64>(), lanes[2]);
+    P.kone_end();
+    if (rest.empty()) return;
+    run_qrcp<T>(P, rest, scratch, work, delta);
+    return;
   }
   if (!large && !force_streamed() && v.size() < 128 && nblk <= 2048) {
     run_qrcp_steps<T>(P, v, scratch, work, delta);
