@@ -52,7 +52,23 @@ PEAKS = {  # MI355X published peaks
     "fp32_vec_TFs": 157.3,
     "fp32_mfma_TFs": 157.3,
 }
-from paper_1508_01835_amd.ifmm import KERNEL_OF_FAMILY, KFAMILIES as FAMILIES  # noqa: E402
+from paper_1508_01835_amd.ifmm import KERNEL_OF_FAMILY, KERNEL_TYPED, KFAMILIES as FAMILIES  # noqa: E402
+
+
+def family_roofline(name, flops, ms, launches, steps, precision):
+    """Roofline entry of a single-kernel family: the rocprof kernel name and the peak it is held to. K_pre runs
+    on the FP64 matrix cores; the other families run on the vector ALUs in the handle's precision (FP32:
+    256 CUs x 2.4 GHz x 256 flop/clk = 157.3 TFLOP/s; FP64: 78.6 TFLOP/s)."""
+    tname = "<float>" if precision == 32 else "<double>"
+    kname = KERNEL_OF_FAMILY[name] + (tname if KERNEL_TYPED[name] else "")
+    if name == "kpre":
+        bound, peak = "mfma", PEAKS["fp64_TFs"]
+    else:
+        bound, peak = "alu", PEAKS["fp32_vec_TFs"] if precision == 32 else PEAKS["fp64_TFs"]
+    achieved = flops / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
+    return {"bound": bound, "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+            "traffic": MEASURED_TRAFFIC.get(kname), "kernel": kname, "launches_per_step": launches / steps,
+            "avg_launch_ms": ms / max(launches, 1), "flops_per_launch": flops / max(launches, 1)}
 
 
 def log(*a):
@@ -190,13 +206,7 @@ def run_cluster3d(args):
     fam_fl = [sum(s_["kfam_flops"][f] for s_ in stats) for f in range(len(FAMILIES))]
     fam_nl = [sum(s_["kfam_launches"][f] for s_ in stats) for f in range(len(FAMILIES))]
     name = FAMILIES[dom_w]
-    kname = KERNEL_OF_FAMILY[name] + "<float>"
-    # this family's kernels run on the vector ALUs in FP32 (157.3 TFLOP/s: 256 CUs x 2.4 GHz x 256 flop/clk)
-    achieved = fam_fl[dom_w] / (fam_ms[dom_w] * 1e-3) / 1e12 if fam_ms[dom_w] > 0 else 0.0
-    roof = {"bound": "alu", "achieved": achieved, "peak": PEAKS["fp32_vec_TFs"], "unit": "TFLOP/s",
-            "frac": achieved / PEAKS["fp32_vec_TFs"], "traffic": MEASURED_TRAFFIC.get(kname), "kernel": kname,
-            "launches_per_step": fam_nl[dom_w] / K, "avg_launch_ms": fam_ms[dom_w] / max(fam_nl[dom_w], 1),
-            "flops_per_launch": fam_fl[dom_w] / max(fam_nl[dom_w], 1)}
+    roof = family_roofline(name, fam_fl[dom_w], fam_ms[dom_w], fam_nl[dom_w], K, 32)
     breakdown = {FAMILIES[f]: round(warm_stats["kfam_ms"][f], 1) for f in range(len(FAMILIES))
                  if warm_stats["kfam_ms"][f] > 0}
     flops32 = float(np.mean([s_["factor_flops"] for s_ in stats]))
@@ -614,15 +624,7 @@ def main():
     fam_nl = [sum(s["kfam_launches"][f] for s in stats) for f in range(len(FAMILIES))]
     dom = max(single, key=lambda f: fam_ms[f])
     name = FAMILIES[dom]
-    # FP64 arithmetic on the vector ALUs (FMA): 256 CUs x 2.4 GHz x 128 flop/clk = 78.6 TFLOP/s
-    achieved = fam_fl[dom] / (fam_ms[dom] * 1e-3) / 1e12
-    roof = {"bound": "alu", "achieved": achieved, "peak": PEAKS["fp64_TFs"], "unit": "TFLOP/s",
-            "frac": achieved / PEAKS["fp64_TFs"],
-            "traffic": MEASURED_TRAFFIC.get(KERNEL_OF_FAMILY[name] + "<double>"),
-            "kernel": KERNEL_OF_FAMILY[name] + "<double>",
-            "launches_per_step": fam_nl[dom] / args.steps,
-            "avg_launch_ms": fam_ms[dom] / max(fam_nl[dom], 1),
-            "flops_per_launch": fam_fl[dom] / max(fam_nl[dom], 1)}
+    roof = family_roofline(name, fam_fl[dom], fam_ms[dom], fam_nl[dom], args.steps, 64)
     if warm_stats is not None:   # every family, from the last warm-up step
         breakdown = {FAMILIES[f]: round(warm_stats["kfam_ms"][f], 2) for f in range(len(FAMILIES))
                      if warm_stats["kfam_ms"][f] > 0}

@@ -605,12 +605,19 @@ inline void build_r2(Problem& P, double sigma0_override) {
           }
         DevBuf dtl = up(P, tl), dwg;
         P.upload(dwg, wg);
+        double fl = 0;   // R_i K~ (r_i q^2 products) then times R_j^T (r_i q r_j), once per unordered pair
+        for (int i = 0; i < lv.nb; ++i)
+          for (int t = lv.in_start[i]; t < lv.in_start[i + 1]; ++t)
+            if (lv.inter[t] > i) fl += 2.0 * R.r[l][i] * q * (q + R.r[l][lv.inter[t]]);
+        P.kone_begin(KF_KPRE, fl);
         hipLaunchKernelGGL(k_kpre_tile, dim3((unsigned)wg.size()), dim3(256), 0, P.stream, dwg.as<KpreWg>(),
-                           dtl.as<int>(), P.ldev[l].m2l_bo.as<int>(), P.ldev[l].inter.as<int>(), P.m2l_nofs,
+                           dtl.as<int>(), P.ldev[l].m2l_bo.as<int>(), P.ldev[l].inter.as<int>(),
+                           P.ldev[l].in_rev.as<int>(), P.m2l_nofs,
                            P.m2l_ocode.as<int>(), q, P.m2l[l].as<double>(), R.R[l].as<double>(),
                            R.droff[l].as<int64_t>(), R.dr[l].as<int>(), R.Kpre[l].as<double>(),
                            R.dkpoff[l].as<int64_t>());
         IFMM_LAUNCH_CHECK();
+        P.kone_end();
         P.sync();   // the launch tables are freed at the end of this scope
       } else if ((int64_t)rmx * q <= SWW)   // a wavefront per pair
         hipLaunchKernelGGL(k_kpre_w, dim3((unsigned)ceil_div(np, WG / WAVE)), dim3(WG), 0, P.stream,

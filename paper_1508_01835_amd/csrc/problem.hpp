@@ -49,7 +49,7 @@ struct FactorStoreBase {
 enum KFam {
   KF_SCHUR = 0, KF_LU, KF_TRSM, KF_QR, KF_SVD, KF_XFORM, KF_SOLVE, KF_MATVEC, KF_OTHER,
   KF_SVD_ROUND, KF_QR_PANEL, KF_QRCP, KF_SVD_SMALL, KF_ROW_XFORM, KF_COL_XFORM, KF_QRCP_STEP, KF_QR_NARROW,
-  KF_COUNT
+  KF_KPRE, KF_COUNT
 };
 static_assert(KF_COUNT <= 24, "the query structure holds 24 families");
 

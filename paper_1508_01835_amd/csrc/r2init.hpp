@@ -135,13 +135,16 @@ __global__ void __launch_bounds__(WG) k_kpre_w(const int* __restrict__ in_start,
 // layout, and multiplies by R_j^T, R_j read straight from memory, j the
 // source at offset o. Every entry is summed in a fixed order (over the table
 // index in steps of 4, then over the source node), whatever the grouping.
+// The kernels are radial, so K~_{-o} = K~_o^T and K_pre(j, i) = K_pre(i, j)^T:
+// each unordered pair is formed once, by its smaller box, and stored both ways.
 struct KpreWg {
   int start, cnt, rb, pos;   // targets tlist[start .. start + cnt), 16-row blocks per target, child position
 };
 
 __global__ void __launch_bounds__(256, 2) k_kpre_tile(const KpreWg* __restrict__ wgs, const int* __restrict__ tlist,
                                                    const int* __restrict__ bo, const int* __restrict__ inter,
-                                                   int nofs, const int* __restrict__ ocode, int q,
+                                                   const int* __restrict__ rev, int nofs,
+                                                   const int* __restrict__ ocode, int q,
                                                    const double* __restrict__ tab, const double* __restrict__ R,
                                                    const int64_t* __restrict__ roff, const int* __restrict__ r,
                                                    double* __restrict__ K, const int64_t* __restrict__ koff) {
@@ -169,14 +172,16 @@ __global__ void __launch_bounds__(256, 2) k_kpre_tile(const KpreWg* __restrict__
   const int* codes = ocode + g.pos * nofs;
   for (int o = 0; o < nofs; ++o) {
     const int t = act ? bo[(int64_t)ti * nofs + o] : -1;
-    if (!__syncthreads_or(t >= 0)) continue;   // also: the previous offset's reads of Ks are done
+    const int j = t >= 0 ? inter[t] : -1;
+    const bool need = j > ti;   // the pair's smaller box forms it
+    if (!__syncthreads_or(need)) continue;   // also: the previous offset's reads of Ks are done
     const double* Kt = tab + (int64_t)codes[o] * q * q;
     for (int e = threadIdx.x; e < 64 * 64; e += 256) {
       const int k = e & 63, n = e >> 6;
       Ks[k][n] = (k < q && n < q) ? Kt[k + (int64_t)n * q] : 0.0;
     }
     __syncthreads();
-    if (t < 0) continue;
+    if (!need) continue;
     v4d x[4];
 #pragma unroll
     for (int cb = 0; cb < 4; ++cb) x[cb] = v4d{0, 0, 0, 0};
@@ -196,7 +201,7 @@ __global__ void __launch_bounds__(256, 2) k_kpre_tile(const KpreWg* __restrict__
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    const int j = inter[t], rj = r[j];
+    const int rj = r[j];
     const double* Rj = R + roff[j];
     const int nyb = (rj + 15) / 16;
     v4d y[4];
@@ -216,13 +221,17 @@ __global__ void __launch_bounds__(256, 2) k_kpre_tile(const KpreWg* __restrict__
       }
     }
     double* out = K + koff[t];
+    double* outT = K + koff[rev[t]];   // K_pre(j, i): rj x ri
 #pragma unroll
     for (int cb = 0; cb < 4; ++cb) {
       const int b = 16 * cb + (lane & 15);
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int a = 16 * rb + 4 * e + (lane >> 4);
-        if (cb < nyb && a < ri && b < rj) out[a + (int64_t)b * ri] = y[cb][e];
+        if (cb < nyb && a < ri && b < rj) {
+          out[a + (int64_t)b * ri] = y[cb][e];
+          outT[b + (int64_t)a * rj] = y[cb][e];
+        }
       }
     }
     // Xs is rewritten only after the next offset's barrier

@@ -47,11 +47,12 @@ class Stats(ctypes.Structure):
 
 KFAMILIES = ["schur_gemm", "pivot_lu", "trsm_w", "qr", "jacobi_svd", "edge_update", "solve", "matvec", "other",
              "svd_round", "qr_panel", "qrcp", "svd_small", "row_xform", "col_xform", "qrcp_step", "qr_narrow",
-             "unused17", "unused18", "unused19", "unused20", "unused21", "unused22", "unused23"]
+             "kpre", "unused18", "unused19", "unused20", "unused21", "unused22", "unused23"]
 # families holding exactly one kernel (per-launch timing), with its name
-KERNEL_OF_FAMILY = {"svd_round": "k_svd_round", "qr_panel": "k_qr_panel", "qrcp": "k_qrcp",
-                    "svd_small": "k_svd_small", "row_xform": "k_row_xform", "col_xform": "k_col_xform",
-                    "qr_narrow": "k_qr_narrow"}
+# families whose timed ranges each hold one launch of one kernel (rocprof name, templated on the element
+# type or not); the other families span several kernels
+KERNEL_OF_FAMILY = {"svd_round": "k_svd_round", "qr_panel": "k_qr_panel", "kpre": "k_kpre_tile"}
+KERNEL_TYPED = {"svd_round": True, "qr_panel": True, "kpre": False}
 
 
 EXPORTS = ["ifmm_default_options", "ifmm_build", "ifmm_factorize", "ifmm_factorize_batch", "ifmm_solve",
