@@ -819,16 +819,48 @@ __global__ void __launch_bounds__(NT) k_qr_cols(const QrJob* __restrict__ js, in
 }
 
 struct QrScratch {
-  DevBuf w, pd, gd, od, nw, od2;
+  DevBuf w, pd, gd, nw;
 };
 
-// Narrow jobs on the one-wavefront kernel. A wavefront streams its rows one
-// after the other, so a tall matrix (M > QR_SEG_MIN) is cut into S row
-// segments of about sqrt(M N) rows (at least 32 >= N, so each segment's
-// triangle is a full N x N); their triangles, stacked into an S N x N matrix,
-// are reduced by a second launch to the job's R. Both stages then stream
-// about sqrt(M N) / 64 chunks per wavefront.
-constexpr int QR_SEG_MIN = 1024;
+// Narrow jobs on the column-per-lane kernel. A wavefront streams its rows one
+// chunk after the other, so the time of a launch is that of its tallest job:
+// a job of more than QR_SEG_MAX rows is cut into segments of about
+// QR_SEG_ROWS rows (at least 64 >= N, so every segment's triangle is a full
+// N x N), and the stacked triangles (S N rows) form the job of the next
+// level, cut again while still too tall (a fixed-order reduction tree).
+constexpr int QR_SEG_MAX = 1024, QR_SEG_ROWS = 512;
+
+template <class T>
+inline void qr_narrow_launch(Problem& P, std::vector<QrJob>& v) {
+  // one launch per column class (16, 32, 64), the jobs of a class contiguous
+  std::stable_sort(v.begin(), v.end(), [](const QrJob& a, const QrJob& b) {
+    return (a.N > 16) + (a.N > 32) < (b.N > 16) + (b.N > 32);
+  });
+  DevBuf unused;
+  const QrJob* dv = P.put(unused, v);
+  size_t b0 = 0;
+  while (b0 < v.size()) {
+    const int cls = (v[b0].N > 16) + (v[b0].N > 32);
+    size_t b1 = b0;
+    while (b1 < v.size() && (v[b1].N > 16) + (v[b1].N > 32) == cls) ++b1;
+    const int n = (int)(b1 - b0);
+    if (cls == 0) {
+      constexpr int per = QrCols<T, 16>::G * QrCols<T, 16>::WAVES;
+      hipLaunchKernelGGL((k_qr_cols<T, 16>), dim3((unsigned)ceil_div(n, per)), dim3(QrCols<T, 16>::WAVES * WAVE), 0,
+                         P.stream, dv + b0, n);
+    } else if (cls == 1) {
+      constexpr int per = QrCols<T, 32>::G * QrCols<T, 32>::WAVES;
+      hipLaunchKernelGGL((k_qr_cols<T, 32>), dim3((unsigned)ceil_div(n, per)), dim3(QrCols<T, 32>::WAVES * WAVE), 0,
+                         P.stream, dv + b0, n);
+    } else {
+      constexpr int per = QrCols<T, 64>::G * QrCols<T, 64>::WAVES;
+      hipLaunchKernelGGL((k_qr_cols<T, 64>), dim3((unsigned)ceil_div(n, per)), dim3(QrCols<T, 64>::WAVES * WAVE), 0,
+                         P.stream, dv + b0, n);
+    }
+    IFMM_LAUNCH_CHECK();
+    b0 = b1;
+  }
+}
 
 template <class T>
 inline void qr_narrow_run(Problem& P, const std::vector<QrJob>& narrow, QrScratch& S) {
@@ -837,82 +869,55 @@ inline void qr_narrow_run(Problem& P, const std::vector<QrJob>& narrow, QrScratc
     const double a = std::max(j.M, j.N), b = std::min(j.M, j.N);
     fl += 2.0 * a * b * b - 2.0 / 3.0 * b * b * b;
   }
-  std::vector<QrJob> s1, s2;
-  s1.reserve(narrow.size());
-  // segments of at least 64 rows: every segment's triangle is a full N x N
-  std::vector<int> nseg(narrow.size(), 1);
+  auto nseg = [](const QrJob& j) { return j.M > QR_SEG_MAX && j.M > j.N ? (int)ceil_div(j.M, QR_SEG_ROWS) : 1; };
+  // stacked triangles of the first level bound every later level (each is at most a quarter of the one before)
   int64_t stack = 0;
-  for (size_t t = 0; t < narrow.size(); ++t) {
-    const auto& j = narrow[t];
-    if (j.M > QR_SEG_MIN && j.M > j.N) {
-      const int64_t seg = std::max<int64_t>(128, (int64_t)std::ceil(std::sqrt((double)j.M * std::max(j.N, 1))));
-      nseg[t] = (int)ceil_div(j.M, seg);
-      stack += (int64_t)nseg[t] * j.N * j.N;
-    }
+  for (const auto& j : narrow) {
+    const int ns = nseg(j);
+    if (ns > 1) stack += (int64_t)ns * j.N * j.N;
   }
-  if (stack > 0 && (size_t)stack * sizeof(T) > S.nw.bytes) {
+  if (stack > 0 && (size_t)stack * 2 * sizeof(T) > S.nw.bytes) {
     P.sync();
-    S.nw.alloc((size_t)stack * sizeof(T) * 5 / 4 + 64, &P.mem);
+    S.nw.alloc((size_t)stack * 2 * sizeof(T) + 64, &P.mem);
   }
-  T* W = stack > 0 ? S.nw.template as<T>() : nullptr;
-  int64_t off = 0;
-  for (size_t t = 0; t < narrow.size(); ++t) {
-    const auto& j = narrow[t];
-    if (nseg[t] == 1) {
-      s1.push_back(j);
-      continue;
-    }
-    const int ns = nseg[t], ld = ns * j.N;
-    const int per = j.M / ns;   // > seg (ns - 1) / ns >= 64 >= N; the last segment takes the rest
-    for (int k = 0; k < ns; ++k) {
-      const int r0 = k * per, mk = k + 1 < ns ? per : j.M - r0;
-      s1.push_back({static_cast<T*>(j.A) + r0, W + off + (int64_t)k * j.N, mk, j.N, j.lda, ld});
-    }
-    s2.push_back({W + off, j.R, ld, j.N, ld, j.ldr});
-    off += (int64_t)ns * j.N * j.N;
-  }
-  if (qr_stats_on()) {
-    int64_t sm = 0, sm2 = 0;
-    int mx = 0, nx = 0, mx2 = 0;
-    for (const auto& j : narrow) { sm += j.M; mx = std::max(mx, j.M); nx = std::max(nx, j.N); }
-    for (const auto& j : s2) { sm2 += j.M; mx2 = std::max(mx2, j.M); }
-    std::fprintf(stderr, "[ifmm-qr] narrow jobs=%zu sumM=%lld maxM=%d maxN=%d stage1=%zu stage2=%zu sumM2=%lld maxM2=%d\n",
-                 narrow.size(), (long long)sm, mx, nx, s1.size(), s2.size(), (long long)sm2, mx2);
-  }
+  T* buf[2] = {stack > 0 ? S.nw.template as<T>() : nullptr, stack > 0 ? S.nw.template as<T>() + stack : nullptr};
+  std::vector<QrJob> cur(narrow), next, run;
+  int levels = 0;
+  int64_t rows0 = 0, rows_more = 0;
   P.kone_begin(KF_QR_NARROW, fl);
-  // one launch per column class (16, 32, 64), jobs of a class contiguous
-  auto launch = [&](std::vector<QrJob>& v, DevBuf& buf) {
-    std::stable_sort(v.begin(), v.end(), [](const QrJob& a, const QrJob& b) {
-      return (a.N > 16) + (a.N > 32) < (b.N > 16) + (b.N > 32);
-    });
-    const QrJob* dv = P.put(buf, v);
-    size_t b0 = 0;
-    while (b0 < v.size()) {
-      const int cls = (v[b0].N > 16) + (v[b0].N > 32);
-      size_t b1 = b0;
-      while (b1 < v.size() && (v[b1].N > 16) + (v[b1].N > 32) == cls) ++b1;
-      const int n = (int)(b1 - b0);
-      if (cls == 0) {
-        constexpr int per = QrCols<T, 16>::G * QrCols<T, 16>::WAVES;
-        hipLaunchKernelGGL((k_qr_cols<T, 16>), dim3((unsigned)ceil_div(n, per)), dim3(QrCols<T, 16>::WAVES * WAVE),
-                           0, P.stream, dv + b0, n);
-      } else if (cls == 1) {
-        constexpr int per = QrCols<T, 32>::G * QrCols<T, 32>::WAVES;
-        hipLaunchKernelGGL((k_qr_cols<T, 32>), dim3((unsigned)ceil_div(n, per)), dim3(QrCols<T, 32>::WAVES * WAVE),
-                           0, P.stream, dv + b0, n);
-      } else {
-        constexpr int per = QrCols<T, 64>::G * QrCols<T, 64>::WAVES;
-        hipLaunchKernelGGL((k_qr_cols<T, 64>), dim3((unsigned)ceil_div(n, per)), dim3(QrCols<T, 64>::WAVES * WAVE),
-                           0, P.stream, dv + b0, n);
+  for (int lev = 0; !cur.empty(); ++lev) {
+    run.clear();
+    next.clear();
+    T* W = buf[lev & 1];
+    int64_t off = 0;
+    for (const auto& j : cur) {
+      (lev == 0 ? rows0 : rows_more) += j.M;
+      const int ns = nseg(j);
+      if (ns == 1) {
+        run.push_back(j);
+        continue;
       }
-      IFMM_LAUNCH_CHECK();
-      b0 = b1;
+      const int ld = ns * j.N;
+      const int per = j.M / ns;   // > QR_SEG_ROWS (ns - 1) / ns >= 256 >= N; the last segment takes the rest
+      for (int k = 0; k < ns; ++k) {
+        const int r0 = k * per, mk = k + 1 < ns ? per : j.M - r0;
+        run.push_back({static_cast<T*>(j.A) + r0, W + off + (int64_t)k * j.N, mk, j.N, j.lda, ld});
+      }
+      next.push_back({W + off, j.R, ld, j.N, ld, j.ldr});
+      off += (int64_t)ns * j.N * j.N;
     }
-  };
-  launch(s1, S.od);
-  if (!s2.empty()) launch(s2, S.od2);
+    qr_narrow_launch<T>(P, run);
+    cur.swap(next);
+    levels = lev + 1;
+  }
   P.kone_end();
   if (P.kt.on && P.kcur >= 0) P.kt.flops[P.kcur] -= fl;
+  if (qr_stats_on()) {
+    int mx = 0, nx = 0;
+    for (const auto& j : narrow) { mx = std::max(mx, j.M); nx = std::max(nx, j.N); }
+    std::fprintf(stderr, "[ifmm-qr] narrow jobs=%zu sumM=%lld maxM=%d maxN=%d levels=%d rows_after_first=%lld\n",
+                 narrow.size(), (long long)rows0, mx, nx, levels, (long long)rows_more);
+  }
 }
 
 template <class T>
@@ -1001,7 +1006,7 @@ inline void qr_blocked(Problem& P, const std::vector<QrJob>& jobs_in, QrScratch&
     ov.push_back({j.A, W + off[b], j.R, j.M, j.N, j.lda, j.ldr});
   }
   if (!ov.empty()) {
-    const QrOut* d = P.put(S.od, ov);
+    const QrOut* d = P.put(S.pd, ov);
     P.kbegin();
     hipLaunchKernelGGL(k_qr_extract<T>, dim3((unsigned)ov.size()), dim3(WG), 0, P.stream, d);
     IFMM_LAUNCH_CHECK();

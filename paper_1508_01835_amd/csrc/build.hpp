@@ -189,6 +189,8 @@ inline void build_near_cache(Problem& P) {
   const char* env = std::getenv("IFMM_NEAR_CACHE");
   if ((env && env[0] == '0') || P.n > (int64_t)WAVE * nb) return;
   const HLevel& lv = T.lev[L];
+  for (int i = 0; i < nb; ++i)   // the product holds a box's neighbours one per lane
+    if (lv.nb_start[i + 1] - lv.nb_start[i] > WAVE) return;
   std::vector<int64_t> off(nb);
   std::vector<int> col(lv.nbr.size());
   int64_t tot = 0;

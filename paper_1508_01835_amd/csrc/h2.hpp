@@ -436,22 +436,31 @@ __global__ void __launch_bounds__(WG) k_l2p_p2p_w(const double* __restrict__ pts
   const int tp = WAVE / G;          // targets per pass
   const int sub = lane % G;
   const int t0 = nb_start[i], t1 = nb_start[i + 1];
+  // with the stored blocks, lane t holds neighbour t's point range and first column (at most 64 neighbours)
+  int64_t nsj = 0;
+  int nmj = 0, ncol = 0;
+  if (nf && lane < t1 - t0) {
+    const int j = nbr[t0 + lane];
+    nsj = leaf_start[j];
+    nmj = (int)(leaf_start[j + 1] - nsj);
+    ncol = nfcol[t0 + lane];
+  }
   for (int rr = 0; rr < nrhs; ++rr) {
     for (int a0 = 0; a0 < m; a0 += tp) {
       const int a = a0 + lane / G;
       const bool act = a < m;
       double acc = 0;
-      if (act) {
-        if (nf) {   // the stored near-field block; same entries, same order
-          const double* B = nf + nfoff[i] + a;
-          for (int t = t0; t < t1; ++t) {
-            const int j = nbr[t];
-            const int64_t sj = leaf_start[j];
-            const int mj = (int)(leaf_start[j + 1] - sj);
-            const double* Bt = B + (int64_t)nfcol[t] * m;
-            for (int u = sub; u < mj; u += G) acc += Bt[(int64_t)u * m] * x[(sj + u) + (int64_t)rr * ldx];
-          }
-        } else {
+      if (nf) {   // the stored near-field block; same entries, same order
+        const double* B = nf + nfoff[i] + a;
+        for (int t = 0; t < t1 - t0; ++t) {   // neighbour t's range and first column, from lane t (all lanes)
+          const int64_t sj = __shfl(nsj, t, WAVE);
+          const int mj = __shfl(nmj, t, WAVE);
+          const int64_t c0 = __shfl(ncol, t, WAVE);
+          if (act)
+            for (int u = sub; u < mj; u += G) acc += B[(c0 + u) * m] * x[(sj + u) + (int64_t)rr * ldx];
+        }
+      } else if (act) {
+        {
           double xa[3] = {0, 0, 0};
           for (int k = 0; k < d; ++k) xa[k] = pts[(s + a) * d + k];
           for (int t = t0; t < t1; ++t) {
