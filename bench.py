@@ -421,7 +421,7 @@ def run_serve(args):
     Server(hbm_budget_bytes=args.serve_budget).run(warm)
     torch.cuda.synchronize()
     reqs = synthetic_requests(args.serve_count, rate=args.rate, n_lo=8192, n_hi=524288, seed=5001)
-    res = Server(hbm_budget_bytes=args.serve_budget, factor_workers=args.factor_workers).run(reqs)
+    res = Server(hbm_budget_bytes=args.serve_budget, factor_workers=args.factor_workers, progress=True).run(reqs)
     out = {
         "metric": "IFMM serving p99 request latency (continuous batching, FP32 factors + FP64 GMRES 1e-10)",
         "value": res["p99_ms"], "unit": "ms", "n_gpus": 1, "steps": 1, "warmup": 1,

@@ -23,6 +23,7 @@ Scheduling (host side; every step of a request runs in the HIP library):
 """
 from __future__ import annotations
 
+import sys
 import threading
 import time
 from collections import OrderedDict
@@ -63,7 +64,7 @@ class _Factor:
 class Server:
     def __init__(self, hbm_budget_bytes: int, kernel=("imq", 0.01, 1.0), order: int = 3, eps: float = 1e-5,
                  leaf_max: int = 64, tol: float = 1e-10, maxit: int = 200, keep_results: bool = False,
-                 factor_workers: int = 2, gmres_iters_estimate: int = 40):
+                 factor_workers: int = 2, gmres_iters_estimate: int = 40, progress: bool = False):
         import torch
         self.torch = torch
         self.budget = int(hbm_budget_bytes)
@@ -71,6 +72,7 @@ class Server:
         self.tol, self.maxit, self.keep = tol, maxit, keep_results
         self.factor_workers = max(1, int(factor_workers))
         self.gmres_iters_estimate = gmres_iters_estimate
+        self.progress = progress          # a line on stderr for every finished solve batch
         self.factors: "OrderedDict[int, _Factor]" = OrderedDict()
         self.bytes_per_point = 4.0e4      # first estimate; replaced by what factorizations use
         self.solve_stream = torch.cuda.Stream()
@@ -116,12 +118,22 @@ class Server:
         torch = self.torch
         cols = [np.random.default_rng(r.seed).standard_normal((f.n, r.nrhs)) for r in reqs]
         B = torch.tensor(np.concatenate(cols, axis=1), device="cuda")
+        # the Krylov storage of a call grows to 2 (maxit + 1) vectors per column in the worst case: the
+        # columns go in groups that keep it within a quarter of the budget (every column is its own GMRES
+        # run, so the grouping changes no result)
+        per_col = 16 * f.n * (self.maxit + 1)
+        group = max(1, (self.budget // 4) // per_col)
         t0 = time.perf_counter()
+        Xs, it, rr = [], 0, 0.0
         with torch.cuda.stream(f.handle.stream):
-            X, it, rr = f.handle.gmres(B, tol=self.tol, maxit=self.maxit)
+            for c0 in range(0, B.shape[1], group):
+                Xg, itg, rrg = f.handle.gmres(B[:, c0:c0 + group].contiguous(), tol=self.tol, maxit=self.maxit)
+                Xs.append(Xg)
+                it, rr = max(it, itg), max(rr, rrg)
+                self.stats["gmres_calls"] += 1
+        X = Xs[0] if len(Xs) == 1 else torch.cat(Xs, dim=1)
         self.stats["solve_busy_s"] += time.perf_counter() - t0
         f.bytes = int(f.handle.stats()["device_bytes"])   # what the handle holds now (the Krylov storage is freed)
-        self.stats["gmres_calls"] += 1
         self.stats["rhs"] += B.shape[1]
         t_done = now()
         Xh = X.cpu().numpy() if self.keep else None
@@ -205,6 +217,10 @@ class Server:
                 f = min(pend, key=lambda f: min(q.arrival for q in f.pending))
                 reqs, f.pending = f.pending, []
                 self._solve_batch(f, reqs, now)
+                if self.progress:
+                    print("[serve] %d / %d requests done, %.1f s (factor of %d points, %d columns)"
+                          % (done + len(reqs), total, now(), f.n, sum(r.nrhs for r in reqs)),
+                          file=sys.stderr, flush=True)
                 done += len(reqs)
                 continue
             if not workers and not fq and arrived < total:
