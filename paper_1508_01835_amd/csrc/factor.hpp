@@ -473,6 +473,50 @@ struct Factorizer {
   }
 
   // ---------------------------------------------------------- recompression
+  // Row and column edge lists of every box of the level (edges exist or not
+  // for the whole level), built once per level on host threads and uploaded.
+  // The first batch of a level builds them while its eliminations run.
+  void ensure_edge_tables(LevelPool<T>& L) {
+    if (L.erow_start.empty()) {
+      // boxes split over host threads, chunks concatenated in order
+      const int nt = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+      std::vector<std::vector<int>> rch(nt), cch(nt), rcnt(nt), ccnt(nt);
+      std::vector<std::thread> th;
+      const int per = (L.nb + nt - 1) / nt;
+      for (int t = 0; t < nt; ++t)
+        th.emplace_back([&, t] {
+          const int j0 = t * per, j1 = std::min(L.nb, j0 + per);
+          for (int j = j0; j < j1; ++j) {
+            int nr = 0, nc = 0;
+            for (int code = 0; code < L.c7; ++code) {
+              const int q = L.B7[(size_t)j * L.c7 + code];
+              if (q < 0) continue;
+              if (L.Kt[(size_t)j * L.c7 + code] >= 0) { rch[t].push_back(code); ++nr; }
+              if (L.Kt[(size_t)q * L.c7 + (L.c7 - 1 - code)] >= 0) { cch[t].push_back(code); ++nc; }
+            }
+            rcnt[t].push_back(nr);
+            ccnt[t].push_back(nc);
+          }
+        });
+      for (auto& x : th) x.join();
+      L.erow_start.assign(L.nb + 1, 0);
+      L.ecol_start.assign(L.nb + 1, 0);
+      int j = 0;
+      for (int t = 0; t < nt; ++t) {
+        L.erow.insert(L.erow.end(), rch[t].begin(), rch[t].end());
+        L.ecol.insert(L.ecol.end(), cch[t].begin(), cch[t].end());
+        for (size_t k = 0; k < rcnt[t].size(); ++k, ++j) {
+          L.erow_start[j + 1] = L.erow_start[j] + rcnt[t][k];
+          L.ecol_start[j + 1] = L.ecol_start[j] + ccnt[t][k];
+        }
+      }
+      P.upload(L.derow_start, L.erow_start);
+      P.upload(L.derow, L.erow);
+      P.upload(L.decol_start, L.ecol_start);
+      P.upload(L.decol, L.ecol);
+    }
+  }
+
   // Plans workspace for the recompressions cs (ncols and box filled in) and
   // runs: gather, QR of MU^T / MV^T, transpose, Jacobi SVD, rank, r_j / t_j,
   // row and column transforms of every edge of the affected boxes, commit.
@@ -670,44 +714,7 @@ struct Factorizer {
     // one task per existing edge (the host holds the edge tables); flops of the
     // basis changes 2 k r cols per edge, with the new rank k bounded by the old
     // rank r (the new ranks are still on the device)
-    if (L.erow_start.empty()) {
-      // boxes split over host threads, chunks concatenated in order
-      const int nt = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-      std::vector<std::vector<int>> rch(nt), cch(nt), rcnt(nt), ccnt(nt);
-      std::vector<std::thread> th;
-      const int per = (L.nb + nt - 1) / nt;
-      for (int t = 0; t < nt; ++t)
-        th.emplace_back([&, t] {
-          const int j0 = t * per, j1 = std::min(L.nb, j0 + per);
-          for (int j = j0; j < j1; ++j) {
-            int nr = 0, nc = 0;
-            for (int code = 0; code < L.c7; ++code) {
-              const int q = L.B7[(size_t)j * L.c7 + code];
-              if (q < 0) continue;
-              if (L.Kt[(size_t)j * L.c7 + code] >= 0) { rch[t].push_back(code); ++nr; }
-              if (L.Kt[(size_t)q * L.c7 + (L.c7 - 1 - code)] >= 0) { cch[t].push_back(code); ++nc; }
-            }
-            rcnt[t].push_back(nr);
-            ccnt[t].push_back(nc);
-          }
-        });
-      for (auto& x : th) x.join();
-      L.erow_start.assign(L.nb + 1, 0);
-      L.ecol_start.assign(L.nb + 1, 0);
-      int j = 0;
-      for (int t = 0; t < nt; ++t) {
-        L.erow.insert(L.erow.end(), rch[t].begin(), rch[t].end());
-        L.ecol.insert(L.ecol.end(), cch[t].begin(), cch[t].end());
-        for (size_t k = 0; k < rcnt[t].size(); ++k, ++j) {
-          L.erow_start[j + 1] = L.erow_start[j] + rcnt[t][k];
-          L.ecol_start[j + 1] = L.ecol_start[j] + ccnt[t][k];
-        }
-      }
-      P.upload(L.derow_start, L.erow_start);
-      P.upload(L.derow, L.erow);
-      P.upload(L.decol_start, L.ecol_start);
-      P.upload(L.decol, L.ecol);
-    }
+    ensure_edge_tables(L);
     // per recompression the first workgroup of its edges; flops estimated as
     // 2 r_j^2 (edges of j) rbar with the level's mean rank rbar (exact counts
     // would need a pass over every edge on the host)
@@ -1000,14 +1007,23 @@ struct Factorizer {
       int64_t fo = 0, po = 0, wo = 0, so = 0;
       int maxF = 0;
       std::vector<CompDesc> cs;
-      std::vector<int> fcode;   // offset code (3^d) of each F node of the box relative to it
-      for (int i : boxes) {
-        ElimDesc e{};
+      // Each box is planned on its own (its F nodes in order, the recompressions
+      // its elimination triggers), on host threads for large batches; offsets
+      // into the class buffers are then assigned in box order, so the plan is
+      // the same whatever the thread count.
+      const int nbx = (int)boxes.size();
+      std::vector<ElimDesc> eb(nbx);
+      std::vector<std::vector<FNode>> fb(nbx);
+      std::vector<std::vector<CompDesc>> cb(nbx);
+      auto plan_box = [&](int x, std::vector<int>& fcode) {
+        const int i = boxes[x];
+        ElimDesc& e = eb[x];
+        std::vector<FNode>& nodes = fb[x];
+        e = ElimDesc{};
         e.box = i;
         e.m = L.m[i];
         e.r = L.r[i];
         e.p = e.m + e.r;
-        e.F0 = (int)Fs.size();
         fcode.clear();
         int f = 0;
         auto push = [&](int type, int b) {
@@ -1031,7 +1047,7 @@ struct Factorizer {
             n.src_row = -1; n.src_col = -1; n.ld_row = 1; n.ld_col = 1;
           }
           f += n.dim;
-          Fs.push_back(n);
+          nodes.push_back(n);
         };
         for (int t = lv.nb_start[i]; t < lv.nb_start[i + 1]; ++t) {
           const int j = lv.nbr[t];
@@ -1042,8 +1058,49 @@ struct Factorizer {
           if (j != i && lv.colour[j] < c) push(1, j);
         }
         push(1, i);
-        e.nF = (int)Fs.size() - e.F0;
+        e.nF = (int)nodes.size();
         e.f = f;
+        e.S = L.St[(size_t)i * L.c3 + offset3(lv, i, i)];
+        e.U = L.Uo[i];
+        e.V = L.Vo[i];
+        // recompressions triggered by this elimination
+        for (int a = 0; a < e.nF; ++a) {
+          const FNode& X = nodes[a];
+          if (X.type != 0) continue;
+          int nc = L.r[X.box];
+          bool any = false;
+          // both are neighbours of i: adjacent iff their offsets from i differ by at most one
+          const uint8_t* adj = &adj3_[(size_t)fcode[a] * c3_];
+          for (int b = 0; b < e.nF; ++b) {
+            if (!adj[fcode[b]]) { nc += nodes[b].dim; any = true; }
+          }
+          if (!any) continue;
+          CompDesc cd{};
+          cd.box = X.box;
+          cd.elim = x;
+          cd.a = a;
+          cd.ncols = nc;
+          cb[x].push_back(cd);
+        }
+      };
+      {
+        const int nt = nbx >= 512 ? (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency())) : 1;
+        auto part = [&](int t) {
+          std::vector<int> fcode;   // offset code (3^d) of each F node of the box relative to it
+          for (int x = t; x < nbx; x += nt) plan_box(x, fcode);
+        };
+        if (nt == 1) {
+          part(0);
+        } else {
+          std::vector<std::thread> th;
+          for (int t = 0; t < nt; ++t) th.emplace_back(part, t);
+          for (auto& h : th) h.join();
+        }
+      }
+      for (int x = 0; x < nbx; ++x) {
+        ElimDesc e = eb[x];
+        e.F0 = (int)Fs.size();
+        Fs.insert(Fs.end(), fb[x].begin(), fb[x].end());
         maxF = std::max(maxF, e.nF);
         e.lu = fo; fo += ((int64_t)e.p * e.p + 1) & ~int64_t(1);
         e.w = fo; fo += ((int64_t)e.p * e.f + 1) & ~int64_t(1);
@@ -1054,28 +1111,7 @@ struct Factorizer {
         e.wx = so; so += ((int64_t)e.m * e.f + 1) & ~int64_t(1);
         e.piv = po; po += e.p;
         e.dlt = wo; wo += ((int64_t)e.f * e.f + 1) & ~int64_t(1);
-        e.S = L.St[(size_t)i * L.c3 + offset3(lv, i, i)];
-        e.U = L.Uo[i];
-        e.V = L.Vo[i];
-        // recompressions triggered by this elimination
-        for (int a = 0; a < e.nF; ++a) {
-          const FNode& X = Fs[e.F0 + a];
-          if (X.type != 0) continue;
-          int nc = L.r[X.box];
-          bool any = false;
-          // both are neighbours of i: adjacent iff their offsets from i differ by at most one
-          const uint8_t* adj = &adj3_[(size_t)fcode[a] * c3_];
-          for (int b = 0; b < e.nF; ++b) {
-            if (!adj[fcode[b]]) { nc += Fs[e.F0 + b].dim; any = true; }
-          }
-          if (!any) continue;
-          CompDesc cd{};
-          cd.box = X.box;
-          cd.elim = (int)el.size();
-          cd.a = a;
-          cd.ncols = nc;
-          cs.push_back(cd);
-        }
+        cs.insert(cs.end(), cb[x].begin(), cb[x].end());
         flops_lu += 2.0 / 3.0 * e.p * (double)e.p * e.p + 2.0 * e.p * (double)e.p * e.f;
         flops_schur += 2.0 * e.f * (double)e.f * e.p;
         flops_other += 2.0 * e.p * (double)e.p * e.p + 2.0 * e.f * (double)e.p * e.m;
@@ -1169,6 +1205,7 @@ struct Factorizer {
       // well-separated fill: recompress the bases of the affected boxes, then redirect
       IFMM_HIP(hipMemcpyAsync(L.drnew.p, L.dr.p, sizeof(int) * lv.nb, hipMemcpyDeviceToDevice, P.stream));
       chk(L, "near_scatter", nullptr, wo);
+      ensure_edge_tables(L);   // host work of the level's first batch while its eliminations run
       hs_launch.stop();
       {
         HostScope hs(P.hprof, "class: recompress");
