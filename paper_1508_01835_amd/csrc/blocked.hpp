@@ -711,7 +711,7 @@ struct QrJob {
 // R-only Householder QR of a narrow M x N matrix (N <= 64), a column per lane:
 // lanes g NP .. g NP + NP - 1 of a wavefront own the columns of job g (NP =
 // 16, 32 or 64, so 4, 2 or 1 jobs per wavefront), and the rows stream through
-// in chunks of QC_CH (each lane holds its column of the chunk in registers)
+// in chunks of QcCh<T> rows (each lane holds its column of the chunk in registers)
 // while the running triangle R sits in LDS, packed by columns, column c with
 // lane c. The chunk is folded into R by one reflector per column j, acting on
 // row j of R and column j of the chunk: column j is broadcast to the job's
@@ -720,7 +720,10 @@ struct QrJob {
 // (alpha = -sign(x0) ||x||, tau = (alpha - x0) / alpha, tau = 0 for a zero
 // column) and each job is scaled once by an exact power of two. A is left as
 // it was; R (min(M, N) x N, ldr, zero below the diagonal) is written at the end.
-constexpr int QC_CH = 32;
+template <class T>
+struct QcCh {   // rows per chunk: a step's latency is paid once for twice the rows in FP32
+  static constexpr int v = sizeof(T) == 4 ? 64 : 32;
+};
 constexpr int QC_NMAX = 64;
 
 template <class T, int NP>
@@ -777,16 +780,17 @@ __global__ void __launch_bounds__(NT) k_qr_cols(const QrJob* __restrict__ js, in
     Mw = max(Mw, __shfl_xor(Mw, o, WAVE));
     Nw = max(Nw, __shfl_xor(Nw, o, WAVE));
   }
-  T x[QC_CH], v[QC_CH];
-  for (int i0 = 0; i0 < Mw; i0 += QC_CH) {
+  constexpr int CH = QcCh<T>::v;
+  T x[CH], v[CH];
+  for (int i0 = 0; i0 < Mw; i0 += CH) {
 #pragma unroll
-    for (int i = 0; i < QC_CH; ++i) x[i] = (col && i0 + i < M) ? ldexp(A[i0 + i + c * lda], sh) : (T)0;
+    for (int i = 0; i < CH; ++i) x[i] = (col && i0 + i < M) ? ldexp(A[i0 + i + c * lda], sh) : (T)0;
     for (int j = 0; j < Nw; ++j) {
       const int src = g * NP + j;   // lane of column j of this job (a zero column when j >= N)
       // four partial sums each: independent chains instead of one 32-long
       T s4[4] = {0, 0, 0, 0}, d4[4] = {0, 0, 0, 0};
 #pragma unroll
-      for (int i = 0; i < QC_CH; ++i) {
+      for (int i = 0; i < CH; ++i) {
         v[i] = qc_bcast<G>(x[i], src);
         s4[i & 3] += v[i] * v[i];
         d4[i & 3] += v[i] * x[i];
@@ -802,10 +806,10 @@ __global__ void __launch_bounds__(NT) k_qr_cols(const QrJob* __restrict__ js, in
           R[qc_tri(j, c)] -= wc;
           const T f = wc * scal;
 #pragma unroll
-          for (int i = 0; i < QC_CH; ++i) x[i] -= f * v[i];
+          for (int i = 0; i < CH; ++i) x[i] -= f * v[i];
         } else if (c == j) {
 #pragma unroll
-          for (int i = 0; i < QC_CH; ++i) x[i] = 0;
+          for (int i = 0; i < CH; ++i) x[i] = 0;
           R[qc_tri(j, j)] = al;
         }
       }
