@@ -42,9 +42,9 @@ sys.path.insert(0, ROOT)
 os.environ.setdefault("IFMM_KTIMING", "1")
 
 # HBM bytes per launch of a roofline kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE counter runs, scaled by
-# what the counters read for a 512 MiB device copy (profiles/k_qr_panel_uniform3d_65536.txt); valid for the
-# kernel version the counters were taken on
-MEASURED_TRAFFIC = {"k_qr_panel<double>": 5.341e8}
+# what the counters read for a 512 MiB device copy (--workload calib); valid for the kernel version the
+# counters were taken on
+MEASURED_TRAFFIC = {"k_qr_panel<float>": 6.698e7}   # HBM bytes per launch, profiles/k_qr_panel_cluster3d_1048576.txt
 
 PEAKS = {  # MI355X published peaks
     "hbm_GBs": 8000.0,
@@ -409,6 +409,20 @@ def run_batch(args):
     print(json.dumps(out))
 
 
+def run_calib():
+    """Counter calibration: three device copies of 512 MiB (FP64 ones), so that rocprofv3's FETCH_SIZE and
+    WRITE_SIZE per dispatch can be compared with the bytes known to move (run under --pmc)."""
+    import torch
+    a = torch.ones(64 << 20, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"metric": "counter calibration copy", "value": a.numel() * 8, "unit": "B per copy",
+                      "copies": 3}))
+
+
 def run_serve(args):
     """Serving loop: Poisson arrivals, 25% factorize (+ one solve) with N log-uniform in [8192, 524288]
     (uniform cube or 8 Gaussian clusters, half each), 75% solves of 1..64 right-hand sides on a resident
@@ -536,7 +550,8 @@ def main():
                     help="timed steps only: no latency, time-to-tolerance or CPU runs (for counter runs)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="end with a 512 MiB device-to-device copy, the reference for HBM byte counters")
-    ap.add_argument("--workload", choices=["cluster3d", "uniform3d", "batch", "serve", "paper"], default="cluster3d")
+    ap.add_argument("--workload", choices=["cluster3d", "uniform3d", "batch", "serve", "paper", "calib"],
+                    default="cluster3d")
     ap.add_argument("--n-per-cluster", type=int, default=131072)
     ap.add_argument("--depth-cluster", type=int, default=7)
     ap.add_argument("--maxit", type=int, default=30, help="GMRES iterations of a timed step at most")
@@ -568,6 +583,9 @@ def main():
         return
     if args.workload == "serve":
         run_serve(args)
+        return
+    if args.workload == "calib":
+        run_calib()
         return
     if args.workload == "cluster3d":
         run_cluster3d(args)
