@@ -74,6 +74,22 @@ typedef struct {
   int64_t hbm_budget_bytes;   /* > 0: fail with IFMM_ERR_OOM rather than let the
                                  handle's device memory exceed this */
   void* stream;               /* hipStream_t; 0 = null stream */
+  /* Optional device allocator of the handle (both set, or both NULL = the
+   * library's own cache of hipMalloc blocks). Every device buffer of the
+   * handle is then taken from dev_alloc(bytes, alloc_ctx), which returns a
+   * device pointer of at least that many bytes aligned to 256 (NULL: the call
+   * fails with IFMM_ERR_OOM), and returned through dev_free(ptr, bytes,
+   * alloc_ctx) with the same byte count. A buffer handed to dev_free may still
+   * be read or written by work already queued on the handle's stream: the
+   * allocator may reuse it only for work ordered after that on the same
+   * stream, or after the stream has been synchronised (stream-ordered reuse,
+   * as PyTorch's caching allocator does when given the handle's stream). The
+   * callbacks may be called from the calling thread and, in
+   * ifmm_factorize_batch, from the library's worker threads, until
+   * ifmm_destroy returns. */
+  void* (*dev_alloc)(size_t bytes, void* alloc_ctx);
+  void (*dev_free)(void* ptr, size_t bytes, void* alloc_ctx);
+  void* alloc_ctx;
 } ifmm_options;
 
 /* Counters and phase times of a handle (host struct, filled by ifmm_query). */

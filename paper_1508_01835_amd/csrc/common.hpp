@@ -78,6 +78,23 @@ struct StreamScope {
   ~StreamScope() { tls_stream() = prev; }
 };
 
+// Device allocator of the handle whose API call runs on this thread (set by
+// AllocScope next to StreamScope); null functions: the library's own pool.
+struct DevAlloc {
+  void* (*alloc)(size_t, void*) = nullptr;
+  void (*free)(void*, size_t, void*) = nullptr;
+  void* ctx = nullptr;
+};
+inline DevAlloc& tls_alloc() {
+  static thread_local DevAlloc a;
+  return a;
+}
+struct AllocScope {
+  DevAlloc prev;
+  explicit AllocScope(const DevAlloc& a) : prev(tls_alloc()) { tls_alloc() = a; }
+  ~AllocScope() { tls_alloc() = prev; }
+};
+
 // Process-wide cache of device blocks. hipMalloc / hipFree cost about 0.1 ms
 // each and serialise host threads, so a build + factorization (hundreds of
 // buffers) and batches of problems would spend much of their time there.
@@ -179,6 +196,7 @@ struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
   MemAccount* acct = nullptr;
+  DevAlloc from;   // the caller's allocator that gave p (null functions: the pool)
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
@@ -186,8 +204,8 @@ struct DevBuf {
   DevBuf& operator=(DevBuf&& o) noexcept {
     if (this != &o) {
       release();
-      p = o.p; bytes = o.bytes; acct = o.acct;
-      o.p = nullptr; o.bytes = 0; o.acct = nullptr;
+      p = o.p; bytes = o.bytes; acct = o.acct; from = o.from;
+      o.p = nullptr; o.bytes = 0; o.acct = nullptr; o.from = DevAlloc();
     }
     return *this;
   }
@@ -196,24 +214,39 @@ struct DevBuf {
     release();
     if (b == 0) b = 256;
     if (a) a->add((int64_t)b);
-    try {
-      p = DevPool::inst().get(b, tls_stream());
-    } catch (...) {
-      if (a) a->sub((int64_t)b);
-      p = nullptr;
-      throw;
+    const DevAlloc& ca = tls_alloc();
+    if (ca.alloc && ca.free) {
+      p = ca.alloc(b, ca.ctx);
+      if (!p || (reinterpret_cast<uintptr_t>(p) & 255)) {
+        if (p) ca.free(p, b, ca.ctx);
+        p = nullptr;
+        if (a) a->sub((int64_t)b);
+        fail(IFMM_ERR_OOM, "the caller's dev_alloc(" + std::to_string(b) + ") gave no 256-byte aligned block");
+      }
+      from = ca;
+    } else {
+      try {
+        p = DevPool::inst().get(b, tls_stream());
+      } catch (...) {
+        if (a) a->sub((int64_t)b);
+        p = nullptr;
+        throw;
+      }
+      from = DevAlloc();
     }
     bytes = b;
     acct = a;
   }
   void release() {
     if (p) {
-      DevPool::inst().put(p, bytes, tls_stream());
+      if (from.free) from.free(p, bytes, from.ctx);
+      else DevPool::inst().put(p, bytes, tls_stream());
       if (acct) acct->sub((int64_t)bytes);
     }
     p = nullptr;
     bytes = 0;
     acct = nullptr;
+    from = DevAlloc();
   }
   template <class T> T* as() const { return static_cast<T*>(p); }
   // Grow (never shrink) to at least b bytes; contents are not kept.

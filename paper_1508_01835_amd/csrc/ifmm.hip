@@ -160,6 +160,9 @@ void ifmm_default_options(ifmm_options* opt) {
   opt->sigma0_override = 0.0;
   opt->hbm_budget_bytes = 0;
   opt->stream = nullptr;
+  opt->dev_alloc = nullptr;
+  opt->dev_free = nullptr;
+  opt->alloc_ctx = nullptr;
 }
 
 const char* ifmm_strerror(int code) {
@@ -194,6 +197,7 @@ int ifmm_build(const double* points, int64_t n, int dim, ifmm_kernel k, int dept
     ifmm_default_options(&o);
     if (opt) o = *opt;
     if (o.precision != 32 && o.precision != 64) fail(IFMM_ERR_ARG, "precision must be 32 or 64");
+    if (!o.dev_alloc != !o.dev_free) fail(IFMM_ERR_ARG, "dev_alloc and dev_free must be given together");
     int q = 1;
     for (int a = 0; a < dim; ++a) q *= cheb_order;
     if (q > SW_MAXC) fail(IFMM_ERR_ARG, "cheb_order^dim above 512");
@@ -206,7 +210,11 @@ int ifmm_build(const double* points, int64_t n, int dim, ifmm_kernel k, int dept
       if (kt && kt[0] == 'm') P.kt.mask = (uint32_t)std::strtoul(kt + 1, nullptr, 16);
     }
     P.stream = static_cast<hipStream_t>(o.stream);
+    P.alloc.alloc = o.dev_alloc;
+    P.alloc.free = o.dev_free;
+    P.alloc.ctx = o.alloc_ctx;
     StreamScope ss(P.stream);
+    AllocScope as(P.alloc);
     IFMM_HIP(hipGetDevice(&P.device));
     scratch_address(P.device);
     P.n = n;
@@ -267,6 +275,7 @@ void factorize_handle(ifmm_handle h) {
     if (!h) fail(IFMM_ERR_ARG, "null handle");
     Problem& P = h->P;
     StreamScope ss(P.stream);
+    AllocScope as(P.alloc);
     P.arena_reset();
     P.factorized = false;
     P.fac.reset();
@@ -364,6 +373,7 @@ int ifmm_solve(ifmm_handle h, const double* b, double* x, int nrhs, int64_t ld) 
     if (!h || !b || !x) fail(IFMM_ERR_ARG, "null pointer");
     Problem& P = h->P;
     StreamScope ss(P.stream);
+    AllocScope as(P.alloc);
     if (!P.factorized) fail(IFMM_ERR_STATE, "ifmm_solve needs a factorized handle");
     if (nrhs < 1 || ld < P.n) fail(IFMM_ERR_ARG, "nrhs must be >= 1 and ld >= n");
     const double t0 = now_ms();
@@ -415,6 +425,7 @@ int ifmm_matvec(ifmm_handle h, const double* x, double* y, int nrhs, int64_t ld)
     if (!h || !x || !y) fail(IFMM_ERR_ARG, "null pointer");
     Problem& P = h->P;
     StreamScope ss(P.stream);
+    AllocScope as(P.alloc);
     if (nrhs < 1 || ld < P.n) fail(IFMM_ERR_ARG, "nrhs must be >= 1 and ld >= n");
     if (x == y) fail(IFMM_ERR_ARG, "x and y must not alias");
     const double t0 = now_ms();
@@ -430,6 +441,7 @@ static int gmres_entry(ifmm_handle op, ifmm_handle prec, const double* b, double
     if (!op || !b || !x) fail(IFMM_ERR_ARG, "null pointer");
     Problem& A = op->P;
     StreamScope ss(A.stream);
+    AllocScope as(A.alloc);
     if (prec) {
       if (A.n != prec->P.n) fail(IFMM_ERR_ARG, "op and prec have different sizes");
       if (!prec->P.factorized) fail(IFMM_ERR_STATE, "the preconditioner handle is not factorized");
@@ -463,7 +475,11 @@ static int gmres_entry(ifmm_handle op, ifmm_handle prec, const double* b, double
         IFMM_HIP(hipEventRecord(ev.a, A.stream));
         IFMM_HIP(hipStreamWaitEvent(M.stream, ev.a, 0));
       }
-      solve_any(M, in, out, nrhs, M.n);
+      {
+        StreamScope ms(M.stream);   // buffers the solve takes belong to the preconditioner handle
+        AllocScope ma(M.alloc);
+        solve_any(M, in, out, nrhs, M.n);
+      }
       if (M.stream != A.stream) {
         IFMM_HIP(hipEventRecord(ev.b, M.stream));
         IFMM_HIP(hipStreamWaitEvent(A.stream, ev.b, 0));

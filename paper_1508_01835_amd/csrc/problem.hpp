@@ -169,6 +169,7 @@ struct Problem {
   KernelFn kf{};
   ChebConst cc{};
   hipStream_t stream = nullptr;
+  DevAlloc alloc;                  // the caller's device allocator (null functions: the pool)
   int device = 0;                  // HIP device current at the build
   MemAccount mem;
   Staging stage;

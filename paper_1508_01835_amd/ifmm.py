@@ -23,10 +23,44 @@ class Kernel(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int), ("param", ctypes.c_double), ("diag_shift", ctypes.c_double)]
 
 
+DevAllocFn = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+DevFreeFn = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+
+
 class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("leaf_max", ctypes.c_int), ("rank_max", ctypes.c_int),
                 ("sigma0_override", ctypes.c_double), ("hbm_budget_bytes", ctypes.c_int64),
-                ("stream", ctypes.c_void_p)]
+                ("stream", ctypes.c_void_p), ("dev_alloc", DevAllocFn), ("dev_free", DevFreeFn),
+                ("alloc_ctx", ctypes.c_void_p)]
+
+
+def torch_allocator(stream):
+    """dev_alloc / dev_free callbacks that take the handle's device buffers from PyTorch's caching
+    allocator on `stream` (the handle's stream), so that the library and PyTorch share one pool.
+    The allocator reuses a freed block only for work ordered after it on that stream, which is what the
+    library's stream-ordered frees need. Keep the returned pair alive as long as the handle."""
+    import torch
+    dev = stream.device.index if stream.device.index is not None else torch.cuda.current_device()
+    counts = {"alloc": 0, "free": 0, "live_bytes": 0}
+
+    def _alloc(nbytes, ctx):
+        try:
+            p = torch.cuda.caching_allocator_alloc(int(nbytes), dev, stream)
+        except Exception:   # out of memory or a torch error: the library fails the call with IFMM_ERR_OOM
+            return None
+        counts["alloc"] += 1
+        counts["live_bytes"] += int(nbytes)
+        return p
+
+    def _free(ptr, nbytes, ctx):
+        try:
+            torch.cuda.caching_allocator_delete(ptr)
+            counts["free"] += 1
+            counts["live_bytes"] -= int(nbytes)
+        except Exception:   # interpreter shutdown: the process is ending anyway
+            pass
+
+    return DevAllocFn(_alloc), DevFreeFn(_free), counts
 
 
 class Stats(ctypes.Structure):
@@ -132,7 +166,7 @@ class IFMM:
 
     def __init__(self, points, kernel: str, param: float, shift: float, depth: int, order: int, eps: float,
                  precision: int = 64, rank_max: int = 0, sigma0: float = 0.0, leaf_max: int = 64,
-                 hbm_budget_bytes: int = 0, stream=None):
+                 hbm_budget_bytes: int = 0, stream=None, torch_alloc: bool = False):
         import torch
         if not points.is_cuda:
             raise ValueError("points must be a CUDA tensor")
@@ -147,6 +181,12 @@ class IFMM:
         opt.hbm_budget_bytes = hbm_budget_bytes
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         opt.stream = ctypes.c_void_p(self.stream.cuda_stream)
+        self.alloc_counts = None
+        if torch_alloc:   # device buffers from PyTorch's caching allocator, on the handle's stream
+            fa, ff, self.alloc_counts = torch_allocator(self.stream)
+            self._alloc_fns = (fa, ff)   # the callbacks outlive every library call of the handle
+            opt.dev_alloc = fa
+            opt.dev_free = ff
         k = Kernel(KERNELS[kernel], float(param), float(shift))
         h = ctypes.c_void_p()
         torch.cuda.current_stream().synchronize()   # the points are ready before the handle's stream reads them

@@ -2,6 +2,8 @@
 import os
 import re
 
+import pytest
+
 from paper_1508_01835_amd import ifmm as binding
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -48,3 +50,37 @@ def test_null_arguments_rejected_without_gpu_work():
     assert lib.ifmm_solve_noalloc(None, None, None, 1, 1) == 1
     assert lib.ifmm_query_ranks(None, 2, None, 0) == 1
     assert lib.ifmm_destroy(None) == 0
+
+
+def test_options_layout_matches_header(tmp_path):
+    """The ctypes mirror of ifmm_options has the C struct's size and field offsets (gcc on the header)."""
+    import ctypes
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    names = [f[0] for f in binding.Options._fields_]
+    src = tmp_path / "layout.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "ifmm.h"\nint main(void) {\n'
+                   '  printf("%zu\\n", sizeof(ifmm_options));\n' +
+                   "".join('  printf("%%zu\\n", offsetof(ifmm_options, %s));\n' % n for n in names) +
+                   "  return 0;\n}\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    assert got[0] == ctypes.sizeof(binding.Options)
+    assert got[1:] == [getattr(binding.Options, n).offset for n in names]
+
+
+def test_allocator_callbacks_default_null_and_come_in_pairs():
+    import ctypes
+    lib = binding.load_library()
+    opt = binding.Options()
+    lib.ifmm_default_options(ctypes.byref(opt))
+    assert not opt.dev_alloc and not opt.dev_free and not opt.alloc_ctx
+    opt.dev_alloc = binding.DevAllocFn(lambda n, c: None)   # dev_free left null: rejected before any GPU work
+    pts = (ctypes.c_double * 20)()
+    h = ctypes.c_void_p()
+    rc = lib.ifmm_build(pts, 10, 2, binding.Kernel(0, 0.01, 1.0), 3, 3, 1e-6, ctypes.byref(opt), ctypes.byref(h))
+    assert rc == 1 and not h.value
+    assert b"dev_alloc" in lib.ifmm_last_error()
