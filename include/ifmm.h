@@ -126,12 +126,16 @@ typedef struct {
      Jacobi SVD, 13 row basis change, 14 column basis change. Family 15
      holds the launches of the step-wise truncated pivoted QR (batches of
      few problems: one launch per Householder step). Family 16 holds one
-     kernel, the one-wavefront QR of matrices at most 32 columns wide.
-     Entries 17-23 are zero. */
+     kernel, the streaming R-only QR of matrices at most 64 columns wide (one
+     column per lane). Family 17 holds one kernel, the products
+     R_i K_o R_j^T of the weighted system by interaction offset. Entries
+     18-23 are zero. */
   double kfam_ms[24];
   double kfam_flops[24];      /* algorithmic flops attributed to the family */
   double kfam_bytes[24];      /* algorithmic bytes attributed to the family */
   int64_t kfam_launches[24];
+  int gmres_restarts;         /* column restarts from the true residual in the
+                                 last ifmm_gmres call (see ifmm_gmres) */
 } ifmm_stats;
 
 typedef struct ifmm_problem* ifmm_handle;
@@ -237,11 +241,15 @@ int ifmm_matvec(ifmm_handle h, const double* x, double* y, int nrhs, int64_t ld)
  * handle, or live on different streams (the calls order the two streams with
  * events). prec = NULL runs GMRES without a preconditioner (the comparison
  * runs of Sec. 3.2); op then need not be factorized. Each column is an
- * independent GMRES run.
+ * independent GMRES run. Rounding can leave the true residual, recomputed at
+ * exit, above tol when the monitored one has met it. Such a column is then
+ * restarted from its true residual with the iterations it has left (x += d,
+ * A~ d = b - A~ x, at most 3 restarts). It is refined alone, so its result
+ * does not depend on the other columns.
  *   b, x        device, n x nrhs, leading dimension ld; x is overwritten;
  *               x and b must not overlap (IFMM_ERR_ARG)
  *   tol         stop when ||b - A~ x|| <= tol ||b|| (per column)
- *   maxit       iteration limit (<= 1000)
+ *   maxit       iteration limit per column, restarts included (<= 1000)
  *   iters_out   host, may be NULL: largest iteration count over the columns
  *   relres_out  host, may be NULL: largest true relative residual at exit
  * IFMM_ERR_NUMERICAL if b holds a NaN or an infinity.

@@ -76,6 +76,12 @@ __global__ void k_combine(const double* __restrict__ Z, const double* __restrict
   x[t + (int64_t)c * ld] = s;
 }
 
+// x += d (n entries)
+__global__ void k_add(double* __restrict__ x, const double* __restrict__ d, int64_t n) {
+  const int64_t e = (int64_t)blockIdx.x * WG + threadIdx.x;
+  if (e < n) x[e] += d[e];
+}
+
 // r -= w (both n x nrhs, leading dimension n)
 __global__ void k_sub(double* __restrict__ r, const double* __restrict__ w, int64_t nv) {
   const int64_t e = (int64_t)blockIdx.x * WG + threadIdx.x;
@@ -95,6 +101,10 @@ struct GmresResult {
   int iters = 0;
   double relres = 0;        // monitored residual at exit (max over columns)
   double true_relres = 0;   // ||b - A x|| / ||b|| at exit (max over columns)
+  std::vector<int> iters_col;       // per column
+  std::vector<double> true_col;     // per column ||b - A x|| / ||b||
+  std::vector<double> bnorm;        // per column ||b||
+  int restarts = 0;                 // column restarts from the true residual
 };
 
 struct GmresWork {
@@ -275,8 +285,13 @@ inline GmresResult gmres_run(Problem& P, GmresWork& G, const std::function<void(
   GmresResult res;
   std::vector<double> rn;
   dots(G.r.as<double>(), nrhs, G.r.as<double>(), rn);
+  res.true_col.assign(nrhs, 0.0);
+  res.bnorm = bnorm;
   for (int c = 0; c < nrhs; ++c)
-    if (bnorm[c] > 0) res.true_relres = std::max(res.true_relres, std::sqrt(rn[c]) / bnorm[c]);
+    if (bnorm[c] > 0) {
+      res.true_col[c] = std::sqrt(rn[c]) / bnorm[c];
+      res.true_relres = std::max(res.true_relres, res.true_col[c]);
+    }
   if (left) {   // preconditioned residual P^-1 (b - A x)
     apply_M(G.r.as<double>(), w);
     dots(w, nrhs, w, rn);
@@ -286,8 +301,70 @@ inline GmresResult gmres_run(Problem& P, GmresWork& G, const std::function<void(
     res.relres = res.true_relres;
   }
   res.iters = 0;
+  res.iters_col = kdone;
   for (int c = 0; c < nrhs; ++c) res.iters = std::max(res.iters, kdone[c]);
   return res;
+}
+
+// Right preconditioning only. A column whose monitored residual met tol while
+// its true residual, recomputed at exit, did not (rounding in the Arnoldi
+// recurrence and in x = Z y) is restarted from that residual: GMRES on
+// A d = b - A x with the iterations the column has left, then x += d and the
+// true residual again; at most `passes` restarts. Columns are refined one at a
+// time (one-column runs), so a column's result does not depend on the others.
+// On entry G.r holds b - A x (n x nrhs, leading dimension n), as gmres_run
+// leaves it; res is updated.
+inline void gmres_restart_columns(Problem& P, GmresWork& G, const std::function<void(const double*, double*)>& A1,
+                                  const std::function<void(const double*, double*)>& M1, const double* b, double* x,
+                                  int nrhs, int64_t ld, double tol, int maxit, GmresResult& res, int passes = 3) {
+  const int64_t n = P.n;
+  auto needs = [&](int c) { return res.true_col[c] > tol && res.iters_col[c] < maxit; };
+  bool any = false;
+  for (int c = 0; c < nrhs; ++c) any = any || needs(c);
+  if (!any) return;
+  DevBuf R, D, part, dot;   // residual columns (one-column runs overwrite G.r), correction, norm partials
+  R.alloc(sizeof(double) * (size_t)(n * nrhs), &P.mem);
+  D.alloc(sizeof(double) * (size_t)n, &P.mem);
+  const int nch = (int)std::max<int64_t>(1, ceil_div(n, DOT_CHUNK));
+  part.alloc(sizeof(double) * (size_t)nch, &P.mem);
+  dot.alloc(sizeof(double), &P.mem);
+  IFMM_HIP(hipMemcpyAsync(R.p, G.r.p, sizeof(double) * (size_t)(n * nrhs), hipMemcpyDeviceToDevice, P.stream));
+  const dim3 g1((unsigned)std::max<int64_t>(1, ceil_div(n, WG)));
+  for (int pass = 0; pass < passes; ++pass) {
+    bool ran = false;
+    for (int c = 0; c < nrhs; ++c) {
+      if (!needs(c)) continue;
+      ran = true;
+      ++res.restarts;
+      double* rc = R.as<double>() + (int64_t)c * n;
+      double* xc = x + (int64_t)c * ld;
+      const GmresResult in =
+          gmres_run(P, G, A1, M1, rc, D.as<double>(), 1, n, tol / res.true_col[c], maxit - res.iters_col[c]);
+      res.iters_col[c] += std::max(1, in.iters);
+      hipLaunchKernelGGL(k_add, g1, dim3(WG), 0, P.stream, xc, (const double*)D.as<double>(), n);
+      IFMM_LAUNCH_CHECK();
+      // r_c = b_c - A x_c, ||r_c|| / ||b_c||
+      A1(xc, D.as<double>());
+      hipLaunchKernelGGL(k_copy_ld, g1, dim3(WG), 0, P.stream, b + (int64_t)c * ld, ld, n, 1, rc, n, 1.0);
+      hipLaunchKernelGGL(k_sub, g1, dim3(WG), 0, P.stream, rc, (const double*)D.as<double>(), n);
+      hipLaunchKernelGGL(k_dots, dim3(1, nch), dim3(WG), 0, P.stream, (const double*)rc, (const double*)rc, n, 1, 1,
+                         nch, part.as<double>());
+      hipLaunchKernelGGL(k_reduce_parts, dim3(1), dim3(WG), 0, P.stream, (const double*)part.as<double>(), 1, nch,
+                         dot.as<double>());
+      IFMM_LAUNCH_CHECK();
+      std::vector<double> rn;
+      P.download(rn, dot.p, 1);
+      res.true_col[c] = res.bnorm[c] > 0 ? std::sqrt(rn[0]) / res.bnorm[c] : 0.0;
+    }
+    if (!ran) break;
+  }
+  res.iters = 0;
+  res.true_relres = 0;
+  for (int c = 0; c < nrhs; ++c) {
+    res.iters = std::max(res.iters, res.iters_col[c]);
+    res.true_relres = std::max(res.true_relres, res.true_col[c]);
+  }
+  res.relres = res.true_relres;
 }
 
 }  // namespace ifmm

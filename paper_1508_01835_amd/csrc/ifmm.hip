@@ -464,10 +464,10 @@ static int gmres_entry(ifmm_handle op, ifmm_handle prec, const double* b, double
     EventPair ev;
     if (prec && prec->P.stream != A.stream) ev.create();
     if (prec && prec->P.stream != A.stream) prec->P.sync();
-    auto applyA = [&](const double* in, double* out) { matvec_any(A, in, out, nrhs, A.n); };
-    auto applyM = [&](const double* in, double* out) {
+    auto applyA_k = [&](const double* in, double* out, int k) { matvec_any(A, in, out, k, A.n); };
+    auto applyM_k = [&](const double* in, double* out, int k) {
       if (!prec) {   // no preconditioner: z = v
-        IFMM_HIP(hipMemcpyAsync(out, in, sizeof(double) * (size_t)A.n * nrhs, hipMemcpyDeviceToDevice, A.stream));
+        IFMM_HIP(hipMemcpyAsync(out, in, sizeof(double) * (size_t)A.n * k, hipMemcpyDeviceToDevice, A.stream));
         return;
       }
       Problem& M = prec->P;
@@ -478,16 +478,21 @@ static int gmres_entry(ifmm_handle op, ifmm_handle prec, const double* b, double
       {
         StreamScope ms(M.stream);   // buffers the solve takes belong to the preconditioner handle
         AllocScope ma(M.alloc);
-        solve_any(M, in, out, nrhs, M.n);
+        solve_any(M, in, out, k, M.n);
       }
       if (M.stream != A.stream) {
         IFMM_HIP(hipEventRecord(ev.b, M.stream));
         IFMM_HIP(hipStreamWaitEvent(A.stream, ev.b, 0));
       }
     };
+    auto applyA = [&](const double* in, double* out) { applyA_k(in, out, nrhs); };
+    auto applyM = [&](const double* in, double* out) { applyM_k(in, out, nrhs); };
+    auto applyA1 = [&](const double* in, double* out) { applyA_k(in, out, 1); };
+    auto applyM1 = [&](const double* in, double* out) { applyM_k(in, out, 1); };
     GmresResult r;
     try {
       r = gmres_run(A, op->G, applyA, applyM, b, x, nrhs, ld, tol, maxit, left);
+      if (!left) gmres_restart_columns(A, op->G, applyA1, applyM1, b, x, nrhs, ld, tol, maxit, r);
     } catch (...) {
       (void)hipStreamSynchronize(A.stream);
       if (prec) (void)hipStreamSynchronize(prec->P.stream);
@@ -499,6 +504,7 @@ static int gmres_entry(ifmm_handle op, ifmm_handle prec, const double* b, double
     op->G.release();   // the Krylov storage is not kept between calls
     A.st.gmres_iters = r.iters;
     A.st.gmres_relres = r.relres;
+    A.st.gmres_restarts = r.restarts;
     if (iters_out) *iters_out = r.iters;
     if (relres_out) *relres_out = r.relres;
     if (true_relres_out) *true_relres_out = r.true_relres;

@@ -45,7 +45,8 @@ struct FactorStoreBase {
 // only): duration, launch count and algorithmic flops / bytes.
 // Families 0-8 group the launches of one phase; families 9-14 hold exactly
 // one kernel each, every launch timed on its own (per-launch averages);
-// family 15 holds the launches of the step-wise pivoted QR.
+// family 15 holds the launches of the step-wise pivoted QR; families 16 and
+// 17 hold one kernel each again (streaming R-only QR, K_pre products).
 enum KFam {
   KF_SCHUR = 0, KF_LU, KF_TRSM, KF_QR, KF_SVD, KF_XFORM, KF_SOLVE, KF_MATVEC, KF_OTHER,
   KF_SVD_ROUND, KF_QR_PANEL, KF_QRCP, KF_SVD_SMALL, KF_ROW_XFORM, KF_COL_XFORM, KF_QRCP_STEP, KF_QR_NARROW,

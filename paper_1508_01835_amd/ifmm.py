@@ -77,7 +77,8 @@ class Stats(ctypes.Structure):
                 ("error_level", ctypes.c_int), ("error_box", ctypes.c_int),
                 ("gmres_iters", ctypes.c_int), ("gmres_relres", ctypes.c_double),
                 ("kfam_ms", ctypes.c_double * 24), ("kfam_flops", ctypes.c_double * 24),
-                ("kfam_bytes", ctypes.c_double * 24), ("kfam_launches", ctypes.c_int64 * 24)]
+                ("kfam_bytes", ctypes.c_double * 24), ("kfam_launches", ctypes.c_int64 * 24),
+                ("gmres_restarts", ctypes.c_int)]
 
 KFAMILIES = ["schur_gemm", "pivot_lu", "trsm_w", "qr", "jacobi_svd", "edge_update", "solve", "matvec", "other",
              "svd_round", "qr_panel", "qrcp", "svd_small", "row_xform", "col_xform", "qrcp_step", "qr_narrow",

@@ -1,11 +1,25 @@
 """Serving loop on one GPU: resident IFMM factors, continuous batching of solves.
 
 Two request kinds:
-  * factorize: points (+ one right-hand side): build a handle with FP32
-    factors, factorize it, keep it resident, then solve its right-hand side;
+  * factorize: points (+ one right-hand side): build and factorize a handle
+    (FP32 factors, FP64 when the FP32 ones fail the probe below), solve the
+    right-hand side on the factorization's worker, keep the factor resident;
   * solve: right-hand sides for a resident factor: FP64 GMRES to the
     tolerance, preconditioned by the FP32 factors (Sec. 3.2 of the paper:
     the IFMM as a preconditioner).
+
+Precision of a factor (factor_with_probe): FP32 factors first. The
+factorize request's own solve is the probe: FP64 GMRES preconditioned by
+them, at most `probe_maxit` iterations. When it does not reach the
+tolerance, the handle is built again with FP64 factors (sigma_0 passed in)
+and eps lowered so that tau = eps sigma_0 is at most shift / 20. The probe
+is needed because the FP32 error depends on the cloud, not on a bound: on
+clustered clouds the FP32 factors lose far more than FP32 rounding at the
+same truncation level as FP64. Measured at 131072 clustered points, the
+FP32 and FP64 solves differ by 4e-5, 8e-3 and 2.4 at shifts 10, 1 and 0.1.
+On the uniform cube the FP32 factors still precondition at sigma_0 / shift
+near 1e5. The kernels served are positive definite, so the shift bounds the
+smallest eigenvalue from below. A tau at or above it leaves GMRES stalled.
 
 Scheduling (host side; every step of a request runs in the HIP library):
   * admission: a factorization starts only when the device bytes of the
@@ -32,6 +46,31 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from .ifmm import IFMM
+
+
+TAU_SHIFT_FRAC = 0.05    # FP64 fallback: tau = eps sigma_0 at most this fraction of the shift
+
+
+def factor_with_probe(points, b, kernel, order: int, eps: float, leaf_max: int, tol: float, maxit: int,
+                      probe_maxit: int = 40, stream=None, depth: int = 0):
+    """Build, factorize and solve one problem: FP32 factors, and if FP64 GMRES preconditioned by them does
+    not reach `tol` within `probe_maxit` iterations, FP64 factors at min(eps, TAU_SHIFT_FRAC shift / sigma_0)
+    and GMRES again with `maxit`. points: CUDA tensor n x 3; b: CUDA tensor (n,) or (n, k); depth 0: from
+    leaf_max. Returns (handle, x, iterations of both GMRES runs, relres)."""
+    k, c, s = kernel
+    h = IFMM(points, k, c, s, depth, order, eps, precision=32, leaf_max=leaf_max, stream=stream)
+    h.factorize()
+    x, it, rr = h.gmres(b, tol=tol, maxit=min(probe_maxit, maxit))
+    if rr <= tol:
+        return h, x, it, rr
+    sigma0 = h.stats()["sigma0"]
+    h.close()
+    eps64 = min(eps, TAU_SHIFT_FRAC * s / sigma0) if s > 0 else eps
+    h = IFMM(points, k, c, s, depth, order, eps64, precision=64, leaf_max=leaf_max, stream=stream,
+             sigma0=sigma0)
+    h.factorize()
+    x, it2, rr = h.gmres(b, tol=tol, maxit=maxit)
+    return h, x, it + it2, rr
 
 
 @dataclass
@@ -77,7 +116,7 @@ class Server:
         self.bytes_per_point = 4.0e4      # first estimate; replaced by what factorizations use
         self.solve_stream = torch.cuda.Stream()
         self.stats = {"factorized_points": 0, "factor_busy_s": 0.0, "solve_busy_s": 0.0, "evicted": 0,
-                      "gmres_calls": 0, "rhs": 0}
+                      "gmres_calls": 0, "rhs": 0, "fp64_factors": 0}
 
     # ------------------------------------------------------------ factors
     def _resident_bytes(self) -> int:
@@ -104,10 +143,12 @@ class Server:
         try:
             with torch.cuda.stream(stream):
                 pts = torch.tensor(req.points, device="cuda")
-                k, c, s = self.kernel
-                h = IFMM(pts, k, c, s, 0, self.order, self.eps, precision=32, leaf_max=self.leaf_max,
-                         stream=stream)
-                h.factorize()
+                b = torch.tensor(np.random.default_rng(req.seed).standard_normal((pts.shape[0], req.nrhs)),
+                                 device="cuda")
+                h, x, it, rr = factor_with_probe(pts, b, self.kernel, self.order, self.eps, self.leaf_max,
+                                                 self.tol, self.maxit, stream=stream)
+                out["x"] = x.cpu().numpy() if self.keep else None
+                out["iters"], out["relres"] = it, rr
             out["handle"] = h
         except Exception as e:   # reported with the request
             out["error"] = e
@@ -191,11 +232,17 @@ class Server:
                 h = out["handle"]
                 st = h.stats()
                 f = _Factor(r.rid, h, h.n, int(st["device_bytes"]), now())
-                self.bytes_per_point = max(self.bytes_per_point * 0.5, 1.2 * f.bytes / f.n)
+                # reservation of later factorizations: the peak of this one per point (build and elimination)
+                self.bytes_per_point = max(self.bytes_per_point * 0.5, 1.2 * st["device_bytes_peak"] / f.n)
+                self.stats["fp64_factors"] += st["precision"] == 64
                 self.factors[r.rid] = f
                 self.stats["factorized_points"] += f.n
                 r.factor = r.rid
-                f.pending.append(r)
+                r.t_done, r.iters, r.relres, r.x = now(), out["iters"], out["relres"], out["x"]
+                done += 1
+                if self.progress:
+                    print("[serve] %d / %d requests done, %.1f s (factorization of %d points, FP%d, %d it)"
+                          % (done, total, now(), f.n, st["precision"], r.iters), file=sys.stderr, flush=True)
             # start admitted factorizations while workers are free
             while len(workers) < self.factor_workers and fq:
                 r = fq[0]

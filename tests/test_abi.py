@@ -52,24 +52,27 @@ def test_null_arguments_rejected_without_gpu_work():
     assert lib.ifmm_destroy(None) == 0
 
 
-def test_options_layout_matches_header(tmp_path):
-    """The ctypes mirror of ifmm_options has the C struct's size and field offsets (gcc on the header)."""
+@pytest.mark.parametrize("cname,mirror", [("ifmm_options", "Options"), ("ifmm_stats", "Stats"),
+                                          ("ifmm_kernel", "Kernel")])
+def test_struct_layout_matches_header(tmp_path, cname, mirror):
+    """The ctypes mirror of a header struct has its size and field offsets (gcc on the header)."""
     import ctypes
     import shutil
     import subprocess
     if shutil.which("gcc") is None:
         pytest.skip("no C compiler")
-    names = [f[0] for f in binding.Options._fields_]
+    cls = getattr(binding, mirror)
+    names = [f[0] for f in cls._fields_]
     src = tmp_path / "layout.c"
     src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "ifmm.h"\nint main(void) {\n'
-                   '  printf("%zu\\n", sizeof(ifmm_options));\n' +
-                   "".join('  printf("%%zu\\n", offsetof(ifmm_options, %s));\n' % n for n in names) +
+                   '  printf("%%zu\\n", sizeof(%s));\n' % cname +
+                   "".join('  printf("%%zu\\n", offsetof(%s, %s));\n' % (cname, n) for n in names) +
                    "  return 0;\n}\n")
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
-    assert got[0] == ctypes.sizeof(binding.Options)
-    assert got[1:] == [getattr(binding.Options, n).offset for n in names]
+    assert got[0] == ctypes.sizeof(cls)
+    assert got[1:] == [getattr(cls, n).offset for n in names]
 
 
 def test_allocator_callbacks_default_null_and_come_in_pairs():
