@@ -33,7 +33,8 @@ namespace ifmm {
 constexpr int SV_KCH = 256;   // widest partial-sum chunk (columns); a launch narrows it to 128 or 64
 constexpr int SV_MIN_WG = 1024;   // while it has fewer workgroups than this. Every right-hand-side
                                   // count uses the same chunks, so columns are solved bitwise alike
-constexpr int SV_KT = 64;     // columns staged in LDS at a time
+constexpr int SV_KT = 64;     // chunk widths are multiples of this
+constexpr int SV_FKT = 256;   // columns of x staged in LDS at a time by the forward kernel
 constexpr int SV_RT = WAVE;   // rows of one partial-sum workgroup (a row per lane)
 constexpr int SV_NW = WG / WAVE;   // its wavefronts, which split the columns
 
@@ -64,16 +65,6 @@ struct BwTask {
   double alpha;
 };
 
-template <class TK>
-__device__ inline int sv_find(const TK* __restrict__ ts, int nt, int b) {
-  int lo = 0, hi = nt - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (ts[mid].chunk0 <= b) lo = mid; else hi = mid - 1;
-  }
-  return lo;
-}
-
 // node of a task owning row (column) k; the nodes of a task are in increasing
 // off, the first at off 0: binary search for the last node with off <= k
 __device__ inline int64_t sv_pos(const SvNode* __restrict__ nodes, int node0, int nnode, int k) {
@@ -85,23 +76,49 @@ __device__ inline int64_t sv_pos(const SvNode* __restrict__ nodes, int node0, in
   return nodes[lo].pos + (k - nodes[lo].off);
 }
 
+// A workgroup copies its task's nodes into LDS first (one round trip for all
+// of them) when there are at most SV_NODE_LDS, so that the searches above run
+// in LDS instead of as chains of dependent global loads; otherwise it
+// searches the global table. Call before the workgroup's first barrier and
+// pass the result to sv_pos_any after it.
+constexpr int SV_NODE_LDS = 128;
+__device__ inline bool sv_nodes_to_lds(const SvNode* __restrict__ nodes, int node0, int nnode, SvNode* nl) {
+  if (nnode > SV_NODE_LDS) return false;
+  for (int a = threadIdx.x; a < nnode; a += WG) nl[a] = nodes[node0 + a];
+  return true;
+}
+__device__ inline int64_t sv_pos_any(bool in_lds, const SvNode* nl, const SvNode* __restrict__ nodes, int node0,
+                                     int nnode, int k) {
+  return in_lds ? sv_pos(nl, 0, nnode, k) : sv_pos(nodes, node0, nnode, k);
+}
+
 // A workgroup takes SV_RT rows of H (a row per lane); its wavefronts split
 // the m columns (k = w mod SV_NW of each staged block) and their sums are
 // added in wavefront order before wavefront 0 writes.
+// column-loop unroll: deep for few right-hand sides, shallower where the
+// NR accumulators per load already fill the registers
+template <int NR>
+constexpr int sv_unroll() { return NR >= 8 ? 4 : 16; }
+
+// The column loop is a chain of dependent adds per lane; its loads are
+// independent, so it is unrolled deep enough to keep many of them in flight
+// (the addition order stays k = w, w + SV_NW, ... whatever the unroll).
 template <class T, int NR>
-__global__ void __launch_bounds__(WG) k_sv_fwd(const FwTask* __restrict__ ts, int nt,
+__global__ void __launch_bounds__(WG) k_sv_fwd(const FwTask* __restrict__ ts, const int* __restrict__ wt,
                                                const SvNode* __restrict__ nodes, T* __restrict__ V, int nrhs,
                                                int r0) {
-  __shared__ T xb[SV_KT * NR];
+  __shared__ T xb[SV_FKT * NR];
   __shared__ T red[(SV_NW - 1) * SV_RT * NR];
-  const FwTask t = ts[sv_find(ts, nt, blockIdx.x)];
+  __shared__ SvNode nl[SV_NODE_LDS];
+  const FwTask t = ts[wt[blockIdx.x]];
+  const bool nlds = sv_nodes_to_lds(nodes, t.node0, t.nnode, nl);
   const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
   const int i = ((int)blockIdx.x - t.chunk0) * SV_RT + lane;
   const T* __restrict__ H = static_cast<const T*>(t.H);
   T acc[NR];
   for (int r = 0; r < NR; ++r) acc[r] = 0;
-  for (int k0 = 0; k0 < t.m; k0 += SV_KT) {
-    const int kn = min(SV_KT, t.m - k0);
+  for (int k0 = 0; k0 < t.m; k0 += SV_FKT) {
+    const int kn = min(SV_FKT, t.m - k0);
     __syncthreads();
     for (int e = threadIdx.x; e < kn * NR; e += WG) {
       const int k = e / NR, r = e % NR;
@@ -109,7 +126,7 @@ __global__ void __launch_bounds__(WG) k_sv_fwd(const FwTask* __restrict__ ts, in
     }
     __syncthreads();
     if (i < t.rows) {
-#pragma unroll 4
+#pragma unroll (sv_unroll<NR>())
       for (int k = w; k < kn; k += SV_NW) {
         const T h = H[i + (int64_t)(k0 + k) * t.ld];
         for (int r = 0; r < NR; ++r) acc[r] += h * xb[k * NR + r];
@@ -127,7 +144,7 @@ __global__ void __launch_bounds__(WG) k_sv_fwd(const FwTask* __restrict__ ts, in
       if (r0 + r < nrhs) V[(t.c_pos + i) * nrhs + r0 + r] = acc[r];
     return;
   }
-  const int64_t pos = sv_pos(nodes, t.node0, t.nnode, i - t.m);
+  const int64_t pos = sv_pos_any(nlds, nl, nodes, t.node0, t.nnode, i - t.m);
   for (int r = 0; r < NR; ++r)
     if (r0 + r < nrhs) V[pos * nrhs + r0 + r] -= acc[r];
 }
@@ -135,36 +152,38 @@ __global__ void __launch_bounds__(WG) k_sv_fwd(const FwTask* __restrict__ ts, in
 // partial sums of rows rc*SV_RT.. over columns kc*kch..; Part row-major with
 // NR. Wavefront w takes the columns k = w (mod SV_NW) of each staged block; the
 // wavefronts' sums are added in wavefront order.
+// The whole chunk of x (at most SV_KCH columns) is staged at once, so the
+// node searches of its columns run side by side, then one unrolled column loop
+// (addition order k = kb + w, kb + w + SV_NW, ...).
 template <class T, int NR>
-__global__ void __launch_bounds__(WG) k_sv_part(const BwTask* __restrict__ ts, int nt,
+__global__ void __launch_bounds__(WG) k_sv_part(const BwTask* __restrict__ ts, const int* __restrict__ wt,
                                                 const SvNode* __restrict__ nodes, const T* __restrict__ V, int nrhs,
                                                 int r0, T* __restrict__ Part) {
-  __shared__ T xb[SV_KT * NR];
+  __shared__ T xb[SV_KCH * NR];
   __shared__ T red[(SV_NW - 1) * SV_RT * NR];
-  const BwTask t = ts[sv_find(ts, nt, blockIdx.x)];
+  __shared__ SvNode nl[SV_NODE_LDS];
+  const BwTask t = ts[wt[blockIdx.x]];
+  const bool nlds = sv_nodes_to_lds(nodes, t.node0, t.nnode, nl);
+  __syncthreads();
   const int local = (int)blockIdx.x - t.chunk0;
   const int rc = local % t.nrc, kc = local / t.nrc;
   const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
   const int i = rc * SV_RT + lane;
   const int kb = kc * t.kch, ke = min(t.cols, kb + t.kch);
+  const int kn = ke - kb;   // <= t.kch <= SV_KCH
   const T* __restrict__ A = static_cast<const T*>(t.A);
   T acc[NR];
   for (int r = 0; r < NR; ++r) acc[r] = 0;
-  for (int k0 = kb; k0 < ke; k0 += SV_KT) {
-    const int kn = min(SV_KT, ke - k0);
-    __syncthreads();
-    for (int e = threadIdx.x; e < kn * NR; e += WG) {
-      const int k = e / NR, r = e % NR;
-      const int64_t pos = sv_pos(nodes, t.node0, t.nnode, k0 + k);
-      xb[e] = r0 + r < nrhs ? V[pos * nrhs + r0 + r] : (T)0;
-    }
-    __syncthreads();
-    if (i < t.rows) {
-#pragma unroll 4
-      for (int k = w; k < kn; k += SV_NW) {
-        const T a = A[i + (int64_t)(k0 + k) * t.ld];
-        for (int r = 0; r < NR; ++r) acc[r] += a * xb[k * NR + r];
-      }
+  for (int k = threadIdx.x; k < kn; k += WG) {
+    const int64_t pos = sv_pos_any(nlds, nl, nodes, t.node0, t.nnode, kb + k);
+    for (int r = 0; r < NR; ++r) xb[k * NR + r] = r0 + r < nrhs ? V[pos * nrhs + r0 + r] : (T)0;
+  }
+  __syncthreads();
+  if (i < t.rows) {
+#pragma unroll (sv_unroll<NR>())
+    for (int k = w; k < kn; k += SV_NW) {
+      const T a = A[i + (int64_t)(kb + k) * t.ld];
+      for (int r = 0; r < NR; ++r) acc[r] += a * xb[k * NR + r];
     }
   }
   if (w > 0)
@@ -179,15 +198,10 @@ __global__ void __launch_bounds__(WG) k_sv_part(const BwTask* __restrict__ ts, i
 
 // out = c + alpha * (sum of the partial sums in chunk order)
 template <class T, int NR>
-__global__ void __launch_bounds__(WG) k_sv_reduce(const BwTask* __restrict__ ts, int nt, T* __restrict__ V, int nrhs,
-                                                  int r0, const T* __restrict__ Part) {
-  int lo = 0, hi = nt - 1;
+__global__ void __launch_bounds__(WG) k_sv_reduce(const BwTask* __restrict__ ts, const int* __restrict__ wt,
+                                                  T* __restrict__ V, int nrhs, int r0, const T* __restrict__ Part) {
   const int b = blockIdx.x;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (ts[mid].chunk0b <= b) lo = mid; else hi = mid - 1;
-  }
-  const BwTask t = ts[lo];
+  const BwTask t = ts[wt[b]];
   // the block's WG rows x NR right-hand sides, consecutive threads on consecutive (row, rhs) pairs
   const int i0 = (b - t.chunk0b) * WG;
   for (int e = threadIdx.x; e < WG * NR; e += WG) {
@@ -228,6 +242,7 @@ struct SolvePlan {
     int kind;                 // 0: forward, 1: partial sums + reduction
     int ntasks, nwg, nwg2;
     DevBuf tasks;             // FwTask or BwTask
+    DevBuf wt, wt2;           // task of every workgroup (int): of the first kernel, of the reduction
   };
   std::vector<Launch> seq;    // in execution order
   DevBuf nodes;               // SvNode, all launches
@@ -254,6 +269,19 @@ struct SolvePlan {
     if (cap) (void)hipStreamDestroy(cap);
   }
 };
+
+// Task of every workgroup of a backward launch: partial sums (nrc x nkc
+// workgroups from chunk0) and reduction (a workgroup per WG rows from chunk0b).
+template <class T>
+inline void bw_tables(Problem& P, typename SolvePlan<T>::Launch& a, const std::vector<BwTask>& bt) {
+  std::vector<int> w((size_t)a.nwg), w2((size_t)a.nwg2);
+  for (size_t t = 0; t < bt.size(); ++t) {
+    for (int j = 0; j < bt[t].nrc * bt[t].nkc; ++j) w[(size_t)bt[t].chunk0 + j] = (int)t;
+    for (int j = 0; j < (int)ceil_div((int64_t)bt[t].rows, WG); ++j) w2[(size_t)bt[t].chunk0b + j] = (int)t;
+  }
+  P.upload(a.wt, w);
+  P.upload(a.wt2, w2);
+}
 
 template <class T>
 inline SolvePlan<T>& solve_plan(Problem& P, FactorStore<T>& F, SolvePlan<T>& S) {
@@ -349,10 +377,17 @@ inline SolvePlan<T>& solve_plan(Problem& P, FactorStore<T>& F, SolvePlan<T>& S) 
       typename SolvePlan<T>::Launch a;
       a.kind = 0; a.ntasks = (int)ft.size(); a.nwg = wg; a.nwg2 = 0;
       P.upload(a.tasks, ft);
+      {
+        std::vector<int> w((size_t)wg);
+        for (size_t t = 0; t < ft.size(); ++t)
+          for (int j = 0; j < (int)ceil_div((int64_t)ft[t].rows, SV_RT); ++j) w[(size_t)ft[t].chunk0 + j] = (int)t;
+        P.upload(a.wt, w);
+      }
       fw.push_back(std::move(a));
       typename SolvePlan<T>::Launch b;
       b.kind = 1; b.ntasks = (int)bt.size(); b.nwg = wgp; b.nwg2 = wgr;
       P.upload(b.tasks, bt);
+      bw_tables<T>(P, b, bt);
       bw.push_back(std::move(b));
     }
   }
@@ -384,6 +419,7 @@ inline SolvePlan<T>& solve_plan(Problem& P, FactorStore<T>& F, SolvePlan<T>& S) 
     a.kind = 1; a.ntasks = 1; a.nwg = b.nrc * b.nkc; a.nwg2 = (int)ceil_div((int64_t)F.ntop, WG);
     std::vector<BwTask> one(1, b);
     P.upload(a.tasks, one);
+    bw_tables<T>(P, a, one);
     S.seq.push_back(std::move(a));
     S.part_rows = std::max(S.part_rows, (int64_t)b.nkc * F.ntop);
     S.factor_elems += (double)F.ntop * F.ntop;
@@ -402,13 +438,13 @@ inline void solve_pass(Problem& P, SolvePlan<T>& S, T* V, T* Part, int nrhs, int
   for (auto& a : S.seq) {
     if (a.kind == 0) {
       hipLaunchKernelGGL((k_sv_fwd<T, NR>), dim3((unsigned)a.nwg), dim3(WG), 0, P.stream,
-                         a.tasks.template as<FwTask>(), a.ntasks, nodes, V, nrhs, r0);
+                         a.tasks.template as<FwTask>(), (const int*)a.wt.template as<int>(), nodes, V, nrhs, r0);
     } else {
       const BwTask* tk = a.tasks.template as<BwTask>();
-      hipLaunchKernelGGL((k_sv_part<T, NR>), dim3((unsigned)a.nwg), dim3(WG), 0, P.stream, tk, a.ntasks, nodes,
-                         (const T*)V, nrhs, r0, Part);
-      hipLaunchKernelGGL((k_sv_reduce<T, NR>), dim3((unsigned)a.nwg2), dim3(WG), 0, P.stream, tk, a.ntasks, V,
-                         nrhs, r0, (const T*)Part);
+      hipLaunchKernelGGL((k_sv_part<T, NR>), dim3((unsigned)a.nwg), dim3(WG), 0, P.stream, tk,
+                         (const int*)a.wt.template as<int>(), nodes, (const T*)V, nrhs, r0, Part);
+      hipLaunchKernelGGL((k_sv_reduce<T, NR>), dim3((unsigned)a.nwg2), dim3(WG), 0, P.stream, tk,
+                         (const int*)a.wt2.template as<int>(), V, nrhs, r0, (const T*)Part);
     }
     IFMM_LAUNCH_CHECK();
   }
