@@ -554,7 +554,7 @@ struct Factorizer {
     }
     T* W = F.work.template as<T>();
     const CompDesc* dc = P.put(F.d3, cs);
-    const LevelView v = L.view(P);
+    LevelView v = L.view(P);   // taken again after grow_boxes, whose uploads may move the tables
     int mmax = 1;
     for (const auto& c : cs) mmax = std::max(mmax, L.m[c.box]);
     hipLaunchKernelGGL(k_comp_gather<T>, dim3((unsigned)cs.size(), (unsigned)ceil_div(mmax, COMP_ROWS)), dim3(WG), 0,
@@ -653,6 +653,7 @@ struct Factorizer {
         for (const auto& c : cs)
           if (rn[c.box] > L.cap[c.box]) want.push_back({c.box, cap_for_rank(rn[c.box], L.m[c.box])});
         grow_boxes(L, want);
+        v = L.view(P);
       }
     }
     if (trace_on()) {   // boxes whose common rank exceeds the resolved directions of one side
@@ -1197,7 +1198,7 @@ struct Factorizer {
       chk(L, "schur", nullptr, wo);
       solve_blocks(el, fac, sol);
       chk(L, "solve_blocks", &F.arena, 0);
-      const LevelView v = L.view(P);
+      LevelView v = L.view(P);
       // near fill: added to existing edges
       hipLaunchKernelGGL(k_near_scatter<T>, dim3((unsigned)el.size(), maxF * maxF), dim3(WG), 0, P.stream, del, dF,
                          v, (const T*)W, L.P());
@@ -1213,6 +1214,7 @@ struct Factorizer {
       }
       HostScope hs_red(P.hprof, "class: redirect");
       chk(L, "recompress", nullptr, 0);
+      v = L.view(P);   // recompress may have grown boxes, which moves the level's tables
       {   // coarse levels (large ranks): batched products; fine levels: one workgroup per pair on the device
         int rmax = 0, mmax = 0;
         for (int x : L.cap) rmax = std::max(rmax, x);

@@ -213,9 +213,12 @@ struct Problem {
 
   void sync() { IFMM_HIP(hipStreamSynchronize(stream)); }
 
+  // The buffer is kept when it is large enough, so a re-upload of a table
+  // does not move it: device views taken earlier (LevelView) stay valid.
   template <class T>
   void upload(DevBuf& b, const std::vector<T>& v) {
-    b.alloc(v.size() * sizeof(T) + 16, &mem);
+    const size_t need = v.size() * sizeof(T) + 16;
+    if (!b.p || b.bytes < need) b.alloc(need, &mem);
     if (!v.empty()) {
       void* h = stage.get(v.size() * sizeof(T));
       std::memcpy(h, v.data(), v.size() * sizeof(T));

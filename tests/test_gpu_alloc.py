@@ -4,7 +4,9 @@ A handle whose device buffers come from PyTorch's caching allocator must
 compute exactly what a handle on the library's own block cache computes
 (the allocator changes where buffers live, no arithmetic), must return every
 block it took by the time it is destroyed, also when a build fails part way,
-and must work from the worker threads of a batched factorization.
+and must work from the worker threads of a batched factorization. The cache
+is filled with NaN blocks first, so a read of a freed or unwritten buffer
+cannot pass unnoticed.
 """
 import ctypes
 
@@ -29,6 +31,11 @@ def test_torch_allocator_equals_own_pool(precision):
     pts, b = to_dev(wl.points), to_dev(wl.rhs)
     res = []
     for torch_alloc in (False, True):
+        if torch_alloc:
+            # PyTorch's cache then holds NaN-filled blocks of many sizes: a buffer read before it is written, or
+            # through a pointer that a re-upload moved, gives NaN or a wild offset instead of the old contents
+            junk = [torch.full((1 << k,), float("nan"), dtype=torch.float64, device="cuda") for k in list(range(5, 22)) * 2]
+            del junk
         torch.cuda.synchronize()
         before = torch.cuda.memory_allocated()
         g = IFMM(pts, wl.kernel, wl.kparam, wl.shift, 3, 3, 1e-6, precision=precision, torch_alloc=torch_alloc)
