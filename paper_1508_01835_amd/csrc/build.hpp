@@ -52,23 +52,20 @@ inline void build_tree(Problem& P, const double* d_points, int depth, int leaf_m
   for (int k = 0; k < d; ++k) T.origin[k] = 0.5 * (lo[k] + hi[k]) - 0.5 * side;
   T.inv = 1.0 / side;
 
-  DevBuf keys_in, keys_out, idx_in, idx_out, tmp;
+  DevBuf keys_in, keys_out, idx_in, idx_out, cnt;
   keys_in.alloc(sizeof(uint64_t) * n, &P.mem);
   keys_out.alloc(sizeof(uint64_t) * n, &P.mem);
   idx_in.alloc(sizeof(int) * n, &P.mem);
   idx_out.alloc(sizeof(int) * n, &P.mem);
+  cnt.alloc(sizeof(int) * (size_t)RS_BINS * (size_t)ceil_div(n, RS_TILE), &P.mem);
   dim3 g;
   grid1(n, g);
-  auto sort_at = [&](int L) {
+  auto sort_at = [&](int L) {   // Morton keys of level L, then a stable sort on their L d bits
     hipLaunchKernelGGL(k_point_keys, g, dim3(WG), 0, P.stream, d_points, n, d, T.origin[0], T.origin[1],
                        T.origin[2], T.inv, L, keys_in.as<uint64_t>(), idx_in.as<int>());
     IFMM_LAUNCH_CHECK();
-    size_t tb = 0;
-    IFMM_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tb, keys_in.as<uint64_t>(), keys_out.as<uint64_t>(),
-                                                idx_in.as<int>(), idx_out.as<int>(), (int)n, 0, L * d, P.stream));
-    tmp.reserve(tb + 16, &P.mem);
-    IFMM_HIP(hipcub::DeviceRadixSort::SortPairs(tmp.p, tb, keys_in.as<uint64_t>(), keys_out.as<uint64_t>(),
-                                                idx_in.as<int>(), idx_out.as<int>(), (int)n, 0, L * d, P.stream));
+    radix_sort_pairs(P.stream, keys_in.as<uint64_t>(), idx_in.as<int>(), keys_out.as<uint64_t>(), idx_out.as<int>(),
+                     n, L * d, cnt.as<int>());
   };
   const int Lmax = d == 3 ? 20 : d == 2 ? 30 : 60;
   int L = depth;

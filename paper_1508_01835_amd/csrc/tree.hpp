@@ -6,12 +6,11 @@
 // are not neighbours) and colours are planned on the host.
 #pragma once
 
-#include <hipcub/hipcub.hpp>
-
 #include <algorithm>
 #include <unordered_map>
 
 #include "common.hpp"
+#include "sort.hpp"
 
 namespace ifmm {
 
