@@ -433,6 +433,39 @@ def run_batch(args):
     print(json.dumps(out))
 
 
+def run_solve(args):
+    """Solve latency alone on the clustered 2^20-point workload: FP32 factors at eps 1e-5, then
+    --latency-reps single-right-hand-side solves (HIP-graph replay), p50 / p99 and the rate over the stored
+    factors. For kernel traces of the substitution without the bench's other legs."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_1508_01835_amd import IFMM
+
+    wl = W.cluster3d(args.n_per_cluster, args.depth_cluster)
+    pts = torch.tensor(wl.points, device="cuda")
+    b = torch.tensor(np.ascontiguousarray(wl.rhs[:, 0]), device="cuda")
+    g = IFMM(pts, wl.kernel, wl.kparam, wl.shift, wl.depth, wl.order, 1e-5, precision=32)
+    g.factorize()
+    lat = []
+    for _ in range(args.latency_reps + 3):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        g.solve(b)
+        torch.cuda.synchronize()
+        lat.append((time.perf_counter() - t) * 1e3)
+    lat = np.array(lat[3:])
+    fb = g.stats()["factor_bytes"]
+    g.close()
+    p50 = float(np.percentile(lat, 50))
+    print(json.dumps({"metric": "IFMM solve latency (1 RHS, FP32 factors)", "value": p50, "unit": "ms",
+                      "p99": float(np.percentile(lat, 99)), "reps": int(lat.size), "factor_bytes": int(fb),
+                      "hbm_GBs_at_p50": fb / (p50 * 1e-3) / 1e9, "higher_is_better": False,
+                      "config": {"workload": "cluster3d_%d: FP32 factors at eps 1e-5, depth %d, order 4"
+                                             % (wl.n, wl.depth)}}))
+
+
 def run_calib():
     """Counter calibration: three device copies of 512 MiB (FP64 ones), so that rocprofv3's FETCH_SIZE and
     WRITE_SIZE per dispatch can be compared with the bytes known to move (run under --pmc)."""
@@ -577,7 +610,7 @@ def main():
                     help="timed steps only: no latency, time-to-tolerance or CPU runs (for counter runs)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="end with a 512 MiB device-to-device copy, the reference for HBM byte counters")
-    ap.add_argument("--workload", choices=["cluster3d", "uniform3d", "batch", "serve", "paper", "calib"],
+    ap.add_argument("--workload", choices=["cluster3d", "uniform3d", "batch", "serve", "paper", "calib", "solve"],
                     default="cluster3d")
     ap.add_argument("--n-per-cluster", type=int, default=131072)
     ap.add_argument("--depth-cluster", type=int, default=7)
@@ -615,6 +648,9 @@ def main():
         return
     if args.workload == "calib":
         run_calib()
+        return
+    if args.workload == "solve":
+        run_solve(args)
         return
     if args.workload == "cluster3d":
         run_cluster3d(args)
