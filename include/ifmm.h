@@ -243,9 +243,11 @@ int ifmm_matvec(ifmm_handle h, const double* x, double* y, int nrhs, int64_t ld)
  * runs of Sec. 3.2); op then need not be factorized. Each column is an
  * independent GMRES run. Rounding can leave the true residual, recomputed at
  * exit, above tol when the monitored one has met it. Such a column is then
- * restarted from its true residual with the iterations it has left (x += d,
- * A~ d = b - A~ x, at most 3 restarts). It is refined alone, so its result
- * does not depend on the other columns.
+ * restarted from its true residual (x += d, A~ d = b - A~ x). There are at
+ * most 3 restarts of at most 10 iterations each, within the iterations the
+ * column has left. The restarts stop when one takes less than 1% off the
+ * residual. The column is refined alone, so its result does not depend on the
+ * other columns.
  *   b, x        device, n x nrhs, leading dimension ld; x is overwritten;
  *               x and b must not overlap (IFMM_ERR_ARG)
  *   tol         stop when ||b - A~ x|| <= tol ||b|| (per column)

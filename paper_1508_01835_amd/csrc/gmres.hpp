@@ -309,16 +309,21 @@ inline GmresResult gmres_run(Problem& P, GmresWork& G, const std::function<void(
 // Right preconditioning only. A column whose monitored residual met tol while
 // its true residual, recomputed at exit, did not (rounding in the Arnoldi
 // recurrence and in x = Z y) is restarted from that residual: GMRES on
-// A d = b - A x with the iterations the column has left, then x += d and the
-// true residual again; at most `passes` restarts. Columns are refined one at a
-// time (one-column runs), so a column's result does not depend on the others.
+// A d = b - A x with at most GMRES_RESTART_ITERS of the iterations the column
+// has left, then x += d and the true residual again; at most `passes`
+// restarts, and none after a restart that took less than 1% off the true
+// residual (the residual is then at the rounding floor of the product itself,
+// where more iterations only cost time). Columns are refined one at a time
+// (one-column runs), so a column's result does not depend on the others.
 // On entry G.r holds b - A x (n x nrhs, leading dimension n), as gmres_run
 // leaves it; res is updated.
+constexpr int GMRES_RESTART_ITERS = 10;
 inline void gmres_restart_columns(Problem& P, GmresWork& G, const std::function<void(const double*, double*)>& A1,
                                   const std::function<void(const double*, double*)>& M1, const double* b, double* x,
                                   int nrhs, int64_t ld, double tol, int maxit, GmresResult& res, int passes = 3) {
   const int64_t n = P.n;
-  auto needs = [&](int c) { return res.true_col[c] > tol && res.iters_col[c] < maxit; };
+  std::vector<char> stalled(nrhs, 0);
+  auto needs = [&](int c) { return !stalled[c] && res.true_col[c] > tol && res.iters_col[c] < maxit; };
   bool any = false;
   for (int c = 0; c < nrhs; ++c) any = any || needs(c);
   if (!any) return;
@@ -338,8 +343,9 @@ inline void gmres_restart_columns(Problem& P, GmresWork& G, const std::function<
       ++res.restarts;
       double* rc = R.as<double>() + (int64_t)c * n;
       double* xc = x + (int64_t)c * ld;
-      const GmresResult in =
-          gmres_run(P, G, A1, M1, rc, D.as<double>(), 1, n, tol / res.true_col[c], maxit - res.iters_col[c]);
+      const double before = res.true_col[c];
+      const GmresResult in = gmres_run(P, G, A1, M1, rc, D.as<double>(), 1, n, tol / before,
+                                       std::min(maxit - res.iters_col[c], GMRES_RESTART_ITERS));
       res.iters_col[c] += std::max(1, in.iters);
       hipLaunchKernelGGL(k_add, g1, dim3(WG), 0, P.stream, xc, (const double*)D.as<double>(), n);
       IFMM_LAUNCH_CHECK();
@@ -355,6 +361,7 @@ inline void gmres_restart_columns(Problem& P, GmresWork& G, const std::function<
       std::vector<double> rn;
       P.download(rn, dot.p, 1);
       res.true_col[c] = res.bnorm[c] > 0 ? std::sqrt(rn[0]) / res.bnorm[c] : 0.0;
+      if (res.true_col[c] > 0.99 * before) stalled[c] = 1;
     }
     if (!ran) break;
   }
