@@ -76,8 +76,8 @@ __global__ void __launch_bounds__(RS_SCAN_WG) k_rs_scan(int* __restrict__ cnt, i
 __global__ void __launch_bounds__(RS_WG) k_rs_scatter(const uint64_t* __restrict__ kin, const int* __restrict__ vin,
                                                       int64_t n, int shift, int ntiles, const int* __restrict__ off,
                                                       uint64_t* __restrict__ kout, int* __restrict__ vout) {
-  __shared__ int run[RS_BINS];               // keys of each digit placed by earlier rounds of this tile
-  __shared__ int wc[RS_WAVES][RS_BINS];      // keys of each digit in each wavefront of this round
+  __shared__ int run[RS_BINS];               // keys of each digit placed by earlier steps of this tile
+  __shared__ int wc[RS_WAVES][RS_BINS];      // keys of each digit in each wavefront of this step
   const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
   run[threadIdx.x] = off[(int64_t)threadIdx.x * ntiles + blockIdx.x];
   for (int v = 0; v < RS_WAVES; ++v) wc[v][threadIdx.x] = 0;
@@ -85,7 +85,7 @@ __global__ void __launch_bounds__(RS_WG) k_rs_scatter(const uint64_t* __restrict
   const int64_t base = (int64_t)blockIdx.x * RS_TILE;
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (WAVE - lane));
   for (int j = 0; j < RS_ITEMS; ++j) {
-    const int64_t i = base + (int64_t)j * RS_WG + threadIdx.x;   // index order = (round, thread)
+    const int64_t i = base + (int64_t)j * RS_WG + threadIdx.x;   // index order = (step, thread)
     const bool ok = i < n;
     const uint64_t key = ok ? kin[i] : 0;
     const int dg = (int)((key >> shift) & (RS_BINS - 1));
